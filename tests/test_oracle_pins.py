@@ -221,16 +221,15 @@ def test_antenna_polarisation_rotation_law():
 
 
 def test_sky_and_orientation_average_is_4_over_25():
-    """<F+^2 ((1+c^2)/2)^2 + Fx^2 c^2> over isotropic sky, psi and cos(iota) = (1/5)(7/15) + (1/5)(1/3) = 4/25."""
+    """Isotropic sky, uniform psi and cos(iota): <|F+ h+ + Fx hx|^2> / |h+(face-on)|^2 = (1/5)(7/15) + (1/5)(1/3) = 4/25."""
     lat, lon, ax, ay = synth.detector_rad("D3")
     _, d = o.detector_geometry(lat, lon, ax, ay)
     xs, ws = np.polynomial.legendre.leggauss(24)
     n_ang = 12
     ras = 2 * math.pi * np.arange(n_ang) / n_ang
     psis = math.pi * np.arange(n_ang) / n_ang
-    ci2_avg = 0.5 * float(np.sum(ws * xs ** 2))
-    ci_f_avg = 0.5 * float(np.sum(ws * (0.5 * (1 + xs ** 2)) ** 2))
-    acc_p, acc_x = 0.0, 0.0
+    # sky part: <F+^2> = <Fx^2> = 1/5 and <F+ Fx> = 0
+    acc_p, acc_x, acc_px = 0.0, 0.0, 0.0
     for s, w in zip(xs, ws):
         dec = math.asin(s)
         for ra in ras:
@@ -238,9 +237,34 @@ def test_sky_and_orientation_average_is_4_over_25():
                 fp, fx = o.antenna(d, torch.tensor(ra, dtype=DT), torch.tensor(dec, dtype=DT), torch.tensor(psi, dtype=DT))
                 acc_p += 0.5 * w * float(fp) ** 2 / n_ang ** 2
                 acc_x += 0.5 * w * float(fx) ** 2 / n_ang ** 2
+                acc_px += 0.5 * w * float(fp) * float(fx) / n_ang ** 2
     assert acc_p == pytest.approx(0.2, abs=1e-12)
     assert acc_x == pytest.approx(0.2, abs=1e-12)
-    assert acc_p * ci_f_avg + acc_x * ci2_avg == pytest.approx(4.0 / 25.0, abs=1e-12)
+    assert abs(acc_px) < 1e-12
+    # orientation part, from the oracle's own polarisations at one frequency
+    f = torch.tensor([100.0], dtype=DT)
+    base = [25.0, 0.8, 0.0, 0.0, 500.0, 0.0, 0.0, 0.0, 0.0, 0.3, 0.0]
+    hp0, _ = o.polarizations(f, torch.tensor(base, dtype=DT))
+    ap, ax_, apx = 0.0, 0.0, 0.0
+    for c, w in zip(xs, ws):
+        th = list(base); th[7] = math.acos(c)
+        hp, hc = o.polarizations(f, torch.tensor(th, dtype=DT))
+        ap += 0.5 * w * float(abs(hp[0]) ** 2 / abs(hp0[0]) ** 2)
+        ax_ += 0.5 * w * float(abs(hc[0]) ** 2 / abs(hp0[0]) ** 2)
+        apx += 0.5 * w * float(torch.real(hp[0] * torch.conj(hc[0])) / abs(hp0[0]) ** 2)
+    assert ap == pytest.approx(7.0 / 15.0, abs=1e-12)
+    assert ax_ == pytest.approx(1.0 / 3.0, abs=1e-12)
+    assert abs(apx) < 1e-12
+    assert acc_p * ap + acc_x * ax_ == pytest.approx(4.0 / 25.0, abs=1e-12)
+
+
+def test_quadrupole_radiation_pattern_edge_on():
+    """Edge-on (iota = pi/2) the cross polarisation vanishes and h_+ is half its face-on amplitude."""
+    f = torch.tensor([30.0, 300.0], dtype=DT)
+    th = torch.tensor([25.0, 0.8, 0.1, 0.2, 500.0, 0.0, 0.0, math.pi / 2, 0.0, 0.3, 0.0], dtype=DT)
+    hp, hc = o.polarizations(f, th)
+    assert float(torch.abs(hc).max()) < 1e-15 * float(torch.abs(hp).max())
+    np.testing.assert_allclose(np.abs(hp.numpy()), 0.5 * spa_amplitude(25.0, 500.0, f.numpy()), rtol=1e-12)
 
 
 def test_time_delay_special_cases():
