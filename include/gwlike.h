@@ -1,0 +1,181 @@
+/*
+ * gwlike.h -- C ABI of the batched frequency-domain compact-binary log-likelihood library
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * The library evaluates, for a batch of B parameter points theta, the Gaussian-noise
+ * log-likelihood ratio of the paper's Eq. 2 (section 2, "Bayesian Inference"):
+ *
+ *     logL(theta) = sum_det [ <d|h(theta)> - 1/2 <h(theta)|h(theta)> ],
+ *     <a|b>       = 4 df Re sum_k conj(a_k) b_k / S_k,
+ *
+ * which is Eq. 2's exponent -(2/T)|d - h|^2 / S summed over independent bins (T = 1/df),
+ * minus the same with h = 0 (the theta-independent 1/(2 pi S) prefactor cancels). The paper
+ * names this evaluation the dominant cost of inference (section 2.2) and the bottleneck that
+ * its parallel nested sampling spreads over processes (section 3, "Parallel prior sampling");
+ * here the batch axis B plays the role of those processes.
+ *
+ * Signal model (the paper names none that is available; these conventions are the library's):
+ * TaylorF2 inspiral, 3.5PN non-spinning phase with aligned-spin 1.5PN (beta) and 2PN (sigma)
+ * terms, Newtonian amplitude A = sqrt(5/24) pi^(-2/3) (G Mc/c^3)^(5/6) c / D_L,
+ *     h_+ = A f^(-7/6) (1 + cos^2 i)/2 e^{-i Psi(f)},  h_x = -i A f^(-7/6) cos(i) e^{-i Psi(f)},
+ *     Psi(f) = 2 pi f t_c - phi_c - pi/4 + 3/(128 eta v^5) sum_k phi_k v^k,  v = (pi G M f / c^3)^(1/3),
+ * projected on L-shaped detectors on a spherical Earth (radius 6.371e6 m):
+ *     h_det = (F_+ h_+ + F_x h_x) e^{-2 pi i f dt_det},  dt_det = -(r_det . k) / c.
+ * Fourier convention x~(f) = int x(t) e^{-2 pi i f t} dt.
+ *
+ * Parameter layout theta[B][11], row-major float64, columns:
+ *   0 chirp mass Mc (Msun, detector frame)   1 q = m2/m1 in (0, 1]   2 chi1   3 chi2 (aligned)
+ *   4 luminosity distance (Mpc)              5 right ascension (rad) 6 declination (rad)
+ *   7 inclination (rad)                      8 polarisation psi (rad) 9 coalescence phase (rad)
+ *   10 geocentre coalescence time t_c (s)
+ * A row with a non-finite value, q outside (0, 1], Mc <= 0, D_L <= 0 or |chi| >= 1 yields
+ * logL = NaN (and a NaN gradient row); the call still returns GWL_OK.
+ *
+ * Conventions for every call:
+ *   - Device pointers are HIP device (HBM) addresses on the current device; host pointers are
+ *     ordinary process memory. The caller owns every buffer it passes; the library owns the
+ *     opaque handles and the device tables inside them.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream). Calls that take a
+ *     stream are asynchronous and stream-ordered: outputs are valid once the stream has
+ *     reached the call. Handles are immutable after creation and may be used concurrently
+ *     from several streams.
+ *   - Argument errors are detected on the host before any launch and return GWL_E_INVALID or
+ *     GWL_E_SHAPE with a message in gwl_last_error(); a failing HIP call returns
+ *     GWL_E_DEVICE. No C++ exception crosses this interface. Nothing is written on error.
+ */
+#ifndef GWLIKE_H
+#define GWLIKE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GWL_OK = 0,
+  GWL_E_INVALID = -1,     /* bad argument value (null pointer, non-positive size, bad PSD, ...) */
+  GWL_E_SHAPE = -2,       /* sizes inconsistent with each other or beyond the supported range    */
+  GWL_E_DEVICE = -3,      /* a HIP runtime call failed (message names it)                      */
+  GWL_E_NOMEM = -4,       /* device allocation failed                                          */
+  GWL_E_UNSUPPORTED = -5, /* valid request this build does not implement                       */
+  GWL_E_INTERNAL = -6
+} gwl_status;
+
+typedef enum { GWL_FP64 = 0, GWL_MIXED = 1 } gwl_precision;
+
+/* Largest detector count per event. */
+#define GWL_MAX_DET 4
+/* Number of parameters per point. */
+#define GWL_NPARAM 11
+
+/* An L-shaped detector: vertex latitude and longitude, azimuths of the x and y arms measured
+ * clockwise from local North (all radians). Arms are horizontal. */
+typedef struct {
+  double lat, lon, xarm_az, yarm_az;
+} gwl_detector;
+
+typedef struct gwl_event_s* gwl_event;
+typedef struct gwl_plan_s* gwl_plan;
+
+/* Thread-local text of the last error on this thread ("" if none). */
+const char* gwl_last_error(void);
+
+/* Library version string. */
+const char* gwl_version(void);
+
+/*
+ * Create an event: one data segment seen by `ndet` detectors on a common frequency grid.
+ *   data   device, float64 [ndet][M][2]  (complex d~_k, interleaved re, im; strain/Hz)
+ *   psd    device, float64 [ndet][M]     (one-sided noise PSD S_k > 0, 1/Hz)
+ *   fgrid  device, float64 [M]           (bin frequencies f_k > 0, Hz)
+ *   dets   host,   gwl_detector [ndet]
+ *   df     frequency spacing = 1/T (s^-1); the 4 df of the inner product uses it
+ *   gmst   Greenwich sidereal angle (rad) of the segment, held fixed across the segment
+ *   flags  0 (reserved)
+ * The call prepares the per-bin tables of the factored likelihood on the device (event
+ * preparation, section 2 Eq. 2 rearranged: u_k = 4 df f_k^(-7/6) conj(d_k)/S_k and
+ * K_det = 4 df sum_k f_k^(-7/3)/S_k) and synchronises `stream` before returning, so the
+ * caller may free data, psd and fgrid afterwards. Returns GWL_E_INVALID if any PSD value is
+ * not finite and positive, any f_k is not finite and positive, or any data value is not finite.
+ */
+gwl_status gwl_event_create(const double* data, const double* psd, const gwl_detector* dets, int ndet,
+                            const double* fgrid, int64_t M, double df, double gmst, unsigned flags,
+                            void* stream, gwl_event* out);
+
+/* Release an event and its device tables. Null is accepted. The caller must ensure no work
+ * using the event is still pending on any stream. */
+gwl_status gwl_event_destroy(gwl_event ev);
+
+/* Query sizes of an event (any pointer may be null). */
+gwl_status gwl_event_info(gwl_event ev, int* ndet, int64_t* M, double* df);
+
+/*
+ * logL for a batch (paper Eq. 2, as the ratio above).
+ *   theta  device, float64 [B][11];  logl device, float64 [B].
+ *   prec   GWL_FP64: every step in float64.
+ *          GWL_MIXED: float64 for the post-Newtonian phase, the time-shift term and its
+ *          reduction modulo one cycle, and for every per-point scalar and reduction; float32
+ *          for the per-bin phasor, complex multiply-accumulate over short blocks of bins.
+ * B = 0 is a no-op. Workspace is taken from the stream-ordered device memory pool.
+ */
+gwl_status gwl_logl_batch(gwl_event ev, const double* theta, int64_t B, gwl_precision prec, double* logl,
+                          void* stream);
+
+/*
+ * logL and its gradient with respect to all 11 parameters (adjoint of the same evaluation,
+ * fused with the forward pass; feeds gradient-based proposals of the sampler in section 3).
+ *   grad   device, float64 [B][11] (same column order as theta).
+ */
+gwl_status gwl_logl_grad(gwl_event ev, const double* theta, int64_t B, gwl_precision prec, double* logl,
+                         double* grad, void* stream);
+
+/*
+ * Detector-frame strain h_det(f_k) for a batch of points (the signal model above), used to
+ * build injections and to check the model on its own.
+ *   theta  device float64 [B][11]; fgrid device float64 [M]; dets host [ndet]
+ *   out    device float64 [B][ndet][M][2] (complex, interleaved)
+ */
+gwl_status gwl_waveform(const double* theta, int64_t B, const gwl_detector* dets, int ndet, const double* fgrid,
+                        int64_t M, double gmst, double* out, void* stream);
+
+/*
+ * Several events of uneven size in one persistent launch (the batch axis of the paper's
+ * parallel prior sampling, section 3, extended across events).
+ * gwl_multi_plan_create builds the work list (event, point group, bin range), sizes the
+ * workspace for the given per-event batch sizes B_e, picks tile shapes, and captures the whole
+ * evaluation (queue reset, per-point set-up, persistent kernel, per-event finalisation) in a
+ * HIP graph bound to the events. The events must outlive the plan.
+ *   evs       host [E] event handles;  B_e host int64 [E] (each >= 0)
+ *   with_grad 0: logL only; 1: logL and gradient
+ */
+gwl_status gwl_multi_plan_create(const gwl_event* evs, int E, const int64_t* B_e, gwl_precision prec,
+                                 int with_grad, gwl_plan* out);
+
+/*
+ * Run a plan. theta[e], logl[e], grad[e] are device pointers ([B_e][11], [B_e], [B_e][11]);
+ * grad may be null when the plan has no gradient. The pointer tables are host arrays of E
+ * entries. If event_latency_us is non-null it receives, per event, the time from the start of
+ * the launch to the completion of that event's results (device clock), and the call then
+ * synchronises `stream`.
+ */
+gwl_status gwl_multi_launch(gwl_plan pl, const double* const* theta, double* const* logl, double* const* grad,
+                            double* event_latency_us, void* stream);
+
+gwl_status gwl_plan_destroy(gwl_plan pl);
+
+/*
+ * Time candidate tile shapes for (event, B, precision, with_grad) on the device and record the
+ * fastest in the JSON cache file `cache_path` (created or updated; null = in-memory only).
+ * Later calls with a matching shape use the cached choice. Synchronises the device.
+ */
+gwl_status gwl_autotune(const char* cache_path, gwl_event ev, int64_t B, gwl_precision prec, int with_grad);
+
+/* Load tile choices from a JSON cache written by gwl_autotune (missing file = GWL_E_INVALID). */
+gwl_status gwl_autotune_load(const char* cache_path);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GWLIKE_H */

@@ -1,0 +1,72 @@
+// Layouts shared by the host runtime and the kernels of the batched log-likelihood library.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+namespace gwl {
+
+constexpr int NPARAM = 11;   // parameters per point
+constexpr int MAXDET = 4;    // detectors per event
+constexpr int NBASIS = 8;    // per-bin phase basis functions g_m(f) (see gwl_device.h)
+constexpr int WAVE = 64;     // CDNA wavefront width: one lane per parameter point
+constexpr int WAVES_PER_BLOCK = 4;
+constexpr int BLOCK = WAVE * WAVES_PER_BLOCK;
+constexpr int NXCD = 8;      // MI355X accelerator complex dies; workgroups are dealt round-robin
+
+// Detector geometry of an event, computed once on the host:
+// dt = detector tensor (xx, yy, zz, xy, xz, yz), r = vertex position (m).
+struct EventGeom {
+  int ndet;
+  double gmst;
+  double dt[MAXDET][6];
+  double r[MAXDET][3];
+};
+
+// Per-event scalars produced on the device by event preparation.
+struct EventConst {
+  double K[MAXDET];   // 4 df sum_k f_k^(-7/3) / S_k
+  double uref;        // power of two >= max |u|: the float32 tables hold u / uref
+  int bad;            // nonzero if an input value was rejected
+  int pad;
+};
+
+// Per-bin rows, one row per frequency bin, read wave-uniformly by the bin loop.
+// Basis: f, x = f^(1/3), w = f^(-5/3), w2 = f^(-1), ln f.
+template <int ND>
+struct RowMixed {          // float64 basis + float32 u / uref per detector (re, im)
+  double f, x, w, w2, lnf;
+  float u[2 * ND];
+};
+template <int ND>
+struct RowF64 {            // float64 basis + float64 u per detector (re, im)
+  double f, x, w, w2, lnf;
+  double u[2 * ND];
+};
+struct RowGradF32 {        // float32 phase basis g_0..g_7 and f, for the adjoint moments
+  float g[NBASIS];
+  float f;
+};
+struct RowGradF64 {        // float64 g_m not already in RowF64: f^-2/3, f^-1/3, f^1/3 ln f, f^2/3
+  double g2, g3, g6, g7;
+};
+
+static_assert(sizeof(RowMixed<1>) == 48 && sizeof(RowMixed<3>) == 64 && sizeof(RowMixed<4>) == 72, "row layout");
+static_assert(sizeof(RowF64<1>) == 56 && sizeof(RowF64<3>) == 88 && sizeof(RowF64<4>) == 104, "row layout");
+static_assert(sizeof(RowGradF32) == 36 && sizeof(RowGradF64) == 32, "row layout");
+
+// Per-point coefficient rows written by the set-up kernel, structure of arrays [row][Bp]:
+constexpr int CO_A = 0;              // a_0..a_7 phase coefficients (cycles)
+constexpr int CO_T = CO_A + NBASIS;  // T_det = t_c + dt_det, MAXDET rows
+constexpr int CO_QR = CO_T + MAXDET; // Re Q_det
+constexpr int CO_QI = CO_QR + MAXDET;// Im Q_det
+constexpr int CO_C0 = CO_QI + MAXDET;// constant phase (cycles)
+constexpr int CO_AMP = CO_C0 + 1;    // amplitude A
+constexpr int NCOEF = CO_AMP + 1;
+
+// Accumulated sums per point, per bin chunk (partials [chunk][z][Bp]):
+//   forward : Z_det (re, im)                                         -> 2 ND
+//   adjoint : + Z1_det = sum f u p (re, im), + Ybar_m (re, im), m < 8 -> 4 ND + 16
+__host__ __device__ constexpr int nz_of(int nd, bool grad) { return grad ? 4 * nd + 2 * NBASIS : 2 * nd; }
+
+}  // namespace gwl

@@ -1,0 +1,48 @@
+// Host-side launch wrappers of the kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "gwl_common.h"
+
+namespace gwl {
+
+// Shape of one bin-loop launch: points in groups of 64 (one wavefront), bins in `nchunk`
+// chunks of `chunk` bins; items = nchunk * ceil(npg / WAVES_PER_BLOCK) workgroups, dealt so
+// that each accelerator die works through a contiguous range of chunks.
+struct LoopShape {
+  int npg;      // point groups = ceil(B / 64)
+  int nchunk;   // bin chunks
+  int chunk;    // bins per chunk
+  int nbpg;     // workgroups per chunk = ceil(npg / WAVES_PER_BLOCK)
+  int items;    // nchunk * nbpg
+  int gper;     // workgroups per die = ceil(items / NXCD)
+};
+LoopShape make_shape(int64_t B, int64_t M, int nchunk);
+
+// event preparation: per-bin tables, K_det and the float32 scale
+hipError_t launch_prep(int nd, const double* data, const double* psd, const double* fgrid, int64_t M, double df,
+                       void* tab64, void* tab32, RowGradF32* g32, RowGradF64* g64, double* blockpart, int nblk,
+                       EventConst* ec, hipStream_t s);
+int prep_blocks(int64_t M);
+
+// per-point set-up: theta[B][11] -> coef[NCOEF][Bp]
+hipError_t launch_setup(int nd, const EventGeom& g, const double* theta, int64_t B, int64_t Bp, double* coef,
+                        hipStream_t s);
+
+// bin loop: coef -> partial sums [nchunk][nz][Bp]
+hipError_t launch_bins(int nd, bool mixed, bool grad, const void* tab, const void* gtab, const void* gtab64,
+                       const double* coef, int64_t B, int64_t Bp, int64_t M, const LoopShape& sh, double* part,
+                       hipStream_t s);
+
+// epilogue: partial sums -> logL[B] (and grad[B][11])
+// `scaled`: the partial sums came from the float32 tables, which hold u / uref
+hipError_t launch_epilogue(int nd, bool grad, bool scaled, const EventGeom& g, const EventConst* ec,
+                           const double* theta, int64_t B, int64_t Bp, int nchunk, const double* part, double* logl,
+                           double* gradout, hipStream_t s);
+
+// model strain on a grid: out[B][nd][M][2]
+hipError_t launch_waveform(int nd, const EventGeom& g, const double* coef, int64_t B, int64_t Bp,
+                           const double* fgrid, int64_t M, double* out, hipStream_t s);
+
+}  // namespace gwl

@@ -1,0 +1,48 @@
+// Internal host-side declarations shared by the runtime's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/gwlike.h"
+#include "gwl_common.h"
+#include "gwl_launch.h"
+
+struct gwl_event_s {
+  int device = 0;
+  int ndet = 0;
+  int64_t M = 0;
+  double df = 0.0;
+  double gmst = 0.0;
+  gwl_detector dets[GWL_MAX_DET] = {};
+  gwl::EventGeom geom = {};
+  void* tab64 = nullptr;             // RowF64<ndet>[M]
+  void* tab32 = nullptr;             // RowMixed<ndet>[M]
+  gwl::RowGradF32* g32 = nullptr;    // [M]
+  gwl::RowGradF64* g64 = nullptr;    // [M]
+  gwl::EventConst* ec = nullptr;     // device copy
+  gwl::EventConst ech = {};          // host copy
+};
+
+namespace gwl {
+
+constexpr int64_t kMaxBatch = (int64_t)1 << 30;
+
+gwl_status fail(gwl_status st, const char* fmt, ...);
+gwl_status hip_fail(hipError_t e, const char* what);
+void clear_error();
+gwl_status check_device(int dev);
+gwl_status make_geom(const gwl_detector* dets, int ndet, double gmst, EventGeom& g);
+size_t row64_bytes(int nd);
+size_t row32_bytes(int nd);
+size_t workspace_bytes(int64_t Bp, int nchunk, int nd, bool grad);
+
+// number of bin chunks for a launch (autotuner cache, else a heuristic)
+int choose_nchunk(const gwl_event_s* ev, int64_t B, bool mixed, bool grad);
+int heuristic_nchunk(int64_t B, int64_t M);
+
+gwl_status run_logl(gwl_event ev, const double* theta, int64_t B, bool mixed, bool grad, const LoopShape& sh,
+                    double* logl, double* gradout, hipStream_t s);
+hipError_t enqueue_logl(gwl_event ev, const double* theta, int64_t B, bool mixed, bool grad, const LoopShape& sh,
+                        double* coef, double* part, double* logl, double* gradout, hipStream_t s);
+
+}  // namespace gwl

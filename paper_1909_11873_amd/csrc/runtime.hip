@@ -1,0 +1,253 @@
+// Host runtime of the C ABI in include/gwlike.h: argument checking, event tables, workspace,
+// launch sequencing, tile choice. All computation happens in the kernels.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+
+#include "../../include/gwlike.h"
+#include "gwl_common.h"
+#include "gwl_launch.h"
+#include "gwl_runtime.h"
+
+using namespace gwl;
+
+namespace gwl {
+
+static thread_local std::string g_err;
+
+gwl_status fail(gwl_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+gwl_status hip_fail(hipError_t e, const char* what) {
+  if (e == hipErrorOutOfMemory) return fail(GWL_E_NOMEM, "%s: %s", what, hipGetErrorString(e));
+  return fail(GWL_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+void clear_error() { g_err.clear(); }
+
+size_t row64_bytes(int nd) { return 40 + 16 * (size_t)nd; }
+size_t row32_bytes(int nd) { return 40 + 8 * (size_t)nd; }
+
+// Detector tensor and vertex of an L-shaped detector (arms horizontal, azimuths clockwise
+// from North) on a spherical Earth.
+static void detector_geometry(const gwl_detector& d, double dt[6], double r[3]) {
+  const double RE = 6.371e6;
+  const double sl = sin(d.lat), cl = cos(d.lat), so = sin(d.lon), co = cos(d.lon);
+  const double north[3] = {-sl * co, -sl * so, cl};
+  const double east[3] = {-so, co, 0.0};
+  double xa[3], ya[3];
+  for (int i = 0; i < 3; ++i) {
+    xa[i] = cos(d.xarm_az) * north[i] + sin(d.xarm_az) * east[i];
+    ya[i] = cos(d.yarm_az) * north[i] + sin(d.yarm_az) * east[i];
+  }
+  const int ii[6] = {0, 1, 2, 0, 0, 1}, jj[6] = {0, 1, 2, 1, 2, 2};
+  for (int m = 0; m < 6; ++m) dt[m] = 0.5 * (xa[ii[m]] * xa[jj[m]] - ya[ii[m]] * ya[jj[m]]);
+  r[0] = RE * cl * co;
+  r[1] = RE * cl * so;
+  r[2] = RE * sl;
+}
+
+gwl_status make_geom(const gwl_detector* dets, int ndet, double gmst, EventGeom& g) {
+  if (!dets) return fail(GWL_E_INVALID, "dets is null");
+  if (ndet < 1 || ndet > GWL_MAX_DET) return fail(GWL_E_SHAPE, "ndet=%d outside [1, %d]", ndet, GWL_MAX_DET);
+  if (!isfinite(gmst)) return fail(GWL_E_INVALID, "gmst is not finite");
+  memset(&g, 0, sizeof g);
+  g.ndet = ndet;
+  g.gmst = gmst;
+  for (int d = 0; d < ndet; ++d) {
+    const gwl_detector& x = dets[d];
+    if (!isfinite(x.lat) || !isfinite(x.lon) || !isfinite(x.xarm_az) || !isfinite(x.yarm_az))
+      return fail(GWL_E_INVALID, "detector %d has a non-finite angle", d);
+    detector_geometry(x, g.dt[d], g.r[d]);
+  }
+  return GWL_OK;
+}
+
+gwl_status check_device(int dev) {
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (cur != dev) return fail(GWL_E_INVALID, "event lives on device %d but device %d is current", dev, cur);
+  return GWL_OK;
+}
+
+}  // namespace gwl
+
+// ------------------------------------------------------------------------------------------------
+// C ABI
+// ------------------------------------------------------------------------------------------------
+extern "C" {
+
+const char* gwl_last_error(void) { return g_err.c_str(); }
+
+const char* gwl_version(void) { return "gwlike 0.1 (gfx950)"; }
+
+gwl_status gwl_event_create(const double* data, const double* psd, const gwl_detector* dets, int ndet,
+                            const double* fgrid, int64_t M, double df, double gmst, unsigned flags, void* stream,
+                            gwl_event* out) {
+  clear_error();
+  if (!out) return fail(GWL_E_INVALID, "out is null");
+  *out = nullptr;
+  if (!data || !psd || !fgrid) return fail(GWL_E_INVALID, "data, psd and fgrid must be device pointers");
+  if (M < 1 || M > (int64_t)1 << 30) return fail(GWL_E_SHAPE, "M=%lld outside [1, 2^30]", (long long)M);
+  if (!(df > 0.0) || !isfinite(df)) return fail(GWL_E_INVALID, "df must be finite and positive");
+  if (flags != 0) return fail(GWL_E_UNSUPPORTED, "flags=0x%x: no flags are implemented", flags);
+  EventGeom g;
+  gwl_status st = make_geom(dets, ndet, gmst, g);
+  if (st != GWL_OK) return st;
+
+  gwl_event ev = new (std::nothrow) gwl_event_s();
+  if (!ev) return fail(GWL_E_NOMEM, "host allocation failed");
+  ev->ndet = ndet;
+  ev->M = M;
+  ev->df = df;
+  ev->gmst = gmst;
+  ev->geom = g;
+  for (int d = 0; d < ndet; ++d) ev->dets[d] = dets[d];
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipGetDevice(&ev->device);
+  const int nblk = prep_blocks(M);
+  double* blockpart = nullptr;
+  if (e == hipSuccess) e = hipMalloc(&ev->tab64, row64_bytes(ndet) * M);
+  if (e == hipSuccess) e = hipMalloc(&ev->tab32, row32_bytes(ndet) * M);
+  if (e == hipSuccess) e = hipMalloc((void**)&ev->g32, sizeof(RowGradF32) * M);
+  if (e == hipSuccess) e = hipMalloc((void**)&ev->g64, sizeof(RowGradF64) * M);
+  if (e == hipSuccess) e = hipMalloc((void**)&ev->ec, sizeof(EventConst));
+  if (e == hipSuccess) e = hipMalloc((void**)&blockpart, sizeof(double) * (ndet + 2) * (size_t)nblk);
+  if (e == hipSuccess)
+    e = launch_prep(ndet, data, psd, fgrid, M, df, ev->tab64, ev->tab32, ev->g32, ev->g64, blockpart, nblk, ev->ec, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&ev->ech, ev->ec, sizeof(EventConst), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (blockpart) (void)hipFree(blockpart);
+  if (e != hipSuccess) {
+    gwl_event_destroy(ev);
+    return hip_fail(e, "event preparation");
+  }
+  if (ev->ech.bad) {
+    gwl_event_destroy(ev);
+    return fail(GWL_E_INVALID, "rejected inputs: every PSD value and frequency must be finite and positive and "
+                               "every data value finite");
+  }
+  *out = ev;
+  return GWL_OK;
+}
+
+gwl_status gwl_event_destroy(gwl_event ev) {
+  if (!ev) return GWL_OK;
+  if (ev->tab64) (void)hipFree(ev->tab64);
+  if (ev->tab32) (void)hipFree(ev->tab32);
+  if (ev->g32) (void)hipFree(ev->g32);
+  if (ev->g64) (void)hipFree(ev->g64);
+  if (ev->ec) (void)hipFree(ev->ec);
+  delete ev;
+  return GWL_OK;
+}
+
+gwl_status gwl_event_info(gwl_event ev, int* ndet, int64_t* M, double* df) {
+  clear_error();
+  if (!ev) return fail(GWL_E_INVALID, "event is null");
+  if (ndet) *ndet = ev->ndet;
+  if (M) *M = ev->M;
+  if (df) *df = ev->df;
+  return GWL_OK;
+}
+
+static gwl_status logl_common(gwl_event ev, const double* theta, int64_t B, gwl_precision prec, double* logl,
+                              double* grad, bool with_grad, void* stream) {
+  clear_error();
+  if (!ev) return fail(GWL_E_INVALID, "event is null");
+  if (B < 0 || B > kMaxBatch) return fail(GWL_E_SHAPE, "B=%lld outside [0, %lld]", (long long)B, (long long)kMaxBatch);
+  if (prec != GWL_FP64 && prec != GWL_MIXED) return fail(GWL_E_INVALID, "unknown precision %d", (int)prec);
+  if (B == 0) return GWL_OK;
+  if (!theta || !logl || (with_grad && !grad)) return fail(GWL_E_INVALID, "theta, logl%s must be device pointers",
+                                                           with_grad ? " and grad" : "");
+  gwl_status st = check_device(ev->device);
+  if (st != GWL_OK) return st;
+  const bool mixed = prec == GWL_MIXED;
+  const LoopShape sh = make_shape(B, ev->M, choose_nchunk(ev, B, mixed, with_grad));
+  return run_logl(ev, theta, B, mixed, with_grad, sh, logl, grad, (hipStream_t)stream);
+}
+
+gwl_status gwl_logl_batch(gwl_event ev, const double* theta, int64_t B, gwl_precision prec, double* logl,
+                          void* stream) {
+  return logl_common(ev, theta, B, prec, logl, nullptr, false, stream);
+}
+
+gwl_status gwl_logl_grad(gwl_event ev, const double* theta, int64_t B, gwl_precision prec, double* logl, double* grad,
+                         void* stream) {
+  return logl_common(ev, theta, B, prec, logl, grad, true, stream);
+}
+
+gwl_status gwl_waveform(const double* theta, int64_t B, const gwl_detector* dets, int ndet, const double* fgrid,
+                        int64_t M, double gmst, double* out, void* stream) {
+  clear_error();
+  EventGeom g;
+  gwl_status st = make_geom(dets, ndet, gmst, g);
+  if (st != GWL_OK) return st;
+  if (B < 0 || B > 65535) return fail(GWL_E_SHAPE, "B=%lld outside [0, 65535]", (long long)B);
+  if (M < 1 || M > (int64_t)1 << 30) return fail(GWL_E_SHAPE, "M=%lld outside [1, 2^30]", (long long)M);
+  if (B == 0) return GWL_OK;
+  if (!theta || !fgrid || !out) return fail(GWL_E_INVALID, "theta, fgrid and out must be device pointers");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t Bp = (B + WAVE - 1) / WAVE * WAVE;
+  double* coef = nullptr;
+  hipError_t e = hipMallocAsync((void**)&coef, sizeof(double) * NCOEF * (size_t)Bp, s);
+  if (e != hipSuccess) return hip_fail(e, "workspace");
+  e = launch_setup(ndet, g, theta, B, Bp, coef, s);
+  if (e == hipSuccess) e = launch_waveform(ndet, g, coef, B, Bp, fgrid, M, out, s);
+  hipError_t e2 = hipFreeAsync(coef, s);
+  if (e != hipSuccess) return hip_fail(e, "waveform launch");
+  if (e2 != hipSuccess) return hip_fail(e2, "workspace release");
+  return GWL_OK;
+}
+
+}  // extern "C"
+
+namespace gwl {
+
+size_t workspace_bytes(int64_t Bp, int nchunk, int nd, bool grad) {
+  return sizeof(double) * ((size_t)NCOEF * Bp + (size_t)nchunk * nz_of(nd, grad) * Bp);
+}
+
+// Set-up, bin loop and epilogue on `s`, with workspace from the stream-ordered pool.
+gwl_status run_logl(gwl_event ev, const double* theta, int64_t B, bool mixed, bool grad, const LoopShape& sh,
+                    double* logl, double* gradout, hipStream_t s) {
+  const int64_t Bp = (int64_t)sh.npg * WAVE;
+  void* ws = nullptr;
+  hipError_t e = hipMallocAsync(&ws, workspace_bytes(Bp, sh.nchunk, ev->ndet, grad), s);
+  if (e != hipSuccess) return hip_fail(e, "workspace");
+  double* coef = (double*)ws;
+  double* part = coef + (size_t)NCOEF * Bp;
+  e = enqueue_logl(ev, theta, B, mixed, grad, sh, coef, part, logl, gradout, s);
+  hipError_t e2 = hipFreeAsync(ws, s);
+  if (e != hipSuccess) return hip_fail(e, "launch");
+  if (e2 != hipSuccess) return hip_fail(e2, "workspace release");
+  return GWL_OK;
+}
+
+hipError_t enqueue_logl(gwl_event ev, const double* theta, int64_t B, bool mixed, bool grad, const LoopShape& sh,
+                        double* coef, double* part, double* logl, double* gradout, hipStream_t s) {
+  const int64_t Bp = (int64_t)sh.npg * WAVE;
+  hipError_t e = launch_setup(ev->ndet, ev->geom, theta, B, Bp, coef, s);
+  if (e == hipSuccess)
+    e = launch_bins(ev->ndet, mixed, grad, mixed ? ev->tab32 : ev->tab64, ev->g32, ev->g64, coef, B, Bp, ev->M, sh,
+                    part, s);
+  if (e == hipSuccess)
+    e = launch_epilogue(ev->ndet, grad, mixed, ev->geom, ev->ec, theta, B, Bp, sh.nchunk, part, logl, gradout, s);
+  return e;
+}
+
+}  // namespace gwl

@@ -1,0 +1,223 @@
+"""Python binding of libgwlike (the C ABI in include/gwlike.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module checks tensor placement, dtype and
+shape, passes device pointers and the current HIP stream, and raises on a non-zero status.
+It fails loudly if the compiled library is missing: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgwlike.so")
+
+GWL_FP64 = 0
+GWL_MIXED = 1
+NPARAM = 11
+MAX_DET = 4
+
+_c_double_p = ctypes.POINTER(ctypes.c_double)
+
+
+class Detector(ctypes.Structure):
+    """An L-shaped detector: latitude, longitude, x- and y-arm azimuths (rad, clockwise from North)."""
+    _fields_ = [("lat", ctypes.c_double), ("lon", ctypes.c_double),
+                ("xarm_az", ctypes.c_double), ("yarm_az", ctypes.c_double)]
+
+
+class GWLError(RuntimeError):
+    def __init__(self, func: str, status: int, msg: str):
+        super().__init__(f"{func} returned {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libgwlike.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build the HIP library first (python -c "
+                           f"'import __graft_entry__ as g; g.build()'); there is no CPU fallback")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, dbl, cint = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+    sig = {
+        "gwl_last_error": ([], ctypes.c_char_p),
+        "gwl_version": ([], ctypes.c_char_p),
+        "gwl_event_create": ([vp, vp, ctypes.POINTER(Detector), cint, vp, i64, dbl, dbl, ctypes.c_uint, vp,
+                              ctypes.POINTER(vp)], cint),
+        "gwl_event_destroy": ([vp], cint),
+        "gwl_event_info": ([vp, ctypes.POINTER(cint), ctypes.POINTER(i64), ctypes.POINTER(dbl)], cint),
+        "gwl_logl_batch": ([vp, vp, i64, cint, vp, vp], cint),
+        "gwl_logl_grad": ([vp, vp, i64, cint, vp, vp, vp], cint),
+        "gwl_waveform": ([vp, i64, ctypes.POINTER(Detector), cint, vp, i64, dbl, vp, vp], cint),
+        "gwl_multi_plan_create": ([ctypes.POINTER(vp), cint, ctypes.POINTER(i64), cint, cint, ctypes.POINTER(vp)],
+                                  cint),
+        "gwl_multi_launch": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), _c_double_p, vp],
+                             cint),
+        "gwl_plan_destroy": ([vp], cint),
+        "gwl_autotune": ([ctypes.c_char_p, vp, i64, cint, cint], cint),
+        "gwl_autotune_load": ([ctypes.c_char_p], cint),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def _check(func: str, status: int) -> None:
+    if status != 0:
+        raise GWLError(func, status, lib().gwl_last_error().decode(errors="replace"))
+
+
+def _prec(precision) -> int:
+    if precision in ("mixed", GWL_MIXED):
+        return GWL_MIXED
+    if precision in ("fp64", "f64", "double", GWL_FP64):
+        return GWL_FP64
+    raise ValueError(f"precision must be 'mixed' or 'fp64', not {precision!r}")
+
+
+def _stream(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _dev(t: torch.Tensor, name: str, dtype: torch.dtype) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    return t.contiguous()
+
+
+def _dets(dets) -> "ctypes.Array[Detector]":
+    rows = [tuple(float(v) for v in d) for d in dets]
+    arr = (Detector * max(1, len(rows)))()
+    for i, r in enumerate(rows):
+        if len(r) != 4:
+            raise ValueError("each detector is (lat, lon, xarm_az, yarm_az) in radians")
+        arr[i] = Detector(*r)
+    return arr, len(rows)
+
+
+class Event:
+    """One segment seen by several detectors: the library's prepared per-bin tables.
+
+    data  complex128 CUDA tensor [ndet, M];  psd float64 CUDA [ndet, M];  fgrid float64 CUDA [M];
+    dets  [ndet] x (lat, lon, xarm_az, yarm_az) radians;  df = 1/T;  gmst in radians.
+    """
+
+    def __init__(self, data: torch.Tensor, psd: torch.Tensor, dets: Sequence, fgrid: torch.Tensor, df: float,
+                 gmst: float = 0.0):
+        data = _dev(data, "data", torch.complex128)
+        psd = _dev(psd, "psd", torch.float64)
+        fgrid = _dev(fgrid, "fgrid", torch.float64)
+        darr, nd = _dets(dets)
+        if data.dim() != 2 or psd.shape != data.shape or fgrid.shape != (data.shape[1],) or data.shape[0] != nd:
+            raise ValueError("shapes must be data [ndet, M], psd [ndet, M], fgrid [M] with ndet = len(dets)")
+        self.ndet, self.M, self.df, self.gmst = nd, int(data.shape[1]), float(df), float(gmst)
+        self.device = data.device
+        h = ctypes.c_void_p()
+        _check("gwl_event_create", lib().gwl_event_create(
+            ctypes.c_void_p(data.data_ptr()), ctypes.c_void_p(psd.data_ptr()), darr, nd,
+            ctypes.c_void_p(fgrid.data_ptr()), self.M, self.df, self.gmst, 0, _stream(data), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if self._h is None:
+            raise ValueError("event is closed")
+        return self._h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            lib().gwl_event_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _theta(theta: torch.Tensor) -> torch.Tensor:
+    theta = _dev(theta, "theta", torch.float64)
+    if theta.dim() != 2 or theta.shape[1] != NPARAM:
+        raise ValueError("theta must be [B, 11]")
+    return theta
+
+
+def logl(theta: torch.Tensor, ev: Event, precision="mixed") -> torch.Tensor:
+    """logL[B] for theta[B, 11] (float64 CUDA)."""
+    theta = _theta(theta)
+    out = torch.empty(theta.shape[0], dtype=torch.float64, device=theta.device)
+    _check("gwl_logl_batch", lib().gwl_logl_batch(ev.handle, ctypes.c_void_p(theta.data_ptr()), theta.shape[0],
+                                                  _prec(precision), ctypes.c_void_p(out.data_ptr()), _stream(theta)))
+    return out
+
+
+def logl_grad(theta: torch.Tensor, ev: Event, precision="mixed"):
+    """(logL[B], dlogL/dtheta[B, 11])."""
+    theta = _theta(theta)
+    out = torch.empty(theta.shape[0], dtype=torch.float64, device=theta.device)
+    grad = torch.empty_like(theta)
+    _check("gwl_logl_grad", lib().gwl_logl_grad(ev.handle, ctypes.c_void_p(theta.data_ptr()), theta.shape[0],
+                                                _prec(precision), ctypes.c_void_p(out.data_ptr()),
+                                                ctypes.c_void_p(grad.data_ptr()), _stream(theta)))
+    return out, grad
+
+
+class LogL(torch.autograd.Function):
+    """logL as a differentiable function of theta; the adjoint is computed in the forward pass."""
+
+    @staticmethod
+    def forward(ctx, theta: torch.Tensor, ev: Event, precision="mixed"):
+        if ctx.needs_input_grad[0]:
+            val, g = logl_grad(theta.detach(), ev, precision)
+            ctx.save_for_backward(g)
+        else:
+            val = logl(theta.detach(), ev, precision)
+        return val
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (g,) = ctx.saved_tensors
+        return grad_out[:, None] * g, None, None
+
+
+def waveform(theta: torch.Tensor, dets: Sequence, fgrid: torch.Tensor, gmst: float = 0.0) -> torch.Tensor:
+    """Model strain h_det(f_k): complex128 [B, ndet, M] on the theta's device."""
+    theta = _theta(theta)
+    fgrid = _dev(fgrid, "fgrid", torch.float64)
+    darr, nd = _dets(dets)
+    M = int(fgrid.shape[0])
+    out = torch.empty(theta.shape[0], nd, M, dtype=torch.complex128, device=theta.device)
+    _check("gwl_waveform", lib().gwl_waveform(ctypes.c_void_p(theta.data_ptr()), theta.shape[0], darr, nd,
+                                              ctypes.c_void_p(fgrid.data_ptr()), M, float(gmst),
+                                              ctypes.c_void_p(out.data_ptr()), _stream(theta)))
+    return out
+
+
+def autotune(ev: Event, batch: int, precision="mixed", with_grad: bool = False,
+             cache_path: Optional[str] = None) -> None:
+    """Time tile shapes for this event and batch size; record the best (in memory and in cache_path)."""
+    path = cache_path.encode() if cache_path else None
+    _check("gwl_autotune", lib().gwl_autotune(path, ev.handle, int(batch), _prec(precision), int(bool(with_grad))))
+
+
+def autotune_load(cache_path: str) -> None:
+    _check("gwl_autotune_load", lib().gwl_autotune_load(cache_path.encode()))
+
+
+def version() -> str:
+    return lib().gwl_version().decode()

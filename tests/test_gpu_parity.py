@@ -1,0 +1,267 @@
+"""GPU parity: the HIP library against the FP64 CPU oracle, through the C ABI.
+
+Tolerances: |logL_gpu - logL_oracle| <= 1e-3 absolute for the mixed-precision kernels (the
+accuracy target of this library) and <= 1e-6 for the float64 kernels; gradients compare
+width-scaled components to 1e-4 relative (see helpers.scaled_grad_error).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import gw_oracle as o
+from paper_1909_11873_amd import gwlike as gw
+from paper_1909_11873_amd import synth
+from tests.helpers import event_inputs, scaled_grad_error
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+TOL = {"mixed": 1e-3, "fp64": 1e-6}
+
+
+def make_event(f, psd, data, dets, df):
+    return gw.Event(torch.tensor(data, device=DEV), torch.tensor(psd, device=DEV), dets,
+                    torch.tensor(f, device=DEV), df)
+
+
+def oracle_logl(theta, f, psd, data, dets, df):
+    return o.logl(theta, data, psd, dets, f, df).numpy()
+
+
+@pytest.fixture(scope="module")
+def c0():
+    spec, f, psd, data, dets = event_inputs(0)
+    ev = make_event(f, psd, data, dets, spec.df)
+    th = synth.theta_batch(spec)
+    th[0] = spec.theta0
+    ref = oracle_logl(th, f, psd, data, dets, spec.df)
+    return spec, ev, th, ref
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_c0_every_point(c0, prec):
+    spec, ev, th, ref = c0
+    got = gw.logl(torch.tensor(th, device=DEV), ev, prec).cpu().numpy()
+    err = np.abs(got - ref)
+    print(f"c0 {prec}: max |dlogL| {err.max():.3e} p99 {np.quantile(err, 0.99):.3e} over {len(th)} points")
+    assert err.max() <= TOL[prec]
+
+
+@pytest.fixture(scope="module")
+def c1():
+    spec, f, psd, data, dets = event_inputs(1)
+    ev = make_event(f, psd, data, dets, spec.df)
+    th = synth.theta_batch(spec)
+    th[0] = spec.theta0
+    rng = np.random.default_rng(77)
+    sample = np.unique(np.concatenate([[0, 1, 63, 64, 65535], rng.choice(len(th), 120, replace=False)]))
+    # also the loudest points of the batch: largest A^2 ~ Mc^(5/3) / d^2
+    loud = np.argsort(th[:, 0] ** (5 / 3) / th[:, 4] ** 2)[-8:]
+    sample = np.unique(np.concatenate([sample, loud]))
+    ref = oracle_logl(th[sample], f, psd, data, dets, spec.df)
+    return spec, ev, th, sample, ref
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_c1_full_batch_sampled(c1, prec):
+    """Full 65536-point launch (the benchmark's launch), compared on sampled points."""
+    spec, ev, th, sample, ref = c1
+    got = gw.logl(torch.tensor(th, device=DEV), ev, prec).cpu().numpy()
+    assert np.all(np.isfinite(got))
+    err = np.abs(got[sample] - ref)
+    print(f"c1 {prec}: max |dlogL| {err.max():.3e} p99 {np.quantile(err, 0.99):.3e} over {len(sample)} sampled "
+          f"points, |logL| up to {np.abs(ref).max():.3e}")
+    assert err.max() <= TOL[prec]
+
+
+def test_c1_mixed_matches_fp64_everywhere(c1):
+    """Across every point of the batch the two kernels agree to the mixed tolerance."""
+    spec, ev, th, sample, ref = c1
+    t = torch.tensor(th, device=DEV)
+    a = gw.logl(t, ev, "fp64").cpu().numpy()
+    b = gw.logl(t, ev, "mixed").cpu().numpy()
+    err = np.abs(a - b)
+    print(f"c1 mixed vs fp64 over all {len(th)}: max {err.max():.3e} p99 {np.quantile(err, 0.99):.3e}")
+    assert err.max() <= TOL["mixed"]
+
+
+def test_c2_long_signal_sampled():
+    spec, f, psd, data, dets = event_inputs(2)
+    ev = make_event(f, psd, data, dets, spec.df)
+    th = synth.theta_batch(spec)
+    th[0] = spec.theta0
+    sample = np.array([0, 1, 2, 1000, 2047, 4095])
+    ref = oracle_logl(th[sample], f, psd, data, dets, spec.df)
+    for prec in ("mixed", "fp64"):
+        got = gw.logl(torch.tensor(th, device=DEV), ev, prec).cpu().numpy()
+        err = np.abs(got[sample] - ref)
+        print(f"c2 {prec}: max |dlogL| {err.max():.3e} (M={len(f)}), logL(theta0)={ref[0]:.4f}")
+        assert err.max() <= TOL[prec]
+
+
+@pytest.mark.parametrize("ndet", [1, 2, 4])
+@pytest.mark.parametrize("nbatch", [1, 70, 193])
+def test_ragged_batches_and_detector_counts(ndet, nbatch):
+    """Batches that are not multiples of 64, several chunks, a bin tail shorter than a block."""
+    spec, f, psd, data, dets = event_inputs(1, f_hi=20.0 + 0.125 * 3000, ndet=ndet)  # M = 3001
+    ev = make_event(f, psd, data, dets, spec.df)
+    th = synth.theta_batch(spec, nbatch)
+    ref = oracle_logl(th[: min(nbatch, 12)], f, psd, data, dets, spec.df)
+    for prec in ("mixed", "fp64"):
+        got = gw.logl(torch.tensor(th, device=DEV), ev, prec).cpu().numpy()
+        assert got.shape == (nbatch,)
+        assert np.abs(got[: len(ref)] - ref).max() <= TOL[prec]
+
+
+@pytest.mark.parametrize("m", [1, 5, 31, 33])
+def test_tiny_grids(m):
+    spec, f, psd, data, dets = event_inputs(1, f_hi=20.0 + 0.125 * (m - 1))
+    assert len(f) == m
+    ev = make_event(f, psd, data, dets, spec.df)
+    th = synth.theta_batch(spec, 65)
+    ref = oracle_logl(th, f, psd, data, dets, spec.df)
+    for prec in ("mixed", "fp64"):
+        got = gw.logl(torch.tensor(th, device=DEV), ev, prec).cpu().numpy()
+        assert np.abs(got - ref).max() <= TOL[prec]
+
+
+def test_empty_batch_and_invalid_rows():
+    spec, f, psd, data, dets = event_inputs(1, f_hi=100.0)
+    ev = make_event(f, psd, data, dets, spec.df)
+    empty = torch.zeros(0, 11, dtype=torch.float64, device=DEV)
+    assert gw.logl(empty, ev).shape == (0,)
+    th = synth.theta_batch(spec, 8)
+    th[1, 1] = 1.5          # q > 1
+    th[2, 4] = -10.0        # negative distance
+    th[3, 0] = float("nan")
+    th[4, 2] = 1.0          # |chi| = 1
+    th[5, 1] = 0.0          # q = 0
+    for prec in ("mixed", "fp64"):
+        got = gw.logl(torch.tensor(th, device=DEV), ev, prec).cpu().numpy()
+        assert np.all(np.isnan(got[1:6]))
+        ref = oracle_logl(th[[0, 6, 7]], f, psd, data, dets, spec.df)
+        assert np.abs(got[[0, 6, 7]] - ref).max() <= TOL[prec]
+        val, g = gw.logl_grad(torch.tensor(th, device=DEV), ev, prec)
+        assert np.all(np.isnan(g.cpu().numpy()[1:6]))
+        assert np.all(np.isfinite(g.cpu().numpy()[[0, 6, 7]]))
+
+
+def test_bad_event_inputs_rejected():
+    spec, f, psd, data, dets = event_inputs(0)
+    bad = psd.copy()
+    bad[0, 17] = 0.0
+    with pytest.raises(gw.GWLError) as ei:
+        make_event(f, bad, data, dets, spec.df)
+    assert ei.value.status == -1
+    bad = data.copy()
+    bad[0, 5] = complex(float("inf"), 0)
+    with pytest.raises(gw.GWLError):
+        make_event(f, psd, bad, dets, spec.df)
+
+
+def test_determinism_bitwise(c1):
+    spec, ev, th, sample, ref = c1
+    t = torch.tensor(th[:5000], device=DEV)
+    for prec in ("mixed", "fp64"):
+        a = gw.logl(t, ev, prec).cpu().numpy()
+        b = gw.logl(t, ev, prec).cpu().numpy()
+        assert np.array_equal(a, b)
+
+
+def test_waveform_matches_oracle_strain():
+    spec, f, psd, data, dets = event_inputs(1)
+    th = synth.theta_batch(spec, 3)
+    th[0] = spec.theta0
+    got = gw.waveform(torch.tensor(th, device=DEV), dets, torch.tensor(f, device=DEV)).cpu().numpy()
+    for b in range(3):
+        ref = o.strain_all(th[b], dets, f).numpy()
+        rel = np.abs(got[b] - ref).max() / np.abs(ref).max()
+        assert rel < 1e-10
+
+
+def test_noiseless_injection_recovers_half_snr2():
+    """d = h(theta0) exactly: logL(theta0) = <h0|h0>/2 on the GPU too."""
+    spec = synth.event_spec(1)
+    f, psd, _, dets = synth.event_arrays(spec)
+    h0 = o.strain_all(spec.theta0, dets, f).numpy()
+    ev = make_event(f, psd, h0, dets, spec.df)
+    hh = sum(float(o.inner(torch.tensor(h0[i]), torch.tensor(h0[i]), torch.tensor(psd[i]), spec.df)) for i in range(3))
+    for prec in ("fp64", "mixed"):
+        got = gw.logl(torch.tensor(spec.theta0[None], device=DEV), ev, prec).cpu().numpy()[0]
+        assert abs(got - 0.5 * hh) <= TOL[prec]
+
+
+# --------------------------------------------------------------------------------------------
+# Gradient
+# --------------------------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def c3():
+    spec, f, psd, data, dets = event_inputs(3)
+    ev = make_event(f, psd, data, dets, spec.df)
+    th = synth.theta_batch(spec)
+    th[0] = spec.theta0
+    sample = np.array([0, 1, 2, 3, 777, 16383])
+    val, grad = o.logl_grad(th[sample], data, psd, dets, f, spec.df)
+    return spec, ev, th, sample, val.numpy(), grad.numpy()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_c3_gradient_against_oracle_autograd(c3, prec):
+    spec, ev, th, sample, vref, gref = c3
+    val, g = gw.logl_grad(torch.tensor(th, device=DEV), ev, prec)
+    val, g = val.cpu().numpy(), g.cpu().numpy()
+    assert np.abs(val[sample] - vref).max() <= TOL[prec]
+    e = scaled_grad_error(g[sample], gref)
+    print(f"c3 {prec}: gradient max scaled rel error {e.max():.3e}")
+    assert e.max() <= 1e-4
+    # forward-only and forward+adjoint agree on logL
+    lone = gw.logl(torch.tensor(th, device=DEV), ev, prec).cpu().numpy()
+    assert np.abs(lone - val).max() <= TOL[prec]
+
+
+def test_c3_gradient_against_central_differences(c3):
+    """GPU float64 logL differenced with relative step 1e-6 of max(|theta_i|, prior width)."""
+    spec, ev, th, sample, vref, gref = c3
+    from tests.helpers import WIDTHS
+    pts = th[sample[:3]]
+    _, g = gw.logl_grad(torch.tensor(pts, device=DEV), ev, "fp64")
+    g = g.cpu().numpy()
+    rows = []
+    for b in range(len(pts)):
+        for j in range(11):
+            h = 1e-6 * max(abs(pts[b, j]), WIDTHS[j])
+            tp, tm = pts[b].copy(), pts[b].copy()
+            tp[j] += h
+            tm[j] -= h
+            rows += [tp, tm]
+    vals = gw.logl(torch.tensor(np.array(rows), device=DEV), ev, "fp64").cpu().numpy()
+    fd = ((vals[0::2] - vals[1::2]) / (2 * np.array([1e-6 * max(abs(pts[b, j]), WIDTHS[j])
+                                                     for b in range(len(pts)) for j in range(11)])))
+    fd = fd.reshape(len(pts), 11)
+    e = scaled_grad_error(g, fd)
+    print(f"c3 fd: max scaled rel error {e.max():.3e}")
+    assert e.max() <= 1e-4
+
+
+def test_autograd_function_backward(c3):
+    spec, ev, th, sample, vref, gref = c3
+    t = torch.tensor(th[sample], device=DEV, requires_grad=True)
+    out = gw.LogL.apply(t, ev, "fp64")
+    w = torch.linspace(0.5, 1.5, len(sample), dtype=torch.float64, device=DEV)
+    (out * w).sum().backward()
+    want = w.cpu().numpy()[:, None] * gref
+    assert scaled_grad_error(t.grad.cpu().numpy(), want).max() <= 1e-4
+
+
+def test_autotune_roundtrip(tmp_path, c1):
+    spec, ev, th, sample, ref = c1
+    path = str(tmp_path / "tiles.json")
+    gw.autotune(ev, 4096, "mixed", False, path)
+    text = open(path).read()
+    assert '"ndet": 3' in text and '"M": 16225' in text
+    gw.autotune_load(path)
+    got = gw.logl(torch.tensor(th[:4096], device=DEV), ev, "mixed").cpu().numpy()
+    idx = sample[sample < 4096]
+    ref_sub = ref[np.searchsorted(sample, idx)]
+    assert np.abs(got[idx] - ref_sub).max() <= TOL["mixed"]
