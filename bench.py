@@ -1,0 +1,258 @@
+#!/usr/bin/env python3
+"""Benchmark: batched log-likelihood evaluations per second on one MI355X.
+
+One step = one pass of the library's forward path (per-point set-up, bin loop, epilogue) over
+the full parameter batch of the chosen workload; inputs are resident in HBM before timing.
+Default workload: 3 detectors, 8 s, 20-2048 Hz (16225 bins per detector), 65536 prior draws,
+mixed precision. Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--config 1|2|3] [--no-cpu-baseline]
+
+The CPU baseline times the FP64 oracle on a bounded sample of the same workload on the
+host's cores before the GPU is touched.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import multiprocessing as mp
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# ---- peaks (MI355X: 256 CUs at 2.4 GHz) --------------------------------------------------
+PEAK_FP64 = 78.6e12    # FP64 vector FLOP/s (published)
+PEAK_FP32 = 157.3e12   # FP32 vector FLOP/s (published; needs packed FMA)
+# transcendental VALU ops (v_sin_f32 / v_cos_f32): half the FP32 lane rate on gfx950,
+# 256 CU x 64 lanes/clk x 2.4 GHz / 2
+PEAK_TRANS = 256 * 64 * 2.4e9 / 2
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_bins_mixed_c1.txt")
+KERNEL_SOURCES = ["paper_1909_11873_amd/csrc/k_bins.hip", "paper_1909_11873_amd/csrc/gwl_common.h",
+                  "paper_1909_11873_amd/csrc/gwl_device.h"]
+
+
+def work_per_point_bin(ndet: int, mixed: bool):
+    """Algorithmic work per (point, frequency bin): (fp64 flops, fp32 flops, transcendental ops).
+
+    Phase polynomial: 7 FMA + 2 MUL in float64 (16 flops). Per detector: the f T_det shift
+    (1 FMA), the reduction to one cycle (1 op), the phasor (sin + cos) and the complex
+    multiply-accumulate u (cos - i sin) (4 FMA). In the float64 kernel sin and cos have no
+    hardware instruction; their work is the polynomial pair evaluated (18 FMA + 3 ops).
+    """
+    if mixed:
+        return 16 + ndet * (2 + 1), ndet * 8, ndet * 2
+    return 16 + ndet * (2 + 1 + 39 + 8), 0, 0
+
+
+def roofline(ndet: int, mixed: bool, nbins: int, npoints: int, seconds: float):
+    f64, f32, tr = work_per_point_bin(ndet, mixed)
+    units = float(nbins) * npoints
+    ops = (f64 + f32 + tr) * units
+    tmin = units * (f64 / PEAK_FP64 + f32 / PEAK_FP32 + tr / PEAK_TRANS)
+    achieved = ops / seconds
+    peak = ops / tmin
+    return achieved / 1e12, peak / 1e12, achieved / peak
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM bytes per bin-loop launch from the committed counter summary, if it matches the source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    text = open(TRAFFIC_FILE).read()
+    m_hash = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
+    m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not (m_hash and m_bytes) or m_hash.group(1) != kernel_hash():
+        return None
+    return float(m_bytes.group(1))
+
+
+# ---- CPU baseline (FP64 oracle) ----------------------------------------------------------
+_W = {}
+
+
+def _worker_init(data, psd, dets, f, df):
+    import torch
+    torch.set_num_threads(1)
+    _W.update(data=data, psd=psd, dets=dets, f=f, df=df)
+
+
+def _worker_eval(theta_rows):
+    from oracle import gw_oracle as o
+    return o.logl(theta_rows, _W["data"], _W["psd"], _W["dets"], _W["f"], _W["df"]).numpy()
+
+
+def cpu_baseline(cfg: int, target_s: float):
+    import numpy as np
+    import torch
+
+    from oracle import gw_oracle as o
+    from paper_1909_11873_amd import synth
+
+    spec = synth.event_spec(cfg)
+    f, psd, nz, dets = synth.event_arrays(spec)
+    data = nz + o.strain_all(spec.theta0, dets, f).numpy()
+    theta = synth.theta_batch(spec)
+    torch.set_num_threads(1)
+    t0 = time.perf_counter()
+    o.logl(theta[:4], data, psd, dets, f, spec.df)
+    per_point = (time.perf_counter() - t0) / 4
+    workers = max(1, min(16, os.cpu_count() or 1))
+    n = int(min(len(theta), max(workers, target_s * workers / per_point)))
+    n = max(workers, n // workers * workers)
+    chunks = np.array_split(theta[:n], workers * 4)
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(workers, initializer=_worker_init, initargs=(data, psd, dets, f, spec.df)) as pool:
+        t0 = time.perf_counter()
+        parts = pool.map(_worker_eval, chunks)
+        wall = time.perf_counter() - t0
+    ref = np.concatenate(parts)
+    return {
+        "value": n / wall, "unit": "evals/s", "cores": workers, "kind": "oracle",
+        "sample": f"first {n} of the {len(theta)} prior draws of the same workload, FP64 torch-CPU oracle, "
+                  f"{workers} single-threaded processes, {wall:.1f} s wall",
+    }, (theta[:n], ref, data, psd, dets, f, spec.df)
+
+
+# ---- GPU leg --------------------------------------------------------------------------------
+def gpu_leg(cfg: int, steps: int, warmup: int, parity_inputs):
+    import numpy as np
+    import torch
+
+    from paper_1909_11873_amd import gwlike as gw
+    from paper_1909_11873_amd import synth
+
+    dev = torch.device("cuda:0")
+    spec = synth.event_spec(cfg)
+    f, psd, nz, dets = synth.event_arrays(spec)
+    ft = torch.tensor(f, device=dev)
+    # injection from the library's own waveform at theta0
+    h0 = gw.waveform(torch.tensor(spec.theta0[None], device=dev), dets, ft)[0]
+    data = torch.tensor(nz, device=dev) + h0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev = gw.Event(data, torch.tensor(psd, device=dev), dets, ft, spec.df)
+    prep_ms = (time.perf_counter() - t0) * 1e3
+    theta = torch.tensor(synth.theta_batch(spec), device=dev)
+    B, M, nd = theta.shape[0], len(f), spec.ndet
+
+    def timed(fn, k, w):
+        for _ in range(w):
+            fn()
+        torch.cuda.synchronize()
+        gw.profile_read()
+        gw.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(k):
+            fn()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        gw.profile_enable(False)
+        n, kms = gw.profile_read()
+        return wall, kms / max(n, 1) / 1e3
+
+    out = {}
+    wall, kern_s = timed(lambda: gw.logl(theta, ev, "mixed"), steps, warmup)
+    out["mixed"] = (wall, kern_s)
+    wall64, kern64 = timed(lambda: gw.logl(theta, ev, "fp64"), max(3, steps // 4), 2)
+    out["fp64"] = (wall64, kern64)
+    # adjoint at the gradient workload's batch (same shapes, 16384 points)
+    tg = theta[:16384]
+    BG = int(tg.shape[0])
+    wg, kg = timed(lambda: gw.logl_grad(tg, ev, "mixed"), max(3, steps // 4), 2)
+    wg64, kg64 = timed(lambda: gw.logl_grad(tg, ev, "fp64"), 3, 1)
+
+    parity = None
+    if parity_inputs is not None:
+        th_s, ref, pdata, ppsd, pdets, pf, pdf = parity_inputs
+        pev = gw.Event(torch.tensor(pdata, device=dev), torch.tensor(ppsd, device=dev), pdets,
+                       torch.tensor(pf, device=dev), pdf)
+        got = gw.logl(torch.tensor(th_s, device=dev), pev, "mixed").cpu().numpy()
+        err = np.abs(got - ref)
+        parity = {"points": int(len(ref)), "max_abs_dlogl": float(err.max()),
+                  "p99_abs_dlogl": float(np.quantile(err, 0.99)), "tolerance": 1e-3}
+        pev.close()
+    ev.close()
+    nsteps64, nsg, nsg64 = max(3, steps // 4), max(3, steps // 4), 3
+    res = {
+        "B": B, "M": M, "ndet": nd, "prep_ms": prep_ms, "parity": parity,
+        "mixed_wall": out["mixed"][0], "mixed_kern": out["mixed"][1],
+        "fp64_evals": B * nsteps64 / out["fp64"][0], "fp64_kern": out["fp64"][1],
+        "grad_mixed_evals": BG * nsg / wg, "grad_fp64_evals": BG * nsg64 / wg64, "grad_batch": BG,
+        "grad_mixed_kern": kg, "grad_fp64_kern": kg64,
+    }
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", type=int, default=1, choices=[1, 2, 3])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="also run one plain device-to-device copy of this many bytes (a known-size reference "
+                         "for the HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path is single-GPU; "
+              f"batch sharding across GPUs needs no exchange and is not measured here)", file=sys.stderr)
+        sys.exit(2)
+
+    cpu, parity_inputs = None, None
+    if not args.no_cpu_baseline:
+        cpu, parity_inputs = cpu_baseline(args.config, args.cpu_seconds)
+
+    if args.copy_bytes > 0:
+        import torch
+        n = args.copy_bytes // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    r = gpu_leg(args.config, args.steps, args.warmup, parity_inputs)
+    B, M, nd = r["B"], r["M"], r["ndet"]
+    value = B * args.steps / r["mixed_wall"]
+    ach, peak, frac = roofline(nd, True, M, B, r["mixed_kern"])
+    a64, p64, f64 = roofline(nd, False, M, B, r["fp64_kern"])
+    traffic = read_traffic()
+    line = {
+        "metric": "logL evals/sec (3 det, 8 s, 20-2048 Hz) mixed vs FP64; frac VALU peak",
+        "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": r["mixed_wall"] / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": f"c{args.config}: {nd} detectors, {M} bins per detector, {B} prior draws per batch",
+                   "ndet": nd, "nbins": M, "batch": B, "precision": "mixed"},
+        "roofline": {"bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": frac,
+                     "traffic": traffic, "kernel": "k_bins_mixed<3,false>",
+                     "kernel_ms": r["mixed_kern"] * 1e3},
+        "cpu_baseline": cpu,
+        "fp64": {"value": r["fp64_evals"], "unit": "evals/s", "kernel_ms": r["fp64_kern"] * 1e3,
+                 "roofline": {"bound": "alu", "achieved": a64, "peak": p64, "unit": "TFLOP/s", "frac": f64}},
+        "grad": {"batch": r["grad_batch"], "mixed_evals_per_s": r["grad_mixed_evals"], "fp64_evals_per_s": r["grad_fp64_evals"],
+                 "mixed_kernel_ms": r["grad_mixed_kern"] * 1e3, "fp64_kernel_ms": r["grad_fp64_kern"] * 1e3},
+        "event_prep_ms": r["prep_ms"],
+        "parity_vs_oracle": r["parity"],
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

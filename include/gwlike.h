@@ -174,6 +174,16 @@ gwl_status gwl_autotune(const char* cache_path, gwl_event ev, int64_t B, gwl_pre
 /* Load tile choices from a JSON cache written by gwl_autotune (missing file = GWL_E_INVALID). */
 gwl_status gwl_autotune_load(const char* cache_path);
 
+/*
+ * Kernel timing for measurement. While enabled, every bin-loop launch made by gwl_logl_batch
+ * and gwl_logl_grad is bracketed by two HIP events recorded on the caller's stream (the
+ * stream the kernel runs on). gwl_profile_read waits for those events and returns the number
+ * of bracketed launches and their summed duration in milliseconds since the previous read,
+ * then forgets them. Either pointer may be null. Disabling keeps unread records.
+ */
+gwl_status gwl_profile_enable(int on);
+gwl_status gwl_profile_read(int64_t* launches, double* total_ms);
+
 #ifdef __cplusplus
 }
 #endif

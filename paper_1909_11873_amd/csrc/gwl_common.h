@@ -27,9 +27,16 @@ struct EventGeom {
 struct EventConst {
   double K[MAXDET];   // 4 df sum_k f_k^(-7/3) / S_k
   double uref;        // power of two >= max |u|: the float32 tables hold u / uref
+  double gain_r;      // 1 / conj(G), G = mean over phases of p_hw conj(p_exact): divides the mean
+  double gain_i;      //   complex gain of the hardware float32 phasor out of the float32 sums
   int bad;            // nonzero if an input value was rejected
   int pad;
 };
+
+// Phases sampled to measure the hardware phasor gain: NGAIN_BLK workgroups x 256 threads x
+// NGAIN_PER phases, uniform on [0, 1) cycles.
+constexpr int NGAIN_BLK = 1024;
+constexpr int NGAIN_PER = 16;
 
 // Per-bin rows, one row per frequency bin, read wave-uniformly by the bin loop.
 // Basis: f, x = f^(1/3), w = f^(-5/3), w2 = f^(-1), ln f.

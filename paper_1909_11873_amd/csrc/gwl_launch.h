@@ -25,6 +25,7 @@ hipError_t launch_prep(int nd, const double* data, const double* psd, const doub
                        void* tab64, void* tab32, RowGradF32* g32, RowGradF64* g64, double* blockpart, int nblk,
                        EventConst* ec, hipStream_t s);
 int prep_blocks(int64_t M);
+size_t prep_scratch_doubles(int nd, int64_t M);  // size of `blockpart`
 
 // per-point set-up: theta[B][11] -> coef[NCOEF][Bp]
 hipError_t launch_setup(int nd, const EventGeom& g, const double* theta, int64_t B, int64_t Bp, double* coef,

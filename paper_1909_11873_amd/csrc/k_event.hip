@@ -18,6 +18,8 @@ constexpr int PREP_BLOCK = 256;
 
 int prep_blocks(int64_t M) { return (int)((M + PREP_BLOCK - 1) / PREP_BLOCK); }
 
+size_t prep_scratch_doubles(int nd, int64_t M) { return (size_t)prep_blocks(M) * (nd + 2) + (size_t)NGAIN_BLK * 2; }
+
 // One thread per bin. Writes the float64 row, the adjoint basis rows, and per-block partial
 // sums (K_det terms, max |u|, count of rejected inputs) reduced in a fixed tree order.
 template <int ND>
@@ -81,22 +83,56 @@ __global__ __launch_bounds__(PREP_BLOCK) void k_prep_bins(const double* __restri
   if (threadIdx.x < ND + 2) blockpart[(int64_t)blockIdx.x * (ND + 2) + threadIdx.x] = red[threadIdx.x][0];
 }
 
+// Mean complex gain of the float32 hardware phasor (v_cos_f32, v_sin_f32 take cycles) against
+// the float64 reference, over phases r_j = (j + 1/2) / N on [0, 1): per-block partial sums of
+// p_hw conj(p_exact), reduced in a fixed tree order.
+__global__ __launch_bounds__(PREP_BLOCK) void k_gain_partial(double* __restrict__ gainpart) {
+  __shared__ double red[2][PREP_BLOCK];
+  const double inv_n = 1.0 / ((double)NGAIN_BLK * PREP_BLOCK * NGAIN_PER);
+  double gr = 0.0, gi = 0.0;
+  for (int j = 0; j < NGAIN_PER; ++j) {
+    const int64_t idx = ((int64_t)blockIdx.x * PREP_BLOCK + threadIdx.x) * NGAIN_PER + j;
+    const float r = (float)(((double)idx + 0.5) * inv_n);
+    const float ch = __builtin_amdgcn_cosf(r), sh = __builtin_amdgcn_sinf(r);
+    double se, ce;
+    sincos_cycles_f64((double)r, se, ce);
+    gr += (double)ch * ce + (double)sh * se;
+    gi += (double)sh * ce - (double)ch * se;
+  }
+  red[0][threadIdx.x] = gr;
+  red[1][threadIdx.x] = gi;
+  __syncthreads();
+  for (int off = PREP_BLOCK / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + off];
+      red[1][threadIdx.x] += red[1][threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 2) gainpart[(int64_t)blockIdx.x * 2 + threadIdx.x] = red[threadIdx.x][0] * inv_n;
+}
+
 // One workgroup: fixed-order reduction of the block partials into the event constants.
 template <int ND>
 __global__ __launch_bounds__(PREP_BLOCK) void k_prep_final(const double* __restrict__ blockpart, int nblk,
+                                                           const double* __restrict__ gainpart,
                                                            EventConst* __restrict__ ec) {
-  __shared__ double red[ND + 2][PREP_BLOCK];
-  double acc[ND + 2];
+  __shared__ double red[ND + 4][PREP_BLOCK];
+  double acc[ND + 4];
 #pragma unroll
-  for (int j = 0; j < ND + 2; ++j) acc[j] = 0.0;
+  for (int j = 0; j < ND + 4; ++j) acc[j] = 0.0;
   for (int b = threadIdx.x; b < nblk; b += PREP_BLOCK) {
 #pragma unroll
     for (int d = 0; d < ND; ++d) acc[d] += blockpart[(int64_t)b * (ND + 2) + d];
     acc[ND] = fmax(acc[ND], blockpart[(int64_t)b * (ND + 2) + ND]);
     acc[ND + 1] += blockpart[(int64_t)b * (ND + 2) + ND + 1];
   }
+  for (int b = threadIdx.x; b < NGAIN_BLK; b += PREP_BLOCK) {
+    acc[ND + 2] += gainpart[2 * b];
+    acc[ND + 3] += gainpart[2 * b + 1];
+  }
 #pragma unroll
-  for (int j = 0; j < ND + 2; ++j) red[j][threadIdx.x] = acc[j];
+  for (int j = 0; j < ND + 4; ++j) red[j][threadIdx.x] = acc[j];
   __syncthreads();
   for (int off = PREP_BLOCK / 2; off > 0; off >>= 1) {
     if (threadIdx.x < off) {
@@ -104,6 +140,8 @@ __global__ __launch_bounds__(PREP_BLOCK) void k_prep_final(const double* __restr
       for (int d = 0; d < ND; ++d) red[d][threadIdx.x] += red[d][threadIdx.x + off];
       red[ND][threadIdx.x] = fmax(red[ND][threadIdx.x], red[ND][threadIdx.x + off]);
       red[ND + 1][threadIdx.x] += red[ND + 1][threadIdx.x + off];
+      red[ND + 2][threadIdx.x] += red[ND + 2][threadIdx.x + off];
+      red[ND + 3][threadIdx.x] += red[ND + 3][threadIdx.x + off];
     }
     __syncthreads();
   }
@@ -114,6 +152,11 @@ __global__ __launch_bounds__(PREP_BLOCK) void k_prep_final(const double* __restr
     const double um = red[ND][0];
     // smallest power of two >= max |u| (exact rescaling of the float32 tables)
     e.uref = (um > 0.0 && isfinite(um)) ? exp2(ceil(log2(um))) : 1.0;
+    // Z_hw ~ conj(G) Z for coherent sums, so the float32 sums are multiplied by 1 / conj(G)
+    const double gr = red[ND + 2][0], gi = red[ND + 3][0];
+    const double g2 = gr * gr + gi * gi;
+    e.gain_r = gr / g2;
+    e.gain_i = gi / g2;
     e.bad = red[ND + 1][0] != 0.0 || !isfinite(um);
     e.pad = 0;
     *ec = e;
@@ -140,9 +183,13 @@ template <int ND>
 static hipError_t prep_nd(const double* data, const double* psd, const double* fgrid, int64_t M, double df, void* tab64,
                           void* tab32, RowGradF32* g32, RowGradF64* g64, double* blockpart, int nblk, EventConst* ec,
                           hipStream_t s) {
+  // blockpart holds nblk * (ND + 2) bin partials followed by NGAIN_BLK * 2 gain partials
+  double* gainpart = blockpart + (size_t)nblk * (ND + 2);
   hipLaunchKernelGGL(k_prep_bins<ND>, dim3(nblk), dim3(PREP_BLOCK), 0, s, data, psd, fgrid, M, df,
                      (RowF64<ND>*)tab64, g32, g64, blockpart);
-  hipLaunchKernelGGL(k_prep_final<ND>, dim3(1), dim3(PREP_BLOCK), 0, s, (const double*)blockpart, nblk, ec);
+  hipLaunchKernelGGL(k_gain_partial, dim3(NGAIN_BLK), dim3(PREP_BLOCK), 0, s, gainpart);
+  hipLaunchKernelGGL(k_prep_final<ND>, dim3(1), dim3(PREP_BLOCK), 0, s, (const double*)blockpart, nblk,
+                     (const double*)gainpart, ec);
   hipLaunchKernelGGL(k_prep_mixed<ND>, dim3(nblk), dim3(PREP_BLOCK), 0, s, (const RowF64<ND>*)tab64, M,
                      (const EventConst*)ec, (RowMixed<ND>*)tab32);
   return hipGetLastError();

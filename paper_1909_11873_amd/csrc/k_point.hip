@@ -64,6 +64,18 @@ __device__ inline void gather(const double* __restrict__ part, int nchunk, int64
   }
 }
 
+// Divide the measured mean gain of the float32 hardware phasor out of every complex sum.
+template <int NZ>
+__device__ inline void apply_gain(const EventConst* __restrict__ ec, double (&acc)[NZ]) {
+  const double gr = ec->gain_r, gi = ec->gain_i;
+#pragma unroll
+  for (int z = 0; z < NZ; z += 2) {
+    const double re = acc[z], im = acc[z + 1];
+    acc[z] = re * gr - im * gi;
+    acc[z + 1] = re * gi + im * gr;
+  }
+}
+
 // logL = sum_det [ uref Re(A E Q_det Z_det) - 1/2 A^2 |Q_det|^2 K_det ],  E = exp(-2 pi i c0).
 template <int ND>
 __global__ __launch_bounds__(PT_BLOCK) void k_epilogue(EventGeom g, const EventConst* __restrict__ ec,
@@ -75,6 +87,7 @@ __global__ __launch_bounds__(PT_BLOCK) void k_epilogue(EventGeom g, const EventC
   constexpr int NZ = nz_of(ND, false);
   double acc[NZ];
   gather<NZ>(part, nchunk, Bp, p, acc);
+  if (scaled) apply_gain<NZ>(ec, acc);
   double th[NPARAM];
 #pragma unroll
   for (int i = 0; i < NPARAM; ++i) th[i] = theta[p * NPARAM + i];
@@ -114,6 +127,7 @@ __global__ __launch_bounds__(PT_BLOCK) void k_epilogue_grad(EventGeom g, const E
   constexpr int NZ = nz_of(ND, true);
   double acc[NZ];
   gather<NZ>(part, nchunk, Bp, p, acc);
+  if (scaled) apply_gain<NZ>(ec, acc);
   D th[NPARAM];
 #pragma unroll
   for (int i = 0; i < NPARAM; ++i) th[i] = dvar<NPARAM>(theta[p * NPARAM + i], i);

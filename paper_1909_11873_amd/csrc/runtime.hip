@@ -9,6 +9,8 @@
 
 #include <mutex>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "../../include/gwlike.h"
 #include "gwl_common.h"
@@ -126,7 +128,7 @@ gwl_status gwl_event_create(const double* data, const double* psd, const gwl_det
   if (e == hipSuccess) e = hipMalloc((void**)&ev->g32, sizeof(RowGradF32) * M);
   if (e == hipSuccess) e = hipMalloc((void**)&ev->g64, sizeof(RowGradF64) * M);
   if (e == hipSuccess) e = hipMalloc((void**)&ev->ec, sizeof(EventConst));
-  if (e == hipSuccess) e = hipMalloc((void**)&blockpart, sizeof(double) * (ndet + 2) * (size_t)nblk);
+  if (e == hipSuccess) e = hipMalloc((void**)&blockpart, sizeof(double) * prep_scratch_doubles(ndet, M));
   if (e == hipSuccess)
     e = launch_prep(ndet, data, psd, fgrid, M, df, ev->tab64, ev->tab32, ev->g32, ev->g64, blockpart, nblk, ev->ec, s);
   if (e == hipSuccess) e = hipMemcpyAsync(&ev->ech, ev->ec, sizeof(EventConst), hipMemcpyDeviceToHost, s);
@@ -238,16 +240,79 @@ gwl_status run_logl(gwl_event ev, const double* theta, int64_t B, bool mixed, bo
   return GWL_OK;
 }
 
+// ---- bin-loop timing (gwl_profile_*) ----
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+static std::vector<std::pair<hipEvent_t, hipEvent_t>> g_prof_events;
+
+static bool prof_begin(hipStream_t s, hipEvent_t& a, hipEvent_t& b) {
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_prof_on) return false;
+  }
+  if (hipEventCreate(&a) != hipSuccess) return false;
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return false;
+  }
+  (void)hipEventRecord(a, s);
+  return true;
+}
+
+static void prof_end(hipStream_t s, hipEvent_t a, hipEvent_t b) {
+  (void)hipEventRecord(b, s);
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_events.emplace_back(a, b);
+}
+
 hipError_t enqueue_logl(gwl_event ev, const double* theta, int64_t B, bool mixed, bool grad, const LoopShape& sh,
                         double* coef, double* part, double* logl, double* gradout, hipStream_t s) {
   const int64_t Bp = (int64_t)sh.npg * WAVE;
   hipError_t e = launch_setup(ev->ndet, ev->geom, theta, B, Bp, coef, s);
+  hipEvent_t pa = nullptr, pb = nullptr;
+  const bool prof = e == hipSuccess && prof_begin(s, pa, pb);
   if (e == hipSuccess)
     e = launch_bins(ev->ndet, mixed, grad, mixed ? ev->tab32 : ev->tab64, ev->g32, ev->g64, coef, B, Bp, ev->M, sh,
                     part, s);
+  if (prof) prof_end(s, pa, pb);
   if (e == hipSuccess)
     e = launch_epilogue(ev->ndet, grad, mixed, ev->geom, ev->ec, theta, B, Bp, sh.nchunk, part, logl, gradout, s);
   return e;
 }
 
 }  // namespace gwl
+
+extern "C" {
+
+gwl_status gwl_profile_enable(int on) {
+  clear_error();
+  std::lock_guard<std::mutex> lk(gwl::g_prof_mu);
+  gwl::g_prof_on = on != 0;
+  return GWL_OK;
+}
+
+gwl_status gwl_profile_read(int64_t* launches, double* total_ms) {
+  clear_error();
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  {
+    std::lock_guard<std::mutex> lk(gwl::g_prof_mu);
+    ev.swap(gwl::g_prof_events);
+  }
+  double tot = 0.0;
+  hipError_t err = hipSuccess;
+  for (auto& p : ev) {
+    hipError_t e = hipEventSynchronize(p.second);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, p.first, p.second);
+    if (e == hipSuccess) tot += ms;
+    else if (err == hipSuccess) err = e;
+    (void)hipEventDestroy(p.first);
+    (void)hipEventDestroy(p.second);
+  }
+  if (launches) *launches = (int64_t)ev.size();
+  if (total_ms) *total_ms = tot;
+  if (err != hipSuccess) return hip_fail(err, "profile read");
+  return GWL_OK;
+}
+
+}  // extern "C"

@@ -65,6 +65,8 @@ def lib() -> ctypes.CDLL:
         "gwl_plan_destroy": ([vp], cint),
         "gwl_autotune": ([ctypes.c_char_p, vp, i64, cint, cint], cint),
         "gwl_autotune_load": ([ctypes.c_char_p], cint),
+        "gwl_profile_enable": ([cint], cint),
+        "gwl_profile_read": ([ctypes.POINTER(i64), ctypes.POINTER(dbl)], cint),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -217,6 +219,19 @@ def autotune(ev: Event, batch: int, precision="mixed", with_grad: bool = False,
 
 def autotune_load(cache_path: str) -> None:
     _check("gwl_autotune_load", lib().gwl_autotune_load(cache_path.encode()))
+
+
+def profile_enable(on: bool = True) -> None:
+    """Bracket every bin-loop launch with HIP events on its stream (measurement aid)."""
+    _check("gwl_profile_enable", lib().gwl_profile_enable(int(bool(on))))
+
+
+def profile_read():
+    """(launches, total_ms) of the bin-loop launches bracketed since the previous read."""
+    n = ctypes.c_int64()
+    ms = ctypes.c_double()
+    _check("gwl_profile_read", lib().gwl_profile_read(ctypes.byref(n), ctypes.byref(ms)))
+    return int(n.value), float(ms.value)
 
 
 def version() -> str:
