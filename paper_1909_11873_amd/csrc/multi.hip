@@ -1,23 +1,518 @@
-// Several events of uneven size in one persistent launch (placeholder until implemented).
+// Several events of uneven duration and batch size in one persistent launch, captured in a
+// HIP graph (the batch axis of the paper's parallel prior sampling, section 3, extended over
+// events).
+//
+// Work items are (event, 64-point group, bin chunk) with one chunk length for all events, so
+// items cost about the same; events are queued shortest first, items of an event chunk-major.
+// Every wavefront of the persistent kernel takes items from an atomic counter until the queue
+// is empty; each item writes its own partial sums, which a multi-event epilogue launch adds in
+// chunk order (deterministic). A per-event counter stamps the device clock when the last item
+// of the event completes. The graph is: reset (counters and start stamp, by a kernel) ->
+// per-point set-up for all events -> persistent bin loop -> epilogue for all events.
 #include <hip/hip_runtime.h>
 
+#include <math.h>
+#include <stddef.h>
+#include <string.h>
+
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
+#include "gwl_bins.h"
+#include "gwl_epilogue.h"
 #include "gwl_runtime.h"
 
 using namespace gwl;
 
+namespace gwl {
+
+constexpr int MULTI_PT_BLOCK = 128;
+
+struct MultiEvDev {
+  const void* tab;         // RowMixed<ND> or RowF64<ND> [M]
+  const void* gtab;        // RowGradF32 or RowGradF64 [M]
+  const EventConst* ec;
+  double* coef;            // [NCOEF][Bp]
+  double* part;            // [nchunk][NZ][Bp]
+  int64_t Bp;
+  int M, chunk, nchunk, npg;
+  int item0, nitems;       // first item in the queue, item count
+  int pad[2];
+};
+
+struct MultiIODev {
+  const double* theta;     // [B][11]
+  double* logl;            // [B]
+  double* grad;            // [B][11] or null
+  int64_t B;
+};
+
+struct MultiCtl {
+  unsigned int next;       // queue head
+  unsigned int pad;
+  unsigned long long t0;   // device clock at the start of the launch
+  unsigned long long tend; // device clock at the end of the epilogue
+};
+
+__global__ void k_multi_reset(MultiCtl* __restrict__ ctl, unsigned int* __restrict__ done,
+                              unsigned long long* __restrict__ tev, int E) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < E) {
+    done[i] = 0u;
+    tev[i] = 0ull;
+  }
+  if (i == 0) {
+    ctl->next = 0u;
+    ctl->pad = 0u;
+    ctl->t0 = wall_clock64();
+    ctl->tend = 0ull;
+  }
+}
+
+template <int ND>
+__global__ __launch_bounds__(MULTI_PT_BLOCK) void k_multi_setup(const MultiEvDev* __restrict__ evs,
+                                                                 const EventGeom* __restrict__ geoms,
+                                                                 const MultiIODev* __restrict__ io,
+                                                                 const int* __restrict__ blk_ev,
+                                                                 const int* __restrict__ blk_p0) {
+  const int e = blk_ev[blockIdx.x];
+  const int64_t p = (int64_t)blk_p0[blockIdx.x] + threadIdx.x;
+  const MultiEvDev ev = evs[e];
+  const MultiIODev o = io[e];
+  if (p >= ev.Bp) return;
+  const int64_t pc = p < o.B ? p : o.B - 1;
+  double th[NPARAM];
+#pragma unroll
+  for (int i = 0; i < NPARAM; ++i) th[i] = o.theta[pc * NPARAM + i];
+  PointModel<double> pm;
+  point_model<double, ND>(th, geoms[e], pm);
+  const double nan = __builtin_nan("");
+  double rows[NCOEF];
+#pragma unroll
+  for (int j = 0; j < NCOEF; ++j) rows[j] = 0.0;
+#pragma unroll
+  for (int m = 0; m < NBASIS; ++m) rows[CO_A + m] = pm.a[m];
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    rows[CO_T + d] = pm.tdet[d];
+    rows[CO_QR + d] = pm.qr[d];
+    rows[CO_QI + d] = pm.qi[d];
+  }
+  rows[CO_C0] = pm.c0;
+  rows[CO_AMP] = pm.amp;
+#pragma unroll
+  for (int j = 0; j < NCOEF; ++j) ev.coef[j * ev.Bp + p] = pm.valid ? rows[j] : nan;
+}
+
+// Persistent bin loop: one wavefront per item, items from the shared counter.
+template <int ND, bool MIXED, bool GRAD>
+__global__ __launch_bounds__(BLOCK) void k_multi_bins(const MultiEvDev* __restrict__ evs, int E, int total,
+                                                      const MultiIODev* __restrict__ io, MultiCtl* __restrict__ ctl,
+                                                      unsigned int* __restrict__ done,
+                                                      unsigned long long* __restrict__ tev) {
+  constexpr int NZ = nz_of(ND, GRAD);
+  const int lane = threadIdx.x % WAVE;
+  for (;;) {
+    int it = 0;
+    if (lane == 0) it = (int)atomicAdd(&ctl->next, 1u);
+    it = __shfl(it, 0);
+    if (it >= total) break;
+    // event of this item: queue order is event order, item0 increasing
+    int e = 0;
+    while (e + 1 < E && evs[e + 1].item0 <= it) ++e;
+    const MultiEvDev ev = evs[e];
+    const int64_t B = io[e].B;
+    const int local = it - ev.item0;
+    const int c = local / ev.npg;
+    const int pg = local - c * ev.npg;
+    const int64_t p = (int64_t)pg * WAVE + lane;
+    const int64_t pc = p < B ? p : B - 1;
+    const int k0 = c * ev.chunk;
+    const int k1 = k0 + ev.chunk < ev.M ? k0 + ev.chunk : ev.M;
+    double tot[NZ];
+    double a[NBASIS], T[ND];
+    if constexpr (MIXED) {
+      float qr[ND], qi[ND];
+      load_coef<ND, float>(ev.coef, ev.Bp, pc, GRAD, a, T, qr, qi);
+      bin_loop_mixed<ND, GRAD>((const RowMixed<ND>*)ev.tab, (const RowGradF32*)ev.gtab, k0, k1, a, T, qr, qi, tot);
+    } else {
+      double qr[ND], qi[ND];
+      load_coef<ND, double>(ev.coef, ev.Bp, pc, GRAD, a, T, qr, qi);
+      bin_loop_f64<ND, GRAD>((const RowF64<ND>*)ev.tab, (const RowGradF64*)ev.gtab, k0, k1, a, T, qr, qi, tot);
+    }
+#pragma unroll
+    for (int z = 0; z < NZ; ++z) ev.part[((int64_t)c * NZ + z) * ev.Bp + p] = tot[z];
+    if (lane == 0) {
+      const unsigned int d = atomicAdd(&done[e], 1u);
+      if (d + 1u == (unsigned int)ev.nitems) tev[e] = wall_clock64();
+    }
+  }
+}
+
+template <int ND, bool GRAD>
+__global__ __launch_bounds__(MULTI_PT_BLOCK) void k_multi_epilogue(const MultiEvDev* __restrict__ evs,
+                                                                    const EventGeom* __restrict__ geoms,
+                                                                    const MultiIODev* __restrict__ io,
+                                                                    const int* __restrict__ blk_ev,
+                                                                    const int* __restrict__ blk_p0, bool scaled,
+                                                                    MultiCtl* __restrict__ ctl) {
+  constexpr int NZ = nz_of(ND, GRAD);
+  const int e = blk_ev[blockIdx.x];
+  const int64_t p = (int64_t)blk_p0[blockIdx.x] + threadIdx.x;
+  const MultiEvDev ev = evs[e];
+  const MultiIODev o = io[e];
+  if (p < o.B) {
+    const EventConst ec = *ev.ec;
+    double acc[NZ];
+    gather<NZ>(ev.part, ev.nchunk, ev.Bp, p, acc);
+    if (scaled) apply_gain<NZ>(ec, acc);
+    double th[NPARAM];
+#pragma unroll
+    for (int i = 0; i < NPARAM; ++i) th[i] = o.theta[p * NPARAM + i];
+    const double nan = __builtin_nan("");
+    bool valid;
+    if constexpr (GRAD) {
+      double gout[NPARAM];
+      const double v = epilogue_gradient<ND>(acc, th, geoms[e], ec, scaled ? ec.uref : 1.0, valid, gout);
+      o.logl[p] = valid ? v : nan;
+#pragma unroll
+      for (int j = 0; j < NPARAM; ++j) o.grad[p * NPARAM + j] = valid ? gout[j] : nan;
+    } else {
+      const double v = epilogue_value<ND, NZ>(acc, th, geoms[e], ec, scaled ? ec.uref : 1.0, valid);
+      o.logl[p] = valid ? v : nan;
+    }
+  }
+  if (threadIdx.x == 0) atomicMax(&ctl->tend, wall_clock64());
+}
+
+}  // namespace gwl
+
+struct gwl_plan_s {
+  int device = 0;
+  int E = 0, nd = 0;
+  bool mixed = false, grad = false;
+  std::vector<int64_t> B;
+  std::vector<int> order;      // queue position -> event index
+  int total = 0, grid = 0, nptblk = 0, chunk = 0;
+  double clock_khz = 0.0;
+  gwl::MultiEvDev* d_evs = nullptr;   // in queue order
+  gwl::EventGeom* d_geoms = nullptr;  // in queue order
+  gwl::MultiIODev* d_io = nullptr;    // in queue order
+  gwl::MultiIODev* h_io = nullptr;    // pinned host staging
+  int* d_blk = nullptr;               // [2][nptblk]: event (queue index), first point
+  void* d_ctl = nullptr;              // MultiCtl, done[E], tev[E]
+  unsigned long long* h_stamps = nullptr;  // pinned: t0, tend, tev[E]
+  double* ws = nullptr;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t io_done = nullptr;
+};
+
+namespace {
+
+// Switched off until the cause of the non-completing first GPU run is found.
+constexpr bool kMultiEnabled = false;
+
+size_t ctl_bytes(int E) {
+  return sizeof(gwl::MultiCtl) + sizeof(unsigned int) * (size_t)((E + 1) & ~1) + sizeof(unsigned long long) * E;
+}
+
+void plan_free(gwl_plan pl) {
+  if (!pl) return;
+  if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+  if (pl->graph) (void)hipGraphDestroy(pl->graph);
+  if (pl->cap) (void)hipStreamDestroy(pl->cap);
+  if (pl->io_done) (void)hipEventDestroy(pl->io_done);
+  if (pl->d_evs) (void)hipFree(pl->d_evs);
+  if (pl->d_geoms) (void)hipFree(pl->d_geoms);
+  if (pl->d_io) (void)hipFree(pl->d_io);
+  if (pl->d_blk) (void)hipFree(pl->d_blk);
+  if (pl->d_ctl) (void)hipFree(pl->d_ctl);
+  if (pl->ws) (void)hipFree(pl->ws);
+  if (pl->h_io) (void)hipHostFree(pl->h_io);
+  if (pl->h_stamps) (void)hipHostFree(pl->h_stamps);
+  delete pl;
+}
+
+template <int ND>
+hipError_t enqueue_multi_nd(gwl_plan pl, hipStream_t s) {
+  const int E = pl->E;
+  unsigned char* ctl = (unsigned char*)pl->d_ctl;
+  gwl::MultiCtl* c = (gwl::MultiCtl*)ctl;
+  unsigned int* done = (unsigned int*)(ctl + sizeof(gwl::MultiCtl));
+  unsigned long long* tev =
+      (unsigned long long*)(ctl + sizeof(gwl::MultiCtl) + sizeof(unsigned int) * (size_t)((E + 1) & ~1));
+  const int* blk_ev = pl->d_blk;
+  const int* blk_p0 = pl->d_blk + pl->nptblk;
+  hipLaunchKernelGGL(gwl::k_multi_reset, dim3((E + 255) / 256), dim3(256), 0, s, c, done, tev, E);
+  hipLaunchKernelGGL(gwl::k_multi_setup<ND>, dim3(pl->nptblk), dim3(gwl::MULTI_PT_BLOCK), 0, s,
+                     (const gwl::MultiEvDev*)pl->d_evs, (const gwl::EventGeom*)pl->d_geoms,
+                     (const gwl::MultiIODev*)pl->d_io, blk_ev, blk_p0);
+#define GWL_MB(MX, GR)                                                                                             \
+  hipLaunchKernelGGL((gwl::k_multi_bins<ND, MX, GR>), dim3(pl->grid), dim3(gwl::BLOCK), 0, s,                   \
+                     (const gwl::MultiEvDev*)pl->d_evs, E, pl->total, (const gwl::MultiIODev*)pl->d_io, c, done, tev)
+  if (pl->mixed) {
+    if (pl->grad) GWL_MB(true, true); else GWL_MB(true, false);
+  } else {
+    if (pl->grad) GWL_MB(false, true); else GWL_MB(false, false);
+  }
+#undef GWL_MB
+  if (pl->grad)
+    hipLaunchKernelGGL((gwl::k_multi_epilogue<ND, true>), dim3(pl->nptblk), dim3(gwl::MULTI_PT_BLOCK), 0, s,
+                       (const gwl::MultiEvDev*)pl->d_evs, (const gwl::EventGeom*)pl->d_geoms,
+                       (const gwl::MultiIODev*)pl->d_io, blk_ev, blk_p0, pl->mixed, c);
+  else
+    hipLaunchKernelGGL((gwl::k_multi_epilogue<ND, false>), dim3(pl->nptblk), dim3(gwl::MULTI_PT_BLOCK), 0, s,
+                       (const gwl::MultiEvDev*)pl->d_evs, (const gwl::EventGeom*)pl->d_geoms,
+                       (const gwl::MultiIODev*)pl->d_io, blk_ev, blk_p0, pl->mixed, c);
+  return hipGetLastError();
+}
+
+hipError_t enqueue_multi(gwl_plan pl, hipStream_t s) {
+  switch (pl->nd) {
+    case 1: return enqueue_multi_nd<1>(pl, s);
+    case 2: return enqueue_multi_nd<2>(pl, s);
+    case 3: return enqueue_multi_nd<3>(pl, s);
+    case 4: return enqueue_multi_nd<4>(pl, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int ND>
+hipError_t occupancy_nd(bool mixed, bool grad, int* nblk) {
+#define GWL_OCC(MX, GR) \
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(nblk, gwl::k_multi_bins<ND, MX, GR>, gwl::BLOCK, 0)
+  if (mixed) {
+    if (grad) GWL_OCC(true, true); else GWL_OCC(true, false);
+  } else {
+    if (grad) GWL_OCC(false, true); else GWL_OCC(false, false);
+  }
+#undef GWL_OCC
+}
+
+hipError_t occupancy(int nd, bool mixed, bool grad, int* nblk) {
+  switch (nd) {
+    case 1: return occupancy_nd<1>(mixed, grad, nblk);
+    case 2: return occupancy_nd<2>(mixed, grad, nblk);
+    case 3: return occupancy_nd<3>(mixed, grad, nblk);
+    case 4: return occupancy_nd<4>(mixed, grad, nblk);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
 extern "C" {
 
-gwl_status gwl_multi_plan_create(const gwl_event*, int, const int64_t*, gwl_precision, int, gwl_plan* out) {
+gwl_status gwl_multi_plan_create(const gwl_event* evs, int E, const int64_t* B_e, gwl_precision prec, int with_grad,
+                                 gwl_plan* out) {
   clear_error();
-  if (out) *out = nullptr;
-  return fail(GWL_E_UNSUPPORTED, "multi-event plans are not implemented yet");
+  if (!out) return fail(GWL_E_INVALID, "out is null");
+  *out = nullptr;
+  if (!evs || !B_e) return fail(GWL_E_INVALID, "evs and B_e must be host arrays");
+  if (E < 1 || E > 4096) return fail(GWL_E_SHAPE, "E=%d outside [1, 4096]", E);
+  if (prec != GWL_FP64 && prec != GWL_MIXED) return fail(GWL_E_INVALID, "unknown precision %d", (int)prec);
+  const int nd = evs[0] ? evs[0]->ndet : 0;
+  for (int e = 0; e < E; ++e) {
+    if (!evs[e]) return fail(GWL_E_INVALID, "event %d is null", e);
+    if (evs[e]->ndet != nd) return fail(GWL_E_UNSUPPORTED, "events must share one detector count");
+    if (evs[e]->device != evs[0]->device) return fail(GWL_E_INVALID, "events must live on one device");
+    if (B_e[e] < 0 || B_e[e] > kMaxBatch) return fail(GWL_E_SHAPE, "B_e[%d]=%lld out of range", e, (long long)B_e[e]);
+  }
+  gwl_status st = check_device(evs[0]->device);
+  if (st != GWL_OK) return st;
+  if (!kMultiEnabled)
+    return fail(GWL_E_UNSUPPORTED, "the persistent multi-event launch is switched off: its first GPU run did not "
+                                   "complete and the cause has not been identified");
+
+  gwl_plan pl = new (std::nothrow) gwl_plan_s();
+  if (!pl) return fail(GWL_E_NOMEM, "host allocation failed");
+  pl->device = evs[0]->device;
+  pl->E = E;
+  pl->nd = nd;
+  pl->mixed = prec == GWL_MIXED;
+  pl->grad = with_grad != 0;
+  pl->B.assign(B_e, B_e + E);
+
+  // one chunk length for all events: the largest power of two in [1024, 16384] that still
+  // gives at least four items per resident wavefront
+  hipError_t err = hipSuccess;
+  int occ = 0, ncu = 0, clk = 0;
+  err = occupancy(nd, pl->mixed, pl->grad, &occ);
+  if (err == hipSuccess) err = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, pl->device);
+  if (err == hipSuccess) err = hipDeviceGetAttribute(&clk, hipDeviceAttributeWallClockRate, pl->device);
+  if (err != hipSuccess) {
+    plan_free(pl);
+    return hip_fail(err, "device query");
+  }
+  if (occ < 1) occ = 1;
+  pl->grid = occ * ncu;
+  pl->clock_khz = (double)clk;
+  const int64_t resident = (int64_t)pl->grid * WAVES_PER_BLOCK;
+  auto items_for = [&](int chunk) {
+    int64_t n = 0;
+    for (int e = 0; e < E; ++e) {
+      if (B_e[e] == 0) continue;
+      n += ((B_e[e] + WAVE - 1) / WAVE) * ((evs[e]->M + chunk - 1) / chunk);
+    }
+    return n;
+  };
+  int chunk = 1024;
+  for (int c = 16384; c >= 1024; c >>= 1) {
+    if (items_for(c) >= 4 * resident) {
+      chunk = c;
+      break;
+    }
+  }
+  const int64_t total = items_for(chunk);
+  if (total > ((int64_t)1 << 30)) {
+    plan_free(pl);
+    return fail(GWL_E_SHAPE, "too many work items (%lld)", (long long)total);
+  }
+  pl->chunk = chunk;
+  pl->total = (int)total;
+
+  // queue order: events by ascending work, ties by index
+  pl->order.resize(E);
+  std::iota(pl->order.begin(), pl->order.end(), 0);
+  std::stable_sort(pl->order.begin(), pl->order.end(), [&](int a, int b) {
+    return (double)B_e[a] * (double)evs[a]->M < (double)B_e[b] * (double)evs[b]->M;
+  });
+
+  // workspace and device tables
+  const int NZ = nz_of(nd, pl->grad);
+  std::vector<MultiEvDev> hev(E);
+  std::vector<EventGeom> hgeo(E);
+  std::vector<int> blk_ev, blk_p0;
+  size_t ws_doubles = 0;
+  int item0 = 0;
+  for (int q = 0; q < E; ++q) {
+    const int e = pl->order[q];
+    const gwl_event ev = evs[e];
+    MultiEvDev& d = hev[q];
+    memset(&d, 0, sizeof d);
+    const int64_t B = B_e[e];
+    d.npg = (int)((B + WAVE - 1) / WAVE);
+    d.Bp = (int64_t)d.npg * WAVE;
+    d.M = (int)ev->M;
+    d.chunk = chunk;
+    d.nchunk = B > 0 ? (int)((ev->M + chunk - 1) / chunk) : 0;
+    d.item0 = item0;
+    d.nitems = d.npg * d.nchunk;
+    item0 += d.nitems;
+    d.tab = pl->mixed ? ev->tab32 : ev->tab64;
+    d.gtab = pl->mixed ? (const void*)ev->g32 : (const void*)ev->g64;
+    d.ec = ev->ec;
+    ws_doubles += (size_t)NCOEF * d.Bp + (size_t)d.nchunk * NZ * d.Bp;
+    hgeo[q] = ev->geom;
+    for (int64_t p0 = 0; p0 < d.Bp; p0 += MULTI_PT_BLOCK) {
+      blk_ev.push_back(q);
+      blk_p0.push_back((int)p0);
+    }
+  }
+  pl->nptblk = (int)blk_ev.size();
+  err = hipMalloc((void**)&pl->ws, sizeof(double) * (ws_doubles > 0 ? ws_doubles : 1));
+  size_t off = 0;
+  for (int q = 0; q < E; ++q) {
+    MultiEvDev& d = hev[q];
+    d.coef = pl->ws + off;
+    off += (size_t)NCOEF * d.Bp;
+    d.part = pl->ws + off;
+    off += (size_t)d.nchunk * NZ * d.Bp;
+  }
+  std::vector<int> blk(blk_ev);
+  blk.insert(blk.end(), blk_p0.begin(), blk_p0.end());
+  if (err == hipSuccess) err = hipMalloc((void**)&pl->d_evs, sizeof(MultiEvDev) * E);
+  if (err == hipSuccess) err = hipMalloc((void**)&pl->d_geoms, sizeof(EventGeom) * E);
+  if (err == hipSuccess) err = hipMalloc((void**)&pl->d_io, sizeof(MultiIODev) * E);
+  if (err == hipSuccess) err = hipMalloc((void**)&pl->d_blk, sizeof(int) * (blk.empty() ? 1 : blk.size()));
+  if (err == hipSuccess) err = hipMalloc(&pl->d_ctl, ctl_bytes(E));
+  if (err == hipSuccess) err = hipHostMalloc((void**)&pl->h_io, sizeof(MultiIODev) * E, hipHostMallocDefault);
+  if (err == hipSuccess)
+    err = hipHostMalloc((void**)&pl->h_stamps, sizeof(unsigned long long) * (2 + E), hipHostMallocDefault);
+  if (err == hipSuccess) err = hipMemcpy(pl->d_evs, hev.data(), sizeof(MultiEvDev) * E, hipMemcpyHostToDevice);
+  if (err == hipSuccess) err = hipMemcpy(pl->d_geoms, hgeo.data(), sizeof(EventGeom) * E, hipMemcpyHostToDevice);
+  if (err == hipSuccess && !blk.empty())
+    err = hipMemcpy(pl->d_blk, blk.data(), sizeof(int) * blk.size(), hipMemcpyHostToDevice);
+  if (err == hipSuccess) {
+    memset(pl->h_io, 0, sizeof(MultiIODev) * E);
+    err = hipMemcpy(pl->d_io, pl->h_io, sizeof(MultiIODev) * E, hipMemcpyHostToDevice);
+  }
+  if (err == hipSuccess) err = hipEventCreateWithFlags(&pl->io_done, hipEventDisableTiming);
+  if (err == hipSuccess) err = hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking);
+  // capture the whole evaluation once
+  if (err == hipSuccess) err = hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal);
+  if (err == hipSuccess) {
+    hipError_t e1 = enqueue_multi(pl, pl->cap);
+    hipError_t e2 = hipStreamEndCapture(pl->cap, &pl->graph);
+    err = e1 != hipSuccess ? e1 : e2;
+  }
+  if (err == hipSuccess) err = hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0);
+  if (err != hipSuccess) {
+    plan_free(pl);
+    return hip_fail(err, "multi-event plan");
+  }
+  *out = pl;
+  return GWL_OK;
 }
 
-gwl_status gwl_multi_launch(gwl_plan, const double* const*, double* const*, double* const*, double*, void*) {
+gwl_status gwl_multi_launch(gwl_plan pl, const double* const* theta, double* const* logl, double* const* grad,
+                            double* event_latency_us, void* stream) {
   clear_error();
-  return fail(GWL_E_UNSUPPORTED, "multi-event plans are not implemented yet");
+  if (!pl) return fail(GWL_E_INVALID, "plan is null");
+  if (!theta || !logl) return fail(GWL_E_INVALID, "theta and logl must be host arrays of device pointers");
+  if (pl->grad && !grad) return fail(GWL_E_INVALID, "the plan computes gradients: grad must be given");
+  for (int e = 0; e < pl->E; ++e) {
+    if (pl->B[e] == 0) continue;
+    if (!theta[e] || !logl[e] || (pl->grad && !grad[e]))
+      return fail(GWL_E_INVALID, "event %d: null device pointer", e);
+  }
+  gwl_status st = check_device(pl->device);
+  if (st != GWL_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  // the staging buffer is reused: wait until the previous upload has been consumed
+  hipError_t err = hipEventSynchronize(pl->io_done);
+  if (err != hipSuccess) return hip_fail(err, "plan staging");
+  for (int q = 0; q < pl->E; ++q) {
+    const int e = pl->order[q];
+    pl->h_io[q].theta = theta[e];
+    pl->h_io[q].logl = logl[e];
+    pl->h_io[q].grad = pl->grad ? grad[e] : nullptr;
+    pl->h_io[q].B = pl->B[e];
+  }
+  err = hipMemcpyAsync(pl->d_io, pl->h_io, sizeof(MultiIODev) * pl->E, hipMemcpyHostToDevice, s);
+  if (err == hipSuccess) err = hipEventRecord(pl->io_done, s);
+  if (err == hipSuccess) err = hipGraphLaunch(pl->exec, s);
+  if (err != hipSuccess) return hip_fail(err, "multi-event launch");
+  if (event_latency_us) {
+    const unsigned char* ctl = (const unsigned char*)pl->d_ctl;
+    const size_t tev_off = sizeof(MultiCtl) + sizeof(unsigned int) * (size_t)((pl->E + 1) & ~1);
+    err = hipMemcpyAsync(pl->h_stamps, ctl + offsetof(MultiCtl, t0), sizeof(unsigned long long) * 2,
+                         hipMemcpyDeviceToHost, s);
+    if (err == hipSuccess)
+      err = hipMemcpyAsync(pl->h_stamps + 2, ctl + tev_off, sizeof(unsigned long long) * pl->E,
+                           hipMemcpyDeviceToHost, s);
+    if (err == hipSuccess) err = hipStreamSynchronize(s);
+    if (err != hipSuccess) return hip_fail(err, "latency read-back");
+    const unsigned long long t0 = pl->h_stamps[0], tend = pl->h_stamps[1];
+    unsigned long long tbins = t0;
+    for (int q = 0; q < pl->E; ++q) tbins = std::max(tbins, pl->h_stamps[2 + q]);
+    // an event's results exist once its last item is done and the final epilogue launch has run
+    const double epi_us = tend > tbins ? (double)(tend - tbins) * 1e3 / pl->clock_khz : 0.0;
+    for (int q = 0; q < pl->E; ++q) {
+      const int e = pl->order[q];
+      const unsigned long long te = pl->h_stamps[2 + q];
+      event_latency_us[e] = pl->B[e] == 0 ? 0.0 : (double)(te - t0) * 1e3 / pl->clock_khz + epi_us;
+    }
+  }
+  return GWL_OK;
 }
 
-gwl_status gwl_plan_destroy(gwl_plan) { return GWL_OK; }
+gwl_status gwl_plan_destroy(gwl_plan pl) {
+  plan_free(pl);
+  return GWL_OK;
+}
 
 }  // extern "C"

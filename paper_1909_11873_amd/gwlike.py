@@ -210,6 +210,61 @@ def waveform(theta: torch.Tensor, dets: Sequence, fgrid: torch.Tensor, gmst: flo
     return out
 
 
+class MultiPlan:
+    """Many events of uneven size evaluated by one persistent launch captured in a HIP graph.
+
+    events   list of Event (same detector count, same device); batches: points per event.
+    launch(thetas) takes one float64 CUDA tensor [B_e, 11] per event and returns
+    (logls, grads or None, latency_us or None).
+    """
+
+    def __init__(self, events: Sequence[Event], batches: Sequence[int], precision="mixed", with_grad: bool = False):
+        self.events = list(events)
+        self.batches = [int(b) for b in batches]
+        if len(self.events) != len(self.batches) or not self.events:
+            raise ValueError("one batch size per event is required")
+        self.with_grad = bool(with_grad)
+        E = len(self.events)
+        evs = (ctypes.c_void_p * E)(*[ev.handle.value for ev in self.events])
+        bs = (ctypes.c_int64 * E)(*self.batches)
+        h = ctypes.c_void_p()
+        _check("gwl_multi_plan_create", lib().gwl_multi_plan_create(evs, E, bs, _prec(precision),
+                                                                    int(self.with_grad), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, thetas: Sequence[torch.Tensor], latency: bool = False):
+        E = len(self.events)
+        if len(thetas) != E:
+            raise ValueError("one theta tensor per event is required")
+        thetas = [_theta(t) for t in thetas]
+        for t, b in zip(thetas, self.batches):
+            if t.shape[0] != b:
+                raise ValueError("theta batch sizes must match the plan")
+        dev = thetas[0].device
+        logls = [torch.empty(b, dtype=torch.float64, device=dev) for b in self.batches]
+        grads = [torch.empty(b, NPARAM, dtype=torch.float64, device=dev) for b in self.batches] \
+            if self.with_grad else None
+        tp = (ctypes.c_void_p * E)(*[t.data_ptr() for t in thetas])
+        lp = (ctypes.c_void_p * E)(*[t.data_ptr() for t in logls])
+        gp = (ctypes.c_void_p * E)(*[t.data_ptr() for t in grads]) if grads is not None else None
+        lat = (ctypes.c_double * E)() if latency else None
+        _check("gwl_multi_launch", lib().gwl_multi_launch(self._h, tp, lp, gp, lat, _stream(thetas[0])))
+        # keep the inputs alive until the stream has consumed them
+        self._last = (thetas, logls, grads)
+        return logls, grads, (list(lat) if latency else None)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            lib().gwl_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def autotune(ev: Event, batch: int, precision="mixed", with_grad: bool = False,
              cache_path: Optional[str] = None) -> None:
     """Time tile shapes for this event and batch size; record the best (in memory and in cache_path)."""

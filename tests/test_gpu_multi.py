@@ -1,0 +1,114 @@
+"""Multi-event persistent launch (HIP graph) against single-event calls and the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import gw_oracle as o
+from paper_1909_11873_amd import gwlike as gw
+from paper_1909_11873_amd import synth
+from tests.helpers import scaled_grad_error
+
+pytestmark = [
+    pytest.mark.gpu,
+    pytest.mark.skip(reason="the persistent multi-event launch is switched off: its first GPU run did not complete "
+                            "and the cause has not been identified; gwl_multi_plan_create returns GWL_E_UNSUPPORTED"),
+]
+DEV = torch.device("cuda:0")
+
+# five events of the uneven-batching workload's kind, band-limited to keep the oracle quick;
+# one event has an empty batch and one a single point
+DURATIONS = [4.0, 16.0, 8.0, 4.0, 32.0]
+BATCHES = [70, 300, 0, 1, 129]
+
+
+def build_events(f_hi=300.0):
+    out = []
+    for i, (dur, b) in enumerate(zip(DURATIONS, BATCHES)):
+        spec = synth.event_spec(4, i)
+        df = 1.0 / dur
+        f = synth.freq_grid(20.0, f_hi, df)
+        s = synth.psd_fit(f)
+        psd = np.stack([s] * 3)
+        nz = np.stack([synth.noise(spec.seed_base + d, s, df) for d in range(3)])
+        dets = np.array([synth.detector_rad(n) for n in spec.det_names])
+        data = nz + o.strain_all(spec.theta0, dets, f).numpy()
+        th = synth.prior_draw(np.random.default_rng(spec.seed_base + 10), b)
+        ev = gw.Event(torch.tensor(data, device=DEV), torch.tensor(psd, device=DEV), dets,
+                      torch.tensor(f, device=DEV), df)
+        out.append(dict(ev=ev, th=th, f=f, psd=psd, data=data, dets=dets, df=df))
+    return out
+
+
+@pytest.fixture(scope="module")
+def events():
+    return build_events()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_multi_forward_matches_single_calls_and_oracle(events, prec):
+    plan = gw.MultiPlan([e["ev"] for e in events], BATCHES, prec, with_grad=False)
+    thetas = [torch.tensor(e["th"], device=DEV).reshape(-1, 11) for e in events]
+    logls, grads, lat = plan.launch(thetas, latency=True)
+    assert grads is None
+    for e, t, l in zip(events, thetas, logls):
+        if t.shape[0] == 0:
+            assert l.shape == (0,)
+            continue
+        single = gw.logl(t, e["ev"], prec).cpu().numpy()
+        got = l.cpu().numpy()
+        assert np.abs(got - single).max() <= (1e-8 if prec == "fp64" else 2e-4)
+        n = min(4, t.shape[0])
+        ref = o.logl(e["th"][:n], e["data"], e["psd"], e["dets"], e["f"], e["df"]).numpy()
+        assert np.abs(got[:n] - ref).max() <= (1e-6 if prec == "fp64" else 1e-3)
+    assert len(lat) == len(events)
+    assert all(x > 0 for x, b in zip(lat, BATCHES) if b > 0)
+    assert lat[BATCHES.index(0)] == 0.0
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_multi_gradient_matches_oracle(events, prec):
+    plan = gw.MultiPlan([e["ev"] for e in events], BATCHES, prec, with_grad=True)
+    thetas = [torch.tensor(e["th"], device=DEV).reshape(-1, 11) for e in events]
+    logls, grads, _ = plan.launch(thetas)
+    for e, t, l, g in zip(events, thetas, logls, grads):
+        if t.shape[0] == 0:
+            continue
+        n = min(2, t.shape[0])
+        v, gr = o.logl_grad(e["th"][:n], e["data"], e["psd"], e["dets"], e["f"], e["df"])
+        assert np.abs(l.cpu().numpy()[:n] - v.numpy()).max() <= (1e-6 if prec == "fp64" else 1e-3)
+        assert scaled_grad_error(g.cpu().numpy()[:n], gr.numpy()).max() <= 1e-4
+    plan.close()
+
+
+def test_multi_graph_replays_are_identical(events):
+    """Replays of the captured graph, with eager work in between, reproduce the first result bitwise."""
+    plan = gw.MultiPlan([e["ev"] for e in events], BATCHES, "mixed", with_grad=True)
+    thetas = [torch.tensor(e["th"], device=DEV).reshape(-1, 11) for e in events]
+    first, gfirst, _ = plan.launch(thetas)
+    first = [x.cpu().numpy() for x in first]
+    gfirst = [x.cpu().numpy() for x in gfirst]
+    for rep in range(4):
+        torch.cuda.synchronize()
+        _ = gw.logl(thetas[1], events[1]["ev"], "mixed")   # eager work between replays
+        again, g, _ = plan.launch(thetas)
+        for a, b in zip(first, again):
+            assert np.array_equal(a, b.cpu().numpy())
+        for a, b in zip(gfirst, g):
+            assert np.array_equal(a, b.cpu().numpy())
+    # new inputs through the same plan
+    th2 = [t.flip(0).contiguous() for t in thetas]
+    l2, _, _ = plan.launch(th2)
+    for e, t, l in zip(events, th2, l2):
+        if t.shape[0]:
+            assert np.abs(l.cpu().numpy() - gw.logl(t, e["ev"], "mixed").cpu().numpy()).max() <= 2e-4
+    plan.close()
+
+
+def test_multi_plan_argument_errors(events):
+    with pytest.raises(ValueError):
+        gw.MultiPlan([events[0]["ev"]], [1, 2])
+    plan = gw.MultiPlan([events[0]["ev"]], [70], "mixed")
+    with pytest.raises(ValueError):
+        plan.launch([torch.zeros(3, 11, dtype=torch.float64, device=DEV)])
+    plan.close()
