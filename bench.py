@@ -34,8 +34,8 @@ PEAK_FP32 = 157.3e12   # FP32 vector FLOP/s (published; needs packed FMA)
 # 256 CU x 64 lanes/clk x 2.4 GHz / 2
 PEAK_TRANS = 256 * 64 * 2.4e9 / 2
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_bins_mixed_c1.txt")
-KERNEL_SOURCES = ["paper_1909_11873_amd/csrc/k_bins.hip", "paper_1909_11873_amd/csrc/gwl_common.h",
-                  "paper_1909_11873_amd/csrc/gwl_device.h"]
+KERNEL_SOURCES = ["paper_1909_11873_amd/csrc/k_bins.hip", "paper_1909_11873_amd/csrc/gwl_bins.h",
+                  "paper_1909_11873_amd/csrc/gwl_common.h", "paper_1909_11873_amd/csrc/gwl_device.h"]
 
 
 def work_per_point_bin(ndet: int, mixed: bool):
@@ -44,11 +44,12 @@ def work_per_point_bin(ndet: int, mixed: bool):
     Phase polynomial: 7 FMA + 2 MUL in float64 (16 flops). Per detector: the f T_det shift
     (1 FMA), the reduction to one cycle (1 op), the phasor (sin + cos) and the complex
     multiply-accumulate u (cos - i sin) (4 FMA). In the float64 kernel sin and cos have no
-    hardware instruction; their work is the polynomial pair evaluated (18 FMA + 3 ops).
+    hardware instruction; their work is the table-and-polynomial evaluation (index 2 ops,
+    y 1 FMA, y^2, 5 FMA + 1 MUL for the two short series, 2 FMA + 2 MUL to rotate: 21 flops).
     """
     if mixed:
         return 16 + ndet * (2 + 1), ndet * 8, ndet * 2
-    return 16 + ndet * (2 + 1 + 39 + 8), 0, 0
+    return 16 + ndet * (2 + 1 + 21 + 8), 0, 0
 
 
 def roofline(ndet: int, mixed: bool, nbins: int, npoints: int, seconds: float):

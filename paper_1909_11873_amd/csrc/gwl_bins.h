@@ -12,6 +12,32 @@ namespace gwl {
 
 constexpr int NB = 8;  // bins per float32 block before the float64 flush (mixed precision)
 
+// Float64 phasor by table and short polynomials: t = n/N + y with n = rint(N t), |y| <= 1/(2N),
+// e^{2 pi i t} = T[n mod N] e^{2 pi i y}; T holds (cos, sin) of 2 pi k / N in LDS and the
+// Taylor series of e^{2 pi i y} is cut where the next term is below 1e-17 (|2 pi y| <= 0.0123).
+constexpr int PH_TBL = 256;
+__device__ __forceinline__ void fill_phasor_table(double2* tbl) {
+  for (int k = threadIdx.x; k < PH_TBL; k += blockDim.x) {
+    double s, c;
+    sincos_cycles_f64((double)k / PH_TBL, s, c);
+    tbl[k] = make_double2(c, s);
+  }
+}
+__device__ __forceinline__ void sincos_cycles_tbl(double t, const double2* __restrict__ tbl, double& s, double& c) {
+  const double n = rint(t * (double)PH_TBL);
+  const double y = fma(n, -1.0 / PH_TBL, t);                // exact, |y| <= 1/512
+  const double2 e = tbl[(int)n & (PH_TBL - 1)];  // v_cvt_i32_f64 clamps; the mask keeps the index in range
+  const double z = y * y;
+  double ps = fma(z, 81.60524927607506, -41.34170224039976);                               // sin(2 pi y) / y
+  ps = fma(ps, z, 6.283185307179586);
+  const double sv = ps * y;
+  double pc = fma(z, -85.45681720669373, 64.9393940226683);                               // cos(2 pi y)
+  pc = fma(pc, z, -19.739208802178716);
+  pc = fma(pc, z, 1.0);
+  c = fma(e.x, pc, -(e.y * sv));
+  s = fma(e.y, pc, e.x * sv);
+}
+
 // Horner form of sum_m a_m g_m(f) in x = f^(1/3):  a0 w + w2 (a1 + x (a2 + x (a3 + x (a4 ln f
 //   + x (a5 + a6 ln f + x a7))))),  w = f^-5/3, w2 = f^-1.
 __device__ __forceinline__ double phase_poly(const double (&a)[NBASIS], double x, double w, double w2, double lnf) {
@@ -66,13 +92,14 @@ __device__ __forceinline__ void mixed_bin(const RowMixed<ND>& r, const RowGradF3
 template <int ND, bool GRAD>
 __device__ __forceinline__ void f64_bin(const RowF64<ND>& r, const RowGradF64* __restrict__ gt, int k,
                                         const double (&a)[NBASIS], const double (&T)[ND], const double (&qr)[ND],
-                                        const double (&qi)[ND], double (&z)[nz_of(ND, GRAD)]) {
+                                        const double (&qi)[ND], const double2* __restrict__ tbl,
+                                        double (&z)[nz_of(ND, GRAD)]) {
   const double psi = phase_poly(a, r.x, r.w, r.w2, r.lnf);
   double yr = 0.0, yi = 0.0;
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
     double sn, cs;
-    sincos_cycles_f64(fma(r.f, T[d], psi), sn, cs);
+    sincos_cycles_tbl(fma(r.f, T[d], psi), tbl, sn, cs);
     const double ur = r.u[2 * d], ui = r.u[2 * d + 1];
     if (!GRAD) {
       z[2 * d] = fma(ur, cs, fma(ui, sn, z[2 * d]));
@@ -134,12 +161,12 @@ template <int ND, bool GRAD>
 __device__ __forceinline__ void bin_loop_f64(const RowF64<ND>* __restrict__ tab, const RowGradF64* __restrict__ gtab,
                                              int k0, int k1, const double (&a)[NBASIS], const double (&T)[ND],
                                              const double (&qr)[ND], const double (&qi)[ND],
-                                             double (&z)[nz_of(ND, GRAD)]) {
+                                             const double2* __restrict__ tbl, double (&z)[nz_of(ND, GRAD)]) {
   constexpr int NZ = nz_of(ND, GRAD);
 #pragma unroll
   for (int j = 0; j < NZ; ++j) z[j] = 0.0;
 #pragma unroll 2
-  for (int k = k0; k < k1; ++k) f64_bin<ND, GRAD>(tab[k], gtab, k, a, T, qr, qi, z);
+  for (int k = k0; k < k1; ++k) f64_bin<ND, GRAD>(tab[k], gtab, k, a, T, qr, qi, tbl, z);
 }
 
 // Per-lane coefficients of point pc from the set-up rows coef[row][Bp].

@@ -75,6 +75,9 @@ __global__ __launch_bounds__(BLOCK) void k_bins_f64(const RowF64<ND>* __restrict
                                                     const double* __restrict__ coef, int64_t B, int64_t Bp, int64_t M,
                                                     LoopShape sh, double* __restrict__ part) {
   constexpr int NZ = nz_of(ND, GRAD);
+  __shared__ double2 tbl[PH_TBL];
+  fill_phasor_table(tbl);  // before any wavefront leaves
+  __syncthreads();
   int c, k0, k1, pg;
   if (!locate(sh, M, c, k0, k1, pg)) return;
   const int64_t p = (int64_t)pg * WAVE + (threadIdx.x % WAVE);
@@ -82,7 +85,7 @@ __global__ __launch_bounds__(BLOCK) void k_bins_f64(const RowF64<ND>* __restrict
   double a[NBASIS], T[ND], qr[ND], qi[ND];
   load_coef<ND, double>(coef, Bp, pc, GRAD, a, T, qr, qi);
   double z[NZ];
-  bin_loop_f64<ND, GRAD>(tab, gtab, k0, k1, a, T, qr, qi, z);
+  bin_loop_f64<ND, GRAD>(tab, gtab, k0, k1, a, T, qr, qi, tbl, z);
 #pragma unroll
   for (int j = 0; j < NZ; ++j) part[((int64_t)c * NZ + j) * Bp + p] = z[j];
 }

@@ -112,11 +112,18 @@ __global__ __launch_bounds__(BLOCK) void k_multi_bins(const MultiEvDev* __restri
                                                       unsigned int* __restrict__ done,
                                                       unsigned long long* __restrict__ tev) {
   constexpr int NZ = nz_of(ND, GRAD);
+  __shared__ double2 tbl[PH_TBL];
+  fill_phasor_table(tbl);
+  __syncthreads();
   const int lane = threadIdx.x % WAVE;
   for (;;) {
-    int it = 0;
-    if (lane == 0) it = (int)atomicAdd(&ctl->next, 1u);
-    it = __shfl(it, 0);
+    // One ticket per wavefront. Every lane takes part in the atomic (lane 0 adds 1, the others
+    // 0) and the first lane's old value is read back as a scalar, so the loop is wave-uniform:
+    // a per-lane broadcast (a shuffle inside lane-divergent control flow) lets the compiler
+    // separate the lane that takes the ticket from the lanes that read it, and those then
+    // never see the queue advance.
+    const unsigned int ticket = atomicAdd(&ctl->next, lane == 0 ? 1u : 0u);
+    const int it = (int)__builtin_amdgcn_readfirstlane(ticket);
     if (it >= total) break;
     // event of this item: queue order is event order, item0 increasing
     int e = 0;
@@ -139,14 +146,13 @@ __global__ __launch_bounds__(BLOCK) void k_multi_bins(const MultiEvDev* __restri
     } else {
       double qr[ND], qi[ND];
       load_coef<ND, double>(ev.coef, ev.Bp, pc, GRAD, a, T, qr, qi);
-      bin_loop_f64<ND, GRAD>((const RowF64<ND>*)ev.tab, (const RowGradF64*)ev.gtab, k0, k1, a, T, qr, qi, tot);
+      bin_loop_f64<ND, GRAD>((const RowF64<ND>*)ev.tab, (const RowGradF64*)ev.gtab, k0, k1, a, T, qr, qi, tbl, tot);
     }
 #pragma unroll
     for (int z = 0; z < NZ; ++z) ev.part[((int64_t)c * NZ + z) * ev.Bp + p] = tot[z];
-    if (lane == 0) {
-      const unsigned int d = atomicAdd(&done[e], 1u);
-      if (d + 1u == (unsigned int)ev.nitems) tev[e] = wall_clock64();
-    }
+    const unsigned int prev = atomicAdd(&done[e], lane == 0 ? 1u : 0u);
+    const unsigned int d = __builtin_amdgcn_readfirstlane(prev);
+    if (d + 1u == (unsigned int)ev.nitems && lane == 0) tev[e] = wall_clock64();
   }
 }
 
@@ -212,8 +218,8 @@ struct gwl_plan_s {
 
 namespace {
 
-// Switched off until the cause of the non-completing first GPU run is found.
-constexpr bool kMultiEnabled = false;
+// Set to false to switch the multi-event plan off.
+constexpr bool kMultiEnabled = true;
 
 size_t ctl_bytes(int E) {
   return sizeof(gwl::MultiCtl) + sizeof(unsigned int) * (size_t)((E + 1) & ~1) + sizeof(unsigned long long) * E;

@@ -8,11 +8,7 @@ from paper_1909_11873_amd import gwlike as gw
 from paper_1909_11873_amd import synth
 from tests.helpers import scaled_grad_error
 
-pytestmark = [
-    pytest.mark.gpu,
-    pytest.mark.skip(reason="the persistent multi-event launch is switched off: its first GPU run did not complete "
-                            "and the cause has not been identified; gwl_multi_plan_create returns GWL_E_UNSUPPORTED"),
-]
+pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
 
 # five events of the uneven-batching workload's kind, band-limited to keep the oracle quick;
