@@ -38,6 +38,38 @@ __device__ __forceinline__ void sincos_cycles_tbl(double t, const double2* __res
   s = fma(e.y, pc, e.x * sv);
 }
 
+// Member-wise row loads, valid for plain and address-space-qualified table pointers.
+template <int ND, class P>
+__device__ __forceinline__ RowMixed<ND> load_row_mixed(P tab, int k) {
+  RowMixed<ND> r;
+  r.f = tab[k].f; r.x = tab[k].x; r.w = tab[k].w; r.w2 = tab[k].w2; r.lnf = tab[k].lnf;
+#pragma unroll
+  for (int j = 0; j < 2 * ND; ++j) r.u[j] = tab[k].u[j];
+  return r;
+}
+template <int ND, class P>
+__device__ __forceinline__ RowF64<ND> load_row_f64(P tab, int k) {
+  RowF64<ND> r;
+  r.f = tab[k].f; r.x = tab[k].x; r.w = tab[k].w; r.w2 = tab[k].w2; r.lnf = tab[k].lnf;
+#pragma unroll
+  for (int j = 0; j < 2 * ND; ++j) r.u[j] = tab[k].u[j];
+  return r;
+}
+template <class P>
+__device__ __forceinline__ RowGradF32 load_grad_f32(P g, int k) {
+  RowGradF32 r;
+#pragma unroll
+  for (int m = 0; m < NBASIS; ++m) r.g[m] = g[k].g[m];
+  r.f = g[k].f;
+  return r;
+}
+template <class P>
+__device__ __forceinline__ RowGradF64 load_grad_f64(P g, int k) {
+  RowGradF64 r;
+  r.g2 = g[k].g2; r.g3 = g[k].g3; r.g6 = g[k].g6; r.g7 = g[k].g7;
+  return r;
+}
+
 // Horner form of sum_m a_m g_m(f) in x = f^(1/3):  a0 w + w2 (a1 + x (a2 + x (a3 + x (a4 ln f
 //   + x (a5 + a6 ln f + x a7))))),  w = f^-5/3, w2 = f^-1.
 __device__ __forceinline__ double phase_poly(const double (&a)[NBASIS], double x, double w, double w2, double lnf) {
@@ -49,14 +81,18 @@ __device__ __forceinline__ double phase_poly(const double (&a)[NBASIS], double x
   return fma(w2, t, w * a[0]);
 }
 
-template <int ND, bool GRAD>
-__device__ __forceinline__ void mixed_bin(const RowMixed<ND>& r, const RowGradF32* __restrict__ gt, int k,
+template <int ND, bool GRAD, class GradP>
+__device__ __forceinline__ void mixed_bin(const RowMixed<ND> r, GradP gt, int k,
                                           const double (&a)[NBASIS], const double (&T)[ND], const float (&qr)[ND],
                                           const float (&qi)[ND], float (&z)[nz_of(ND, GRAD)]) {
   const double psi = phase_poly(a, r.x, r.w, r.w2, r.lnf);
   float yr = 0.0f, yi = 0.0f;
   float fk = 0.0f;
-  if (GRAD) fk = gt[k].f;
+  RowGradF32 g;
+  if (GRAD) {
+    g = load_grad_f32(gt, k);
+    fk = g.f;
+  }
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
     const double ph = fma(r.f, T[d], psi);
@@ -80,7 +116,6 @@ __device__ __forceinline__ void mixed_bin(const RowMixed<ND>& r, const RowGradF3
     }
   }
   if (GRAD) {
-    const RowGradF32 g = gt[k];
 #pragma unroll
     for (int m = 0; m < NBASIS; ++m) {
       z[4 * ND + 2 * m] = fmaf(g.g[m], yr, z[4 * ND + 2 * m]);
@@ -89,8 +124,8 @@ __device__ __forceinline__ void mixed_bin(const RowMixed<ND>& r, const RowGradF3
   }
 }
 
-template <int ND, bool GRAD>
-__device__ __forceinline__ void f64_bin(const RowF64<ND>& r, const RowGradF64* __restrict__ gt, int k,
+template <int ND, bool GRAD, class GradP>
+__device__ __forceinline__ void f64_bin(const RowF64<ND> r, GradP gt, int k,
                                         const double (&a)[NBASIS], const double (&T)[ND], const double (&qr)[ND],
                                         const double (&qi)[ND], const double2* __restrict__ tbl,
                                         double (&z)[nz_of(ND, GRAD)]) {
@@ -116,7 +151,7 @@ __device__ __forceinline__ void f64_bin(const RowF64<ND>& r, const RowGradF64* _
     }
   }
   if (GRAD) {
-    const RowGradF64 g = gt[k];
+    const RowGradF64 g = load_grad_f64(gt, k);
     const double gm[NBASIS] = {r.w, r.w2, g.g2, g.g3, r.lnf, r.x, g.g6, g.g7};
 #pragma unroll
     for (int m = 0; m < NBASIS; ++m) {
@@ -128,8 +163,8 @@ __device__ __forceinline__ void f64_bin(const RowF64<ND>& r, const RowGradF64* _
 
 // The bin loop of one wavefront: points in lanes, bins [k0, k1) of one event.
 // Mixed precision: float32 sums over blocks of NB bins, each block added into float64.
-template <int ND, bool GRAD>
-__device__ __forceinline__ void bin_loop_mixed(const RowMixed<ND>* __restrict__ tab, const RowGradF32* __restrict__ gtab,
+template <int ND, bool GRAD, class TabP, class GradP>
+__device__ __forceinline__ void bin_loop_mixed(TabP tab, GradP gtab,
                                                int k0, int k1, const double (&a)[NBASIS], const double (&T)[ND],
                                                const float (&qr)[ND], const float (&qi)[ND],
                                                double (&tot)[nz_of(ND, GRAD)]) {
@@ -142,7 +177,7 @@ __device__ __forceinline__ void bin_loop_mixed(const RowMixed<ND>* __restrict__ 
 #pragma unroll
     for (int j = 0; j < NZ; ++j) z[j] = 0.0f;
 #pragma unroll 2
-    for (int j = 0; j < NB; ++j) mixed_bin<ND, GRAD>(tab[k + j], gtab, k + j, a, T, qr, qi, z);
+    for (int j = 0; j < NB; ++j) mixed_bin<ND, GRAD, GradP>(load_row_mixed<ND>(tab, k + j), gtab, k + j, a, T, qr, qi, z);
 #pragma unroll
     for (int j = 0; j < NZ; ++j) tot[j] += (double)z[j];
   }
@@ -150,15 +185,15 @@ __device__ __forceinline__ void bin_loop_mixed(const RowMixed<ND>* __restrict__ 
     float z[NZ];
 #pragma unroll
     for (int j = 0; j < NZ; ++j) z[j] = 0.0f;
-    for (; k < k1; ++k) mixed_bin<ND, GRAD>(tab[k], gtab, k, a, T, qr, qi, z);
+    for (; k < k1; ++k) mixed_bin<ND, GRAD, GradP>(load_row_mixed<ND>(tab, k), gtab, k, a, T, qr, qi, z);
 #pragma unroll
     for (int j = 0; j < NZ; ++j) tot[j] += (double)z[j];
   }
 }
 
 // Float64: sums in float64 throughout.
-template <int ND, bool GRAD>
-__device__ __forceinline__ void bin_loop_f64(const RowF64<ND>* __restrict__ tab, const RowGradF64* __restrict__ gtab,
+template <int ND, bool GRAD, class TabP, class GradP>
+__device__ __forceinline__ void bin_loop_f64(TabP tab, GradP gtab,
                                              int k0, int k1, const double (&a)[NBASIS], const double (&T)[ND],
                                              const double (&qr)[ND], const double (&qi)[ND],
                                              const double2* __restrict__ tbl, double (&z)[nz_of(ND, GRAD)]) {
@@ -166,8 +201,16 @@ __device__ __forceinline__ void bin_loop_f64(const RowF64<ND>* __restrict__ tab,
 #pragma unroll
   for (int j = 0; j < NZ; ++j) z[j] = 0.0;
 #pragma unroll 2
-  for (int k = k0; k < k1; ++k) f64_bin<ND, GRAD>(tab[k], gtab, k, a, T, qr, qi, tbl, z);
+  for (int k = k0; k < k1; ++k) f64_bin<ND, GRAD, GradP>(load_row_f64<ND>(tab, k), gtab, k, a, T, qr, qi, tbl, z);
 }
+
+// Read-only tables reached through a pointer held in memory (not a kernel argument) are read
+// through the constant address space: the compiler can then use scalar loads for wave-uniform
+// addresses, as it does for `const __restrict__` kernel arguments.
+template <class T>
+using const_as_ptr = const __attribute__((address_space(4))) T*;
+template <class T>
+using global_as_ptr = __attribute__((address_space(1))) T*;
 
 // Per-lane coefficients of point pc from the set-up rows coef[row][Bp].
 template <int ND, class QT>

@@ -107,7 +107,7 @@ __global__ __launch_bounds__(MULTI_PT_BLOCK) void k_multi_setup(const MultiEvDev
 
 // Persistent bin loop: one wavefront per item, items from the shared counter.
 template <int ND, bool MIXED, bool GRAD>
-__global__ __launch_bounds__(BLOCK) void k_multi_bins(const MultiEvDev* __restrict__ evs, int E, int total,
+__global__ __launch_bounds__(BLOCK, (ND <= 3 ? 4 : 3)) void k_multi_bins(const MultiEvDev* __restrict__ evs, int E, int total,
                                                       const MultiIODev* __restrict__ io, MultiCtl* __restrict__ ctl,
                                                       unsigned int* __restrict__ done,
                                                       unsigned long long* __restrict__ tev) {
@@ -142,14 +142,17 @@ __global__ __launch_bounds__(BLOCK) void k_multi_bins(const MultiEvDev* __restri
     if constexpr (MIXED) {
       float qr[ND], qi[ND];
       load_coef<ND, float>(ev.coef, ev.Bp, pc, GRAD, a, T, qr, qi);
-      bin_loop_mixed<ND, GRAD>((const RowMixed<ND>*)ev.tab, (const RowGradF32*)ev.gtab, k0, k1, a, T, qr, qi, tot);
+      bin_loop_mixed<ND, GRAD>((const_as_ptr<RowMixed<ND>>)ev.tab, (const_as_ptr<RowGradF32>)ev.gtab, k0, k1, a, T,
+                               qr, qi, tot);
     } else {
       double qr[ND], qi[ND];
       load_coef<ND, double>(ev.coef, ev.Bp, pc, GRAD, a, T, qr, qi);
-      bin_loop_f64<ND, GRAD>((const RowF64<ND>*)ev.tab, (const RowGradF64*)ev.gtab, k0, k1, a, T, qr, qi, tbl, tot);
+      bin_loop_f64<ND, GRAD>((const_as_ptr<RowF64<ND>>)ev.tab, (const_as_ptr<RowGradF64>)ev.gtab, k0, k1, a, T, qr,
+                             qi, tbl, tot);
     }
+    global_as_ptr<double> part = (global_as_ptr<double>)ev.part;
 #pragma unroll
-    for (int z = 0; z < NZ; ++z) ev.part[((int64_t)c * NZ + z) * ev.Bp + p] = tot[z];
+    for (int z = 0; z < NZ; ++z) part[((int64_t)c * NZ + z) * ev.Bp + p] = tot[z];
     const unsigned int prev = atomicAdd(&done[e], lane == 0 ? 1u : 0u);
     const unsigned int d = __builtin_amdgcn_readfirstlane(prev);
     if (d + 1u == (unsigned int)ev.nitems && lane == 0) tev[e] = wall_clock64();
