@@ -172,14 +172,23 @@ __device__ __forceinline__ void bin_loop_mixed(TabP tab, GradP gtab,
 #pragma unroll
   for (int z = 0; z < NZ; ++z) tot[z] = 0.0;
   int k = k0;
-  for (; k + NB <= k1; k += NB) {
-    float z[NZ];
+  if (k + NB <= k1) {
+    // each bin's row is requested one bin ahead of its use; the tables carry TAB_PAD zero rows
+    // after the last bin, so the look-ahead read past a chunk's end stays in bounds
+    RowMixed<ND> cur = load_row_mixed<ND>(tab, k);
+    for (; k + NB <= k1; k += NB) {
+      float z[NZ];
 #pragma unroll
-    for (int j = 0; j < NZ; ++j) z[j] = 0.0f;
+      for (int j = 0; j < NZ; ++j) z[j] = 0.0f;
 #pragma unroll 2
-    for (int j = 0; j < NB; ++j) mixed_bin<ND, GRAD, GradP>(load_row_mixed<ND>(tab, k + j), gtab, k + j, a, T, qr, qi, z);
+      for (int j = 0; j < NB; ++j) {
+        const RowMixed<ND> nxt = load_row_mixed<ND>(tab, k + j + 1);
+        mixed_bin<ND, GRAD, GradP>(cur, gtab, k + j, a, T, qr, qi, z);
+        cur = nxt;
+      }
 #pragma unroll
-    for (int j = 0; j < NZ; ++j) tot[j] += (double)z[j];
+      for (int j = 0; j < NZ; ++j) tot[j] += (double)z[j];
+    }
   }
   if (k < k1) {
     float z[NZ];
@@ -200,8 +209,14 @@ __device__ __forceinline__ void bin_loop_f64(TabP tab, GradP gtab,
   constexpr int NZ = nz_of(ND, GRAD);
 #pragma unroll
   for (int j = 0; j < NZ; ++j) z[j] = 0.0;
+  if (k0 >= k1) return;
+  RowF64<ND> cur = load_row_f64<ND>(tab, k0);  // rows requested one bin ahead (see bin_loop_mixed)
 #pragma unroll 2
-  for (int k = k0; k < k1; ++k) f64_bin<ND, GRAD, GradP>(load_row_f64<ND>(tab, k), gtab, k, a, T, qr, qi, tbl, z);
+  for (int k = k0; k < k1; ++k) {
+    const RowF64<ND> nxt = load_row_f64<ND>(tab, k + 1);
+    f64_bin<ND, GRAD, GradP>(cur, gtab, k, a, T, qr, qi, tbl, z);
+    cur = nxt;
+  }
 }
 
 // Read-only tables reached through a pointer held in memory (not a kernel argument) are read

@@ -38,7 +38,9 @@ struct EventConst {
 constexpr int NGAIN_BLK = 1024;
 constexpr int NGAIN_PER = 16;
 
-// Per-bin rows, one row per frequency bin, read wave-uniformly by the bin loop.
+// Per-bin rows, one row per frequency bin, read wave-uniformly by the bin loop. The row tables
+// are allocated with TAB_PAD zero rows after the last bin (look-ahead reads).
+constexpr int TAB_PAD = 8;
 // Basis: f, x = f^(1/3), w = f^(-5/3), w2 = f^(-1), ln f.
 template <int ND>
 struct RowMixed {          // float64 basis + float32 u / uref per detector (re, im)

@@ -123,8 +123,12 @@ gwl_status gwl_event_create(const double* data, const double* psd, const gwl_det
   hipError_t e = hipGetDevice(&ev->device);
   const int nblk = prep_blocks(M);
   double* blockpart = nullptr;
-  if (e == hipSuccess) e = hipMalloc(&ev->tab64, row64_bytes(ndet) * M);
-  if (e == hipSuccess) e = hipMalloc(&ev->tab32, row32_bytes(ndet) * M);
+  if (e == hipSuccess) e = hipMalloc(&ev->tab64, row64_bytes(ndet) * (M + TAB_PAD));
+  if (e == hipSuccess) e = hipMalloc(&ev->tab32, row32_bytes(ndet) * (M + TAB_PAD));
+  if (e == hipSuccess)
+    e = hipMemsetAsync((char*)ev->tab64 + row64_bytes(ndet) * M, 0, row64_bytes(ndet) * TAB_PAD, s);
+  if (e == hipSuccess)
+    e = hipMemsetAsync((char*)ev->tab32 + row32_bytes(ndet) * M, 0, row32_bytes(ndet) * TAB_PAD, s);
   if (e == hipSuccess) e = hipMalloc((void**)&ev->g32, sizeof(RowGradF32) * M);
   if (e == hipSuccess) e = hipMalloc((void**)&ev->g64, sizeof(RowGradF64) * M);
   if (e == hipSuccess) e = hipMalloc((void**)&ev->ec, sizeof(EventConst));
