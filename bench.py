@@ -6,7 +6,7 @@ the full parameter batch of the chosen workload; inputs are resident in HBM befo
 Default workload: 3 detectors, 8 s, 20-2048 Hz (16225 bins per detector), 65536 prior draws,
 mixed precision. Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--config 1|2|3] [--no-cpu-baseline]
+  python bench.py [--steps K] [--warmup W] [--config 1|2|3|4] [--no-cpu-baseline]
 
 The CPU baseline times the FP64 oracle on a bounded sample of the same workload on the
 host's cores before the GPU is touched.
@@ -38,22 +38,31 @@ KERNEL_SOURCES = ["paper_1909_11873_amd/csrc/k_bins.hip", "paper_1909_11873_amd/
                   "paper_1909_11873_amd/csrc/gwl_common.h", "paper_1909_11873_amd/csrc/gwl_device.h"]
 
 
-def work_per_point_bin(ndet: int, mixed: bool):
+def work_per_point_bin(ndet: int, mixed: bool, grad: bool = False):
     """Algorithmic work per (point, frequency bin): (fp64 flops, fp32 flops, transcendental ops).
 
-    Phase polynomial: 7 FMA + 2 MUL in float64 (16 flops). Per detector: the f T_det shift
-    (1 FMA), the reduction to one cycle (1 op), the phasor (sin + cos) and the complex
-    multiply-accumulate u (cos - i sin) (4 FMA). In the float64 kernel sin and cos have no
-    hardware instruction; their work is the table-and-polynomial evaluation (index 2 ops,
+    FMA counts 2 flops. Phase polynomial: 7 FMA + 2 MUL in float64 (16 flops). Per detector:
+    the f T_det shift (1 FMA), the reduction to one cycle (1 op), the phasor (sin + cos) and the
+    complex multiply-accumulate u (cos - i sin) (4 FMA). In the float64 kernel sin and cos have
+    no hardware instruction; their work is the table-and-polynomial evaluation (index 2 ops,
     y 1 FMA, y^2, 5 FMA + 1 MUL for the two short series, 2 FMA + 2 MUL to rotate: 21 flops).
+    The adjoint replaces the multiply-accumulate by the explicit product w = u p (2 MUL + 2 FMA),
+    its sum (2 ADD), y_det = Im(c_det w) (MUL + FMA), the f-weighted sum of y_det (FMA) and the
+    sum over detectors (ADD, one fewer than detectors): 14 flops per detector - 1; then the 8
+    basis moments (8 FMA).
     """
+    if grad:
+        moments = 14 * ndet - 1 + 16
+        if mixed:
+            return 16 + ndet * (2 + 1), moments, ndet * 2
+        return 16 + ndet * (2 + 1 + 21) + moments, 0, 0
     if mixed:
         return 16 + ndet * (2 + 1), ndet * 8, ndet * 2
     return 16 + ndet * (2 + 1 + 21 + 8), 0, 0
 
 
-def roofline(ndet: int, mixed: bool, nbins: int, npoints: int, seconds: float):
-    f64, f32, tr = work_per_point_bin(ndet, mixed)
+def roofline(ndet: int, mixed: bool, nbins: float, npoints: float, seconds: float, grad: bool = False):
+    f64, f32, tr = work_per_point_bin(ndet, mixed, grad)
     units = float(nbins) * npoints
     ops = (f64 + f32 + tr) * units
     tmin = units * (f64 / PEAK_FP64 + f32 / PEAK_FP32 + tr / PEAK_TRANS)
@@ -199,24 +208,92 @@ def gpu_leg(cfg: int, steps: int, warmup: int, parity_inputs):
     return res
 
 
-def multi_leg(steps: int, warmup: int, nevents: int = 64):
+def _worker_value_grad(args):
+    """Oracle value and gradient of a few points of one event, in points of 8; compute seconds."""
+    import numpy as np
+
+    from oracle import gw_oracle as o
+    th, data, psd, dets, f, df = args
+    t0 = time.perf_counter()
+    vs, gs = [], []
+    for i in range(0, len(th), 8):
+        v, g = o.logl_grad(th[i:i + 8], data, psd, dets, f, df)
+        vs.append(v.numpy())
+        gs.append(g.numpy())
+    return np.concatenate(vs), np.concatenate(gs), time.perf_counter() - t0
+
+
+def multi_inputs(nevents: int, oracle_injection: bool):
+    """Per event: (spec, fgrid, psd, data or noise, dets, theta). With oracle_injection the data
+    carry the FP64 oracle's signal at the event's theta0; otherwise the caller injects."""
+    from paper_1909_11873_amd import synth
+    out = []
+    for e in range(nevents):
+        spec = synth.event_spec(4, e)
+        f, psd, nz, dets = synth.event_arrays(spec)
+        if oracle_injection:
+            from oracle import gw_oracle as o
+            nz = nz + o.strain_all(spec.theta0, dets, f).numpy()
+        out.append((spec, f, psd, nz, dets, synth.theta_batch(spec)))
+    return out
+
+
+def cpu_baseline_multi(inputs, target_s: float):
+    """The FP64 oracle's value and gradient on the first k points of every event, k sized to about
+    target_s seconds on the host's cores; projected to the whole workload per event."""
+    import torch
+
+    from oracle import gw_oracle as o
+    torch.set_num_threads(1)
+    big = max(inputs, key=lambda x: len(x[1]))
+    t0 = time.perf_counter()
+    o.logl(big[5][:1], big[3], big[2], big[4], big[1], big[0].df)
+    per_bin = 3.0 * (time.perf_counter() - t0) / len(big[1])   # value + gradient: about 3x the value
+    # torch's autograd engine opens the GPU in every process that runs a backward pass: the
+    # gradient workers stay one below the box's limit of 16 GPU processes, and this process
+    # runs no backward pass itself
+    workers = max(1, min(15, os.cpu_count() or 1))
+    mbins = sum(len(x[1]) for x in inputs)
+    k = max(1, min(64, int(target_s * workers / (per_bin * mbins))))
+    order = sorted(range(len(inputs)), key=lambda e: -len(inputs[e][1]))   # longest first
+    tasks = [(inputs[e][5][:k], inputs[e][3], inputs[e][2], inputs[e][4], inputs[e][1], inputs[e][0].df)
+             for e in order]
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(workers, initializer=_worker_init, initargs=(None, None, None, None, None)) as pool:
+        t0 = time.perf_counter()
+        res = pool.map(_worker_value_grad, tasks, chunksize=1)
+        wall = time.perf_counter() - t0
+    refs = [None] * len(inputs)
+    full_s = 0.0
+    for e, (v, g, sec) in zip(order, res):
+        refs[e] = (v, g)
+        full_s += sec * inputs[e][0].batch / k
+    total = sum(x[0].batch for x in inputs)
+    sampled = k * len(inputs)
+    return {
+        "value": total / (full_s / workers), "unit": "evals/s", "cores": workers, "kind": "oracle",
+        "sample": f"value and gradient of the first {k} points of each of the {len(inputs)} events ({sampled} points, "
+                  f"FP64 torch-CPU oracle, {workers} single-threaded processes, {wall:.1f} s wall); each event's "
+                  f"compute time scaled by B_e/{k} and the sum divided over the {workers} processes",
+    }, (k, refs)
+
+
+def multi_leg(steps: int, warmup: int, inputs, cpu=None, refs=None):
     """All events of the uneven workload in one persistent mixed-precision launch, forward + gradient."""
     import numpy as np
     import torch
 
     from paper_1909_11873_amd import gwlike as gw
-    from paper_1909_11873_amd import synth
 
     dev = torch.device("cuda:0")
     events, thetas, batches, bins = [], [], [], []
-    for e in range(nevents):
-        spec = synth.event_spec(4, e)
-        f, psd, nz, dets = synth.event_arrays(spec)
+    for spec, f, psd, data, dets, th in inputs:
         ft = torch.tensor(f, device=dev)
-        h0 = gw.waveform(torch.tensor(spec.theta0[None], device=dev), dets, ft)[0]
-        ev = gw.Event(torch.tensor(nz, device=dev) + h0, torch.tensor(psd, device=dev), dets, ft, spec.df)
-        events.append(ev)
-        thetas.append(torch.tensor(synth.theta_batch(spec), device=dev))
+        dt = torch.tensor(data, device=dev)
+        if refs is None:   # no oracle data: inject with the library's own waveform at theta0
+            dt = dt + gw.waveform(torch.tensor(spec.theta0[None], device=dev), dets, ft)[0]
+        events.append(gw.Event(dt, torch.tensor(psd, device=dev), dets, ft, spec.df))
+        thetas.append(torch.tensor(th, device=dev))
         batches.append(spec.batch)
         bins.append(len(f))
     plan = gw.MultiPlan(events, batches, "mixed", with_grad=True)
@@ -228,24 +305,53 @@ def multi_leg(steps: int, warmup: int, nevents: int = 64):
         plan.launch(thetas)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    _, _, lat = plan.launch(thetas, latency=True)
+    logls, grads, lat = plan.launch(thetas, latency=True)
     lat = np.array(lat)
     total = int(sum(batches))
     pb = float(np.dot(batches, bins))
+    parity = None
+    if refs is not None:
+        k, ref = refs
+        dl, ge = [], []
+        for (v, g), l, gg in zip(ref, logls, grads):
+            dl.append(np.abs(l[:k].cpu().numpy() - v))
+            ge.append(scaled_grad_error(gg[:k].cpu().numpy(), g))
+        dl, ge = np.concatenate(dl), np.concatenate(ge)
+        parity = {"points": int(len(dl)), "max_abs_dlogl": float(dl.max()),
+                  "p99_abs_dlogl": float(np.quantile(dl, 0.99)), "tolerance": 1e-3,
+                  "max_scaled_grad_error": float(ge.max()), "grad_tolerance": 1e-4}
     plan.close()
     for ev in events:
         ev.close()
+    ach, peak, frac = roofline(3, True, pb, 1.0, wall / steps, grad=True)
     return {
         "metric": "total logL+gradient evals/s, 64 uneven events in one persistent launch (mixed)",
         "value": total * steps / wall, "unit": "evals/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
         "ms_per_step": wall / steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64+f32", "data": "synthetic",
-        "config": {"workload": f"c4: {nevents} events, 3 detectors, durations {min(bins)}-{max(bins)} bins, "
-                               f"{total} points in total", "events": nevents, "points": total,
+        "config": {"workload": f"c4: {len(inputs)} events, 3 detectors, durations {min(bins)}-{max(bins)} bins, "
+                               f"{total} points in total", "events": len(inputs), "points": total,
                    "point_bins": pb, "precision": "mixed", "gradient": True},
+        "roofline": {"bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": frac, "traffic": None,
+                     "kernel": "whole graph launch (set-up, k_multi_bins<3,mixed,grad>, epilogue)"},
         "latency_us": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "max": float(lat.max())},
+        "cpu_baseline": cpu,
+        "parity_vs_oracle": parity,
     }
+
+
+# prior widths scale the gradient components before their error is taken
+WIDTHS = (50.0, 0.8, 1.8, 1.8, 1900.0, 2 * math.pi, math.pi, math.pi, math.pi, 2 * math.pi, 0.2)
+
+
+def scaled_grad_error(g, gref):
+    """Per-component error of width-scaled gradients, relative to max(|g_i|, 1e-3 max_i |g_i|)."""
+    import numpy as np
+    w = np.array(WIDTHS)
+    gs, rs = np.asarray(g) * w, np.asarray(gref) * w
+    scale = np.maximum(np.abs(rs), 1e-3 * np.max(np.abs(rs), axis=-1, keepdims=True))
+    return np.abs(gs - rs) / scale
 
 
 def main():
@@ -266,7 +372,11 @@ def main():
         sys.exit(2)
 
     if args.config == 4:
-        print(json.dumps(multi_leg(args.steps, args.warmup)))
+        inputs = multi_inputs(64, not args.no_cpu_baseline)
+        cpu, refs = None, None
+        if not args.no_cpu_baseline:
+            cpu, refs = cpu_baseline_multi(inputs, args.cpu_seconds)
+        print(json.dumps(multi_leg(args.steps, args.warmup, inputs, cpu, refs)))
         return
 
     cpu, parity_inputs = None, None
@@ -301,7 +411,11 @@ def main():
         "fp64": {"value": r["fp64_evals"], "unit": "evals/s", "kernel_ms": r["fp64_kern"] * 1e3,
                  "roofline": {"bound": "alu", "achieved": a64, "peak": p64, "unit": "TFLOP/s", "frac": f64}},
         "grad": {"batch": r["grad_batch"], "mixed_evals_per_s": r["grad_mixed_evals"], "fp64_evals_per_s": r["grad_fp64_evals"],
-                 "mixed_kernel_ms": r["grad_mixed_kern"] * 1e3, "fp64_kernel_ms": r["grad_fp64_kern"] * 1e3},
+                 "mixed_kernel_ms": r["grad_mixed_kern"] * 1e3, "fp64_kernel_ms": r["grad_fp64_kern"] * 1e3,
+                 "mixed_roofline": dict(zip(("achieved", "peak", "frac"), roofline(nd, True, M, r["grad_batch"],
+                                                                                  r["grad_mixed_kern"], True))),
+                 "fp64_roofline": dict(zip(("achieved", "peak", "frac"), roofline(nd, False, M, r["grad_batch"],
+                                                                                 r["grad_fp64_kern"], True)))},
         "event_prep_ms": r["prep_ms"],
         "parity_vs_oracle": r["parity"],
     }

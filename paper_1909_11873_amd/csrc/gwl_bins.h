@@ -83,10 +83,10 @@ __device__ __forceinline__ double phase_poly(const double (&a)[NBASIS], double x
 
 template <int ND, bool GRAD, class GradP>
 __device__ __forceinline__ void mixed_bin(const RowMixed<ND> r, GradP gt, int k,
-                                          const double (&a)[NBASIS], const double (&T)[ND], const float (&qr)[ND],
-                                          const float (&qi)[ND], float (&z)[nz_of(ND, GRAD)]) {
+                                          const double (&a)[NBASIS], const double (&T)[ND], const float (&cr)[ND],
+                                          const float (&ci)[ND], float (&z)[nz_of(ND, GRAD)]) {
   const double psi = phase_poly(a, r.x, r.w, r.w2, r.lnf);
-  float yr = 0.0f, yi = 0.0f;
+  float y = 0.0f;
   float fk = 0.0f;
   RowGradF32 g;
   if (GRAD) {
@@ -109,28 +109,24 @@ __device__ __forceinline__ void mixed_bin(const RowMixed<ND> r, GradP gt, int k,
       const float wi = fmaf(ui, cs, -(ur * sn));
       z[2 * d] += wr;
       z[2 * d + 1] += wi;
-      z[2 * ND + 2 * d] = fmaf(fk, wr, z[2 * ND + 2 * d]);
-      z[2 * ND + 2 * d + 1] = fmaf(fk, wi, z[2 * ND + 2 * d + 1]);
-      yr = fmaf(qr[d], wr, fmaf(-qi[d], wi, yr));
-      yi = fmaf(qr[d], wi, fmaf(qi[d], wr, yi));
+      const float yd = fmaf(cr[d], wi, ci[d] * wr);  // Im(c_det w)
+      z[2 * ND + d] = fmaf(fk, yd, z[2 * ND + d]);
+      y = d == 0 ? yd : y + yd;
     }
   }
   if (GRAD) {
 #pragma unroll
-    for (int m = 0; m < NBASIS; ++m) {
-      z[4 * ND + 2 * m] = fmaf(g.g[m], yr, z[4 * ND + 2 * m]);
-      z[4 * ND + 2 * m + 1] = fmaf(g.g[m], yi, z[4 * ND + 2 * m + 1]);
-    }
+    for (int m = 0; m < NBASIS; ++m) z[3 * ND + m] = fmaf(g.g[m], y, z[3 * ND + m]);
   }
 }
 
 template <int ND, bool GRAD, class GradP>
 __device__ __forceinline__ void f64_bin(const RowF64<ND> r, GradP gt, int k,
-                                        const double (&a)[NBASIS], const double (&T)[ND], const double (&qr)[ND],
-                                        const double (&qi)[ND], const double2* __restrict__ tbl,
+                                        const double (&a)[NBASIS], const double (&T)[ND], const double (&cr)[ND],
+                                        const double (&ci)[ND], const double2* __restrict__ tbl,
                                         double (&z)[nz_of(ND, GRAD)]) {
   const double psi = phase_poly(a, r.x, r.w, r.w2, r.lnf);
-  double yr = 0.0, yi = 0.0;
+  double y = 0.0;
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
     double sn, cs;
@@ -144,20 +140,16 @@ __device__ __forceinline__ void f64_bin(const RowF64<ND> r, GradP gt, int k,
       const double wi = fma(ui, cs, -(ur * sn));
       z[2 * d] += wr;
       z[2 * d + 1] += wi;
-      z[2 * ND + 2 * d] = fma(r.f, wr, z[2 * ND + 2 * d]);
-      z[2 * ND + 2 * d + 1] = fma(r.f, wi, z[2 * ND + 2 * d + 1]);
-      yr = fma(qr[d], wr, fma(-qi[d], wi, yr));
-      yi = fma(qr[d], wi, fma(qi[d], wr, yi));
+      const double yd = fma(cr[d], wi, ci[d] * wr);  // Im(c_det w)
+      z[2 * ND + d] = fma(r.f, yd, z[2 * ND + d]);
+      y = d == 0 ? yd : y + yd;
     }
   }
   if (GRAD) {
     const RowGradF64 g = load_grad_f64(gt, k);
     const double gm[NBASIS] = {r.w, r.w2, g.g2, g.g3, r.lnf, r.x, g.g6, g.g7};
 #pragma unroll
-    for (int m = 0; m < NBASIS; ++m) {
-      z[4 * ND + 2 * m] = fma(gm[m], yr, z[4 * ND + 2 * m]);
-      z[4 * ND + 2 * m + 1] = fma(gm[m], yi, z[4 * ND + 2 * m + 1]);
-    }
+    for (int m = 0; m < NBASIS; ++m) z[3 * ND + m] = fma(gm[m], y, z[3 * ND + m]);
   }
 }
 
@@ -166,7 +158,7 @@ __device__ __forceinline__ void f64_bin(const RowF64<ND> r, GradP gt, int k,
 template <int ND, bool GRAD, class TabP, class GradP>
 __device__ __forceinline__ void bin_loop_mixed(TabP tab, GradP gtab,
                                                int k0, int k1, const double (&a)[NBASIS], const double (&T)[ND],
-                                               const float (&qr)[ND], const float (&qi)[ND],
+                                               const float (&cr)[ND], const float (&ci)[ND],
                                                double (&tot)[nz_of(ND, GRAD)]) {
   constexpr int NZ = nz_of(ND, GRAD);
 #pragma unroll
@@ -183,7 +175,7 @@ __device__ __forceinline__ void bin_loop_mixed(TabP tab, GradP gtab,
 #pragma unroll 2
       for (int j = 0; j < NB; ++j) {
         const RowMixed<ND> nxt = load_row_mixed<ND>(tab, k + j + 1);
-        mixed_bin<ND, GRAD, GradP>(cur, gtab, k + j, a, T, qr, qi, z);
+        mixed_bin<ND, GRAD, GradP>(cur, gtab, k + j, a, T, cr, ci, z);
         cur = nxt;
       }
 #pragma unroll
@@ -194,7 +186,7 @@ __device__ __forceinline__ void bin_loop_mixed(TabP tab, GradP gtab,
     float z[NZ];
 #pragma unroll
     for (int j = 0; j < NZ; ++j) z[j] = 0.0f;
-    for (; k < k1; ++k) mixed_bin<ND, GRAD, GradP>(load_row_mixed<ND>(tab, k), gtab, k, a, T, qr, qi, z);
+    for (; k < k1; ++k) mixed_bin<ND, GRAD, GradP>(load_row_mixed<ND>(tab, k), gtab, k, a, T, cr, ci, z);
 #pragma unroll
     for (int j = 0; j < NZ; ++j) tot[j] += (double)z[j];
   }
@@ -204,7 +196,7 @@ __device__ __forceinline__ void bin_loop_mixed(TabP tab, GradP gtab,
 template <int ND, bool GRAD, class TabP, class GradP>
 __device__ __forceinline__ void bin_loop_f64(TabP tab, GradP gtab,
                                              int k0, int k1, const double (&a)[NBASIS], const double (&T)[ND],
-                                             const double (&qr)[ND], const double (&qi)[ND],
+                                             const double (&cr)[ND], const double (&ci)[ND],
                                              const double2* __restrict__ tbl, double (&z)[nz_of(ND, GRAD)]) {
   constexpr int NZ = nz_of(ND, GRAD);
 #pragma unroll
@@ -214,7 +206,7 @@ __device__ __forceinline__ void bin_loop_f64(TabP tab, GradP gtab,
 #pragma unroll 2
   for (int k = k0; k < k1; ++k) {
     const RowF64<ND> nxt = load_row_f64<ND>(tab, k + 1);
-    f64_bin<ND, GRAD, GradP>(cur, gtab, k, a, T, qr, qi, tbl, z);
+    f64_bin<ND, GRAD, GradP>(cur, gtab, k, a, T, cr, ci, tbl, z);
     cur = nxt;
   }
 }
@@ -230,14 +222,14 @@ using global_as_ptr = __attribute__((address_space(1))) T*;
 // Per-lane coefficients of point pc from the set-up rows coef[row][Bp].
 template <int ND, class QT>
 __device__ __forceinline__ void load_coef(const double* __restrict__ coef, int64_t Bp, int64_t pc, bool grad,
-                                          double (&a)[NBASIS], double (&T)[ND], QT (&qr)[ND], QT (&qi)[ND]) {
+                                          double (&a)[NBASIS], double (&T)[ND], QT (&cr)[ND], QT (&ci)[ND]) {
 #pragma unroll
   for (int m = 0; m < NBASIS; ++m) a[m] = coef[(CO_A + m) * Bp + pc];
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
     T[d] = coef[(CO_T + d) * Bp + pc];
-    qr[d] = grad ? (QT)coef[(CO_QR + d) * Bp + pc] : (QT)0;
-    qi[d] = grad ? (QT)coef[(CO_QI + d) * Bp + pc] : (QT)0;
+    cr[d] = grad ? (QT)coef[(CO_CR + d) * Bp + pc] : (QT)0;
+    ci[d] = grad ? (QT)coef[(CO_CI + d) * Bp + pc] : (QT)0;
   }
 }
 

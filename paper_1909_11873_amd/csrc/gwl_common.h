@@ -71,11 +71,15 @@ constexpr int CO_QR = CO_T + MAXDET; // Re Q_det
 constexpr int CO_QI = CO_QR + MAXDET;// Im Q_det
 constexpr int CO_C0 = CO_QI + MAXDET;// constant phase (cycles)
 constexpr int CO_AMP = CO_C0 + 1;    // amplitude A
-constexpr int NCOEF = CO_AMP + 1;
+constexpr int CO_CR = CO_AMP + 1;    // Re c_det, adjoint projection c_det = E G Q_det (MAXDET rows)
+constexpr int CO_CI = CO_CR + MAXDET;// Im c_det
+constexpr int NCOEF = CO_CI + MAXDET;
 
-// Accumulated sums per point, per bin chunk (partials [chunk][z][Bp]):
-//   forward : Z_det (re, im)                                         -> 2 ND
-//   adjoint : + Z1_det = sum f u p (re, im), + Ybar_m (re, im), m < 8 -> 4 ND + 16
-__host__ __device__ constexpr int nz_of(int nd, bool grad) { return grad ? 4 * nd + 2 * NBASIS : 2 * nd; }
+// Accumulated sums per point, per bin chunk (partials [chunk][z][Bp]), with w = u p the
+// per-bin product of one detector and y_det = Im(c_det w):
+//   forward : Z_det = sum w (re, im)                                     -> 2 ND
+//   adjoint : + sum f y_det (one real per detector), + sum_k g_m sum_det y_det (m < 8)
+//                                                                         -> 3 ND + 8
+__host__ __device__ constexpr int nz_of(int nd, bool grad) { return grad ? 3 * nd + NBASIS : 2 * nd; }
 
 }  // namespace gwl

@@ -1,6 +1,6 @@
-// Float64 epilogue of one point, shared by the single-event and multi-event kernels:
-// the log-likelihood ratio from the accumulated complex sums and, for the adjoint, its
-// gradient with respect to all 11 parameters.
+// Float64 per-point work shared by the single-event and multi-event kernels: the set-up rows
+// before the bin loop, and the epilogue after it (the log-likelihood ratio from the
+// accumulated sums and, for the adjoint, its gradient with respect to all 11 parameters).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -10,12 +10,43 @@
 
 namespace gwl {
 
-// Divide the measured mean gain of the float32 hardware phasor out of every complex sum.
-template <int NZ>
+// Set-up rows (layout CO_*) of one point; false if the point is outside the model's domain.
+// (gr, gi) undoes the mean gain of the bin loop's phasor (1 for float64 tables). It enters
+// the adjoint projection factors c_det = E G Q_det, E = exp(-2 pi i c0), through which the
+// adjoint bin loop keeps only the one real part of each moment that the gradient uses.
+template <int ND>
+__device__ inline bool setup_rows(const double (&th)[NPARAM], const EventGeom& g, double gr, double gi,
+                                  double (&rows)[NCOEF]) {
+  PointModel<double> pm;
+  point_model<double, ND>(th, g, pm);
+#pragma unroll
+  for (int j = 0; j < NCOEF; ++j) rows[j] = 0.0;
+#pragma unroll
+  for (int m = 0; m < NBASIS; ++m) rows[CO_A + m] = pm.a[m];
+  const double c0 = pm.c0 - rint(pm.c0);
+  double es, ecs;
+  sincos_cycles_f64(c0, es, ecs);
+  const double egr = ecs * gr + es * gi, egi = ecs * gi - es * gr;  // E G
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    rows[CO_T + d] = pm.tdet[d];
+    rows[CO_QR + d] = pm.qr[d];
+    rows[CO_QI + d] = pm.qi[d];
+    rows[CO_CR + d] = egr * pm.qr[d] - egi * pm.qi[d];
+    rows[CO_CI + d] = egr * pm.qi[d] + egi * pm.qr[d];
+  }
+  rows[CO_C0] = pm.c0;
+  rows[CO_AMP] = pm.amp;
+  return pm.valid;
+}
+
+// Divide the measured mean gain of the float32 hardware phasor out of the complex sums Z_det
+// (the leading 2 ND entries; the adjoint moments carry the gain in c_det).
+template <int ND, int NZ>
 __device__ inline void apply_gain(const EventConst& ec, double (&acc)[NZ]) {
   const double gr = ec.gain_r, gi = ec.gain_i;
 #pragma unroll
-  for (int z = 0; z < NZ; z += 2) {
+  for (int z = 0; z < 2 * ND; z += 2) {
     const double re = acc[z], im = acc[z + 1];
     acc[z] = re * gr - im * gi;
     acc[z + 1] = re * gi + im * gr;
@@ -57,11 +88,14 @@ __device__ inline double epilogue_value(const double (&acc)[NZ], const double (&
   return out;
 }
 
-// Gradient. The bin loop accumulated, per point,
-//   Z_det  = sum_k u p,  Z1_det = sum_k f u p,  Ybar_m = sum_k g_m(f_k) sum_det Q_det u p
-// with p = exp(-2 pi i (psi_k + f_k T_det)). Then
+// Gradient. With w_det = u p, p = exp(-2 pi i (psi_k + f_k T_det)) and y_det = Im(c_det w_det),
+// the bin loop accumulated per point
+//   Z_det = sum_k w_det,  Z1_det = sum_k f_k y_det,  Y_m = sum_k g_m(f_k) sum_det y_det.
+// The phase coefficients a_m and the shifts T_det enter logL only through p, so
 //   dlogL = sum_det [ uref Re(d(A E Q_det) Z_det) - 1/2 d(A^2 |Q|^2) K_det ]
-//         + uref Re(-2 pi i A E [ sum_m da_m Ybar_m + sum_det dT_det Q_det Z1_det ]).
+//         + 2 pi uref A [ sum_m da_m Y_m + sum_det dT_det Z1_det ]
+// (the second line is Re(-2 pi i uref A E G Q_det sum_k (da.g + f_k dT_det) w_det) written
+// with c_det = E G Q_det).
 // Every d(.) comes from one-direction dual numbers pushed through the same point model, one
 // parameter at a time (11 passes; this keeps the register footprint of the epilogue small).
 template <int ND>
@@ -93,23 +127,12 @@ __device__ inline double epilogue_gradient(const double (&acc)[nz_of(ND, true)],
       const D hh = pm.amp * pm.amp * (pm.qr[d] * pm.qr[d] + pm.qi[d] * pm.qi[d]) * ec.K[d];
       tot = tot + dh - 0.5 * hh;
     }
-    // P = uref A E (values); moment term Re(-2 pi i P S) = 2 pi Im(P S)
-    const double pr = uref * pm.amp.v * er.v, pi_ = uref * pm.amp.v * ei.v;
-    double sr = 0.0, si = 0.0;
+    double sm = 0.0;
 #pragma unroll
-    for (int m = 0; m < NBASIS; ++m) {
-      sr += pm.a[m].d[0] * acc[4 * ND + 2 * m];
-      si += pm.a[m].d[0] * acc[4 * ND + 2 * m + 1];
-    }
+    for (int m = 0; m < NBASIS; ++m) sm += pm.a[m].d[0] * acc[3 * ND + m];
 #pragma unroll
-    for (int d = 0; d < ND; ++d) {
-      const double z1r = acc[2 * ND + 2 * d], z1i = acc[2 * ND + 2 * d + 1];
-      const double qr = pm.qr[d].v, qi = pm.qi[d].v;
-      const double dt = pm.tdet[d].d[0];
-      sr += dt * (qr * z1r - qi * z1i);
-      si += dt * (qr * z1i + qi * z1r);
-    }
-    gout[j] = tot.d[0] + kTwoPi * (pr * si + pi_ * sr);
+    for (int d = 0; d < ND; ++d) sm += pm.tdet[d].d[0] * acc[2 * ND + d];
+    gout[j] = tot.d[0] + kTwoPi * uref * pm.amp.v * sm;
     value = tot.v;
     valid = pm.valid;
   }

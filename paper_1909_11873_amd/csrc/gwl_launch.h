@@ -27,9 +27,10 @@ hipError_t launch_prep(int nd, const double* data, const double* psd, const doub
 int prep_blocks(int64_t M);
 size_t prep_scratch_doubles(int nd, int64_t M);  // size of `blockpart`
 
-// per-point set-up: theta[B][11] -> coef[NCOEF][Bp]
-hipError_t launch_setup(int nd, const EventGeom& g, const double* theta, int64_t B, int64_t Bp, double* coef,
-                        hipStream_t s);
+// per-point set-up: theta[B][11] -> coef[NCOEF][Bp]; `scaled` (float32 tables) takes the
+// phasor gain from *ec into the adjoint projection rows, ec may be null when it is false
+hipError_t launch_setup(int nd, const EventGeom& g, const EventConst* ec, bool scaled, const double* theta, int64_t B,
+                        int64_t Bp, double* coef, hipStream_t s);
 
 // bin loop: coef -> partial sums [nchunk][nz][Bp]
 hipError_t launch_bins(int nd, bool mixed, bool grad, const void* tab, const void* gtab, const void* gtab64,

@@ -61,10 +61,10 @@ __global__ __launch_bounds__(BLOCK) void k_bins_mixed(const RowMixed<ND>* __rest
   const int64_t p = (int64_t)pg * WAVE + (threadIdx.x % WAVE);
   const int64_t pc = p < B ? p : B - 1;
   double a[NBASIS], T[ND];
-  float qr[ND], qi[ND];
-  load_coef<ND, float>(coef, Bp, pc, GRAD, a, T, qr, qi);
+  float cr[ND], ci[ND];
+  load_coef<ND, float>(coef, Bp, pc, GRAD, a, T, cr, ci);
   double tot[NZ];
-  bin_loop_mixed<ND, GRAD>(tab, gtab, k0, k1, a, T, qr, qi, tot);
+  bin_loop_mixed<ND, GRAD>(tab, gtab, k0, k1, a, T, cr, ci, tot);
 #pragma unroll
   for (int z = 0; z < NZ; ++z) part[((int64_t)c * NZ + z) * Bp + p] = tot[z];
 }
@@ -82,10 +82,10 @@ __global__ __launch_bounds__(BLOCK) void k_bins_f64(const RowF64<ND>* __restrict
   if (!locate(sh, M, c, k0, k1, pg)) return;
   const int64_t p = (int64_t)pg * WAVE + (threadIdx.x % WAVE);
   const int64_t pc = p < B ? p : B - 1;
-  double a[NBASIS], T[ND], qr[ND], qi[ND];
-  load_coef<ND, double>(coef, Bp, pc, GRAD, a, T, qr, qi);
+  double a[NBASIS], T[ND], cr[ND], ci[ND];
+  load_coef<ND, double>(coef, Bp, pc, GRAD, a, T, cr, ci);
   double z[NZ];
-  bin_loop_f64<ND, GRAD>(tab, gtab, k0, k1, a, T, qr, qi, tbl, z);
+  bin_loop_f64<ND, GRAD>(tab, gtab, k0, k1, a, T, cr, ci, tbl, z);
 #pragma unroll
   for (int j = 0; j < NZ; ++j) part[((int64_t)c * NZ + j) * Bp + p] = z[j];
 }

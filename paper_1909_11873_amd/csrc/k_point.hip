@@ -13,44 +13,37 @@ namespace gwl {
 constexpr int PT_BLOCK = 128;
 
 template <int ND>
-__global__ __launch_bounds__(PT_BLOCK) void k_setup(EventGeom g, const double* __restrict__ theta, int64_t B,
-                                                    int64_t Bp, double* __restrict__ coef) {
+__global__ __launch_bounds__(PT_BLOCK) void k_setup(EventGeom g, const EventConst* __restrict__ ec, bool scaled,
+                                                    const double* __restrict__ theta, int64_t B, int64_t Bp,
+                                                    double* __restrict__ coef) {
   const int64_t p = (int64_t)blockIdx.x * PT_BLOCK + threadIdx.x;
   if (p >= Bp) return;
   double th[NPARAM];
   const int64_t pc = p < B ? p : B - 1;  // padding lanes repeat the last point
 #pragma unroll
   for (int i = 0; i < NPARAM; ++i) th[i] = theta[pc * NPARAM + i];
-  PointModel<double> pm;
-  point_model<double, ND>(th, g, pm);
-  const double nan = __builtin_nan("");
+  const double gr = scaled ? ec->gain_r : 1.0, gi = scaled ? ec->gain_i : 0.0;
   double rows[NCOEF];
+  const bool valid = setup_rows<ND>(th, g, gr, gi, rows);
+  const double nan = __builtin_nan("");
 #pragma unroll
-  for (int j = 0; j < NCOEF; ++j) rows[j] = 0.0;
-#pragma unroll
-  for (int m = 0; m < NBASIS; ++m) rows[CO_A + m] = pm.a[m];
-#pragma unroll
-  for (int d = 0; d < ND; ++d) {
-    rows[CO_T + d] = pm.tdet[d];
-    rows[CO_QR + d] = pm.qr[d];
-    rows[CO_QI + d] = pm.qi[d];
-  }
-  rows[CO_C0] = pm.c0;
-  rows[CO_AMP] = pm.amp;
-#pragma unroll
-  for (int j = 0; j < NCOEF; ++j) coef[j * Bp + p] = pm.valid ? rows[j] : nan;
+  for (int j = 0; j < NCOEF; ++j) coef[j * Bp + p] = valid ? rows[j] : nan;
 }
 
-hipError_t launch_setup(int nd, const EventGeom& g, const double* theta, int64_t B, int64_t Bp, double* coef,
-                        hipStream_t s) {
+hipError_t launch_setup(int nd, const EventGeom& g, const EventConst* ec, bool scaled, const double* theta, int64_t B,
+                        int64_t Bp, double* coef, hipStream_t s) {
+  if (scaled && !ec) return hipErrorInvalidValue;
   dim3 grid((unsigned)((Bp + PT_BLOCK - 1) / PT_BLOCK));
+#define GWL_SETUP(N) \
+  case N: hipLaunchKernelGGL(k_setup<N>, grid, dim3(PT_BLOCK), 0, s, g, ec, scaled, theta, B, Bp, coef); break;
   switch (nd) {
-    case 1: hipLaunchKernelGGL(k_setup<1>, grid, dim3(PT_BLOCK), 0, s, g, theta, B, Bp, coef); break;
-    case 2: hipLaunchKernelGGL(k_setup<2>, grid, dim3(PT_BLOCK), 0, s, g, theta, B, Bp, coef); break;
-    case 3: hipLaunchKernelGGL(k_setup<3>, grid, dim3(PT_BLOCK), 0, s, g, theta, B, Bp, coef); break;
-    case 4: hipLaunchKernelGGL(k_setup<4>, grid, dim3(PT_BLOCK), 0, s, g, theta, B, Bp, coef); break;
+    GWL_SETUP(1)
+    GWL_SETUP(2)
+    GWL_SETUP(3)
+    GWL_SETUP(4)
     default: return hipErrorInvalidValue;
   }
+#undef GWL_SETUP
   return hipGetLastError();
 }
 
@@ -65,7 +58,7 @@ __global__ __launch_bounds__(PT_BLOCK) void k_epilogue(EventGeom g, const EventC
   const EventConst e = *ec;
   double acc[NZ];
   gather<NZ>(part, nchunk, Bp, p, acc);
-  if (scaled) apply_gain<NZ>(e, acc);
+  if (scaled) apply_gain<ND>(e, acc);
   double th[NPARAM];
 #pragma unroll
   for (int i = 0; i < NPARAM; ++i) th[i] = theta[p * NPARAM + i];
@@ -85,7 +78,7 @@ __global__ __launch_bounds__(PT_BLOCK) void k_epilogue_grad(EventGeom g, const E
   const EventConst e = *ec;
   double acc[NZ];
   gather<NZ>(part, nchunk, Bp, p, acc);
-  if (scaled) apply_gain<NZ>(e, acc);
+  if (scaled) apply_gain<ND>(e, acc);
   double th[NPARAM], gout[NPARAM];
 #pragma unroll
   for (int i = 0; i < NPARAM; ++i) th[i] = theta[p * NPARAM + i];

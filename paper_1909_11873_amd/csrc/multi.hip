@@ -75,7 +75,7 @@ __global__ __launch_bounds__(MULTI_PT_BLOCK) void k_multi_setup(const MultiEvDev
                                                                  const EventGeom* __restrict__ geoms,
                                                                  const MultiIODev* __restrict__ io,
                                                                  const int* __restrict__ blk_ev,
-                                                                 const int* __restrict__ blk_p0) {
+                                                                 const int* __restrict__ blk_p0, bool scaled) {
   const int e = blk_ev[blockIdx.x];
   const int64_t p = (int64_t)blk_p0[blockIdx.x] + threadIdx.x;
   const MultiEvDev ev = evs[e];
@@ -85,24 +85,13 @@ __global__ __launch_bounds__(MULTI_PT_BLOCK) void k_multi_setup(const MultiEvDev
   double th[NPARAM];
 #pragma unroll
   for (int i = 0; i < NPARAM; ++i) th[i] = o.theta[pc * NPARAM + i];
-  PointModel<double> pm;
-  point_model<double, ND>(th, geoms[e], pm);
-  const double nan = __builtin_nan("");
+  const EventConst* ec = ev.ec;
+  const double gr = scaled ? ec->gain_r : 1.0, gi = scaled ? ec->gain_i : 0.0;
   double rows[NCOEF];
+  const bool valid = setup_rows<ND>(th, geoms[e], gr, gi, rows);
+  const double nan = __builtin_nan("");
 #pragma unroll
-  for (int j = 0; j < NCOEF; ++j) rows[j] = 0.0;
-#pragma unroll
-  for (int m = 0; m < NBASIS; ++m) rows[CO_A + m] = pm.a[m];
-#pragma unroll
-  for (int d = 0; d < ND; ++d) {
-    rows[CO_T + d] = pm.tdet[d];
-    rows[CO_QR + d] = pm.qr[d];
-    rows[CO_QI + d] = pm.qi[d];
-  }
-  rows[CO_C0] = pm.c0;
-  rows[CO_AMP] = pm.amp;
-#pragma unroll
-  for (int j = 0; j < NCOEF; ++j) ev.coef[j * ev.Bp + p] = pm.valid ? rows[j] : nan;
+  for (int j = 0; j < NCOEF; ++j) ev.coef[j * ev.Bp + p] = valid ? rows[j] : nan;
 }
 
 // Persistent bin loop: one wavefront per item, items from the shared counter.
@@ -140,15 +129,15 @@ __global__ __launch_bounds__(BLOCK, (ND <= 3 ? 4 : 3)) void k_multi_bins(const M
     double tot[NZ];
     double a[NBASIS], T[ND];
     if constexpr (MIXED) {
-      float qr[ND], qi[ND];
-      load_coef<ND, float>(ev.coef, ev.Bp, pc, GRAD, a, T, qr, qi);
+      float cr[ND], ci[ND];
+      load_coef<ND, float>(ev.coef, ev.Bp, pc, GRAD, a, T, cr, ci);
       bin_loop_mixed<ND, GRAD>((const_as_ptr<RowMixed<ND>>)ev.tab, (const_as_ptr<RowGradF32>)ev.gtab, k0, k1, a, T,
-                               qr, qi, tot);
+                               cr, ci, tot);
     } else {
-      double qr[ND], qi[ND];
-      load_coef<ND, double>(ev.coef, ev.Bp, pc, GRAD, a, T, qr, qi);
-      bin_loop_f64<ND, GRAD>((const_as_ptr<RowF64<ND>>)ev.tab, (const_as_ptr<RowGradF64>)ev.gtab, k0, k1, a, T, qr,
-                             qi, tbl, tot);
+      double cr[ND], ci[ND];
+      load_coef<ND, double>(ev.coef, ev.Bp, pc, GRAD, a, T, cr, ci);
+      bin_loop_f64<ND, GRAD>((const_as_ptr<RowF64<ND>>)ev.tab, (const_as_ptr<RowGradF64>)ev.gtab, k0, k1, a, T, cr,
+                             ci, tbl, tot);
     }
     global_as_ptr<double> part = (global_as_ptr<double>)ev.part;
 #pragma unroll
@@ -175,7 +164,7 @@ __global__ __launch_bounds__(MULTI_PT_BLOCK) void k_multi_epilogue(const MultiEv
     const EventConst ec = *ev.ec;
     double acc[NZ];
     gather<NZ>(ev.part, ev.nchunk, ev.Bp, p, acc);
-    if (scaled) apply_gain<NZ>(ec, acc);
+    if (scaled) apply_gain<ND>(ec, acc);
     double th[NPARAM];
 #pragma unroll
     for (int i = 0; i < NPARAM; ++i) th[i] = o.theta[p * NPARAM + i];
@@ -258,7 +247,7 @@ hipError_t enqueue_multi_nd(gwl_plan pl, hipStream_t s) {
   hipLaunchKernelGGL(gwl::k_multi_reset, dim3((E + 255) / 256), dim3(256), 0, s, c, done, tev, E);
   hipLaunchKernelGGL(gwl::k_multi_setup<ND>, dim3(pl->nptblk), dim3(gwl::MULTI_PT_BLOCK), 0, s,
                      (const gwl::MultiEvDev*)pl->d_evs, (const gwl::EventGeom*)pl->d_geoms,
-                     (const gwl::MultiIODev*)pl->d_io, blk_ev, blk_p0);
+                     (const gwl::MultiIODev*)pl->d_io, blk_ev, blk_p0, pl->mixed);
 #define GWL_MB(MX, GR)                                                                                             \
   hipLaunchKernelGGL((gwl::k_multi_bins<ND, MX, GR>), dim3(pl->grid), dim3(gwl::BLOCK), 0, s,                   \
                      (const gwl::MultiEvDev*)pl->d_evs, E, pl->total, (const gwl::MultiIODev*)pl->d_io, c, done, tev)

@@ -212,7 +212,7 @@ gwl_status gwl_waveform(const double* theta, int64_t B, const gwl_detector* dets
   double* coef = nullptr;
   hipError_t e = hipMallocAsync((void**)&coef, sizeof(double) * NCOEF * (size_t)Bp, s);
   if (e != hipSuccess) return hip_fail(e, "workspace");
-  e = launch_setup(ndet, g, theta, B, Bp, coef, s);
+  e = launch_setup(ndet, g, nullptr, false, theta, B, Bp, coef, s);
   if (e == hipSuccess) e = launch_waveform(ndet, g, coef, B, Bp, fgrid, M, out, s);
   hipError_t e2 = hipFreeAsync(coef, s);
   if (e != hipSuccess) return hip_fail(e, "waveform launch");
@@ -272,7 +272,7 @@ static void prof_end(hipStream_t s, hipEvent_t a, hipEvent_t b) {
 hipError_t enqueue_logl(gwl_event ev, const double* theta, int64_t B, bool mixed, bool grad, const LoopShape& sh,
                         double* coef, double* part, double* logl, double* gradout, hipStream_t s) {
   const int64_t Bp = (int64_t)sh.npg * WAVE;
-  hipError_t e = launch_setup(ev->ndet, ev->geom, theta, B, Bp, coef, s);
+  hipError_t e = launch_setup(ev->ndet, ev->geom, ev->ec, mixed, theta, B, Bp, coef, s);
   hipEvent_t pa = nullptr, pb = nullptr;
   const bool prof = e == hipSuccess && prof_begin(s, pa, pb);
   if (e == hipSuccess)

@@ -108,3 +108,43 @@ def test_multi_plan_argument_errors(events):
     with pytest.raises(ValueError):
         plan.launch([torch.zeros(3, 11, dtype=torch.float64, device=DEV)])
     plan.close()
+
+
+def test_c4_full_workload_sampled():
+    """All 64 uneven events at full size in one mixed-precision launch with gradients (the launch the
+    benchmark times); sampled points of every event against the FP64 oracle."""
+    from tests.helpers import event_inputs
+
+    evs, ths, inputs = [], [], []
+    for e in range(64):
+        spec, f, psd, data, dets = event_inputs(4, e)
+        evs.append(gw.Event(torch.tensor(data, device=DEV), torch.tensor(psd, device=DEV), dets,
+                            torch.tensor(f, device=DEV), spec.df))
+        th = synth.theta_batch(spec)
+        th[0] = spec.theta0
+        ths.append(th)
+        inputs.append((f, psd, data, dets, spec.df))
+    batches = [len(t) for t in ths]
+    plan = gw.MultiPlan(evs, batches, "mixed", with_grad=True)
+    logls, grads, lat = plan.launch([torch.tensor(t, device=DEV) for t in ths], latency=True)
+    worst, worst_g = 0.0, 0.0
+    for e, (th, l, g, inp) in enumerate(zip(ths, logls, grads, inputs)):
+        f, psd, data, dets, df = inp
+        b = len(th)
+        sample = np.unique([0, 1, b // 2, b - 1])
+        ref = o.logl(th[sample], data, psd, dets, f, df).numpy()
+        err = np.abs(l.cpu().numpy()[sample] - ref)
+        worst = max(worst, float(err.max()))
+        assert err.max() <= 1e-3, (e, len(f), err)
+        if e % 4 == 0:
+            j = int(sample[1])
+            _, gr = o.logl_grad(th[j:j + 1], data, psd, dets, f, df)
+            ge = scaled_grad_error(g.cpu().numpy()[j:j + 1], gr.numpy())
+            worst_g = max(worst_g, float(ge.max()))
+            assert ge.max() <= 1e-4, (e, len(f), ge)
+    print(f"c4: {sum(batches)} points, max |dlogL| {worst:.3e}, max scaled grad error {worst_g:.3e}, "
+          f"latency p50 {np.percentile(lat, 50):.0f} us p99 {np.percentile(lat, 99):.0f} us")
+    assert all(x > 0 for x in lat)
+    plan.close()
+    for ev in evs:
+        ev.close()
