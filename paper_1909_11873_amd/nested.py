@@ -1,0 +1,253 @@
+"""Static parallel nested sampling on one GPU, driving the batched likelihood.
+
+This is the paper's section 3 ("Parallel Nested Sampling") and its algorithm "Static Parallel
+Nested Sampling" with the pool of workers replaced by one batch of candidates per iteration.
+Everything stays on the device; one iteration is a fixed sequence of launches with no host
+synchronisation (the host reads the stop flag every few iterations):
+
+  1. L_min is the first live log-likelihood (the live set is kept sorted ascending).
+  2. n candidates in the unit cube: prior draws (the paper's proposal), draws from the bounding
+     ellipsoid of the live points (the "bounding distribution" the algorithm re-evaluates each
+     iteration), or a caller's proposal function.
+  3. Prior transform and ln L of the whole batch (for the GW likelihood: the library's kernels).
+  4. Candidates in the cube with L >= L_min are accepted (n' of them).
+  5. The paper replaces the worst live point by each accepted candidate in turn. Taken in
+     ascending order of L, that sequence removes exactly the n' lowest of the K + n' points
+     (live and accepted): every candidate is then at or above the point it replaces, so the
+     removed points come out in ascending order. One stable sort of the merged set therefore
+     does the whole replacement loop: rejected candidates first, then the n' dead points in
+     ascending L, then the K new live points.
+  6. Prior volume: the first dead point of the iteration shrinks X by the largest of K uniform
+     draws (ln X -= 1/K), the j-th (j >= 2) by the largest of K + n' - j + 1; this is the paper's
+     ln X_i = -i/K when n' = 1. Evidence by the Riemann sum of dX_i L_i.
+  7. Stop when the remaining volume can change ln Z by at most eps: ln(Z + L_max X) - ln Z <= eps.
+
+At the end the K live points join the dead ones with equal shares of the last volume, and the
+posterior weights are p_i = L_i dX_i / Z.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+import time
+from typing import Callable, Optional
+
+import numpy as np
+import torch
+
+
+@dataclasses.dataclass
+class NSResult:
+    u: np.ndarray            # [N, d] dead points (then the final live points) in the unit cube
+    theta: np.ndarray        # [N, d] the same points after the prior transform
+    logl: np.ndarray         # [N]
+    log_dx: np.ndarray       # [N] ln of each point's prior-volume share
+    log_x: np.ndarray        # [N] ln X after each dead point (final live points: the shares left)
+    logz: float
+    logz_err: float          # sqrt(H / K)
+    log_w: np.ndarray        # [N] ln posterior weight
+    information: float       # H in nats
+    niter: int
+    ncall: int
+    n_accepted: np.ndarray   # [niter] accepted candidates per iteration
+    seconds: float
+
+    def speedup(self) -> float:
+        """Serial iterations the run replaced: K ln(1/X_end) / iterations (the measured S)."""
+        nd = len(self.logl) - self.nlive
+        return -self.log_x[nd - 1] * self.nlive / max(self.niter, 1) if nd > 0 else 0.0
+
+    nlive: int = 0
+
+
+def speedup_law(n: float, nlive: float) -> float:
+    """The paper's speed-up relation S(n, K) = K ln(1 + n/K)."""
+    return nlive * math.log1p(n / nlive)
+
+
+def gw_prior_transform(mc_range=(10.0, 60.0), dl_range=(100.0, 2000.0), tc_half=0.1, spins=True):
+    """Unit cube -> the 11 parameters (mc, q, chi1, chi2, dl, ra, dec, iota, psi, phic, tc) by the
+    inverse CDFs of the prior: uniform mc, q in [0.2, 1], spins in [-0.9, 0.9], distance with
+    density ~ d^2, isotropic sky and orientation, uniform angles and coalescence time."""
+    lo3, hi3 = dl_range[0] ** 3, dl_range[1] ** 3
+
+    def transform(u: torch.Tensor) -> torch.Tensor:
+        th = torch.empty_like(u)
+        th[:, 0] = mc_range[0] + (mc_range[1] - mc_range[0]) * u[:, 0]
+        th[:, 1] = 0.2 + 0.8 * u[:, 1]
+        if spins:
+            th[:, 2] = -0.9 + 1.8 * u[:, 2]
+            th[:, 3] = -0.9 + 1.8 * u[:, 3]
+        else:
+            th[:, 2:4] = 0.0
+        th[:, 4] = torch.pow(lo3 + u[:, 4] * (hi3 - lo3), 1.0 / 3.0)
+        th[:, 5] = 2.0 * math.pi * u[:, 5]
+        th[:, 6] = torch.asin(2.0 * u[:, 6] - 1.0)
+        th[:, 7] = torch.acos(2.0 * u[:, 7] - 1.0)
+        th[:, 8] = math.pi * u[:, 8]
+        th[:, 9] = 2.0 * math.pi * u[:, 9]
+        th[:, 10] = -tc_half + 2.0 * tc_half * u[:, 10]
+        return th
+    return transform
+
+
+class ParallelNestedSampler:
+    """K live points, n candidates per iteration, everything on `device`.
+
+    loglike(theta[n, d]) -> ln L[n] (float64 tensors on the device; NaN counts as -inf).
+    prior_transform(u[n, d]) -> theta[n, d]; identity if None.
+    proposal: "prior", "ellipsoid", or a function (it, live_u, live_l) -> u[n, d].
+    """
+
+    def __init__(self, loglike: Callable, ndim: int, nlive: int, batch: int,
+                 prior_transform: Optional[Callable] = None, device="cuda:0", seed: int = 0,
+                 proposal="ellipsoid", enlarge: float = 1.25, volume: str = "order", check_every: int = 8):
+        if nlive < 2 or batch < 1 or ndim < 1:
+            raise ValueError("need nlive >= 2, batch >= 1, ndim >= 1")
+        if volume not in ("order", "paper"):
+            raise ValueError("volume is 'order' or 'paper'")
+        self.loglike, self.d, self.K, self.n = loglike, ndim, nlive, batch
+        self.transform = prior_transform if prior_transform is not None else (lambda u: u)
+        self.dev = torch.device(device)
+        self.gen = torch.Generator(device=self.dev)
+        self.gen.manual_seed(seed)
+        self.proposal, self.enlarge, self.volume = proposal, enlarge, volume
+        self.check_every = max(1, int(check_every))
+
+    # ---- proposals -------------------------------------------------------------------------
+    def _prior(self):
+        return torch.rand(self.n, self.d, generator=self.gen, device=self.dev, dtype=torch.float64)
+
+    def _ellipsoid(self, live_u):
+        """Uniform draws in the bounding ellipsoid of the live points, its volume enlarged."""
+        d = self.d
+        mu = live_u.mean(0)
+        x = live_u - mu
+        cov = x.T @ x / (self.K - 1) + 1e-12 * torch.eye(d, dtype=torch.float64, device=self.dev)
+        chol, _ = torch.linalg.cholesky_ex(cov)
+        y = torch.linalg.solve_triangular(chol, x.T, upper=False)           # [d, K]
+        r2 = (y * y).sum(0).max()                                            # all live points inside
+        scale = torch.sqrt(r2) * self.enlarge ** (1.0 / d)
+        z = torch.randn(self.n, d, generator=self.gen, device=self.dev, dtype=torch.float64)
+        z = z / z.norm(dim=1, keepdim=True)
+        rad = torch.rand(self.n, 1, generator=self.gen, device=self.dev, dtype=torch.float64) ** (1.0 / d)
+        return mu + scale * (z * rad) @ chol.T
+
+    def _propose(self, it, live_u, live_l):
+        if callable(self.proposal):
+            return self.proposal(it, live_u, live_l)
+        if self.proposal == "prior":
+            return self._prior()
+        if self.proposal == "ellipsoid":
+            return self._ellipsoid(live_u)
+        raise ValueError(f"unknown proposal {self.proposal!r}")
+
+    def _loglike(self, u):
+        inside = ((u >= 0.0) & (u <= 1.0)).all(dim=1)
+        l = self.loglike(self.transform(u.clamp(0.0, 1.0)))
+        l = torch.where(torch.isnan(l), torch.full_like(l, -math.inf), l)
+        return l, inside
+
+    # ---- the run ---------------------------------------------------------------------------
+    def run(self, eps: float = 0.1, max_iter: int = 100000, live_u: Optional[torch.Tensor] = None) -> NSResult:
+        K, n, d, dev = self.K, self.n, self.d, self.dev
+        f64 = dict(dtype=torch.float64, device=dev)
+        t0 = time.perf_counter()
+        if live_u is None:
+            live_u = torch.rand(K, d, generator=self.gen, **f64)
+        live_u = live_u.to(**f64).contiguous()
+        live_l, _ = self._loglike(live_u)
+        o = torch.argsort(live_l, stable=True)
+        live_u, live_l = live_u[o], live_l[o]
+
+        cap = K * 64 + n * self.check_every
+        dead_u = torch.empty(cap + 1, d, **f64)      # the last row takes the writes of non-dead slots
+        dead_l = torch.empty(cap + 1, **f64)
+        dead_ldx = torch.empty(cap + 1, **f64)
+        dead_lx = torch.empty(cap + 1, **f64)
+        n_acc = torch.zeros(max(1, min(max_iter, 1 << 16)), dtype=torch.int64, device=dev)
+        n_dead = torch.zeros((), dtype=torch.int64, device=dev)
+        ln_x = torch.zeros((), **f64)
+        ln_z = torch.full((), -math.inf, **f64)
+        stop = torch.zeros((), dtype=torch.bool, device=dev)
+        pos = torch.arange(n, device=dev)
+        ones_k = torch.ones(K, dtype=torch.bool, device=dev)
+        it = 0
+        synced_dead = 0
+        while it < max_iter:
+            if it % self.check_every == 0 and it > 0:
+                if bool(stop):
+                    break
+                synced_dead = int(n_dead)
+            if synced_dead + n * (self.check_every + 1) > cap:      # grow the dead buffers
+                synced_dead = int(n_dead)
+                new_cap = max(2 * cap, synced_dead + n * (self.check_every + 1))
+                dead_u, dead_l, dead_ldx, dead_lx = (torch.cat([b[:cap], torch.empty((new_cap - cap + 1,) + b.shape[1:], **f64)])
+                                                     for b in (dead_u, dead_l, dead_ldx, dead_lx))
+                cap = new_cap
+            if it >= n_acc.numel():
+                n_acc = torch.cat([n_acc, torch.zeros_like(n_acc)])
+            lmin = live_l[0]
+            cu = self._propose(it, live_u, live_l).to(**f64)
+            cl, inside = self._loglike(cu)
+            # iterations launched after the stop test passed (before the host reads the flag)
+            # accept nothing and change nothing
+            acc = inside & (cl >= lmin) & ~stop
+            nacc = acc.sum()
+            n_acc[it] = torch.where(stop, -1, nacc)
+            # merged stable sort: by L (live before candidates on ties), then rejected first
+            all_l = torch.cat([live_l, cl])
+            all_u = torch.cat([live_u, cu])
+            flag = torch.cat([ones_k, acc]).to(torch.int8)
+            i1 = torch.argsort(all_l, stable=True)
+            idx = i1[torch.argsort(flag[i1], stable=True)]
+            sl, su = all_l[idx], all_u[idx]
+            live_l, live_u = sl[n:].contiguous(), su[n:].contiguous()
+            # dead points: merged positions [n - n', n), rank j = 1..n'
+            j = pos - (n - nacc) + 1
+            valid = j >= 1
+            if self.volume == "order":
+                dec = torch.where(j == 1, 1.0 / K, 1.0 / (K + nacc - j + 1).clamp(min=1).to(torch.float64))
+            else:
+                dec = torch.full((n,), 1.0 / K, **f64)
+            dec = torch.where(valid, dec, torch.zeros_like(dec))
+            cum = torch.cumsum(dec, 0)
+            ldx = ln_x - (cum - dec) + torch.log(-torch.expm1(-dec))
+            contrib = torch.where(valid, sl[:n] + ldx, torch.full_like(ldx, -math.inf))
+            ln_z = torch.logaddexp(ln_z, torch.logsumexp(contrib, 0))
+            dst = torch.where(valid, n_dead + j - 1, torch.full_like(j, cap))
+            dead_l.index_copy_(0, dst, sl[:n])
+            dead_u.index_copy_(0, dst, su[:n])
+            dead_ldx.index_copy_(0, dst, ldx)
+            dead_lx.index_copy_(0, dst, ln_x - cum)
+            ln_x = ln_x - cum[-1]
+            n_dead = n_dead + nacc
+            bound = torch.logaddexp(ln_z, live_l[-1] + ln_x) - ln_z
+            stop = stop | ((nacc > 0) & (bound <= eps))
+            it += 1
+        if dev.type == "cuda":
+            torch.cuda.synchronize(dev)
+        nd = int(n_dead)
+        n_acc = n_acc[:it].cpu().numpy()
+        n_acc = n_acc[n_acc >= 0]
+        it = len(n_acc)
+        # final live points: ascending, equal shares of the last volume
+        lx = float(ln_x)
+        share = lx - math.log(K)
+        lz = float(ln_z)
+        fin_l = live_l.cpu().numpy()
+        lz = float(np.logaddexp(lz, np.logaddexp.reduce(fin_l + share))) if K else lz
+        u = torch.cat([dead_u[:nd], live_u]).cpu().numpy()
+        logl = np.concatenate([dead_l[:nd].cpu().numpy(), fin_l])
+        log_dx = np.concatenate([dead_ldx[:nd].cpu().numpy(), np.full(K, share)])
+        rem = np.array([lx + math.log((K - m) / K) if m < K else -math.inf for m in range(1, K + 1)])
+        log_x = np.concatenate([dead_lx[:nd].cpu().numpy(), rem])
+        log_w = logl + log_dx - lz
+        w = np.exp(log_w)
+        finite = np.isfinite(logl)
+        h = float(np.sum(w[finite] * (logl[finite] - lz)))
+        theta = self.transform(torch.tensor(u, **f64)).cpu().numpy() if len(u) else u
+        return NSResult(u=u, theta=theta, logl=logl, log_dx=log_dx, log_x=log_x, logz=lz,
+                        logz_err=math.sqrt(max(h, 0.0) / K), log_w=log_w, information=h, niter=it,
+                        ncall=K + n * it, n_accepted=n_acc,
+                        seconds=time.perf_counter() - t0, nlive=K)

@@ -1,0 +1,130 @@
+"""The device nested-sampling driver against the nested-sampling oracle.
+
+Both consume the same candidate stream (random numbers are inputs, drawn by one seeded numpy
+generator per side) and the same analytic likelihood, so the dead-point sequence, the prior
+volumes and the evidence must agree to rounding. The radial likelihood has no ties, so the dead
+points' coordinates must agree too. The CPU cases run the driver on host tensors; the GPU cases
+run the same comparison on the device and a full run on the GW likelihood.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import ns_oracle as ns
+from paper_1909_11873_amd import nested
+from tests.test_ns_oracle import ball_proposer, prior_proposer, radial
+
+
+def torch_radial(s):
+    return lambda th: -((th - 0.5) ** 2).sum(dim=1) / (2 * s * s)
+
+
+def wrap(numpy_proposer, dev):
+    """The same proposal function on device tensors."""
+    def propose(it, live_u, live_l):
+        c = numpy_proposer(it, live_u.cpu().numpy(), live_l.cpu().numpy())
+        return torch.tensor(c, dtype=torch.float64, device=dev)
+    return propose
+
+
+def compare(dev, kind, n, K=60, d=3, s=0.06, eps=0.05, seed=21):
+    live = np.random.default_rng(seed).random((K, d))
+    mk = (lambda: ball_proposer(d, n, s, seed + 1)) if kind == "ball" else (lambda: prior_proposer(d, n, seed + 1))
+    ref = ns.run(radial(s), live, mk(), eps=eps)
+    smp = nested.ParallelNestedSampler(torch_radial(s), d, K, n, device=dev, proposal=wrap(mk(), dev),
+                                       check_every=3)
+    got = smp.run(eps=eps, live_u=torch.tensor(live))
+    assert got.niter == ref["niter"]
+    np.testing.assert_array_equal(got.n_accepted, ref["n_accepted"])
+    np.testing.assert_allclose(got.logl, ref["logl"], rtol=0, atol=1e-9)
+    np.testing.assert_allclose(got.u, ref["u"], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(got.log_x[:-1], ref["log_x"][:-1], rtol=0, atol=1e-10)
+    np.testing.assert_allclose(got.log_dx, ref["log_dx"], rtol=0, atol=1e-10)
+    assert got.logz == pytest.approx(ref["logz"], abs=1e-10)
+    return got, ref
+
+
+@pytest.mark.parametrize("kind,n", [("ball", 1), ("ball", 16), ("ball", 500), ("prior", 64), ("prior", 1000)])
+def test_driver_matches_oracle_on_host(kind, n):
+    compare(torch.device("cpu"), kind, n)
+
+
+def test_driver_paper_volume_option_matches_oracle():
+    d, K, s, n = 2, 30, 0.1, 50
+    live = np.random.default_rng(3).random((K, d))
+    ref = ns.run(radial(s), live, ball_proposer(d, n, s, 4), eps=0.1, volume="paper")
+    got = nested.ParallelNestedSampler(torch_radial(s), d, K, n, device="cpu", volume="paper",
+                                       proposal=wrap(ball_proposer(d, n, s, 4), "cpu")).run(
+        eps=0.1, live_u=torch.tensor(live))
+    np.testing.assert_allclose(got.log_x[:-1], ref["log_x"][:-1], atol=1e-10)
+    assert got.logz == pytest.approx(ref["logz"], abs=1e-10)
+
+
+def test_driver_ellipsoid_proposal_on_host():
+    """The driver's own bounding-ellipsoid proposal: evidence and moments of the radial Gaussian."""
+    d, K, s = 3, 300, 0.07
+    smp = nested.ParallelNestedSampler(torch_radial(s), d, K, 512, device="cpu", seed=5)
+    res = smp.run(eps=0.01)
+    z_true = d * math.log(math.sqrt(2 * math.pi) * s * math.erf(0.5 / (s * math.sqrt(2))))
+    assert abs(res.logz - z_true) < 4 * res.logz_err + 0.05
+    w = np.exp(res.log_w)
+    var = np.sum(w[:, None] * (res.u - np.sum(w[:, None] * res.u, 0)) ** 2, 0)
+    np.testing.assert_allclose(var, s * s, rtol=0.25)
+    nd = len(res.logl) - K
+    assert np.all(np.diff(res.logl[:nd]) >= 0)
+
+
+def test_speedup_law():
+    assert nested.speedup_law(1, 2000) == pytest.approx(1.0, rel=3e-4)
+    # the values quoted beside the paper's scaling test (K = 2000)
+    for cores, s in [(16, 15.94), (64, 63.0), (320, 296.8), (640, 555.3)]:
+        assert nested.speedup_law(cores, 2000) == pytest.approx(s, abs=0.06)
+
+
+def test_gw_prior_transform_matches_synthetic_prior_draws():
+    from paper_1909_11873_amd import synth
+    u = np.random.default_rng(8).random((1000, 11))
+    th = nested.gw_prior_transform()(torch.tensor(u)).numpy()
+    rng = np.random.default_rng(8)
+    ref = synth.prior_draw(rng, 1000)
+    np.testing.assert_allclose(th, ref, rtol=1e-12, atol=1e-12)
+
+
+DEV = torch.device("cuda:0")
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("kind,n", [("ball", 16), ("prior", 1000)])
+def test_driver_matches_oracle_on_gpu(kind, n):
+    compare(DEV, kind, n)
+
+
+@pytest.mark.gpu
+def test_gw_nested_sampling_recovers_the_injection():
+    """A full run on the GW likelihood (one detector, 4 s, 20-1024 Hz, no spins) through the
+    library's mixed-precision kernels: the chirp mass posterior covers the injected value and the
+    run reaches the injection's likelihood."""
+    from oracle import gw_oracle as o
+    from paper_1909_11873_amd import gwlike as gw
+    from tests.helpers import event_inputs
+
+    spec, f, psd, data, dets = event_inputs(0)
+    ev = gw.Event(torch.tensor(data, device=DEV), torch.tensor(psd, device=DEV), dets,
+                  torch.tensor(f, device=DEV), spec.df)
+    l0 = float(o.logl(spec.theta0[None], data, psd, dets, f, spec.df)[0])
+    smp = nested.ParallelNestedSampler(lambda th: gw.logl(th, ev, "mixed"), 11, 400, 4096, device=DEV, seed=3,
+                                       prior_transform=nested.gw_prior_transform(spins=False))
+    res = smp.run(eps=0.1, max_iter=20000)
+    w = np.exp(res.log_w)
+    mc = np.sum(w * res.theta[:, 0])
+    mc_sd = math.sqrt(np.sum(w * (res.theta[:, 0] - mc) ** 2))
+    print(f"GW NS: {res.niter} iterations, {res.ncall} calls, {res.seconds:.1f} s, lnZ {res.logz:.2f} +- "
+          f"{res.logz_err:.2f}, H {res.information:.1f}, mc {mc:.3f} +- {mc_sd:.3f}, logL(theta0) {l0:.2f}, "
+          f"max logL {res.logl.max():.2f}, speed-up {res.speedup():.1f}")
+    assert res.niter < 20000
+    assert abs(mc - spec.theta0[0]) < 5 * mc_sd + 0.05
+    assert res.logl.max() > l0 - 5.0
+    assert np.isfinite(res.logz) and res.logz > 0
+    ev.close()
