@@ -164,6 +164,22 @@ gwl_status gwl_multi_launch(gwl_plan pl, const double* const* theta, double* con
 
 gwl_status gwl_plan_destroy(gwl_plan pl);
 
+/* Shape of a plan: the bin-chunk length shared by all events, whether events are queued by
+ * descending work (1) or ascending work (0), and the number of work items. Any pointer may be
+ * null. */
+gwl_status gwl_plan_info(gwl_plan pl, int* chunk, int* descending, int64_t* items);
+
+/*
+ * Time candidate shapes of a multi-event plan for this workload (events, B_e, precision,
+ * with_grad) and record the fastest in the JSON cache `cache_path` (null = in memory only):
+ * chunk lengths 1024..16384 bins and both queue orders, each timed over three graph launches on
+ * synthetic valid parameter points. gwl_multi_plan_create then uses the recorded shape for the
+ * same workload (same event order, B_e and bin counts). Allocates a plan per candidate and
+ * synchronises the device. GWL_E_SHAPE if no candidate fits.
+ */
+gwl_status gwl_multi_autotune(const char* cache_path, const gwl_event* evs, int E, const int64_t* B_e,
+                              gwl_precision prec, int with_grad);
+
 /*
  * Time candidate tile shapes for (event, B, precision, with_grad) on the device and record the
  * fastest in the JSON cache file `cache_path` (created or updated; null = in-memory only).

@@ -40,6 +40,15 @@ size_t workspace_bytes(int64_t Bp, int nchunk, int nd, bool grad);
 int choose_nchunk(const gwl_event_s* ev, int64_t B, bool mixed, bool grad);
 int heuristic_nchunk(int64_t B, int64_t M);
 
+// multi-event plans: build with an explicit chunk length (0 = heuristic) and queue order; the
+// tuner's cached choice for a workload (chunk 0 and ascending order when none is cached)
+gwl_status build_plan(const gwl_event* evs, int E, const int64_t* B_e, gwl_precision prec, int with_grad,
+                      int chunk_req, bool descending, gwl_plan* out);
+void choose_multi_shape(const gwl_event* evs, int E, const int64_t* B_e, bool mixed, bool grad, int* chunk,
+                        bool* descending);
+// fill theta[B][11] with valid parameter points (timing inputs)
+hipError_t fill_theta(double* theta, int64_t B, hipStream_t s);
+
 gwl_status run_logl(gwl_event ev, const double* theta, int64_t B, bool mixed, bool grad, const LoopShape& sh,
                     double* logl, double* gradout, hipStream_t s);
 hipError_t enqueue_logl(gwl_event ev, const double* theta, int64_t B, bool mixed, bool grad, const LoopShape& sh,

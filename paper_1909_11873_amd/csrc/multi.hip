@@ -96,7 +96,7 @@ __global__ __launch_bounds__(MULTI_PT_BLOCK) void k_multi_setup(const MultiEvDev
 
 // Persistent bin loop: one wavefront per item, items from the shared counter.
 template <int ND, bool MIXED, bool GRAD>
-__global__ __launch_bounds__(BLOCK, (ND <= 3 ? 4 : 3)) void k_multi_bins(const MultiEvDev* __restrict__ evs, int E, int total,
+__global__ __launch_bounds__(BLOCK, (ND <= 3 ? (GRAD && MIXED ? 5 : 4) : 3)) void k_multi_bins(const MultiEvDev* __restrict__ evs, int E, int total,
                                                       const MultiIODev* __restrict__ io, MultiCtl* __restrict__ ctl,
                                                       unsigned int* __restrict__ done,
                                                       unsigned long long* __restrict__ tev) {
@@ -193,6 +193,7 @@ struct gwl_plan_s {
   std::vector<int64_t> B;
   std::vector<int> order;      // queue position -> event index
   int total = 0, grid = 0, nptblk = 0, chunk = 0;
+  bool descending = false;     // queue order: events by descending work instead of ascending
   double clock_khz = 0.0;
   gwl::MultiEvDev* d_evs = nullptr;   // in queue order
   gwl::EventGeom* d_geoms = nullptr;  // in queue order
@@ -302,11 +303,11 @@ hipError_t occupancy(int nd, bool mixed, bool grad, int* nblk) {
 
 }  // namespace
 
-extern "C" {
+namespace gwl {
 
-gwl_status gwl_multi_plan_create(const gwl_event* evs, int E, const int64_t* B_e, gwl_precision prec, int with_grad,
-                                 gwl_plan* out) {
-  clear_error();
+// Build a plan with a given chunk length (0: the heuristic) and queue order.
+gwl_status build_plan(const gwl_event* evs, int E, const int64_t* B_e, gwl_precision prec, int with_grad,
+                      int chunk_req, bool descending, gwl_plan* out) {
   if (!out) return fail(GWL_E_INVALID, "out is null");
   *out = nullptr;
   if (!evs || !B_e) return fail(GWL_E_INVALID, "evs and B_e must be host arrays");
@@ -364,6 +365,7 @@ gwl_status gwl_multi_plan_create(const gwl_event* evs, int E, const int64_t* B_e
       break;
     }
   }
+  if (chunk_req > 0) chunk = chunk_req;
   const int64_t total = items_for(chunk);
   if (total > ((int64_t)1 << 30)) {
     plan_free(pl);
@@ -372,11 +374,13 @@ gwl_status gwl_multi_plan_create(const gwl_event* evs, int E, const int64_t* B_e
   pl->chunk = chunk;
   pl->total = (int)total;
 
-  // queue order: events by ascending work, ties by index
+  // queue order: events by ascending (or descending) work, ties by index
+  pl->descending = descending;
   pl->order.resize(E);
   std::iota(pl->order.begin(), pl->order.end(), 0);
   std::stable_sort(pl->order.begin(), pl->order.end(), [&](int a, int b) {
-    return (double)B_e[a] * (double)evs[a]->M < (double)B_e[b] * (double)evs[b]->M;
+    const double wa = (double)B_e[a] * (double)evs[a]->M, wb = (double)B_e[b] * (double)evs[b]->M;
+    return descending ? wa > wb : wa < wb;
   });
 
   // workspace and device tables
@@ -453,6 +457,32 @@ gwl_status gwl_multi_plan_create(const gwl_event* evs, int E, const int64_t* B_e
     return hip_fail(err, "multi-event plan");
   }
   *out = pl;
+  return GWL_OK;
+}
+
+}  // namespace gwl
+
+extern "C" {
+
+gwl_status gwl_multi_plan_create(const gwl_event* evs, int E, const int64_t* B_e, gwl_precision prec, int with_grad,
+                                 gwl_plan* out) {
+  clear_error();
+  int chunk = 0;
+  bool desc = false;
+  if (evs && B_e && E >= 1 && E <= 4096) {
+    bool ok = true;
+    for (int e = 0; e < E; ++e) ok &= evs[e] != nullptr;
+    if (ok) choose_multi_shape(evs, E, B_e, prec == GWL_MIXED, with_grad != 0, &chunk, &desc);
+  }
+  return build_plan(evs, E, B_e, prec, with_grad, chunk, desc, out);
+}
+
+gwl_status gwl_plan_info(gwl_plan pl, int* chunk, int* descending, int64_t* items) {
+  clear_error();
+  if (!pl) return fail(GWL_E_INVALID, "plan is null");
+  if (chunk) *chunk = pl->chunk;
+  if (descending) *descending = pl->descending ? 1 : 0;
+  if (items) *items = pl->total;
   return GWL_OK;
 }
 

@@ -37,6 +37,36 @@ struct Entry {
 std::mutex g_mu;
 std::map<Key, Entry> g_cache;
 
+// Multi-event plans: keyed by detector count, precision, gradient, event count and a hash of
+// the (B_e, M_e) list in event order.
+struct MKey {
+  int nd, mixed, grad, E;
+  unsigned long long sig;
+  bool operator<(const MKey& o) const {
+    return std::tie(nd, mixed, grad, E, sig) < std::tie(o.nd, o.mixed, o.grad, o.E, o.sig);
+  }
+};
+struct MEntry {
+  int chunk, descending;
+  double ms;
+};
+std::map<MKey, MEntry> g_mcache;
+
+MKey make_mkey(const gwl_event* evs, int E, const int64_t* B_e, bool mixed, bool grad) {
+  unsigned long long h = 1469598103934665603ull;  // FNV-1a, 64 bit
+  auto mix = [&](unsigned long long v) {
+    for (int i = 0; i < 8; ++i) {
+      h ^= (v >> (8 * i)) & 0xffull;
+      h *= 1099511628211ull;
+    }
+  };
+  for (int e = 0; e < E; ++e) {
+    mix((unsigned long long)B_e[e]);
+    mix((unsigned long long)evs[e]->M);
+  }
+  return MKey{evs[0]->ndet, mixed ? 1 : 0, grad ? 1 : 0, E, h};
+}
+
 int pow2_ceil(int64_t x) {
   int b = 1;
   while (b < x && b < (1 << 30)) b <<= 1;
@@ -57,10 +87,16 @@ bool load_cache(const char* path) {
     Key k;
     Entry e;
     long long M;
+    MKey mk;
+    MEntry me;
     if (sscanf(line, " {\"ndet\": %d, \"mixed\": %d, \"grad\": %d, \"M\": %lld, \"npg_bucket\": %d, \"nchunk\": %d, \"ms\": %lf}",
                &k.nd, &k.mixed, &k.grad, &M, &k.npg_bucket, &e.nchunk, &e.ms) == 7) {
       k.M = M;
       g_cache[k] = e;
+    } else if (sscanf(line, " {\"multi\": 1, \"ndet\": %d, \"mixed\": %d, \"grad\": %d, \"events\": %d, \"sig\": \"%llx\", "
+                      "\"chunk\": %d, \"descending\": %d, \"ms\": %lf}",
+                      &mk.nd, &mk.mixed, &mk.grad, &mk.E, &mk.sig, &me.chunk, &me.descending, &me.ms) == 8) {
+      g_mcache[mk] = me;
     }
   }
   fclose(f);
@@ -73,11 +109,17 @@ bool save_cache(const char* path) {
   std::lock_guard<std::mutex> lk(g_mu);
   fprintf(f, "{\"arch\": \"gfx950\", \"entries\": [\n");
   size_t i = 0;
+  const size_t n = g_cache.size() + g_mcache.size();
   for (const auto& kv : g_cache) {
     const Key& k = kv.first;
     fprintf(f, "  {\"ndet\": %d, \"mixed\": %d, \"grad\": %d, \"M\": %lld, \"npg_bucket\": %d, \"nchunk\": %d, \"ms\": %.6f}%s\n",
-            k.nd, k.mixed, k.grad, (long long)k.M, k.npg_bucket, kv.second.nchunk, kv.second.ms,
-            ++i < g_cache.size() ? "," : "");
+            k.nd, k.mixed, k.grad, (long long)k.M, k.npg_bucket, kv.second.nchunk, kv.second.ms, ++i < n ? "," : "");
+  }
+  for (const auto& kv : g_mcache) {
+    const MKey& k = kv.first;
+    fprintf(f, "  {\"multi\": 1, \"ndet\": %d, \"mixed\": %d, \"grad\": %d, \"events\": %d, \"sig\": \"%016llx\", "
+               "\"chunk\": %d, \"descending\": %d, \"ms\": %.6f}%s\n",
+            k.nd, k.mixed, k.grad, k.E, k.sig, kv.second.chunk, kv.second.descending, kv.second.ms, ++i < n ? "," : "");
   }
   fprintf(f, "]}\n");
   fclose(f);
@@ -106,6 +148,24 @@ int heuristic_nchunk(int64_t B, int64_t M) {
   if (want > maxc) want = maxc;
   if (want < 1) want = 1;
   return (int)want;
+}
+
+hipError_t fill_theta(double* theta, int64_t B, hipStream_t s) {
+  if (B <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_theta, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, theta, B);
+  return hipGetLastError();
+}
+
+void choose_multi_shape(const gwl_event* evs, int E, const int64_t* B_e, bool mixed, bool grad, int* chunk,
+                        bool* descending) {
+  *chunk = 0;
+  *descending = false;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (g_mcache.empty()) return;
+  auto it = g_mcache.find(make_mkey(evs, E, B_e, mixed, grad));
+  if (it == g_mcache.end()) return;
+  *chunk = it->second.chunk;
+  *descending = it->second.descending != 0;
 }
 
 int choose_nchunk(const gwl_event_s* ev, int64_t B, bool mixed, bool grad) {
@@ -202,6 +262,90 @@ gwl_status gwl_autotune(const char* cache_path, gwl_event ev, int64_t B, gwl_pre
   {
     std::lock_guard<std::mutex> lk(g_mu);
     g_cache[make_key(ev->ndet, mixed, grad, ev->M, B)] = Entry{best, best_ms};
+  }
+  if (cache_path && !save_cache(cache_path)) return fail(GWL_E_INVALID, "cannot write %s", cache_path);
+  return GWL_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+gwl_status gwl_multi_autotune(const char* cache_path, const gwl_event* evs, int E, const int64_t* B_e,
+                              gwl_precision prec, int with_grad) {
+  clear_error();
+  if (!evs || !B_e) return fail(GWL_E_INVALID, "evs and B_e must be host arrays");
+  if (E < 1 || E > 4096) return fail(GWL_E_SHAPE, "E=%d outside [1, 4096]", E);
+  if (prec != GWL_FP64 && prec != GWL_MIXED) return fail(GWL_E_INVALID, "unknown precision %d", (int)prec);
+  int64_t total = 0;
+  for (int e = 0; e < E; ++e) {
+    if (!evs[e]) return fail(GWL_E_INVALID, "event %d is null", e);
+    if (B_e[e] < 0 || B_e[e] > kMaxBatch) return fail(GWL_E_SHAPE, "B_e[%d] out of range", e);
+    total += B_e[e];
+  }
+  gwl_status st = check_device(evs[0]->device);
+  if (st != GWL_OK) return st;
+  if (cache_path) load_cache(cache_path);  // keep entries of other shapes
+  const bool mixed = prec == GWL_MIXED, grad = with_grad != 0;
+
+  // synthetic inputs for every event, in one allocation each for theta, logl and grad
+  const size_t nt = (size_t)(total > 0 ? total : 1);
+  double *theta = nullptr, *logl = nullptr, *gout = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t err = hipMalloc((void**)&theta, sizeof(double) * NPARAM * nt);
+  if (err == hipSuccess) err = hipMalloc((void**)&logl, sizeof(double) * nt);
+  if (err == hipSuccess && grad) err = hipMalloc((void**)&gout, sizeof(double) * NPARAM * nt);
+  if (err == hipSuccess) err = fill_theta(theta, total, 0);
+  if (err == hipSuccess) err = hipEventCreate(&e0);
+  if (err == hipSuccess) err = hipEventCreate(&e1);
+  std::vector<const double*> tp(E);
+  std::vector<double*> lp(E), gp(E);
+  int64_t off = 0;
+  for (int e = 0; e < E; ++e) {
+    tp[e] = theta + NPARAM * off;
+    lp[e] = logl + off;
+    gp[e] = grad ? gout + NPARAM * off : nullptr;
+    off += B_e[e];
+  }
+  int best_chunk = 0, best_desc = 0;
+  double best_ms = 1e300;
+  for (int chunk = 1024; err == hipSuccess && chunk <= 16384; chunk <<= 1) {
+    for (int desc = 0; desc < 2 && err == hipSuccess; ++desc) {
+      gwl_plan pl = nullptr;
+      if (build_plan(evs, E, B_e, prec, with_grad, chunk, desc != 0, &pl) != GWL_OK) {
+        clear_error();  // this candidate does not fit (too many items): skip it
+        continue;
+      }
+      float ms_min = 1e30f;
+      for (int rep = 0; rep < 4 && err == hipSuccess; ++rep) {
+        err = hipEventRecord(e0, 0);
+        if (err == hipSuccess &&
+            gwl_multi_launch(pl, tp.data(), lp.data(), grad ? gp.data() : nullptr, nullptr, nullptr) != GWL_OK)
+          err = hipErrorLaunchFailure;
+        if (err == hipSuccess) err = hipEventRecord(e1, 0);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        if (rep > 0 && ms < ms_min) ms_min = ms;  // the first launch is a warm-up
+      }
+      gwl_plan_destroy(pl);
+      if (err == hipSuccess && ms_min < best_ms) {
+        best_ms = ms_min;
+        best_chunk = chunk;
+        best_desc = desc;
+      }
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (theta) (void)hipFree(theta);
+  if (logl) (void)hipFree(logl);
+  if (gout) (void)hipFree(gout);
+  if (err != hipSuccess) return hip_fail(err, "multi-event autotune");
+  if (best_chunk == 0) return fail(GWL_E_SHAPE, "no candidate plan fits this workload");
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_mcache[make_mkey(evs, E, B_e, mixed, grad)] = MEntry{best_chunk, best_desc, best_ms};
   }
   if (cache_path && !save_cache(cache_path)) return fail(GWL_E_INVALID, "cannot write %s", cache_path);
   return GWL_OK;

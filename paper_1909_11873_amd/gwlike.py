@@ -63,6 +63,8 @@ def lib() -> ctypes.CDLL:
         "gwl_multi_launch": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), _c_double_p, vp],
                              cint),
         "gwl_plan_destroy": ([vp], cint),
+        "gwl_plan_info": ([vp, ctypes.POINTER(cint), ctypes.POINTER(cint), ctypes.POINTER(i64)], cint),
+        "gwl_multi_autotune": ([ctypes.c_char_p, ctypes.POINTER(vp), cint, ctypes.POINTER(i64), cint, cint], cint),
         "gwl_autotune": ([ctypes.c_char_p, vp, i64, cint, cint], cint),
         "gwl_autotune_load": ([ctypes.c_char_p], cint),
         "gwl_profile_enable": ([cint], cint),
@@ -253,6 +255,12 @@ class MultiPlan:
         self._last = (thetas, logls, grads)
         return logls, grads, (list(lat) if latency else None)
 
+    def info(self):
+        """(chunk length in bins, queued by descending work, number of work items)."""
+        c, d, n = ctypes.c_int(), ctypes.c_int(), ctypes.c_int64()
+        _check("gwl_plan_info", lib().gwl_plan_info(self._h, ctypes.byref(c), ctypes.byref(d), ctypes.byref(n)))
+        return c.value, bool(d.value), n.value
+
     def close(self) -> None:
         if getattr(self, "_h", None) is not None:
             lib().gwl_plan_destroy(self._h)
@@ -270,6 +278,18 @@ def autotune(ev: Event, batch: int, precision="mixed", with_grad: bool = False,
     """Time tile shapes for this event and batch size; record the best (in memory and in cache_path)."""
     path = cache_path.encode() if cache_path else None
     _check("gwl_autotune", lib().gwl_autotune(path, ev.handle, int(batch), _prec(precision), int(bool(with_grad))))
+
+
+def multi_autotune(events: Sequence[Event], batches: Sequence[int], precision="mixed", with_grad: bool = False,
+                   cache_path: Optional[str] = None) -> None:
+    """Time multi-event plan shapes for this workload; MultiPlan then uses the fastest."""
+    E = len(events)
+    if E == 0 or len(batches) != E:
+        raise ValueError("one batch size per event is required")
+    evs = (ctypes.c_void_p * E)(*[ev.handle.value for ev in events])
+    bs = (ctypes.c_int64 * E)(*[int(b) for b in batches])
+    path = cache_path.encode() if cache_path else None
+    _check("gwl_multi_autotune", lib().gwl_multi_autotune(path, evs, E, bs, _prec(precision), int(bool(with_grad))))
 
 
 def autotune_load(cache_path: str) -> None:

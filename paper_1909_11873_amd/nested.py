@@ -8,7 +8,9 @@ synchronisation (the host reads the stop flag every few iterations):
   1. L_min is the first live log-likelihood (the live set is kept sorted ascending).
   2. n candidates in the unit cube: prior draws (the paper's proposal), draws from the bounding
      ellipsoid of the live points (the "bounding distribution" the algorithm re-evaluates each
-     iteration), or a caller's proposal function.
+     iteration), gradient-guided walks inside the current contour (Galilean Monte Carlo: straight
+     steps from live points, reflected off the contour along the likelihood gradient, which the
+     library's adjoint provides for a whole batch at once), or a caller's proposal function.
   3. Prior transform and ln L of the whole batch (for the GW likelihood: the library's kernels).
   4. Candidates in the cube with L >= L_min are accepted (n' of them).
   5. The paper replaces the worst live point by each accepted candidate in turn. Taken in
@@ -96,12 +98,14 @@ class ParallelNestedSampler:
 
     loglike(theta[n, d]) -> ln L[n] (float64 tensors on the device; NaN counts as -inf).
     prior_transform(u[n, d]) -> theta[n, d]; identity if None.
-    proposal: "prior", "ellipsoid", or a function (it, live_u, live_l) -> u[n, d].
+    proposal: "prior", "ellipsoid", "gmc", or a function (it, live_u, live_l) -> u[n, d].
+    loglike_grad(theta[n, d]) -> (ln L[n], d ln L / d theta [n, d]): needed for "gmc".
     """
 
     def __init__(self, loglike: Callable, ndim: int, nlive: int, batch: int,
                  prior_transform: Optional[Callable] = None, device="cuda:0", seed: int = 0,
-                 proposal="ellipsoid", enlarge: float = 1.25, volume: str = "order", check_every: int = 8):
+                 proposal="ellipsoid", enlarge: float = 1.25, volume: str = "order", check_every: int = 8,
+                 loglike_grad: Optional[Callable] = None, gmc_steps: int = 8):
         if nlive < 2 or batch < 1 or ndim < 1:
             raise ValueError("need nlive >= 2, batch >= 1, ndim >= 1")
         if volume not in ("order", "paper"):
@@ -113,6 +117,11 @@ class ParallelNestedSampler:
         self.gen.manual_seed(seed)
         self.proposal, self.enlarge, self.volume = proposal, enlarge, volume
         self.check_every = max(1, int(check_every))
+        if proposal == "gmc" and loglike_grad is None:
+            raise ValueError("proposal 'gmc' needs loglike_grad")
+        self.loglike_grad, self.gmc_steps = loglike_grad, max(1, int(gmc_steps))
+        self.gmc_scale = 0.5            # step length in units of the live points' spread, adapted
+        self.extra_calls = 0
 
     # ---- proposals -------------------------------------------------------------------------
     def _prior(self):
@@ -133,6 +142,63 @@ class ParallelNestedSampler:
         rad = torch.rand(self.n, 1, generator=self.gen, device=self.dev, dtype=torch.float64) ** (1.0 / d)
         return mu + scale * (z * rad) @ chol.T
 
+    def _grad_u(self, u):
+        """ln L and its gradient in the unit cube (chain rule through the prior transform)."""
+        uu = u.detach().clone().requires_grad_(True)
+        with torch.enable_grad():
+            th = self.transform(uu)
+            l, g = self.loglike_grad(th.detach())
+            th.backward(g)
+        gu = uu.grad
+        l = torch.where(torch.isnan(l), torch.full_like(l, -math.inf), l)
+        gu = torch.where(torch.isfinite(gu), gu, torch.zeros_like(gu))
+        return l.detach(), gu
+
+    @staticmethod
+    def _reflect_cube(x, v):
+        """Mirror positions (and the velocity components) that left the unit cube."""
+        lo, hi = x < 0.0, x > 1.0
+        x = torch.where(lo, -x, torch.where(hi, 2.0 - x, x))
+        v = torch.where(lo | hi, -v, v)
+        return x.clamp(0.0, 1.0), v
+
+    def _gmc(self, live_u, live_l):
+        """Galilean Monte Carlo inside the contour L >= L_min, one chain per candidate.
+
+        Each chain starts at a random live point with a random velocity of length
+        gmc_scale x (spread of the live points). A step moves straight ahead; if the new point is
+        below L_min the velocity is reflected off the contour, v -> v - 2 (v.n) n with n the unit
+        gradient of ln L there, and the step is retried from that point; if that also fails the
+        velocity reverses. Chains that never moved are returned outside the cube (rejected), so no
+        live point is duplicated."""
+        n, d = self.n, self.d
+        lmin = live_l[0]
+        start = torch.randint(0, self.K, (n,), generator=self.gen, device=self.dev)
+        x = live_u[start]
+        spread = live_u.std(0).clamp(min=1e-9)
+        z = torch.randn(n, d, generator=self.gen, device=self.dev, dtype=torch.float64)
+        v = self.gmc_scale * spread * z / z.norm(dim=1, keepdim=True)
+        moved = torch.zeros(n, dtype=torch.bool, device=self.dev)
+        acc_moves = torch.zeros((), dtype=torch.float64, device=self.dev)
+        for _ in range(self.gmc_steps):
+            x1, v1 = self._reflect_cube(x + v, v)
+            l1, g1 = self._grad_u(x1)
+            ok1 = l1 >= lmin
+            nrm = g1 / g1.norm(dim=1, keepdim=True).clamp(min=1e-300)
+            vr = v1 - 2.0 * (v1 * nrm).sum(1, keepdim=True) * nrm
+            x2, vr = self._reflect_cube(x1 + vr, vr)
+            l2, _ = self._loglike(x2)
+            ok2 = ~ok1 & (l2 >= lmin)
+            x = torch.where(ok1[:, None], x1, torch.where(ok2[:, None], x2, x))
+            v = torch.where(ok1[:, None], v1, torch.where(ok2[:, None], vr, -v))
+            moved = moved | ok1 | ok2
+            acc_moves = acc_moves + ok1.to(torch.float64).mean()
+        self.extra_calls += 2 * n * self.gmc_steps
+        # fraction of straight steps that stayed inside the contour; the host reads it at its
+        # sync points and adapts the step length towards one half
+        self._gmc_rate = acc_moves / self.gmc_steps
+        return torch.where(moved[:, None], x, torch.full_like(x, 2.0))
+
     def _propose(self, it, live_u, live_l):
         if callable(self.proposal):
             return self.proposal(it, live_u, live_l)
@@ -140,6 +206,8 @@ class ParallelNestedSampler:
             return self._prior()
         if self.proposal == "ellipsoid":
             return self._ellipsoid(live_u)
+        if self.proposal == "gmc":
+            return self._gmc(live_u, live_l)
         raise ValueError(f"unknown proposal {self.proposal!r}")
 
     def _loglike(self, u):
@@ -153,6 +221,7 @@ class ParallelNestedSampler:
         K, n, d, dev = self.K, self.n, self.d, self.dev
         f64 = dict(dtype=torch.float64, device=dev)
         t0 = time.perf_counter()
+        self.extra_calls = 0
         if live_u is None:
             live_u = torch.rand(K, d, generator=self.gen, **f64)
         live_u = live_u.to(**f64).contiguous()
@@ -179,6 +248,9 @@ class ParallelNestedSampler:
                 if bool(stop):
                     break
                 synced_dead = int(n_dead)
+                if self.proposal == "gmc":   # step-length adaptation at the host's sync points
+                    rate = float(self._gmc_rate)
+                    self.gmc_scale *= 1.25 if rate > 0.5 else 0.8
             if synced_dead + n * (self.check_every + 1) > cap:      # grow the dead buffers
                 synced_dead = int(n_dead)
                 new_cap = max(2 * cap, synced_dead + n * (self.check_every + 1))
@@ -249,5 +321,5 @@ class ParallelNestedSampler:
         theta = self.transform(torch.tensor(u, **f64)).cpu().numpy() if len(u) else u
         return NSResult(u=u, theta=theta, logl=logl, log_dx=log_dx, log_x=log_x, logz=lz,
                         logz_err=math.sqrt(max(h, 0.0) / K), log_w=log_w, information=h, niter=it,
-                        ncall=K + n * it, n_accepted=n_acc,
+                        ncall=K + n * it + self.extra_calls, n_accepted=n_acc,
                         seconds=time.perf_counter() - t0, nlive=K)

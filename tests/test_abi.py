@@ -59,6 +59,10 @@ def test_error_codes_without_device_work():
     assert L.gwl_waveform(None, 1, dets, 1, fake, 10, 0.0, fake, None) == -1
     assert L.gwl_waveform(fake, 0, dets, 1, fake, 10, 0.0, fake, None) == 0  # empty batch: no-op
     assert L.gwl_autotune_load(b"/nonexistent/cache.json") == -1
+    # multi-event plan calls without events or plan
+    assert L.gwl_multi_autotune(None, None, 1, None, 1, 0) == -1
+    assert L.gwl_plan_info(None, None, None, None) == -1
+    assert L.gwl_multi_plan_create(None, 1, None, 1, 0, ctypes.byref(h)) == -1
 
 
 def test_python_binding_rejects_cpu_tensors():

@@ -101,6 +101,36 @@ def test_multi_graph_replays_are_identical(events):
     plan.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_multi_autotune_roundtrip(events, prec, tmp_path):
+    """The tuner times plan shapes, records the fastest, and a new plan for the same workload
+    takes it; its results match the heuristic plan's."""
+    evs = [e["ev"] for e in events]
+    thetas = [torch.tensor(e["th"], device=DEV).reshape(-1, 11) for e in events]
+    base = gw.MultiPlan(evs, BATCHES, prec, with_grad=True)
+    l0, g0, _ = base.launch(thetas)
+    path = str(tmp_path / "tune.json")
+    gw.multi_autotune(evs, BATCHES, prec, with_grad=True, cache_path=path)
+    text = open(path).read()
+    assert '"multi": 1' in text
+    import json
+    entry = [x for x in json.loads(text)["entries"] if x.get("multi") == 1 and x["mixed"] == (prec == "mixed")][0]
+    plan = gw.MultiPlan(evs, BATCHES, prec, with_grad=True)
+    chunk, desc, items = plan.info()
+    assert (chunk, int(desc)) == (entry["chunk"], entry["descending"])
+    assert items > 0
+    l1, g1, _ = plan.launch(thetas)
+    tol = 1e-9 if prec == "fp64" else 2e-4
+    for a, b, ga, gb, t in zip(l0, l1, g0, g1, thetas):
+        if t.shape[0]:
+            assert np.abs(a.cpu().numpy() - b.cpu().numpy()).max() <= tol
+            scale = np.abs(ga.cpu().numpy()).max()
+            assert np.abs(ga.cpu().numpy() - gb.cpu().numpy()).max() <= 1e-6 * scale
+    gw.autotune_load(path)   # the file parses back
+    plan.close()
+    base.close()
+
+
 def test_multi_plan_argument_errors(events):
     with pytest.raises(ValueError):
         gw.MultiPlan([events[0]["ev"]], [1, 2])
