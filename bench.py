@@ -34,6 +34,9 @@ PEAK_FP32 = 157.3e12   # FP32 vector FLOP/s (published; needs packed FMA)
 # 256 CU x 64 lanes/clk x 2.4 GHz / 2
 PEAK_TRANS = 256 * 64 * 2.4e9 / 2
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_bins_mixed_c1.txt")
+# tile shapes measured on an MI355X by the library's autotuner (gwl_autotune / gwl_multi_autotune);
+# loaded so that timed launches use a fixed, tuned shape; --retune measures them again
+TUNE_FILE = os.path.join(ROOT, "paper_1909_11873_amd", "tuning_gfx950.json")
 KERNEL_SOURCES = ["paper_1909_11873_amd/csrc/k_bins.hip", "paper_1909_11873_amd/csrc/gwl_bins.h",
                   "paper_1909_11873_amd/csrc/gwl_common.h", "paper_1909_11873_amd/csrc/gwl_device.h"]
 
@@ -79,16 +82,27 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic():
-    """HBM bytes per bin-loop launch from the committed counter summary, if it matches the source."""
+def read_traffic(nchunk: int):
+    """HBM bytes per bin-loop launch from the committed counter summary, if it was taken with the
+    same kernel source and the same launch shape (number of bin chunks)."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     text = open(TRAFFIC_FILE).read()
     m_hash = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
     m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    if not (m_hash and m_bytes) or m_hash.group(1) != kernel_hash():
+    m_shape = re.search(r"launch_nchunk:\s*(\d+)", text)
+    if not (m_hash and m_bytes and m_shape) or m_hash.group(1) != kernel_hash() or int(m_shape.group(1)) != nchunk:
         return None
     return float(m_bytes.group(1))
+
+
+def load_or_tune(tune_out):
+    """Use the committed tile shapes unless asked to measure them again."""
+    from paper_1909_11873_amd import gwlike as gw
+    if tune_out is None and os.path.exists(TUNE_FILE):
+        gw.autotune_load(TUNE_FILE)
+        return False
+    return True
 
 
 # ---- CPU baseline (FP64 oracle) ----------------------------------------------------------
@@ -139,7 +153,7 @@ def cpu_baseline(cfg: int, target_s: float):
 
 
 # ---- GPU leg --------------------------------------------------------------------------------
-def gpu_leg(cfg: int, steps: int, warmup: int, parity_inputs):
+def gpu_leg(cfg: int, steps: int, warmup: int, parity_inputs, tune_out=None):
     import numpy as np
     import torch
 
@@ -159,12 +173,16 @@ def gpu_leg(cfg: int, steps: int, warmup: int, parity_inputs):
     prep_ms = (time.perf_counter() - t0) * 1e3
     theta = torch.tensor(synth.theta_batch(spec), device=dev)
     B, M, nd = theta.shape[0], len(f), spec.ndet
-    # tile shapes for the timed launches, from the library's autotuner (not timed)
+    # tile shapes for the timed launches: the committed autotuner results, or measured now (not timed)
     t_tune = time.perf_counter()
-    for prec in ("mixed", "fp64"):
-        gw.autotune(ev, B, prec, with_grad=False)
-        gw.autotune(ev, min(B, 16384), prec, with_grad=True)
+    if load_or_tune(tune_out):
+        for prec in ("mixed", "fp64"):
+            gw.autotune(ev, B, prec, with_grad=False, cache_path=tune_out)
+            gw.autotune(ev, min(B, 16384), prec, with_grad=True, cache_path=tune_out)
     t_tune = time.perf_counter() - t_tune
+    shapes = {"mixed": gw.launch_shape(ev, B, "mixed"), "fp64": gw.launch_shape(ev, B, "fp64"),
+              "mixed_grad": gw.launch_shape(ev, min(B, 16384), "mixed", True),
+              "fp64_grad": gw.launch_shape(ev, min(B, 16384), "fp64", True)}
 
     def timed(fn, k, w):
         for _ in range(w):
@@ -206,6 +224,7 @@ def gpu_leg(cfg: int, steps: int, warmup: int, parity_inputs):
     nsteps64, nsg, nsg64 = max(3, steps // 4), max(3, steps // 4), 3
     res = {
         "B": B, "M": M, "ndet": nd, "prep_ms": prep_ms, "parity": parity, "autotune_s": t_tune,
+        "shapes": {k: {"nchunk": v[0], "chunk_bins": v[1]} for k, v in shapes.items()},
         "mixed_wall": out["mixed"][0], "mixed_kern": out["mixed"][1],
         "fp64_evals": B * nsteps64 / out["fp64"][0], "fp64_kern": out["fp64"][1],
         "grad_mixed_evals": BG * nsg / wg, "grad_fp64_evals": BG * nsg64 / wg64, "grad_batch": BG,
@@ -284,7 +303,7 @@ def cpu_baseline_multi(inputs, target_s: float):
     }, (k, refs)
 
 
-def multi_leg(steps: int, warmup: int, inputs, cpu=None, refs=None):
+def multi_leg(steps: int, warmup: int, inputs, cpu=None, refs=None, tune_out=None):
     """All events of the uneven workload in one persistent mixed-precision launch, forward + gradient."""
     import numpy as np
     import torch
@@ -303,7 +322,8 @@ def multi_leg(steps: int, warmup: int, inputs, cpu=None, refs=None):
         batches.append(spec.batch)
         bins.append(len(f))
     t_tune = time.perf_counter()
-    gw.multi_autotune(events, batches, "mixed", with_grad=True)    # plan shape for this workload
+    if load_or_tune(tune_out):                                       # plan shape for this workload
+        gw.multi_autotune(events, batches, "mixed", with_grad=True, cache_path=tune_out)
     t_tune = time.perf_counter() - t_tune
     plan = gw.MultiPlan(events, batches, "mixed", with_grad=True)
     chunk, desc, items = plan.info()
@@ -446,6 +466,8 @@ def main():
     ap.add_argument("--ns-batches", default="128,256,512,1024,2048")
     ap.add_argument("--ns-eps", type=float, default=0.1)
     ap.add_argument("--ns-proposal", default="gmc", choices=["gmc", "ellipsoid", "prior"])
+    ap.add_argument("--retune", metavar="CACHE", default=None,
+                    help="measure the tile shapes again (written to CACHE) instead of loading " + TUNE_FILE)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run one plain device-to-device copy of this many bytes (a known-size reference "
                          "for the HBM byte counters)")
@@ -466,7 +488,7 @@ def main():
         cpu, refs = None, None
         if not args.no_cpu_baseline:
             cpu, refs = cpu_baseline_multi(inputs, args.cpu_seconds)
-        print(json.dumps(multi_leg(args.steps, args.warmup, inputs, cpu, refs)))
+        print(json.dumps(multi_leg(args.steps, args.warmup, inputs, cpu, refs, args.retune)))
         return
 
     cpu, parity_inputs = None, None
@@ -481,12 +503,12 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    r = gpu_leg(args.config, args.steps, args.warmup, parity_inputs)
+    r = gpu_leg(args.config, args.steps, args.warmup, parity_inputs, args.retune)
     B, M, nd = r["B"], r["M"], r["ndet"]
     value = B * args.steps / r["mixed_wall"]
     ach, peak, frac = roofline(nd, True, M, B, r["mixed_kern"])
     a64, p64, f64 = roofline(nd, False, M, B, r["fp64_kern"])
-    traffic = read_traffic()
+    traffic = read_traffic(r["shapes"]["mixed"]["nchunk"]) if args.config == 1 else None
     line = {
         "metric": "logL evals/sec (3 det, 8 s, 20-2048 Hz) mixed vs FP64; frac VALU peak",
         "value": value, "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -506,7 +528,7 @@ def main():
                                                                                   r["grad_mixed_kern"], True))),
                  "fp64_roofline": dict(zip(("achieved", "peak", "frac"), roofline(nd, False, M, r["grad_batch"],
                                                                                  r["grad_fp64_kern"], True)))},
-        "event_prep_ms": r["prep_ms"], "autotune_s": r["autotune_s"],
+        "event_prep_ms": r["prep_ms"], "autotune_s": r["autotune_s"], "shapes": r["shapes"],
         "parity_vs_oracle": r["parity"],
     }
     print(json.dumps(line))

@@ -187,6 +187,12 @@ gwl_status gwl_multi_autotune(const char* cache_path, const gwl_event* evs, int 
  */
 gwl_status gwl_autotune(const char* cache_path, gwl_event ev, int64_t B, gwl_precision prec, int with_grad);
 
+/* The bin-loop shape a gwl_logl_batch / gwl_logl_grad call with these arguments would use: the
+ * number of bin chunks and the chunk length in bins (from the autotuner's cache, else the
+ * heuristic). Either output pointer may be null. */
+gwl_status gwl_launch_shape(gwl_event ev, int64_t B, gwl_precision prec, int with_grad, int* nchunk,
+                            int* chunk_bins);
+
 /* Load tile choices from a JSON cache written by gwl_autotune (missing file = GWL_E_INVALID). */
 gwl_status gwl_autotune_load(const char* cache_path);
 

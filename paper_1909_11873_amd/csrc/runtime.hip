@@ -197,6 +197,18 @@ gwl_status gwl_logl_grad(gwl_event ev, const double* theta, int64_t B, gwl_preci
   return logl_common(ev, theta, B, prec, logl, grad, true, stream);
 }
 
+gwl_status gwl_launch_shape(gwl_event ev, int64_t B, gwl_precision prec, int with_grad, int* nchunk,
+                            int* chunk_bins) {
+  clear_error();
+  if (!ev) return fail(GWL_E_INVALID, "event is null");
+  if (B < 1 || B > kMaxBatch) return fail(GWL_E_SHAPE, "B=%lld outside [1, %lld]", (long long)B, (long long)kMaxBatch);
+  if (prec != GWL_FP64 && prec != GWL_MIXED) return fail(GWL_E_INVALID, "unknown precision %d", (int)prec);
+  const LoopShape sh = make_shape(B, ev->M, choose_nchunk(ev, B, prec == GWL_MIXED, with_grad != 0));
+  if (nchunk) *nchunk = sh.nchunk;
+  if (chunk_bins) *chunk_bins = sh.chunk;
+  return GWL_OK;
+}
+
 gwl_status gwl_waveform(const double* theta, int64_t B, const gwl_detector* dets, int ndet, const double* fgrid,
                         int64_t M, double gmst, double* out, void* stream) {
   clear_error();

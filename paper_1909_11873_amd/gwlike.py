@@ -6,8 +6,10 @@ It fails loudly if the compiled library is missing: there is no CPU fallback.
 """
 from __future__ import annotations
 
+import collections
 import ctypes
 import os
+import weakref
 from typing import Optional, Sequence
 
 import torch
@@ -67,6 +69,7 @@ def lib() -> ctypes.CDLL:
         "gwl_multi_autotune": ([ctypes.c_char_p, ctypes.POINTER(vp), cint, ctypes.POINTER(i64), cint, cint], cint),
         "gwl_autotune": ([ctypes.c_char_p, vp, i64, cint, cint], cint),
         "gwl_autotune_load": ([ctypes.c_char_p], cint),
+        "gwl_launch_shape": ([vp, i64, cint, cint, ctypes.POINTER(cint), ctypes.POINTER(cint)], cint),
         "gwl_profile_enable": ([cint], cint),
         "gwl_profile_read": ([ctypes.POINTER(i64), ctypes.POINTER(dbl)], cint),
     }
@@ -181,6 +184,44 @@ def logl_grad(theta: torch.Tensor, ev: Event, precision="mixed"):
     return out, grad
 
 
+# one-shot calls: events built on first use and kept for the same (live) input tensors
+_EVENT_CACHE: "collections.OrderedDict" = collections.OrderedDict()
+_EVENT_CACHE_MAX = 8
+
+
+def _cached_event(data, psd, dets, fgrid, df, gmst) -> Event:
+    dets_key = tuple(tuple(float(x) for x in d) for d in dets)
+    key = (data.data_ptr(), data._version, psd.data_ptr(), psd._version, fgrid.data_ptr(), fgrid._version,
+           dets_key, float(df) if df is not None else None, float(gmst))
+    hit = _EVENT_CACHE.get(key)
+    if hit is not None:
+        refs, ev = hit
+        if all(r() is t for r, t in zip(refs, (data, psd, fgrid))):   # the same tensors, still alive
+            _EVENT_CACHE.move_to_end(key)
+            return ev
+        del _EVENT_CACHE[key]
+    if df is None:
+        df = float(fgrid[1] - fgrid[0]) if fgrid.numel() > 1 else 1.0
+    ev = Event(data, psd, dets, fgrid, df, gmst)
+    _EVENT_CACHE[key] = ((weakref.ref(data), weakref.ref(psd), weakref.ref(fgrid)), ev)
+    while len(_EVENT_CACHE) > _EVENT_CACHE_MAX:
+        _EVENT_CACHE.popitem(last=False)[1][1].close()
+    return ev
+
+
+def logl_batch(theta: torch.Tensor, data: torch.Tensor, psd: torch.Tensor, dets: Sequence, fgrid: torch.Tensor,
+               df: Optional[float] = None, precision="mixed", gmst: float = 0.0) -> torch.Tensor:
+    """One-shot logL[B]: the event tables are built on the first call for these data, PSD and
+    grid tensors and reused while the same tensors are passed again (df defaults to the grid step)."""
+    return logl(theta, _cached_event(data, psd, dets, fgrid, df, gmst), precision)
+
+
+def logl_grad_batch(theta: torch.Tensor, data: torch.Tensor, psd: torch.Tensor, dets: Sequence,
+                    fgrid: torch.Tensor, df: Optional[float] = None, precision="mixed", gmst: float = 0.0):
+    """One-shot (logL[B], dlogL/dtheta[B, 11]), with the same event reuse as logl_batch."""
+    return logl_grad(theta, _cached_event(data, psd, dets, fgrid, df, gmst), precision)
+
+
 class LogL(torch.autograd.Function):
     """logL as a differentiable function of theta; the adjoint is computed in the forward pass."""
 
@@ -290,6 +331,14 @@ def multi_autotune(events: Sequence[Event], batches: Sequence[int], precision="m
     bs = (ctypes.c_int64 * E)(*[int(b) for b in batches])
     path = cache_path.encode() if cache_path else None
     _check("gwl_multi_autotune", lib().gwl_multi_autotune(path, evs, E, bs, _prec(precision), int(bool(with_grad))))
+
+
+def launch_shape(ev: Event, batch: int, precision="mixed", with_grad: bool = False):
+    """(number of bin chunks, chunk length in bins) that a call with these arguments would use."""
+    n, c = ctypes.c_int(), ctypes.c_int()
+    _check("gwl_launch_shape", lib().gwl_launch_shape(ev.handle, int(batch), _prec(precision), int(bool(with_grad)),
+                                                      ctypes.byref(n), ctypes.byref(c)))
+    return n.value, c.value
 
 
 def autotune_load(cache_path: str) -> None:

@@ -90,6 +90,25 @@ def gw_prior_transform(mc_range=(10.0, 60.0), dl_range=(100.0, 2000.0), tc_half=
         th[:, 9] = 2.0 * math.pi * u[:, 9]
         th[:, 10] = -tc_half + 2.0 * tc_half * u[:, 10]
         return th
+
+    def jacobian(u: torch.Tensor) -> torch.Tensor:
+        """d theta_i / d u_i (the transform acts column by column)."""
+        j = torch.empty_like(u)
+        j[:, 0] = mc_range[1] - mc_range[0]
+        j[:, 1] = 0.8
+        j[:, 2:4] = 1.8 if spins else 0.0
+        j[:, 4] = (hi3 - lo3) / 3.0 * torch.pow(lo3 + u[:, 4] * (hi3 - lo3), -2.0 / 3.0)
+        j[:, 5] = 2.0 * math.pi
+        s6 = 1.0 - (2.0 * u[:, 6] - 1.0) ** 2
+        s7 = 1.0 - (2.0 * u[:, 7] - 1.0) ** 2
+        j[:, 6] = 2.0 / torch.sqrt(s6.clamp(min=1e-300))
+        j[:, 7] = -2.0 / torch.sqrt(s7.clamp(min=1e-300))
+        j[:, 8] = math.pi
+        j[:, 9] = 2.0 * math.pi
+        j[:, 10] = 2.0 * tc_half
+        return j
+
+    transform.jacobian = jacobian
     return transform
 
 
@@ -105,7 +124,7 @@ class ParallelNestedSampler:
     def __init__(self, loglike: Callable, ndim: int, nlive: int, batch: int,
                  prior_transform: Optional[Callable] = None, device="cuda:0", seed: int = 0,
                  proposal="ellipsoid", enlarge: float = 1.25, volume: str = "order", check_every: int = 8,
-                 loglike_grad: Optional[Callable] = None, gmc_steps: int = 8):
+                 loglike_grad: Optional[Callable] = None, gmc_steps: int = 20):
         if nlive < 2 or batch < 1 or ndim < 1:
             raise ValueError("need nlive >= 2, batch >= 1, ndim >= 1")
         if volume not in ("order", "paper"):
@@ -144,6 +163,12 @@ class ParallelNestedSampler:
 
     def _grad_u(self, u):
         """ln L and its gradient in the unit cube (chain rule through the prior transform)."""
+        jac = getattr(self.transform, "jacobian", None)
+        if jac is not None:
+            l, g = self.loglike_grad(self.transform(u))
+            gu = g * jac(u)
+            l = torch.where(torch.isnan(l), torch.full_like(l, -math.inf), l)
+            return l, torch.where(torch.isfinite(gu), gu, torch.zeros_like(gu))
         uu = u.detach().clone().requires_grad_(True)
         with torch.enable_grad():
             th = self.transform(uu)

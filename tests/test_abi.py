@@ -62,6 +62,7 @@ def test_error_codes_without_device_work():
     # multi-event plan calls without events or plan
     assert L.gwl_multi_autotune(None, None, 1, None, 1, 0) == -1
     assert L.gwl_plan_info(None, None, None, None) == -1
+    assert L.gwl_launch_shape(None, 10, 1, 0, None, None) == -1
     assert L.gwl_multi_plan_create(None, 1, None, 1, 0, ctypes.byref(h)) == -1
 
 

@@ -265,3 +265,24 @@ def test_autotune_roundtrip(tmp_path, c1):
     idx = sample[sample < 4096]
     ref_sub = ref[np.searchsorted(sample, idx)]
     assert np.abs(got[idx] - ref_sub).max() <= TOL["mixed"]
+
+
+def test_one_shot_logl_batch_reuses_its_event():
+    """logl_batch(theta, data, psd, dets, fgrid): same values as an explicit event; the event is
+    built once for the same tensors and rebuilt when the data change."""
+    spec, f, psd, data, dets = event_inputs(1, f_hi=300.0)
+    d, p, ft = (torch.tensor(x, device=DEV) for x in (data, psd, f))
+    th = torch.tensor(synth.theta_batch(spec, 100), device=DEV)
+    ev = make_event(f, psd, data, dets, spec.df)
+    ref = gw.logl(th, ev, "fp64").cpu().numpy()
+    a = gw.logl_batch(th, d, p, dets, ft, spec.df, "fp64").cpu().numpy()
+    n0 = len(gw._EVENT_CACHE)
+    b = gw.logl_batch(th, d, p, dets, ft, spec.df, "fp64").cpu().numpy()
+    assert len(gw._EVENT_CACHE) == n0
+    np.testing.assert_array_equal(a, ref)
+    np.testing.assert_array_equal(b, ref)
+    v, g = gw.logl_grad_batch(th, d, p, dets, ft, spec.df, "fp64")
+    np.testing.assert_allclose(v.cpu().numpy(), ref, rtol=0, atol=1e-9)
+    d.mul_(0.0)                                      # new data version: the event is rebuilt
+    z = gw.logl_batch(th, d, p, dets, ft, spec.df, "fp64").cpu().numpy()
+    assert np.all(z <= 0.0)                          # logL = -<h|h>/2 without data

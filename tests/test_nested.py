@@ -99,6 +99,15 @@ def test_speedup_law():
         assert nested.speedup_law(cores, 2000) == pytest.approx(s, abs=0.06)
 
 
+def test_gw_prior_transform_jacobian():
+    """The analytic Jacobian of the prior transform against autograd."""
+    tr = nested.gw_prior_transform()
+    u = torch.tensor(np.random.default_rng(4).uniform(0.02, 0.98, (50, 11)), requires_grad=True)
+    th = tr(u)
+    th.sum().backward()
+    np.testing.assert_allclose(tr.jacobian(u.detach()).numpy(), u.grad.numpy(), rtol=1e-12)
+
+
 def test_gw_prior_transform_matches_synthetic_prior_draws():
     from paper_1909_11873_amd import synth
     u = np.random.default_rng(8).random((1000, 11))
