@@ -152,8 +152,24 @@ def cpu_baseline(cfg: int, target_s: float):
     }, (theta[:n], ref, data, psd, dets, f, spec.df)
 
 
+def _rb_oracle_sample(cfg: int, eps: float):
+    """A function that evaluates the oracle's relative binning (same event data as the CPU
+    baseline, fiducial theta0) on a few points; the summary data are built here, on the host."""
+    from oracle import gw_oracle as o
+    from oracle import rb_oracle as rbo
+    from paper_1909_11873_amd import synth
+    spec = synth.event_spec(cfg)
+    f, psd, nz, dets = synth.event_arrays(spec)
+    data = nz + o.strain_all(spec.theta0, dets, f).numpy()
+    summ = rbo.summary(data, psd, dets, f, spec.df, spec.theta0, eps)
+
+    def run(theta):
+        return theta, rbo.logl(theta, summ, psd, dets, f, spec.df).numpy()
+    return run, data
+
+
 # ---- GPU leg --------------------------------------------------------------------------------
-def gpu_leg(cfg: int, steps: int, warmup: int, parity_inputs, tune_out=None):
+def gpu_leg(cfg: int, steps: int, warmup: int, parity_inputs, tune_out=None, rb_eps=0.1, rb_inputs=None):
     import numpy as np
     import torch
 
@@ -210,6 +226,39 @@ def gpu_leg(cfg: int, steps: int, warmup: int, parity_inputs, tune_out=None):
     wg, kg = timed(lambda: gw.logl_grad(tg, ev, "mixed"), max(3, steps // 4), 2)
     wg64, kg64 = timed(lambda: gw.logl_grad(tg, ev, "fp64"), 3, 1)
 
+    # relative binning against theta0 (the injection) on the same event: cost and accuracy
+    rb = None
+    if rb_eps > 0:
+        rev = gw.Event(data, torch.tensor(psd, device=dev), dets, ft, spec.df, fiducial=spec.theta0, rb_eps=rb_eps)
+        rng = np.random.default_rng(77)
+        # offsets of the order of the posterior width: a binary black hole (c1, c3), or the long
+        # low-mass signal (c2), whose chirp mass is measured some hundred times more finely
+        step = (np.array([0.05, 0.01, 0.02, 0.02, 10.0, 0.01, 0.01, 0.02, 0.02, 0.05, 1e-4]) if spec.mc_range[1] > 5
+                else np.array([2e-4, 0.005, 0.005, 0.005, 5.0, 0.005, 0.005, 0.01, 0.01, 0.02, 2e-5])) * 0.3
+        near = torch.tensor(spec.theta0 + step * rng.standard_normal((B, 11)), device=dev)
+        wr, kr = timed(lambda: gw.logl(near, rev, "mixed"), steps, warmup)
+        wr64, kr64 = timed(lambda: gw.logl(near, rev, "fp64"), steps, warmup)
+        a = gw.logl(near, rev, "fp64").cpu().numpy()
+        b = gw.logl(near, ev, "fp64").cpu().numpy()
+        am = gw.logl(near, rev, "mixed").cpu().numpy()
+        rb = {"eps": rb_eps, "edges": rev.rb_edges, "bins": M, "mixed_evals_per_s": B * steps / wr,
+              "fp64_evals_per_s": B * steps / wr64, "mixed_kernel_ms": kr * 1e3, "fp64_kernel_ms": kr64 * 1e3,
+              "points": "theta0 plus Gaussian offsets of standard deviation " + ", ".join(f"{x:.3g}" for x in step),
+              "max_abs_dlogl_vs_full_fp64": float(np.abs(a - b).max()),
+              "median_abs_dlogl_vs_full_fp64": float(np.median(np.abs(a - b))),
+              "max_abs_dlogl_mixed_vs_fp64": float(np.abs(am - a).max())}
+        rev.close()
+        if rb_inputs is not None:       # the oracle's relative binning on the oracle-injected data
+            run, pdata = rb_inputs
+            pev = gw.Event(torch.tensor(pdata, device=dev), torch.tensor(psd, device=dev), dets, ft, spec.df,
+                           fiducial=spec.theta0, rb_eps=rb_eps)
+            th_s, ref_rb = run(near[:16].cpu().numpy())
+            got = gw.logl(torch.tensor(th_s, device=dev), pev, "mixed").cpu().numpy()
+            got64 = gw.logl(torch.tensor(th_s, device=dev), pev, "fp64").cpu().numpy()
+            rb["parity_vs_rb_oracle"] = {"points": len(th_s), "max_abs_dlogl_mixed": float(np.abs(got - ref_rb).max()),
+                                         "max_abs_dlogl_fp64": float(np.abs(got64 - ref_rb).max()), "tolerance": 1e-3}
+            pev.close()
+
     parity = None
     if parity_inputs is not None:
         th_s, ref, pdata, ppsd, pdets, pf, pdf = parity_inputs
@@ -228,7 +277,7 @@ def gpu_leg(cfg: int, steps: int, warmup: int, parity_inputs, tune_out=None):
         "mixed_wall": out["mixed"][0], "mixed_kern": out["mixed"][1],
         "fp64_evals": B * nsteps64 / out["fp64"][0], "fp64_kern": out["fp64"][1],
         "grad_mixed_evals": BG * nsg / wg, "grad_fp64_evals": BG * nsg64 / wg64, "grad_batch": BG,
-        "grad_mixed_kern": kg, "grad_fp64_kern": kg64,
+        "grad_mixed_kern": kg, "grad_fp64_kern": kg64, "rb": rb,
     }
     return res
 
@@ -468,6 +517,8 @@ def main():
     ap.add_argument("--ns-proposal", default="gmc", choices=["gmc", "ellipsoid", "prior"])
     ap.add_argument("--retune", metavar="CACHE", default=None,
                     help="measure the tile shapes again (written to CACHE) instead of loading " + TUNE_FILE)
+    ap.add_argument("--rb-eps", type=float, default=0.1,
+                    help="also time relative binning against theta0 with this edge spacing (0: skip)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run one plain device-to-device copy of this many bytes (a known-size reference "
                          "for the HBM byte counters)")
@@ -503,7 +554,10 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    r = gpu_leg(args.config, args.steps, args.warmup, parity_inputs, args.retune)
+    rb_inputs = None
+    if parity_inputs is not None and args.rb_eps > 0:
+        rb_inputs = _rb_oracle_sample(args.config, args.rb_eps)
+    r = gpu_leg(args.config, args.steps, args.warmup, parity_inputs, args.retune, args.rb_eps, rb_inputs)
     B, M, nd = r["B"], r["M"], r["ndet"]
     value = B * args.steps / r["mixed_wall"]
     ach, peak, frac = roofline(nd, True, M, B, r["mixed_kern"])
@@ -529,6 +583,7 @@ def main():
                  "fp64_roofline": dict(zip(("achieved", "peak", "frac"), roofline(nd, False, M, r["grad_batch"],
                                                                                  r["grad_fp64_kern"], True)))},
         "event_prep_ms": r["prep_ms"], "autotune_s": r["autotune_s"], "shapes": r["shapes"],
+        "relative_binning": r["rb"],
         "parity_vs_oracle": r["parity"],
     }
     print(json.dumps(line))

@@ -103,6 +103,26 @@ gwl_status gwl_event_create(const double* data, const double* psd, const gwl_det
                             const double* fgrid, int64_t M, double df, double gmst, unsigned flags,
                             void* stream, gwl_event* out);
 
+/*
+ * Relative binning (paper section 5: summary data against a fiducial waveform). Same inputs as
+ * gwl_event_create plus the fiducial point theta_fid (host, float64 [11]) and the edge spacing
+ * eps (radians). The edges are the grid bins where floor(dpsi(f)/eps) changes, plus both ends,
+ * with dpsi(f) = 2 pi sum_g sign(g) (f/f_g)^g over g = -5/3, -2/3, 1, 5/3, 7/3 (f_g = f_hi for
+ * g > 0, f_lo for g < 0). Per detector and edge the event keeps the summary data
+ * V_e = sum_k u_k p0_k hat_e(f_k) (u_k as above, p0_k the fiducial's phasor, hat_e the
+ * piecewise-linear function that is 1 at edge e and 0 at its neighbours). Calls on this event
+ * then evaluate <d|h> as Re sum_e V_e rho(f_e) with rho the phasor of the phase difference from
+ * the fiducial (linear interpolation of h/h0 between edges), on the edges only, and <h|h>
+ * exactly. Accurate for points whose phase differs from the fiducial's by much less than eps
+ * across any two edges. GWL_E_INVALID if theta_fid is outside the model's domain.
+ */
+gwl_status gwl_event_create_rb(const double* data, const double* psd, const gwl_detector* dets, int ndet,
+                               const double* fgrid, int64_t M, double df, double gmst, const double* theta_fid,
+                               double eps, unsigned flags, void* stream, gwl_event* out);
+
+/* Relative-binning sizes: number of edges (0 for an ordinary event) and of grid bins. */
+gwl_status gwl_event_rb_info(gwl_event ev, int64_t* nedge, int64_t* nbins);
+
 /* Release an event and its device tables. Null is accepted. The caller must ensure no work
  * using the event is still pending on any stream. */
 gwl_status gwl_event_destroy(gwl_event ev);

@@ -31,6 +31,10 @@ struct EventConst {
   double gain_i;      //   complex gain of the hardware float32 phasor out of the float32 sums
   int bad;            // nonzero if an input value was rejected
   int pad;
+  // Relative binning: the fiducial waveform's phase coefficients and detector shifts. The set-up
+  // subtracts them, so the bin loop evaluates the phase of h / h0 on the edges. Zero otherwise.
+  double fa[NBASIS];
+  double fT[MAXDET];
 };
 
 // Phases sampled to measure the hardware phasor gain: NGAIN_BLK workgroups x 256 threads x

@@ -11,25 +11,28 @@
 namespace gwl {
 
 // Set-up rows (layout CO_*) of one point; false if the point is outside the model's domain.
-// (gr, gi) undoes the mean gain of the bin loop's phasor (1 for float64 tables). It enters
-// the adjoint projection factors c_det = E G Q_det, E = exp(-2 pi i c0), through which the
-// adjoint bin loop keeps only the one real part of each moment that the gradient uses.
+// With `scaled` (float32 tables) the event's (gain_r, gain_i) undoes the mean gain of the bin
+// loop's phasor (1 for float64 tables). It enters the adjoint projection factors
+// c_det = E G Q_det, E = exp(-2 pi i c0), through which the adjoint bin loop keeps only the one
+// real part of each moment that the gradient uses. A relative-binning event's fiducial phase
+// coefficients and shifts are subtracted from the bin loop's rows (ec may be null: no offsets).
 template <int ND>
-__device__ inline bool setup_rows(const double (&th)[NPARAM], const EventGeom& g, double gr, double gi,
+__device__ inline bool setup_rows(const double (&th)[NPARAM], const EventGeom& g, const EventConst* ec, bool scaled,
                                   double (&rows)[NCOEF]) {
+  const double gr = (scaled && ec) ? ec->gain_r : 1.0, gi = (scaled && ec) ? ec->gain_i : 0.0;
   PointModel<double> pm;
   point_model<double, ND>(th, g, pm);
 #pragma unroll
   for (int j = 0; j < NCOEF; ++j) rows[j] = 0.0;
 #pragma unroll
-  for (int m = 0; m < NBASIS; ++m) rows[CO_A + m] = pm.a[m];
+  for (int m = 0; m < NBASIS; ++m) rows[CO_A + m] = pm.a[m] - (ec ? ec->fa[m] : 0.0);
   const double c0 = pm.c0 - rint(pm.c0);
   double es, ecs;
   sincos_cycles_f64(c0, es, ecs);
   const double egr = ecs * gr + es * gi, egi = ecs * gi - es * gr;  // E G
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
-    rows[CO_T + d] = pm.tdet[d];
+    rows[CO_T + d] = pm.tdet[d] - (ec ? ec->fT[d] : 0.0);
     rows[CO_QR + d] = pm.qr[d];
     rows[CO_QI + d] = pm.qi[d];
     rows[CO_CR + d] = egr * pm.qr[d] - egi * pm.qi[d];

@@ -43,6 +43,16 @@ hipError_t launch_epilogue(int nd, bool grad, bool scaled, const EventGeom& g, c
                            const double* theta, int64_t B, int64_t Bp, int nchunk, const double* part, double* logl,
                            double* gradout, hipStream_t s);
 
+// float32 rows from float64 rows: tab32 = (basis, u / ec->uref)
+hipError_t launch_prep_mixed(int nd, const void* tab64, int64_t M, const EventConst* ec, void* tab32, hipStream_t s);
+
+// relative binning: edge rows from the fine rows (fine64 etc.), the edge indices eidx[nedge] and
+// the fiducial in ec->fa, ec->fT; w is scratch of rb_scratch_doubles(nd, nedge); sets ec->uref
+size_t rb_scratch_doubles(int nd, int nedge);
+hipError_t launch_rb(int nd, const void* fine64, const RowGradF32* fine32g, const RowGradF64* fine64g,
+                     const int64_t* eidx, int nedge, double* w, EventConst* ec, void* tab64, void* tab32,
+                     RowGradF32* g32, RowGradF64* g64, hipStream_t s);
+
 // model strain on a grid: out[B][nd][M][2]
 hipError_t launch_waveform(int nd, const EventGeom& g, const double* coef, int64_t B, int64_t Bp,
                            const double* fgrid, int64_t M, double* out, hipStream_t s);

@@ -10,7 +10,8 @@
 struct gwl_event_s {
   int device = 0;
   int ndet = 0;
-  int64_t M = 0;
+  int64_t M = 0;                     // rows the bin loop walks (bins, or edges for relative binning)
+  int64_t M_full = 0;                // bins of the grid (relative binning), else 0
   double df = 0.0;
   double gmst = 0.0;
   gwl_detector dets[GWL_MAX_DET] = {};

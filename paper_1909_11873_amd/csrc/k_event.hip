@@ -159,6 +159,10 @@ __global__ __launch_bounds__(PREP_BLOCK) void k_prep_final(const double* __restr
     e.gain_i = gi / g2;
     e.bad = red[ND + 1][0] != 0.0 || !isfinite(um);
     e.pad = 0;
+#pragma unroll
+    for (int m = 0; m < NBASIS; ++m) e.fa[m] = 0.0;
+#pragma unroll
+    for (int d = 0; d < MAXDET; ++d) e.fT[d] = 0.0;
     *ec = e;
   }
 }
@@ -177,6 +181,18 @@ __global__ __launch_bounds__(PREP_BLOCK) void k_prep_mixed(const RowF64<ND>* __r
 #pragma unroll
   for (int j = 0; j < 2 * ND; ++j) o.u[j] = (float)(r.u[j] * inv);
   tab32[k] = o;
+}
+
+hipError_t launch_prep_mixed(int nd, const void* tab64, int64_t M, const EventConst* ec, void* tab32, hipStream_t s) {
+  const dim3 grid((unsigned)prep_blocks(M));
+  switch (nd) {
+    case 1: hipLaunchKernelGGL(k_prep_mixed<1>, grid, dim3(PREP_BLOCK), 0, s, (const RowF64<1>*)tab64, M, ec, (RowMixed<1>*)tab32); break;
+    case 2: hipLaunchKernelGGL(k_prep_mixed<2>, grid, dim3(PREP_BLOCK), 0, s, (const RowF64<2>*)tab64, M, ec, (RowMixed<2>*)tab32); break;
+    case 3: hipLaunchKernelGGL(k_prep_mixed<3>, grid, dim3(PREP_BLOCK), 0, s, (const RowF64<3>*)tab64, M, ec, (RowMixed<3>*)tab32); break;
+    case 4: hipLaunchKernelGGL(k_prep_mixed<4>, grid, dim3(PREP_BLOCK), 0, s, (const RowF64<4>*)tab64, M, ec, (RowMixed<4>*)tab32); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 template <int ND>

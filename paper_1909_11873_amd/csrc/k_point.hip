@@ -22,9 +22,8 @@ __global__ __launch_bounds__(PT_BLOCK) void k_setup(EventGeom g, const EventCons
   const int64_t pc = p < B ? p : B - 1;  // padding lanes repeat the last point
 #pragma unroll
   for (int i = 0; i < NPARAM; ++i) th[i] = theta[pc * NPARAM + i];
-  const double gr = scaled ? ec->gain_r : 1.0, gi = scaled ? ec->gain_i : 0.0;
   double rows[NCOEF];
-  const bool valid = setup_rows<ND>(th, g, gr, gi, rows);
+  const bool valid = setup_rows<ND>(th, g, ec, scaled, rows);
   const double nan = __builtin_nan("");
 #pragma unroll
   for (int j = 0; j < NCOEF; ++j) coef[j * Bp + p] = valid ? rows[j] : nan;

@@ -85,10 +85,8 @@ __global__ __launch_bounds__(MULTI_PT_BLOCK) void k_multi_setup(const MultiEvDev
   double th[NPARAM];
 #pragma unroll
   for (int i = 0; i < NPARAM; ++i) th[i] = o.theta[pc * NPARAM + i];
-  const EventConst* ec = ev.ec;
-  const double gr = scaled ? ec->gain_r : 1.0, gi = scaled ? ec->gain_i : 0.0;
   double rows[NCOEF];
-  const bool valid = setup_rows<ND>(th, geoms[e], gr, gi, rows);
+  const bool valid = setup_rows<ND>(th, geoms[e], ev.ec, scaled, rows);
   const double nan = __builtin_nan("");
 #pragma unroll
   for (int j = 0; j < NCOEF; ++j) ev.coef[j * ev.Bp + p] = valid ? rows[j] : nan;

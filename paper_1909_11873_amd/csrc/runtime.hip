@@ -151,6 +151,124 @@ gwl_status gwl_event_create(const double* data, const double* psd, const gwl_det
   return GWL_OK;
 }
 
+// Relative-binning edges on the grid: the bins where floor(dpsi(f) / eps) changes, plus both
+// ends, with dpsi(f) = 2 pi sum_gamma sign(gamma) (f / f_gamma)^gamma over the post-Newtonian
+// phase power laws gamma = -5/3, -2/3, 1, 5/3, 7/3 (f_gamma = f_hi for gamma > 0, f_lo below):
+// the largest phase difference between two waveforms of the model grows no faster than dpsi.
+static std::vector<int64_t> rb_edges(const std::vector<double>& f, double eps) {
+  const double flo = f.front(), fhi = f.back();
+  const double gam[5] = {-5.0 / 3.0, -2.0 / 3.0, 1.0, 5.0 / 3.0, 7.0 / 3.0};
+  auto dpsi = [&](double x) {
+    double s = 0.0;
+    for (double g : gam) s += (g > 0 ? 1.0 : -1.0) * pow(x / (g > 0 ? fhi : flo), g);
+    return 2.0 * M_PI * s;
+  };
+  std::vector<int64_t> idx{0};
+  double prev = floor(dpsi(f[0]) / eps);
+  for (size_t k = 1; k < f.size(); ++k) {
+    const double c = floor(dpsi(f[k]) / eps);
+    if (c != prev) idx.push_back((int64_t)k);
+    prev = c;
+  }
+  if (idx.back() != (int64_t)f.size() - 1) idx.push_back((int64_t)f.size() - 1);
+  return idx;
+}
+
+gwl_status gwl_event_create_rb(const double* data, const double* psd, const gwl_detector* dets, int ndet,
+                               const double* fgrid, int64_t M, double df, double gmst, const double* theta_fid,
+                               double eps, unsigned flags, void* stream, gwl_event* out) {
+  clear_error();
+  if (!out) return fail(GWL_E_INVALID, "out is null");
+  *out = nullptr;
+  if (!theta_fid) return fail(GWL_E_INVALID, "theta_fid must be a host array of 11 values");
+  for (int i = 0; i < NPARAM; ++i)
+    if (!isfinite(theta_fid[i])) return fail(GWL_E_INVALID, "theta_fid[%d] is not finite", i);
+  if (!(eps > 0.0) || !isfinite(eps)) return fail(GWL_E_INVALID, "eps must be finite and positive");
+  gwl_event ev = nullptr;
+  gwl_status st = gwl_event_create(data, psd, dets, ndet, fgrid, M, df, gmst, flags, stream, &ev);
+  if (st != GWL_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  // grid on the host, edges
+  std::vector<double> fh((size_t)M);
+  hipError_t e = hipMemcpyAsync(fh.data(), fgrid, sizeof(double) * M, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    gwl_event_destroy(ev);
+    return hip_fail(e, "grid read-back");
+  }
+  const std::vector<int64_t> idx = rb_edges(fh, eps);
+  const int nedge = (int)idx.size();
+  // fiducial coefficients through the ordinary set-up (no offsets, no gain)
+  double *th = nullptr, *coef = nullptr, *w = nullptr;
+  int64_t* d_idx = nullptr;
+  void *tab64 = nullptr, *tab32 = nullptr;
+  RowGradF32* g32 = nullptr;
+  RowGradF64* g64 = nullptr;
+  std::vector<double> hcoef((size_t)NCOEF * WAVE);
+  const int nd = ev->ndet;
+  e = hipMalloc((void**)&th, sizeof(double) * NPARAM);
+  if (e == hipSuccess) e = hipMalloc((void**)&coef, sizeof(double) * NCOEF * WAVE);
+  if (e == hipSuccess) e = hipMemcpyAsync(th, theta_fid, sizeof(double) * NPARAM, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_setup(nd, ev->geom, nullptr, false, th, 1, WAVE, coef, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(hcoef.data(), coef, sizeof(double) * NCOEF * WAVE, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  bool fid_ok = e == hipSuccess;
+  if (fid_ok) {
+    for (int m = 0; m < NBASIS; ++m) {
+      ev->ech.fa[m] = hcoef[(size_t)(CO_A + m) * WAVE];
+      fid_ok &= isfinite(ev->ech.fa[m]);
+    }
+    for (int d = 0; d < MAXDET; ++d) ev->ech.fT[d] = d < nd ? hcoef[(size_t)(CO_T + d) * WAVE] : 0.0;
+    for (int d = 0; d < nd; ++d) fid_ok &= isfinite(ev->ech.fT[d]);
+  }
+  if (e == hipSuccess && !fid_ok) {
+    (void)hipFree(th);
+    (void)hipFree(coef);
+    gwl_event_destroy(ev);
+    return fail(GWL_E_INVALID, "theta_fid is outside the model's domain");
+  }
+  // edge tables
+  if (e == hipSuccess) e = hipMemcpyAsync(ev->ec, &ev->ech, sizeof(EventConst), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMalloc((void**)&d_idx, sizeof(int64_t) * nedge);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_idx, idx.data(), sizeof(int64_t) * nedge, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMalloc((void**)&w, sizeof(double) * rb_scratch_doubles(nd, nedge));
+  if (e == hipSuccess) e = hipMalloc(&tab64, row64_bytes(nd) * (nedge + TAB_PAD));
+  if (e == hipSuccess) e = hipMalloc(&tab32, row32_bytes(nd) * (nedge + TAB_PAD));
+  if (e == hipSuccess) e = hipMemsetAsync((char*)tab64 + row64_bytes(nd) * nedge, 0, row64_bytes(nd) * TAB_PAD, s);
+  if (e == hipSuccess) e = hipMemsetAsync((char*)tab32 + row32_bytes(nd) * nedge, 0, row32_bytes(nd) * TAB_PAD, s);
+  if (e == hipSuccess) e = hipMalloc((void**)&g32, sizeof(RowGradF32) * nedge);
+  if (e == hipSuccess) e = hipMalloc((void**)&g64, sizeof(RowGradF64) * nedge);
+  if (e == hipSuccess) e = launch_rb(nd, ev->tab64, ev->g32, ev->g64, d_idx, nedge, w, ev->ec, tab64, tab32, g32, g64, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&ev->ech, ev->ec, sizeof(EventConst), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(th);
+  (void)hipFree(coef);
+  if (d_idx) (void)hipFree(d_idx);
+  if (w) (void)hipFree(w);
+  if (e != hipSuccess) {
+    if (tab64) (void)hipFree(tab64);
+    if (tab32) (void)hipFree(tab32);
+    if (g32) (void)hipFree(g32);
+    if (g64) (void)hipFree(g64);
+    gwl_event_destroy(ev);
+    return hip_fail(e, "relative-binning tables");
+  }
+  // the event now walks the edges
+  (void)hipFree(ev->tab64);
+  (void)hipFree(ev->tab32);
+  (void)hipFree(ev->g32);
+  (void)hipFree(ev->g64);
+  ev->tab64 = tab64;
+  ev->tab32 = tab32;
+  ev->g32 = g32;
+  ev->g64 = g64;
+  ev->M_full = ev->M;
+  ev->M = nedge;
+  *out = ev;
+  return GWL_OK;
+}
+
 gwl_status gwl_event_destroy(gwl_event ev) {
   if (!ev) return GWL_OK;
   if (ev->tab64) (void)hipFree(ev->tab64);
@@ -159,6 +277,14 @@ gwl_status gwl_event_destroy(gwl_event ev) {
   if (ev->g64) (void)hipFree(ev->g64);
   if (ev->ec) (void)hipFree(ev->ec);
   delete ev;
+  return GWL_OK;
+}
+
+gwl_status gwl_event_rb_info(gwl_event ev, int64_t* nedge, int64_t* nbins) {
+  clear_error();
+  if (!ev) return fail(GWL_E_INVALID, "event is null");
+  if (nedge) *nedge = ev->M_full ? ev->M : 0;
+  if (nbins) *nbins = ev->M_full ? ev->M_full : ev->M;
   return GWL_OK;
 }
 

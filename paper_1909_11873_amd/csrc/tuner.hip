@@ -141,10 +141,11 @@ __global__ void k_fill_theta(double* theta, int64_t B) {
 namespace gwl {
 
 int heuristic_nchunk(int64_t B, int64_t M) {
-  // aim for ~8 wavefronts per SIMD (1024 SIMDs) with chunks of at least 512 bins
+  // aim for ~8 wavefronts per SIMD (1024 SIMDs) with chunks of at least 64 bins (short
+  // grids, e.g. relative-binning edges, still fill the chip)
   const int64_t npg = (B + WAVE - 1) / WAVE;
   int64_t want = (8192 + npg - 1) / npg;
-  const int64_t maxc = (M + 511) / 512;
+  const int64_t maxc = (M + 63) / 64;
   if (want > maxc) want = maxc;
   if (want < 1) want = 1;
   return (int)want;

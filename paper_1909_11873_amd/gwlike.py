@@ -56,6 +56,9 @@ def lib() -> ctypes.CDLL:
         "gwl_event_create": ([vp, vp, ctypes.POINTER(Detector), cint, vp, i64, dbl, dbl, ctypes.c_uint, vp,
                               ctypes.POINTER(vp)], cint),
         "gwl_event_destroy": ([vp], cint),
+        "gwl_event_create_rb": ([vp, vp, ctypes.POINTER(Detector), cint, vp, i64, dbl, dbl, _c_double_p, dbl,
+                                 ctypes.c_uint, vp, ctypes.POINTER(vp)], cint),
+        "gwl_event_rb_info": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64)], cint),
         "gwl_event_info": ([vp, ctypes.POINTER(cint), ctypes.POINTER(i64), ctypes.POINTER(dbl)], cint),
         "gwl_logl_batch": ([vp, vp, i64, cint, vp, vp], cint),
         "gwl_logl_grad": ([vp, vp, i64, cint, vp, vp, vp], cint),
@@ -121,10 +124,12 @@ class Event:
 
     data  complex128 CUDA tensor [ndet, M];  psd float64 CUDA [ndet, M];  fgrid float64 CUDA [M];
     dets  [ndet] x (lat, lon, xarm_az, yarm_az) radians;  df = 1/T;  gmst in radians.
+    fiducial  optional 11 parameters: relative binning against that waveform, with edges spaced
+              rb_eps radians of the phase bound apart (see gwl_event_create_rb).
     """
 
     def __init__(self, data: torch.Tensor, psd: torch.Tensor, dets: Sequence, fgrid: torch.Tensor, df: float,
-                 gmst: float = 0.0):
+                 gmst: float = 0.0, fiducial=None, rb_eps: float = 0.1):
         data = _dev(data, "data", torch.complex128)
         psd = _dev(psd, "psd", torch.float64)
         fgrid = _dev(fgrid, "fgrid", torch.float64)
@@ -134,10 +139,27 @@ class Event:
         self.ndet, self.M, self.df, self.gmst = nd, int(data.shape[1]), float(df), float(gmst)
         self.device = data.device
         h = ctypes.c_void_p()
-        _check("gwl_event_create", lib().gwl_event_create(
-            ctypes.c_void_p(data.data_ptr()), ctypes.c_void_p(psd.data_ptr()), darr, nd,
-            ctypes.c_void_p(fgrid.data_ptr()), self.M, self.df, self.gmst, 0, _stream(data), ctypes.byref(h)))
+        if fiducial is None:
+            _check("gwl_event_create", lib().gwl_event_create(
+                ctypes.c_void_p(data.data_ptr()), ctypes.c_void_p(psd.data_ptr()), darr, nd,
+                ctypes.c_void_p(fgrid.data_ptr()), self.M, self.df, self.gmst, 0, _stream(data), ctypes.byref(h)))
+        else:
+            fid = [float(x) for x in fiducial]
+            if len(fid) != NPARAM:
+                raise ValueError("fiducial must have 11 parameters")
+            fid = (ctypes.c_double * NPARAM)(*fid)
+            _check("gwl_event_create_rb", lib().gwl_event_create_rb(
+                ctypes.c_void_p(data.data_ptr()), ctypes.c_void_p(psd.data_ptr()), darr, nd,
+                ctypes.c_void_p(fgrid.data_ptr()), self.M, self.df, self.gmst, fid, float(rb_eps), 0, _stream(data),
+                ctypes.byref(h)))
         self._h = h
+        self.rb_edges = self.rb_info()[0]
+
+    def rb_info(self):
+        """(number of relative-binning edges or 0, number of grid bins)."""
+        ne, nb = ctypes.c_int64(), ctypes.c_int64()
+        _check("gwl_event_rb_info", lib().gwl_event_rb_info(self.handle, ctypes.byref(ne), ctypes.byref(nb)))
+        return ne.value, nb.value
 
     @property
     def handle(self) -> ctypes.c_void_p:
