@@ -146,7 +146,7 @@ def cpu_baseline(cfg: int, target_s: float):
         wall = time.perf_counter() - t0
     ref = np.concatenate(parts)
     return {
-        "value": n / wall, "unit": "evals/s", "cores": workers, "kind": "oracle",
+        "value": n / wall, "unit": "evals/s", "cores": workers, "kind": "oracle", "value_1core": 1.0 / per_point,
         "sample": f"first {n} of the {len(theta)} prior draws of the same workload, FP64 torch-CPU oracle, "
                   f"{workers} single-threaded processes, {wall:.1f} s wall",
     }, (theta[:n], ref, data, psd, dets, f, spec.df)

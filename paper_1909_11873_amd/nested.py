@@ -188,29 +188,35 @@ class ParallelNestedSampler:
         return x.clamp(0.0, 1.0), v
 
     def _gmc(self, live_u, live_l):
-        """Galilean Monte Carlo inside the contour L >= L_min, one chain per candidate.
+        """Galilean Monte Carlo inside the contour L >= L_min, one chain per candidate, in the
+        coordinates that whiten the live points (y = L^-1 (u - mean), C = L L^T their covariance;
+        the uniform prior stays uniform under this affine map).
 
-        Each chain starts at a random live point with a random velocity of length
-        gmc_scale x (spread of the live points). A step moves straight ahead; if the new point is
-        below L_min the velocity is reflected off the contour, v -> v - 2 (v.n) n with n the unit
-        gradient of ln L there, and the step is retried from that point; if that also fails the
-        velocity reverses. Chains that never moved are returned outside the cube (rejected), so no
-        live point is duplicated."""
+        Each chain starts at a random live point with a random isotropic velocity of length
+        gmc_scale in y. A step moves straight ahead; if the new point is below L_min the velocity
+        is reflected off the contour, v_y -> v_y - 2 (v_y.n) n with n the unit gradient of ln L in
+        y (in u: v -> v - 2 (v.g) / (g^T C g) C g, g the gradient in u), and the step is retried
+        from that point; if that also fails the velocity reverses. The cube's faces mirror the
+        position. Chains that never moved are returned outside the cube (rejected), so no live
+        point is duplicated."""
         n, d = self.n, self.d
         lmin = live_l[0]
         start = torch.randint(0, self.K, (n,), generator=self.gen, device=self.dev)
         x = live_u[start]
-        spread = live_u.std(0).clamp(min=1e-9)
+        xc = live_u - live_u.mean(0)
+        cov = xc.T @ xc / (self.K - 1) + 1e-14 * torch.eye(d, dtype=torch.float64, device=self.dev)
+        chol, _ = torch.linalg.cholesky_ex(cov)
         z = torch.randn(n, d, generator=self.gen, device=self.dev, dtype=torch.float64)
-        v = self.gmc_scale * spread * z / z.norm(dim=1, keepdim=True)
+        v = self.gmc_scale * (z / z.norm(dim=1, keepdim=True)) @ chol.T
         moved = torch.zeros(n, dtype=torch.bool, device=self.dev)
         acc_moves = torch.zeros((), dtype=torch.float64, device=self.dev)
         for _ in range(self.gmc_steps):
             x1, v1 = self._reflect_cube(x + v, v)
             l1, g1 = self._grad_u(x1)
             ok1 = l1 >= lmin
-            nrm = g1 / g1.norm(dim=1, keepdim=True).clamp(min=1e-300)
-            vr = v1 - 2.0 * (v1 * nrm).sum(1, keepdim=True) * nrm
+            cg = g1 @ cov
+            gcg = (g1 * cg).sum(1, keepdim=True).clamp(min=1e-300)
+            vr = v1 - 2.0 * (v1 * g1).sum(1, keepdim=True) / gcg * cg
             x2, vr = self._reflect_cube(x1 + vr, vr)
             l2, _ = self._loglike(x2)
             ok2 = ~ok1 & (l2 >= lmin)

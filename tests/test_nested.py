@@ -92,6 +92,27 @@ def test_gmc_proposal_on_host():
     assert res.ncall > K + 256 * res.niter     # the walks' own evaluations are counted
 
 
+def test_gmc_correlated_gaussian_on_host():
+    """A normalised, strongly correlated Gaussian (rho = 0.98) inside the cube: ln Z = 0."""
+    s, rho = 0.05, 0.98
+    cov = s * s * torch.tensor([[1.0, rho, 0.0], [rho, 1.0, 0.0], [0.0, 0.0, 1.0]], dtype=torch.float64)
+    prec = torch.linalg.inv(cov)
+    norm = -0.5 * math.log((2 * math.pi) ** 3 * float(torch.linalg.det(cov)))
+
+    def ll(th):
+        x = th - 0.5
+        return norm - 0.5 * ((x @ prec) * x).sum(1)
+
+    lg = lambda th: (ll(th), -((th - 0.5) @ prec))
+    res = nested.ParallelNestedSampler(ll, 3, 300, 128, device="cpu", seed=9, proposal="gmc", loglike_grad=lg,
+                                       gmc_steps=10).run(eps=0.01)
+    assert abs(res.logz) < 4 * res.logz_err + 0.1, (res.logz, res.logz_err)
+    w = np.exp(res.log_w)
+    m = np.sum(w[:, None] * res.u, 0)
+    c = np.einsum("i,ij,ik->jk", w, res.u - m, res.u - m)
+    assert c[0, 1] / math.sqrt(c[0, 0] * c[1, 1]) == pytest.approx(rho, abs=0.02)
+
+
 def test_speedup_law():
     assert nested.speedup_law(1, 2000) == pytest.approx(1.0, rel=3e-4)
     # the values quoted beside the paper's scaling test (K = 2000)
