@@ -120,6 +120,21 @@ gwl_status gwl_event_create_rb(const double* data, const double* psd, const gwl_
                                const double* fgrid, int64_t M, double df, double gmst, const double* theta_fid,
                                double eps, unsigned flags, void* stream, gwl_event* out);
 
+/*
+ * Detector calibration model (paper section 2: amplitude and phase corrections at frequency
+ * nodes, typically ten per detector). Same inputs as gwl_event_create plus nnode (4..16). The
+ * model becomes h_cal,det(f) = h_det(f) (1 + dA_det(f)) exp(i dphi_det(f)), dA and dphi cubic
+ * Catmull-Rom splines in ln f through nnode node values at frequencies spaced uniformly in ln f
+ * from the first to the last grid bin (a linearly extrapolated ghost node beyond each end).
+ * On such an event gwl_logl_batch and gwl_logl_grad take theta [B][11 + 2 nnode ndet]: the 11
+ * signal parameters, then per detector its nnode amplitude values followed by its nnode phase
+ * values (radians); grad has the same shape. <h|h> stays exact (per-event spline moments).
+ * Not usable in multi-event plans (GWL_E_UNSUPPORTED).
+ */
+gwl_status gwl_event_create_cal(const double* data, const double* psd, const gwl_detector* dets, int ndet,
+                                const double* fgrid, int64_t M, double df, double gmst, int nnode, unsigned flags,
+                                void* stream, gwl_event* out);
+
 /* Relative-binning sizes: number of edges (0 for an ordinary event) and of grid bins. */
 gwl_status gwl_event_rb_info(gwl_event ev, int64_t* nedge, int64_t* nbins);
 

@@ -86,4 +86,27 @@ constexpr int NCOEF = CO_CI + MAXDET;
 //                                                                         -> 3 ND + 8
 __host__ __device__ constexpr int nz_of(int nd, bool grad) { return grad ? 3 * nd + NBASIS : 2 * nd; }
 
+// Detector calibration model: per detector, nnode amplitude and nnode phase node values
+// interpolated in ln f by a cubic spline whose value at a bin depends on the four nodes around
+// it. The weights of those four nodes are per-bin constants; the window of four nodes is fixed
+// over a node interval, and the bin loop's chunks never cross an interval.
+constexpr int MAXNODE = 16;
+struct RowCal32 {
+  float w[4];
+};
+struct RowCal64 {
+  double w[4];
+};
+struct CalShape {
+  int nnode;              // nodes per detector
+  int nint;               // node intervals = nnode - 1
+  int pieces;             // chunks per interval
+  int npg, nbpg, items, gper;
+  int j0[MAXNODE];        // first node of each interval's window of four
+  int64_t kb[MAXNODE];    // first bin of each interval; kb[nint] = M
+};
+// Calibrated sums: Z_det (2 ND); adjoint: + the uncalibrated model's moments (ND + 8) + per
+// detector the window moments of the amplitude (4) and phase (4) nodes
+__host__ __device__ constexpr int nz_cal(int nd, bool grad) { return grad ? 11 * nd + NBASIS : 2 * nd; }
+
 }  // namespace gwl

@@ -53,6 +53,13 @@ hipError_t launch_rb(int nd, const void* fine64, const RowGradF32* fine32g, cons
                      const int64_t* eidx, int nedge, double* w, EventConst* ec, void* tab64, void* tab32,
                      RowGradF32* g32, RowGradF64* g64, hipStream_t s);
 
+// calibrated model: set-up, bin loop and epilogue for theta[B][P], P = 11 + 2 nnode nd;
+// kcal per detector K1 [nnode], K2 [nnode][nnode]; calc is scratch [2 nnode nd][Bp]
+hipError_t launch_cal(int nd, bool mixed, bool grad, const EventGeom& g, const EventConst* ec, const double* kcal,
+                      const void* tab, const void* gtab, const void* calw, const double* theta, int P, int64_t B,
+                      int64_t Bp, const CalShape& sh, double* coef, double* calc, double* part, double* logl,
+                      double* gradout, hipStream_t s);
+
 // model strain on a grid: out[B][nd][M][2]
 hipError_t launch_waveform(int nd, const EventGeom& g, const double* coef, int64_t B, int64_t Bp,
                            const double* fgrid, int64_t M, double* out, hipStream_t s);

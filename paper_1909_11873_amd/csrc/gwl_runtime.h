@@ -12,6 +12,13 @@ struct gwl_event_s {
   int ndet = 0;
   int64_t M = 0;                     // rows the bin loop walks (bins, or edges for relative binning)
   int64_t M_full = 0;                // bins of the grid (relative binning), else 0
+  // calibration model (ncal nodes per detector, 0 = none)
+  int ncal = 0;
+  gwl::RowCal32* cal32 = nullptr;    // [M] window weights
+  gwl::RowCal64* cal64 = nullptr;
+  double* kcal = nullptr;            // per detector: K1 [ncal], K2 [ncal][ncal]
+  int cal_j0[gwl::MAXNODE] = {};
+  int64_t cal_kb[gwl::MAXNODE] = {};
   double df = 0.0;
   double gmst = 0.0;
   gwl_detector dets[GWL_MAX_DET] = {};

@@ -1,0 +1,323 @@
+// Detector calibration model (paper section 2, "Models and parameter spaces": amplitude and
+// phase corrections at frequency nodes, ten per detector): the calibrated model is
+//   h_cal,det(f) = h_det(f) (1 + dA_det(f)) exp(i dphi_det(f)),
+// dA and dphi cubic Catmull-Rom splines in ln f through the node values (theta columns
+// 11 + 2 n det .. : n amplitude values, then n phase values in radians).
+//
+// The bin loop is the ordinary one with one more complex factor per (point, detector, bin):
+// the spline value is a four-term dot product of per-bin weights (RowCal, wave-uniform) with the
+// point's four window node values (VGPRs, fixed over a node interval, so chunks never cross an
+// interval). <h_cal|h_cal> needs no per-bin work: with K_k = 4 df f_k^-7/3 / S_k,
+//   sum_k K_k (1 + dA_k)^2 = K + 2 alpha.K1 + alpha.K2.alpha,
+// K1_j = sum_k K_k w_kj and K2_jl = sum_k K_k w_kj w_kl computed once per event (alpha the
+// amplitude node values, w_kj the spline weight of node j at bin k).
+//
+// Adjoint: besides the uncalibrated moments (with w = u p replaced by the calibrated product),
+// per detector and window node i the sums sum_k w_ki Re(c q_k) (amplitude) and
+// sum_k w_ki Im(c w_cal,k) (phase), q = u p exp(i dphi), w_cal = (1 + dA) q.
+#include <hip/hip_runtime.h>
+
+#include "gwl_bins.h"
+#include "gwl_common.h"
+#include "gwl_device.h"
+#include "gwl_epilogue.h"
+#include "gwl_launch.h"
+
+namespace gwl {
+
+constexpr int CAL_PT_BLOCK = 128;
+
+template <int ND>
+__global__ __launch_bounds__(CAL_PT_BLOCK) void k_setup_cal(EventGeom g, const EventConst* __restrict__ ec, bool scaled,
+                                                            const double* __restrict__ theta, int P, int ncal,
+                                                            int64_t B, int64_t Bp, double* __restrict__ coef,
+                                                            double* __restrict__ calc) {
+  const int64_t p = (int64_t)blockIdx.x * CAL_PT_BLOCK + threadIdx.x;
+  if (p >= Bp) return;
+  const int64_t pc = p < B ? p : B - 1;
+  double th[NPARAM];
+#pragma unroll
+  for (int i = 0; i < NPARAM; ++i) th[i] = theta[pc * P + i];
+  double rows[NCOEF];
+  bool valid = setup_rows<ND>(th, g, ec, scaled, rows);
+  for (int j = 0; j < ncal; ++j) {
+    const double v = theta[pc * P + NPARAM + j];
+    valid &= isfinite(v);
+    calc[(int64_t)j * Bp + p] = v;
+  }
+  const double nan = __builtin_nan("");
+#pragma unroll
+  for (int j = 0; j < NCOEF; ++j) coef[j * Bp + p] = valid ? rows[j] : nan;
+}
+
+// One bin of the calibrated loop. T_ is float (mixed: hardware phasors, float32 products) or
+// double (float64: table phasor).
+template <int ND, bool GRAD, class T_, class Row, class CalRow, class GradP>
+__device__ __forceinline__ void cal_bin(const Row r, const CalRow cw, GradP gt, int k, const double (&a)[NBASIS],
+                                        const double (&T)[ND], const T_ (&cr)[ND], const T_ (&ci)[ND],
+                                        const T_ (&ca)[ND][4], const T_ (&cp)[ND][4], const double2* tbl,
+                                        T_ (&z)[nz_cal(ND, GRAD)]) {
+  constexpr bool MIXED = sizeof(T_) == 4;
+  constexpr int MA = 3 * ND + NBASIS, MB = MA + 4 * ND;
+  const double psi = phase_poly(a, r.x, r.w, r.w2, r.lnf);
+  T_ y = 0, fk = 0;
+  T_ gm[NBASIS];
+  if constexpr (GRAD) {
+    if constexpr (MIXED) {
+      const RowGradF32 g = load_grad_f32(gt, k);
+#pragma unroll
+      for (int m = 0; m < NBASIS; ++m) gm[m] = g.g[m];
+      fk = g.f;
+    } else {
+      const RowGradF64 g = load_grad_f64(gt, k);
+      gm[0] = r.w; gm[1] = r.w2; gm[2] = g.g2; gm[3] = g.g3; gm[4] = r.lnf; gm[5] = r.x; gm[6] = g.g6; gm[7] = g.g7;
+      fk = r.f;
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    T_ da = cw.w[0] * ca[d][0], dp = cw.w[0] * cp[d][0];
+#pragma unroll
+    for (int i = 1; i < 4; ++i) {
+      da = fma(cw.w[i], ca[d][i], da);
+      dp = fma(cw.w[i], cp[d][i], dp);
+    }
+    // q = u p exp(i dphi) = u exp(-2 pi i (phi - dphi / 2 pi)): the calibration phase joins the
+    // model phase before the reduction, so one phasor (with its gain correction) serves both
+    const double ph = fma((double)dp, -0.15915494309189535, fma(r.f, T[d], psi));
+    T_ cs, sn;
+    if constexpr (MIXED) {
+      const float rr = (float)__builtin_amdgcn_fract(ph);
+      cs = __builtin_amdgcn_cosf(rr);
+      sn = __builtin_amdgcn_sinf(rr);
+    } else {
+      sincos_cycles_tbl(ph, tbl, sn, cs);
+    }
+    const T_ ur = r.u[2 * d], ui = r.u[2 * d + 1];
+    const T_ qr = fma(ur, cs, ui * sn);
+    const T_ qi = fma(ui, cs, -(ur * sn));
+    const T_ g1 = (T_)1 + da;
+    const T_ vr = g1 * qr, vi = g1 * qi;            // calibrated product
+    z[2 * d] += vr;
+    z[2 * d + 1] += vi;
+    if constexpr (GRAD) {
+      const T_ yd = fma(cr[d], vi, ci[d] * vr);     // Im(c w_cal)
+      const T_ ya = fma(cr[d], qr, -(ci[d] * qi));  // Re(c q)
+      z[2 * ND + d] = fma(fk, yd, z[2 * ND + d]);
+      y = d == 0 ? yd : y + yd;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        z[MA + 4 * d + i] = fma(cw.w[i], ya, z[MA + 4 * d + i]);
+        z[MB + 4 * d + i] = fma(cw.w[i], yd, z[MB + 4 * d + i]);
+      }
+    }
+  }
+  if constexpr (GRAD) {
+#pragma unroll
+    for (int m = 0; m < NBASIS; ++m) z[3 * ND + m] = fma(gm[m], y, z[3 * ND + m]);
+  }
+}
+
+// Workgroup -> (chunk, point group) as in the plain loop; a chunk is a piece of one interval.
+__device__ __forceinline__ bool locate_cal(const CalShape& sh, int& c, int& j, int64_t& k0, int64_t& k1, int& pg) {
+  const int bid = blockIdx.x;
+  const int item = (bid % NXCD) * sh.gper + bid / NXCD;
+  if (item >= sh.items) return false;
+  c = item / sh.nbpg;
+  pg = (item - c * sh.nbpg) * WAVES_PER_BLOCK + (int)(threadIdx.x / WAVE);
+  if (pg >= sh.npg) return false;
+  j = c / sh.pieces;
+  const int q = c - j * sh.pieces;
+  const int64_t a = sh.kb[j], len = sh.kb[j + 1] - a;
+  k0 = a + len * q / sh.pieces;
+  k1 = a + len * (q + 1) / sh.pieces;
+  return true;
+}
+
+template <int ND, bool MIXED, bool GRAD>
+__global__ __launch_bounds__(BLOCK) void k_bins_cal(const void* __restrict__ tabv, const void* __restrict__ gtabv,
+                                                    const void* __restrict__ calwv, const double* __restrict__ coef,
+                                                    const double* __restrict__ calc, int64_t B, int64_t Bp,
+                                                    CalShape sh, double* __restrict__ part) {
+  typedef typename std::conditional<MIXED, float, double>::type T_;
+  constexpr int NZ = nz_cal(ND, GRAD);
+  __shared__ double2 tbl[PH_TBL];
+  if constexpr (!MIXED) {
+    fill_phasor_table(tbl);
+    __syncthreads();
+  }
+  int c, j, pg;
+  int64_t k0, k1;
+  if (!locate_cal(sh, c, j, k0, k1, pg)) return;
+  const int64_t p = (int64_t)pg * WAVE + (threadIdx.x % WAVE);
+  const int64_t pc = p < B ? p : B - 1;
+  double a[NBASIS], T[ND];
+  T_ cr[ND], ci[ND];
+  load_coef<ND, T_>(coef, Bp, pc, GRAD, a, T, cr, ci);
+  T_ ca[ND][4], cp[ND][4];
+  const int n = sh.nnode, j0 = sh.j0[j];
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      ca[d][i] = (T_)calc[(int64_t)(2 * n * d + j0 + i) * Bp + pc];
+      cp[d][i] = (T_)calc[(int64_t)(2 * n * d + n + j0 + i) * Bp + pc];
+    }
+  }
+  double tot[NZ];
+#pragma unroll
+  for (int zz = 0; zz < NZ; ++zz) tot[zz] = 0.0;
+  if constexpr (MIXED) {
+    const RowMixed<ND>* tab = (const RowMixed<ND>*)tabv;
+    const RowGradF32* gt = (const RowGradF32*)gtabv;
+    const RowCal32* cw = (const RowCal32*)calwv;
+    for (int64_t kb = k0; kb < k1; kb += NB) {
+      const int64_t ke = kb + NB < k1 ? kb + NB : k1;
+      float z[NZ];
+#pragma unroll
+      for (int zz = 0; zz < NZ; ++zz) z[zz] = 0.0f;
+      for (int64_t k = kb; k < ke; ++k)
+        cal_bin<ND, GRAD, float>(load_row_mixed<ND>(tab, (int)k), cw[k], gt, (int)k, a, T, cr, ci, ca, cp, tbl, z);
+#pragma unroll
+      for (int zz = 0; zz < NZ; ++zz) tot[zz] += (double)z[zz];
+    }
+  } else {
+    const RowF64<ND>* tab = (const RowF64<ND>*)tabv;
+    const RowGradF64* gt = (const RowGradF64*)gtabv;
+    const RowCal64* cw = (const RowCal64*)calwv;
+    for (int64_t k = k0; k < k1; ++k)
+      cal_bin<ND, GRAD, double>(load_row_f64<ND>(tab, (int)k), cw[k], gt, (int)k, a, T, cr, ci, ca, cp, tbl, tot);
+  }
+#pragma unroll
+  for (int zz = 0; zz < NZ; ++zz) part[((int64_t)c * NZ + zz) * Bp + p] = tot[zz];
+}
+
+// Epilogue: gather the chunks (window moments to their nodes), then value and gradient.
+template <int ND, bool GRAD>
+__global__ __launch_bounds__(CAL_PT_BLOCK) void k_epilogue_cal(EventGeom g, const EventConst* __restrict__ ec,
+                                                               const double* __restrict__ kcal, const double* __restrict__ theta,
+                                                               int P, int64_t B, int64_t Bp, CalShape sh, bool scaled,
+                                                               const double* __restrict__ part, double* __restrict__ logl,
+                                                               double* __restrict__ grad) {
+  const int64_t p = (int64_t)blockIdx.x * CAL_PT_BLOCK + threadIdx.x;
+  if (p >= B) return;
+  constexpr int NZ = nz_cal(ND, GRAD), NZU = nz_of(ND, GRAD);
+  constexpr int MA = 3 * ND + NBASIS, MB = MA + 4 * ND;
+  const int n = sh.nnode, nchunk = sh.nint * sh.pieces;
+  const EventConst e = *ec;
+  double acc[NZU];
+#pragma unroll
+  for (int zz = 0; zz < NZU; ++zz) acc[zz] = 0.0;
+  double mA[ND][MAXNODE], mB[ND][MAXNODE];
+#pragma unroll
+  for (int d = 0; d < ND; ++d)
+    for (int i = 0; i < MAXNODE; ++i) mA[d][i] = mB[d][i] = 0.0;
+  for (int c = 0; c < nchunk; ++c) {
+#pragma unroll
+    for (int zz = 0; zz < NZU; ++zz) acc[zz] += part[((int64_t)c * NZ + zz) * Bp + p];
+    if constexpr (GRAD) {
+      const int j0 = sh.j0[c / sh.pieces];
+#pragma unroll
+      for (int d = 0; d < ND; ++d)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          mA[d][j0 + i] += part[((int64_t)c * NZ + MA + 4 * d + i) * Bp + p];
+          mB[d][j0 + i] += part[((int64_t)c * NZ + MB + 4 * d + i) * Bp + p];
+        }
+    }
+  }
+  if (scaled) apply_gain<ND>(e, acc);
+  const double uref = scaled ? e.uref : 1.0;
+  double th[NPARAM];
+#pragma unroll
+  for (int i = 0; i < NPARAM; ++i) th[i] = theta[p * P + i];
+  // per detector: effective K = K + 2 alpha.K1 + alpha.K2.alpha, and its gradient 2 (K1 + K2 alpha)
+  EventConst ek = e;
+  double dk[ND][MAXNODE];
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    const double* al = theta + p * P + NPARAM + 2 * n * d;
+    const double* K1 = kcal + (int64_t)d * (n + n * n);
+    const double* K2 = K1 + n;
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) {
+      double r = K1[i];
+      for (int l = 0; l < n; ++l) r += K2[i * n + l] * al[l];
+      dk[d][i] = 2.0 * r;
+      s += al[i] * (2.0 * K1[i] + (r - K1[i]));
+    }
+    ek.K[d] = e.K[d] + s;
+  }
+  bool valid;
+  const double nan = __builtin_nan("");
+  if constexpr (!GRAD) {
+    const double v = epilogue_value<ND, NZU>(acc, th, g, ek, uref, valid);
+    logl[p] = valid ? v : nan;
+  } else {
+    double gout[NPARAM];
+    const double v = epilogue_gradient<ND>(acc, th, g, ek, uref, valid, gout);
+    logl[p] = valid ? v : nan;
+#pragma unroll
+    for (int i = 0; i < NPARAM; ++i) grad[p * P + i] = valid ? gout[i] : nan;
+    // calibration node gradients
+    PointModel<double> pm;
+    point_model<double, ND>(th, g, pm);
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      const double hh = pm.amp * pm.amp * (pm.qr[d] * pm.qr[d] + pm.qi[d] * pm.qi[d]);
+      for (int i = 0; i < n; ++i) {
+        const double ga = uref * pm.amp * mA[d][i] - 0.5 * hh * dk[d][i];
+        const double gp = -uref * pm.amp * mB[d][i];
+        grad[p * P + NPARAM + 2 * n * d + i] = valid ? ga : nan;
+        grad[p * P + NPARAM + 2 * n * d + n + i] = valid ? gp : nan;
+      }
+    }
+  }
+}
+
+template <int ND>
+static hipError_t cal_nd(bool mixed, bool grad, const EventGeom& g, const EventConst* ec, const double* kcal,
+                         const void* tab, const void* gtab, const void* calw, const double* theta, int P, int64_t B,
+                         int64_t Bp, const CalShape& sh, double* coef, double* calc, double* part, double* logl,
+                         double* gradout, hipStream_t s) {
+  const int ncal = 2 * sh.nnode * ND;
+  hipLaunchKernelGGL(k_setup_cal<ND>, dim3((unsigned)((Bp + CAL_PT_BLOCK - 1) / CAL_PT_BLOCK)), dim3(CAL_PT_BLOCK), 0,
+                     s, g, ec, mixed, theta, P, ncal, B, Bp, coef, calc);
+  const dim3 grid((unsigned)(sh.gper * NXCD)), block(BLOCK);
+#define GWL_CB(MX, GR) \
+  hipLaunchKernelGGL((k_bins_cal<ND, MX, GR>), grid, block, 0, s, tab, gtab, calw, (const double*)coef, \
+                     (const double*)calc, B, Bp, sh, part)
+  if (mixed) {
+    if (grad) GWL_CB(true, true); else GWL_CB(true, false);
+  } else {
+    if (grad) GWL_CB(false, true); else GWL_CB(false, false);
+  }
+#undef GWL_CB
+  const dim3 egrid((unsigned)((B + CAL_PT_BLOCK - 1) / CAL_PT_BLOCK));
+  if (grad)
+    hipLaunchKernelGGL((k_epilogue_cal<ND, true>), egrid, dim3(CAL_PT_BLOCK), 0, s, g, ec, kcal, theta, P, B, Bp, sh,
+                       mixed, (const double*)part, logl, gradout);
+  else
+    hipLaunchKernelGGL((k_epilogue_cal<ND, false>), egrid, dim3(CAL_PT_BLOCK), 0, s, g, ec, kcal, theta, P, B, Bp, sh,
+                       mixed, (const double*)part, logl, gradout);
+  return hipGetLastError();
+}
+
+hipError_t launch_cal(int nd, bool mixed, bool grad, const EventGeom& g, const EventConst* ec, const double* kcal,
+                      const void* tab, const void* gtab, const void* calw, const double* theta, int P, int64_t B,
+                      int64_t Bp, const CalShape& sh, double* coef, double* calc, double* part, double* logl,
+                      double* gradout, hipStream_t s) {
+  switch (nd) {
+#define GWL_CN(N)                                                                                                      \
+  case N:                                                                                                              \
+    return cal_nd<N>(mixed, grad, g, ec, kcal, tab, gtab, calw, theta, P, B, Bp, sh, coef, calc, part, logl, gradout, s);
+    GWL_CN(1)
+    GWL_CN(2)
+    GWL_CN(3)
+    GWL_CN(4)
+#undef GWL_CN
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace gwl

@@ -315,6 +315,7 @@ gwl_status build_plan(const gwl_event* evs, int E, const int64_t* B_e, gwl_preci
   for (int e = 0; e < E; ++e) {
     if (!evs[e]) return fail(GWL_E_INVALID, "event %d is null", e);
     if (evs[e]->ndet != nd) return fail(GWL_E_UNSUPPORTED, "events must share one detector count");
+    if (evs[e]->ncal > 0) return fail(GWL_E_UNSUPPORTED, "event %d has a calibration model: not in multi-event plans", e);
     if (evs[e]->device != evs[0]->device) return fail(GWL_E_INVALID, "events must live on one device");
     if (B_e[e] < 0 || B_e[e] > kMaxBatch) return fail(GWL_E_SHAPE, "B_e[%d]=%lld out of range", e, (long long)B_e[e]);
   }

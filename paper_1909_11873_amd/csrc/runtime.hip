@@ -7,6 +7,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <string>
 #include <utility>
@@ -269,8 +270,102 @@ gwl_status gwl_event_create_rb(const double* data, const double* psd, const gwl_
   return GWL_OK;
 }
 
+// Calibration spline tables (host, float64): per bin the Catmull-Rom weights of the four nodes
+// around it in ln f, with the linearly extrapolated ghost node beyond either end folded into
+// the real end nodes, expressed over the interval's window of four real nodes; the interval
+// starts; and per detector K1_j = sum_k K_k w_kj, K2_jl = sum_k K_k w_kj w_kl, K_k = 4 df
+// f_k^-7/3 / S_k.
+static void cal_tables(const std::vector<double>& f, const std::vector<double>& psd, int nd, double df, int n,
+                       std::vector<double>& w, int* j0, int64_t* kb, std::vector<double>& kcal) {
+  const int64_t M = (int64_t)f.size();
+  const double x0 = log(f.front()), x1 = log(f.back());
+  const double h = n > 1 ? (x1 - x0) / (n - 1) : 1.0;
+  w.assign((size_t)M * 4, 0.0);
+  std::vector<double> W((size_t)M * n, 0.0);  // weights over all nodes (for K1, K2)
+  std::vector<int> jk((size_t)M);
+  for (int j = 0; j < n - 1; ++j) j0[j] = std::min(std::max(j - 1, 0), n - 4);
+  for (int64_t k = 0; k < M; ++k) {
+    double s = (log(f[k]) - x0) / h;
+    s = std::min(std::max(s, 0.0), (double)(n - 1));
+    const int j = std::min(std::max((int)floor(s), 0), n - 2);
+    const double t = s - j;
+    double cw[4] = {0.5 * (-t + 2 * t * t - t * t * t), 0.5 * (2 - 5 * t * t + 3 * t * t * t),
+                    0.5 * (t + 4 * t * t - 3 * t * t * t), 0.5 * (-t * t + t * t * t)};  // nodes j-1 .. j+2
+    double wn[MAXNODE + 2] = {};  // over nodes -1 .. n
+    for (int i = 0; i < 4; ++i) wn[j - 1 + i + 1] += cw[i];
+    wn[1] += 2.0 * wn[0];          // ghost -1 = 2 v0 - v1
+    wn[2] -= wn[0];
+    wn[n] += 2.0 * wn[n + 1];      // ghost n = 2 v_{n-1} - v_{n-2}
+    wn[n - 1] -= wn[n + 1];
+    for (int i = 0; i < 4; ++i) w[(size_t)k * 4 + i] = wn[j0[j] + i + 1];
+    for (int i = 0; i < n; ++i) W[(size_t)k * n + i] = wn[i + 1];
+    jk[(size_t)k] = j;
+  }
+  for (int j = 0; j <= n - 1; ++j) kb[j] = M;
+  for (int64_t k = M - 1; k >= 0; --k) kb[jk[(size_t)k]] = k;
+  kb[0] = 0;
+  for (int j = n - 2; j >= 1; --j) kb[j] = std::min(kb[j], kb[j + 1]);  // empty intervals start where the next does
+  kb[n - 1] = M;
+  kcal.assign((size_t)nd * (n + n * n), 0.0);
+  for (int d = 0; d < nd; ++d) {
+    double* K1 = kcal.data() + (size_t)d * (n + n * n);
+    double* K2 = K1 + n;
+    for (int64_t k = 0; k < M; ++k) {
+      const double Kk = 4.0 * df * pow(f[k], -7.0 / 3.0) / psd[(size_t)d * M + k];
+      const double* Wk = W.data() + (size_t)k * n;
+      for (int i = 0; i < n; ++i) {
+        if (Wk[i] == 0.0) continue;
+        K1[i] += Kk * Wk[i];
+        for (int l = 0; l < n; ++l) K2[i * n + l] += Kk * Wk[i] * Wk[l];
+      }
+    }
+  }
+}
+
+gwl_status gwl_event_create_cal(const double* data, const double* psd, const gwl_detector* dets, int ndet,
+                                const double* fgrid, int64_t M, double df, double gmst, int nnode, unsigned flags,
+                                void* stream, gwl_event* out) {
+  clear_error();
+  if (!out) return fail(GWL_E_INVALID, "out is null");
+  *out = nullptr;
+  if (nnode < 4 || nnode > MAXNODE) return fail(GWL_E_SHAPE, "nnode=%d outside [4, %d]", nnode, MAXNODE);
+  gwl_event ev = nullptr;
+  gwl_status st = gwl_event_create(data, psd, dets, ndet, fgrid, M, df, gmst, flags, stream, &ev);
+  if (st != GWL_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<double> fh((size_t)M), ph((size_t)M * ndet);
+  hipError_t e = hipMemcpyAsync(fh.data(), fgrid, sizeof(double) * M, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(ph.data(), psd, sizeof(double) * M * ndet, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    gwl_event_destroy(ev);
+    return hip_fail(e, "grid read-back");
+  }
+  std::vector<double> w, kc;
+  cal_tables(fh, ph, ndet, df, nnode, w, ev->cal_j0, ev->cal_kb, kc);
+  std::vector<RowCal32> w32((size_t)M);
+  for (int64_t k = 0; k < M; ++k)
+    for (int i = 0; i < 4; ++i) w32[(size_t)k].w[i] = (float)w[(size_t)k * 4 + i];
+  e = hipMalloc((void**)&ev->cal32, sizeof(RowCal32) * M);
+  if (e == hipSuccess) e = hipMalloc((void**)&ev->cal64, sizeof(RowCal64) * M);
+  if (e == hipSuccess) e = hipMalloc((void**)&ev->kcal, sizeof(double) * kc.size());
+  if (e == hipSuccess) e = hipMemcpy(ev->cal32, w32.data(), sizeof(RowCal32) * M, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ev->cal64, w.data(), sizeof(RowCal64) * M, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ev->kcal, kc.data(), sizeof(double) * kc.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    gwl_event_destroy(ev);
+    return hip_fail(e, "calibration tables");
+  }
+  ev->ncal = nnode;
+  *out = ev;
+  return GWL_OK;
+}
+
 gwl_status gwl_event_destroy(gwl_event ev) {
   if (!ev) return GWL_OK;
+  if (ev->cal32) (void)hipFree(ev->cal32);
+  if (ev->cal64) (void)hipFree(ev->cal64);
+  if (ev->kcal) (void)hipFree(ev->kcal);
   if (ev->tab64) (void)hipFree(ev->tab64);
   if (ev->tab32) (void)hipFree(ev->tab32);
   if (ev->g32) (void)hipFree(ev->g32);
@@ -297,6 +392,40 @@ gwl_status gwl_event_info(gwl_event ev, int* ndet, int64_t* M, double* df) {
   return GWL_OK;
 }
 
+// Calibrated evaluation: chunks are pieces of node intervals; workspace from the stream pool.
+static gwl_status run_logl_cal(gwl_event ev, const double* theta, int64_t B, bool mixed, bool grad, double* logl,
+                               double* gradout, hipStream_t s) {
+  const int nd = ev->ndet, n = ev->ncal;
+  CalShape sh;
+  memset(&sh, 0, sizeof sh);
+  sh.nnode = n;
+  sh.nint = n - 1;
+  sh.npg = (int)((B + WAVE - 1) / WAVE);
+  const int want = heuristic_nchunk(B, ev->M);
+  sh.pieces = std::max(1, (want + sh.nint - 1) / sh.nint);
+  sh.nbpg = (sh.npg + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+  sh.items = sh.nint * sh.pieces * sh.nbpg;
+  sh.gper = (sh.items + NXCD - 1) / NXCD;
+  for (int j = 0; j < n - 1; ++j) sh.j0[j] = ev->cal_j0[j];
+  for (int j = 0; j < n; ++j) sh.kb[j] = ev->cal_kb[j];
+  const int64_t Bp = (int64_t)sh.npg * WAVE;
+  const int nchunk = sh.nint * sh.pieces, ncal = 2 * n * nd;
+  const size_t bytes = sizeof(double) * ((size_t)NCOEF * Bp + (size_t)ncal * Bp + (size_t)nchunk * nz_cal(nd, grad) * Bp);
+  void* ws = nullptr;
+  hipError_t e = hipMallocAsync(&ws, bytes, s);
+  if (e != hipSuccess) return hip_fail(e, "workspace");
+  double* coef = (double*)ws;
+  double* calc = coef + (size_t)NCOEF * Bp;
+  double* part = calc + (size_t)ncal * Bp;
+  e = launch_cal(nd, mixed, grad, ev->geom, ev->ec, ev->kcal, mixed ? ev->tab32 : ev->tab64,
+                 mixed ? (const void*)ev->g32 : (const void*)ev->g64, mixed ? (const void*)ev->cal32 : (const void*)ev->cal64,
+                 theta, NPARAM + ncal, B, Bp, sh, coef, calc, part, logl, gradout, s);
+  hipError_t e2 = hipFreeAsync(ws, s);
+  if (e != hipSuccess) return hip_fail(e, "launch");
+  if (e2 != hipSuccess) return hip_fail(e2, "workspace release");
+  return GWL_OK;
+}
+
 static gwl_status logl_common(gwl_event ev, const double* theta, int64_t B, gwl_precision prec, double* logl,
                               double* grad, bool with_grad, void* stream) {
   clear_error();
@@ -309,6 +438,7 @@ static gwl_status logl_common(gwl_event ev, const double* theta, int64_t B, gwl_
   gwl_status st = check_device(ev->device);
   if (st != GWL_OK) return st;
   const bool mixed = prec == GWL_MIXED;
+  if (ev->ncal > 0) return run_logl_cal(ev, theta, B, mixed, with_grad, logl, grad, (hipStream_t)stream);
   const LoopShape sh = make_shape(B, ev->M, choose_nchunk(ev, B, mixed, with_grad));
   return run_logl(ev, theta, B, mixed, with_grad, sh, logl, grad, (hipStream_t)stream);
 }

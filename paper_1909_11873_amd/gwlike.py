@@ -59,6 +59,8 @@ def lib() -> ctypes.CDLL:
         "gwl_event_create_rb": ([vp, vp, ctypes.POINTER(Detector), cint, vp, i64, dbl, dbl, _c_double_p, dbl,
                                  ctypes.c_uint, vp, ctypes.POINTER(vp)], cint),
         "gwl_event_rb_info": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64)], cint),
+        "gwl_event_create_cal": ([vp, vp, ctypes.POINTER(Detector), cint, vp, i64, dbl, dbl, cint, ctypes.c_uint, vp,
+                                  ctypes.POINTER(vp)], cint),
         "gwl_event_info": ([vp, ctypes.POINTER(cint), ctypes.POINTER(i64), ctypes.POINTER(dbl)], cint),
         "gwl_logl_batch": ([vp, vp, i64, cint, vp, vp], cint),
         "gwl_logl_grad": ([vp, vp, i64, cint, vp, vp, vp], cint),
@@ -126,10 +128,12 @@ class Event:
     dets  [ndet] x (lat, lon, xarm_az, yarm_az) radians;  df = 1/T;  gmst in radians.
     fiducial  optional 11 parameters: relative binning against that waveform, with edges spaced
               rb_eps radians of the phase bound apart (see gwl_event_create_rb).
+    calibration_nodes  optional n >= 4: a calibration model per detector (see gwl_event_create_cal);
+              theta then has 11 + 2 n ndet columns.
     """
 
     def __init__(self, data: torch.Tensor, psd: torch.Tensor, dets: Sequence, fgrid: torch.Tensor, df: float,
-                 gmst: float = 0.0, fiducial=None, rb_eps: float = 0.1):
+                 gmst: float = 0.0, fiducial=None, rb_eps: float = 0.1, calibration_nodes: int = 0):
         data = _dev(data, "data", torch.complex128)
         psd = _dev(psd, "psd", torch.float64)
         fgrid = _dev(fgrid, "fgrid", torch.float64)
@@ -139,7 +143,15 @@ class Event:
         self.ndet, self.M, self.df, self.gmst = nd, int(data.shape[1]), float(df), float(gmst)
         self.device = data.device
         h = ctypes.c_void_p()
-        if fiducial is None:
+        self.ncal = int(calibration_nodes)
+        if self.ncal and fiducial is not None:
+            raise ValueError("relative binning and the calibration model cannot be combined")
+        if self.ncal:
+            _check("gwl_event_create_cal", lib().gwl_event_create_cal(
+                ctypes.c_void_p(data.data_ptr()), ctypes.c_void_p(psd.data_ptr()), darr, nd,
+                ctypes.c_void_p(fgrid.data_ptr()), self.M, self.df, self.gmst, self.ncal, 0, _stream(data),
+                ctypes.byref(h)))
+        elif fiducial is None:
             _check("gwl_event_create", lib().gwl_event_create(
                 ctypes.c_void_p(data.data_ptr()), ctypes.c_void_p(psd.data_ptr()), darr, nd,
                 ctypes.c_void_p(fgrid.data_ptr()), self.M, self.df, self.gmst, 0, _stream(data), ctypes.byref(h)))
@@ -179,16 +191,17 @@ class Event:
             pass
 
 
-def _theta(theta: torch.Tensor) -> torch.Tensor:
+def _theta(theta: torch.Tensor, ev: Optional["Event"] = None) -> torch.Tensor:
     theta = _dev(theta, "theta", torch.float64)
-    if theta.dim() != 2 or theta.shape[1] != NPARAM:
-        raise ValueError("theta must be [B, 11]")
+    width = NPARAM + (2 * ev.ncal * ev.ndet if ev is not None else 0)
+    if theta.dim() != 2 or theta.shape[1] != width:
+        raise ValueError(f"theta must be [B, {width}]")
     return theta
 
 
 def logl(theta: torch.Tensor, ev: Event, precision="mixed") -> torch.Tensor:
-    """logL[B] for theta[B, 11] (float64 CUDA)."""
-    theta = _theta(theta)
+    """logL[B] for theta[B, 11] (float64 CUDA; 11 + 2 n ndet columns on a calibrated event)."""
+    theta = _theta(theta, ev)
     out = torch.empty(theta.shape[0], dtype=torch.float64, device=theta.device)
     _check("gwl_logl_batch", lib().gwl_logl_batch(ev.handle, ctypes.c_void_p(theta.data_ptr()), theta.shape[0],
                                                   _prec(precision), ctypes.c_void_p(out.data_ptr()), _stream(theta)))
@@ -196,8 +209,8 @@ def logl(theta: torch.Tensor, ev: Event, precision="mixed") -> torch.Tensor:
 
 
 def logl_grad(theta: torch.Tensor, ev: Event, precision="mixed"):
-    """(logL[B], dlogL/dtheta[B, 11])."""
-    theta = _theta(theta)
+    """(logL[B], dlogL/dtheta[B, P]), P the width of theta."""
+    theta = _theta(theta, ev)
     out = torch.empty(theta.shape[0], dtype=torch.float64, device=theta.device)
     grad = torch.empty_like(theta)
     _check("gwl_logl_grad", lib().gwl_logl_grad(ev.handle, ctypes.c_void_p(theta.data_ptr()), theta.shape[0],

@@ -1,0 +1,102 @@
+"""The calibrated likelihood on the GPU (gwl_event_create_cal) against the calibration oracle."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import cal_oracle as cal
+from oracle import gw_oracle as o
+from paper_1909_11873_amd import gwlike as gw
+from paper_1909_11873_amd import synth
+from tests.helpers import WIDTHS, event_inputs
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def cal_theta(theta11, nd, n, rng, sigma):
+    k = theta11.shape[0]
+    c = rng.normal(0.0, sigma, (k, 2 * n * nd))
+    return np.concatenate([theta11, c], axis=1)
+
+
+def make(cfg, n, f_hi=None, ndet=None):
+    spec, f, psd, data, dets = event_inputs(cfg, f_hi=f_hi, ndet=ndet)
+    t = lambda x: torch.tensor(x, device=DEV)
+    ev = gw.Event(t(data), t(psd), dets, t(f), spec.df, calibration_nodes=n)
+    return spec, f, psd, data, dets, ev
+
+
+@pytest.mark.parametrize("n", [4, 10, 16])
+def test_zero_calibration_is_the_plain_model(n):
+    spec, f, psd, data, dets, ev = make(1, n, f_hi=400.0)
+    t = lambda x: torch.tensor(x, device=DEV)
+    plain = gw.Event(t(data), t(psd), dets, t(f), spec.df)
+    th = synth.theta_batch(spec, 150)
+    thc = np.concatenate([th, np.zeros((150, 2 * n * 3))], axis=1)
+    for prec, tol in (("fp64", 1e-9), ("mixed", 2e-4)):
+        a = gw.logl(t(thc), ev, prec).cpu().numpy()
+        b = gw.logl(t(th), plain, prec).cpu().numpy()
+        assert np.all(np.abs(a - b) <= tol * np.maximum(1.0, np.abs(b)))
+
+
+@pytest.mark.parametrize("ndet,n", [(3, 10), (1, 4), (2, 16)])
+def test_calibrated_logl_matches_the_oracle(ndet, n):
+    spec, f, psd, data, dets, ev = make(1, n, f_hi=20.0 + 0.125 * 3000, ndet=ndet)   # 3001 bins
+    rng = np.random.default_rng(ndet * 100 + n)
+    th = cal_theta(synth.theta_batch(spec, 70), ndet, n, rng, 0.05)
+    th[0, :11] = spec.theta0
+    ref = cal.logl(th[:12], data, psd, dets, f, spec.df, n).numpy()
+    for prec, tol in (("fp64", 1e-9), ("mixed", 1e-3)):
+        got = gw.logl(torch.tensor(th, device=DEV), ev, prec).cpu().numpy()[:12]
+        err = np.abs(got - ref)
+        print(f"calibrated ndet {ndet} n {n} {prec}: max |dlogL| {err.max():.3e}")
+        assert np.all(err <= tol * (np.maximum(1.0, np.abs(ref)) if prec == "fp64" else 1.0))
+
+
+def test_calibrated_full_size_sampled():
+    """c1 (16,225 bins, 3 detectors, 10 nodes each), the full 65,536-point launch, sampled."""
+    n = 10
+    spec, f, psd, data, dets, ev = make(1, n)
+    rng = np.random.default_rng(3)
+    th = cal_theta(synth.theta_batch(spec), 3, n, rng, 0.05)
+    th[0, :11] = spec.theta0
+    sample = np.array([0, 1, 2, 4096, 40000, 65535])
+    ref = cal.logl(th[sample], data, psd, dets, f, spec.df, n).numpy()
+    got = gw.logl(torch.tensor(th, device=DEV), ev, "mixed").cpu().numpy()[sample]
+    err = np.abs(got - ref)
+    print(f"calibrated c1 full size mixed: max |dlogL| {err.max():.3e}, logL(theta0) {ref[0]:.2f}")
+    assert err.max() <= 1e-3
+
+
+def test_calibrated_gradient_matches_the_oracle():
+    n, nd = 10, 3
+    spec, f, psd, data, dets, ev = make(1, n, f_hi=400.0)
+    rng = np.random.default_rng(9)
+    th = cal_theta(np.stack([spec.theta0, synth.theta_batch(spec, 2)[1]]), nd, n, rng, 0.05)
+    _, gref = cal.logl_grad(th, data, psd, dets, f, spec.df, n)
+    widths = np.concatenate([WIDTHS, np.full(2 * n * nd, 0.1)])
+    for prec, tol in (("fp64", 1e-8), ("mixed", 1e-4)):
+        _, g = gw.logl_grad(torch.tensor(th, device=DEV), ev, prec)
+        gs, rs = g.cpu().numpy() * widths, gref.numpy() * widths
+        scale = np.maximum(np.abs(rs), 1e-3 * np.abs(rs).max(axis=1, keepdims=True))
+        err = np.abs(gs - rs) / scale
+        print(f"calibrated gradient {prec}: max scaled error {err.max():.3e} (signal {err[:, :11].max():.3e}, "
+              f"calibration {err[:, 11:].max():.3e})")
+        assert err.max() <= tol
+
+
+def test_tiny_grid_with_empty_node_intervals():
+    """Fewer bins than node intervals: empty chunks are harmless."""
+    n = 10
+    spec, f, psd, data, dets, ev = make(1, n, f_hi=20.0 + 0.125 * 6)   # 7 bins
+    rng = np.random.default_rng(2)
+    th = cal_theta(synth.theta_batch(spec, 5), 3, n, rng, 0.05)
+    ref = cal.logl(th, data, psd, dets, f, spec.df, n).numpy()
+    got = gw.logl(torch.tensor(th, device=DEV), ev, "fp64").cpu().numpy()
+    np.testing.assert_allclose(got, ref, rtol=1e-9, atol=1e-9)
+
+
+def test_calibrated_events_rejected_by_multi_plans():
+    spec, f, psd, data, dets, ev = make(1, 10, f_hi=100.0)
+    with pytest.raises(gw.GWLError):
+        gw.MultiPlan([ev], [10], "mixed")
