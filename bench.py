@@ -74,6 +74,10 @@ def roofline(ndet: int, mixed: bool, nbins: float, npoints: float, seconds: floa
     return achieved / 1e12, peak / 1e12, achieved / peak
 
 
+def NPARAM_ALL(nd: int, nodes: int) -> int:
+    return 11 + 2 * nodes * nd
+
+
 def kernel_hash() -> str:
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
@@ -169,7 +173,8 @@ def _rb_oracle_sample(cfg: int, eps: float):
 
 
 # ---- GPU leg --------------------------------------------------------------------------------
-def gpu_leg(cfg: int, steps: int, warmup: int, parity_inputs, tune_out=None, rb_eps=0.1, rb_inputs=None):
+def gpu_leg(cfg: int, steps: int, warmup: int, parity_inputs, tune_out=None, rb_eps=0.1, rb_inputs=None,
+            cal_nodes=10):
     import numpy as np
     import torch
 
@@ -259,6 +264,35 @@ def gpu_leg(cfg: int, steps: int, warmup: int, parity_inputs, tune_out=None, rb_
                                          "max_abs_dlogl_fp64": float(np.abs(got64 - ref_rb).max()), "tolerance": 1e-3}
             pev.close()
 
+    # detector calibration model: cal_nodes amplitude and phase nodes per detector, node values
+    # N(0, 0.05) (the relative amplitude and the phase in radians), on the same batch
+    cal = None
+    if cal_nodes > 0:
+        cev = gw.Event(data, torch.tensor(psd, device=dev), dets, ft, spec.df, calibration_nodes=cal_nodes)
+        crng = np.random.default_rng(5)
+        cth = torch.cat([theta, torch.tensor(crng.normal(0.0, 0.05, (B, 2 * cal_nodes * nd)), device=dev)], dim=1)
+        wc, _ = timed(lambda: gw.logl(cth, cev, "mixed"), max(3, steps // 4), 2)
+        wc64, _ = timed(lambda: gw.logl(cth, cev, "fp64"), 3, 1)
+        cg = cth[:min(B, 16384)]
+        wcg, _ = timed(lambda: gw.logl_grad(cg, cev, "mixed"), 3, 1)
+        cal = {"nodes": cal_nodes, "parameters": NPARAM_ALL(nd, cal_nodes),
+               "mixed_evals_per_s": B * max(3, steps // 4) / wc, "fp64_evals_per_s": B * 3 / wc64,
+               "mixed_grad_evals_per_s": int(cg.shape[0]) * 3 / wcg, "grad_batch": int(cg.shape[0])}
+        if parity_inputs is not None:
+            from oracle import cal_oracle as co
+            th_s, _, pdata, ppsd, pdets, pf, pdf = parity_inputs
+            pev = gw.Event(torch.tensor(pdata, device=dev), torch.tensor(ppsd, device=dev), pdets,
+                           torch.tensor(pf, device=dev), pdf, calibration_nodes=cal_nodes)
+            cs = np.concatenate([th_s[:8], crng.normal(0.0, 0.05, (8, 2 * cal_nodes * nd))], axis=1)
+            ref_c = co.logl(cs, pdata, ppsd, pdets, pf, pdf, cal_nodes).numpy()
+            got_c = gw.logl(torch.tensor(cs, device=dev), pev, "mixed").cpu().numpy()
+            got_c64 = gw.logl(torch.tensor(cs, device=dev), pev, "fp64").cpu().numpy()
+            cal["parity_vs_cal_oracle"] = {"points": 8, "max_abs_dlogl_mixed": float(np.abs(got_c - ref_c).max()),
+                                           "max_abs_dlogl_fp64": float(np.abs(got_c64 - ref_c).max()),
+                                           "tolerance": 1e-3}
+            pev.close()
+        cev.close()
+
     parity = None
     if parity_inputs is not None:
         th_s, ref, pdata, ppsd, pdets, pf, pdf = parity_inputs
@@ -277,7 +311,7 @@ def gpu_leg(cfg: int, steps: int, warmup: int, parity_inputs, tune_out=None, rb_
         "mixed_wall": out["mixed"][0], "mixed_kern": out["mixed"][1],
         "fp64_evals": B * nsteps64 / out["fp64"][0], "fp64_kern": out["fp64"][1],
         "grad_mixed_evals": BG * nsg / wg, "grad_fp64_evals": BG * nsg64 / wg64, "grad_batch": BG,
-        "grad_mixed_kern": kg, "grad_fp64_kern": kg64, "rb": rb,
+        "grad_mixed_kern": kg, "grad_fp64_kern": kg64, "rb": rb, "cal": cal,
     }
     return res
 
@@ -519,6 +553,8 @@ def main():
                     help="measure the tile shapes again (written to CACHE) instead of loading " + TUNE_FILE)
     ap.add_argument("--rb-eps", type=float, default=0.1,
                     help="also time relative binning against theta0 with this edge spacing (0: skip)")
+    ap.add_argument("--cal-nodes", type=int, default=10,
+                    help="also time the detector calibration model with this many nodes per detector (0: skip)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run one plain device-to-device copy of this many bytes (a known-size reference "
                          "for the HBM byte counters)")
@@ -557,7 +593,8 @@ def main():
     rb_inputs = None
     if parity_inputs is not None and args.rb_eps > 0:
         rb_inputs = _rb_oracle_sample(args.config, args.rb_eps)
-    r = gpu_leg(args.config, args.steps, args.warmup, parity_inputs, args.retune, args.rb_eps, rb_inputs)
+    r = gpu_leg(args.config, args.steps, args.warmup, parity_inputs, args.retune, args.rb_eps, rb_inputs,
+                args.cal_nodes)
     B, M, nd = r["B"], r["M"], r["ndet"]
     value = B * args.steps / r["mixed_wall"]
     ach, peak, frac = roofline(nd, True, M, B, r["mixed_kern"])
@@ -583,7 +620,7 @@ def main():
                  "fp64_roofline": dict(zip(("achieved", "peak", "frac"), roofline(nd, False, M, r["grad_batch"],
                                                                                  r["grad_fp64_kern"], True)))},
         "event_prep_ms": r["prep_ms"], "autotune_s": r["autotune_s"], "shapes": r["shapes"],
-        "relative_binning": r["rb"],
+        "relative_binning": r["rb"], "calibration": r["cal"],
         "parity_vs_oracle": r["parity"],
     }
     print(json.dumps(line))
