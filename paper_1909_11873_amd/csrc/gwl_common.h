@@ -97,13 +97,14 @@ struct RowCal32 {
 struct RowCal64 {
   double w[4];
 };
+constexpr int MAXCALCHUNK = 96;
 struct CalShape {
   int nnode;              // nodes per detector
-  int nint;               // node intervals = nnode - 1
-  int pieces;             // chunks per interval
+  int nchunk;             // chunks; each lies inside one node interval
   int npg, nbpg, items, gper;
   int j0[MAXNODE];        // first node of each interval's window of four
-  int64_t kb[MAXNODE];    // first bin of each interval; kb[nint] = M
+  int cj[MAXCALCHUNK];    // interval of each chunk
+  int ck[MAXCALCHUNK + 1];// first bin of each chunk; ck[nchunk] = M
 };
 // Calibrated sums: Z_det (2 ND); adjoint: + the uncalibrated model's moments (ND + 8) + per
 // detector the window moments of the amplitude (4) and phase (4) nodes

@@ -118,7 +118,8 @@ __device__ __forceinline__ void cal_bin(const Row r, const CalRow cw, GradP gt, 
   }
 }
 
-// Workgroup -> (chunk, point group) as in the plain loop; a chunk is a piece of one interval.
+// Workgroup -> (chunk, point group) as in the plain loop; a chunk is a piece of one interval
+// (intervals are cut into pieces of similar length, so chunks cost about the same).
 __device__ __forceinline__ bool locate_cal(const CalShape& sh, int& c, int& j, int64_t& k0, int64_t& k1, int& pg) {
   const int bid = blockIdx.x;
   const int item = (bid % NXCD) * sh.gper + bid / NXCD;
@@ -126,11 +127,9 @@ __device__ __forceinline__ bool locate_cal(const CalShape& sh, int& c, int& j, i
   c = item / sh.nbpg;
   pg = (item - c * sh.nbpg) * WAVES_PER_BLOCK + (int)(threadIdx.x / WAVE);
   if (pg >= sh.npg) return false;
-  j = c / sh.pieces;
-  const int q = c - j * sh.pieces;
-  const int64_t a = sh.kb[j], len = sh.kb[j + 1] - a;
-  k0 = a + len * q / sh.pieces;
-  k1 = a + len * (q + 1) / sh.pieces;
+  j = sh.cj[c];
+  k0 = sh.ck[c];
+  k1 = sh.ck[c + 1];
   return true;
 }
 
@@ -171,22 +170,52 @@ __global__ __launch_bounds__(BLOCK) void k_bins_cal(const void* __restrict__ tab
     const RowMixed<ND>* tab = (const RowMixed<ND>*)tabv;
     const RowGradF32* gt = (const RowGradF32*)gtabv;
     const RowCal32* cw = (const RowCal32*)calwv;
-    for (int64_t kb = k0; kb < k1; kb += NB) {
-      const int64_t ke = kb + NB < k1 ? kb + NB : k1;
-      float z[NZ];
+    // float32 blocks of NB bins added into float64; each bin's rows are requested one bin ahead
+    // (the tables carry zero padding rows past the last bin)
+    int k = (int)k0;
+    const int kend = (int)k1;
+    if (k < kend) {
+      RowMixed<ND> cur = load_row_mixed<ND>(tab, k);
+      RowCal32 cwc = cw[k];
+      for (; k + NB <= kend; k += NB) {
+        float z[NZ];
 #pragma unroll
-      for (int zz = 0; zz < NZ; ++zz) z[zz] = 0.0f;
-      for (int64_t k = kb; k < ke; ++k)
-        cal_bin<ND, GRAD, float>(load_row_mixed<ND>(tab, (int)k), cw[k], gt, (int)k, a, T, cr, ci, ca, cp, tbl, z);
+        for (int zz = 0; zz < NZ; ++zz) z[zz] = 0.0f;
+#pragma unroll 2
+        for (int jj = 0; jj < NB; ++jj) {
+          const RowMixed<ND> nxt = load_row_mixed<ND>(tab, k + jj + 1);
+          const RowCal32 cwn = cw[k + jj + 1];
+          cal_bin<ND, GRAD, float>(cur, cwc, gt, k + jj, a, T, cr, ci, ca, cp, tbl, z);
+          cur = nxt;
+          cwc = cwn;
+        }
 #pragma unroll
-      for (int zz = 0; zz < NZ; ++zz) tot[zz] += (double)z[zz];
+        for (int zz = 0; zz < NZ; ++zz) tot[zz] += (double)z[zz];
+      }
+      if (k < kend) {
+        float z[NZ];
+#pragma unroll
+        for (int zz = 0; zz < NZ; ++zz) z[zz] = 0.0f;
+        for (; k < kend; ++k) cal_bin<ND, GRAD, float>(load_row_mixed<ND>(tab, k), cw[k], gt, k, a, T, cr, ci, ca, cp, tbl, z);
+#pragma unroll
+        for (int zz = 0; zz < NZ; ++zz) tot[zz] += (double)z[zz];
+      }
     }
   } else {
     const RowF64<ND>* tab = (const RowF64<ND>*)tabv;
     const RowGradF64* gt = (const RowGradF64*)gtabv;
     const RowCal64* cw = (const RowCal64*)calwv;
-    for (int64_t k = k0; k < k1; ++k)
-      cal_bin<ND, GRAD, double>(load_row_f64<ND>(tab, (int)k), cw[k], gt, (int)k, a, T, cr, ci, ca, cp, tbl, tot);
+    if (k0 < k1) {
+      RowF64<ND> cur = load_row_f64<ND>(tab, (int)k0);
+      RowCal64 cwc = cw[k0];
+      for (int k = (int)k0; k < (int)k1; ++k) {
+        const RowF64<ND> nxt = load_row_f64<ND>(tab, k + 1);
+        const RowCal64 cwn = cw[k + 1];
+        cal_bin<ND, GRAD, double>(cur, cwc, gt, k, a, T, cr, ci, ca, cp, tbl, tot);
+        cur = nxt;
+        cwc = cwn;
+      }
+    }
   }
 #pragma unroll
   for (int zz = 0; zz < NZ; ++zz) part[((int64_t)c * NZ + zz) * Bp + p] = tot[zz];
@@ -203,7 +232,7 @@ __global__ __launch_bounds__(CAL_PT_BLOCK) void k_epilogue_cal(EventGeom g, cons
   if (p >= B) return;
   constexpr int NZ = nz_cal(ND, GRAD), NZU = nz_of(ND, GRAD);
   constexpr int MA = 3 * ND + NBASIS, MB = MA + 4 * ND;
-  const int n = sh.nnode, nchunk = sh.nint * sh.pieces;
+  const int n = sh.nnode, nchunk = sh.nchunk;
   const EventConst e = *ec;
   double acc[NZU];
 #pragma unroll
@@ -216,7 +245,7 @@ __global__ __launch_bounds__(CAL_PT_BLOCK) void k_epilogue_cal(EventGeom g, cons
 #pragma unroll
     for (int zz = 0; zz < NZU; ++zz) acc[zz] += part[((int64_t)c * NZ + zz) * Bp + p];
     if constexpr (GRAD) {
-      const int j0 = sh.j0[c / sh.pieces];
+      const int j0 = sh.j0[sh.cj[c]];
 #pragma unroll
       for (int d = 0; d < ND; ++d)
 #pragma unroll

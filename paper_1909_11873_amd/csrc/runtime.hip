@@ -346,11 +346,16 @@ gwl_status gwl_event_create_cal(const double* data, const double* psd, const gwl
   std::vector<RowCal32> w32((size_t)M);
   for (int64_t k = 0; k < M; ++k)
     for (int i = 0; i < 4; ++i) w32[(size_t)k].w[i] = (float)w[(size_t)k * 4 + i];
-  e = hipMalloc((void**)&ev->cal32, sizeof(RowCal32) * M);
-  if (e == hipSuccess) e = hipMalloc((void**)&ev->cal64, sizeof(RowCal64) * M);
+  // TAB_PAD zero rows past the last bin: the bin loop requests each row one bin ahead
+  w32.resize((size_t)(M + TAB_PAD));
+  for (int64_t k = M; k < M + TAB_PAD; ++k)
+    for (int i = 0; i < 4; ++i) w32[(size_t)k].w[i] = 0.0f;
+  w.resize((size_t)(M + TAB_PAD) * 4, 0.0);
+  e = hipMalloc((void**)&ev->cal32, sizeof(RowCal32) * (M + TAB_PAD));
+  if (e == hipSuccess) e = hipMalloc((void**)&ev->cal64, sizeof(RowCal64) * (M + TAB_PAD));
   if (e == hipSuccess) e = hipMalloc((void**)&ev->kcal, sizeof(double) * kc.size());
-  if (e == hipSuccess) e = hipMemcpy(ev->cal32, w32.data(), sizeof(RowCal32) * M, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(ev->cal64, w.data(), sizeof(RowCal64) * M, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ev->cal32, w32.data(), sizeof(RowCal32) * (M + TAB_PAD), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ev->cal64, w.data(), sizeof(RowCal64) * (M + TAB_PAD), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(ev->kcal, kc.data(), sizeof(double) * kc.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     gwl_event_destroy(ev);
@@ -399,17 +404,29 @@ static gwl_status run_logl_cal(gwl_event ev, const double* theta, int64_t B, boo
   CalShape sh;
   memset(&sh, 0, sizeof sh);
   sh.nnode = n;
-  sh.nint = n - 1;
   sh.npg = (int)((B + WAVE - 1) / WAVE);
-  const int want = heuristic_nchunk(B, ev->M);
-  sh.pieces = std::max(1, (want + sh.nint - 1) / sh.nint);
+  // chunks of about M / want bins, none crossing a node interval (intervals in ln f hold very
+  // different numbers of bins, so each is cut into its own number of pieces)
+  const int want = std::min(heuristic_nchunk(B, ev->M), MAXCALCHUNK - (n - 1));
+  const int64_t target = std::max<int64_t>(1, (ev->M + want - 1) / want);
+  int nc = 0;
+  for (int j = 0; j < n - 1; ++j) {
+    const int64_t a = ev->cal_kb[j], len = ev->cal_kb[j + 1] - a;
+    const int pieces = (int)std::max<int64_t>(1, (len + target - 1) / target);
+    if (nc + pieces > MAXCALCHUNK) return fail(GWL_E_INTERNAL, "calibrated loop: too many chunks");
+    for (int q = 0; q < pieces; ++q, ++nc) {
+      sh.cj[nc] = j;
+      sh.ck[nc] = (int)(a + len * q / pieces);
+    }
+  }
+  sh.ck[nc] = (int)ev->M;
+  sh.nchunk = nc;
   sh.nbpg = (sh.npg + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
-  sh.items = sh.nint * sh.pieces * sh.nbpg;
+  sh.items = sh.nchunk * sh.nbpg;
   sh.gper = (sh.items + NXCD - 1) / NXCD;
   for (int j = 0; j < n - 1; ++j) sh.j0[j] = ev->cal_j0[j];
-  for (int j = 0; j < n; ++j) sh.kb[j] = ev->cal_kb[j];
   const int64_t Bp = (int64_t)sh.npg * WAVE;
-  const int nchunk = sh.nint * sh.pieces, ncal = 2 * n * nd;
+  const int nchunk = sh.nchunk, ncal = 2 * n * nd;
   const size_t bytes = sizeof(double) * ((size_t)NCOEF * Bp + (size_t)ncal * Bp + (size_t)nchunk * nz_cal(nd, grad) * Bp);
   void* ws = nullptr;
   hipError_t e = hipMallocAsync(&ws, bytes, s);
