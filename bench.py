@@ -475,7 +475,7 @@ def scaled_grad_error(g, gref):
     return np.abs(gs - rs) / scale
 
 
-def ns_leg(cfg: int, nlive: int, batches, eps: float, proposal: str = "gmc", snr: float = 20.0, seed: int = 1):
+def ns_leg(cfg: int, nlive: int, batches, eps: float, proposal: str = "slice", snr: float = 20.0, seed: int = 1):
     """Static parallel nested sampling on one event through the mixed-precision kernels, once per
     batch size. The injection sits at the event's theta0 moved in distance to an optimal SNR of
     `snr`. Reports iterations, accepted candidates per iteration, the paper's speed-up
@@ -507,6 +507,7 @@ def ns_leg(cfg: int, nlive: int, batches, eps: float, proposal: str = "gmc", snr
         kw = dict(device=dev, seed=seed, prior_transform=transform, proposal=proposal)
         if proposal == "gmc":
             kw.update(loglike_grad=lambda th: gw.logl_grad(th, ev, "mixed"), gmc_steps=10)
+        last = None
         smp = nested.ParallelNestedSampler(lambda th: gw.logl(th, ev, "mixed"), 11, nlive, n, **kw)
         smp.run(eps=1e3, max_iter=2)           # warm-up (kernels, allocator)
         torch.cuda.synchronize()
@@ -521,6 +522,14 @@ def ns_leg(cfg: int, nlive: int, batches, eps: float, proposal: str = "gmc", snr
                      "logz_err": res.logz_err, "information": res.information, "mc_mean": mc,
                      "max_logl": float(res.logl.max())})
         print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+        last = res
+    # an evidence estimate independent of nested sampling: importance sampling with a proposal
+    # fitted to the last run's posterior
+    wl = np.exp(last.log_w)
+    post = last.u[np.random.default_rng(0).choice(len(wl), size=20000, p=wl / wl.sum())]
+    lz_is, rel_is, ess_is = nested.importance_logz(post, lambda th: gw.logl(th, ev, "mixed"), transform, dev)
+    print(json.dumps({"importance_sampling_logz": lz_is, "relative_error": rel_is, "ess": ess_is}),
+          file=sys.stderr, flush=True)
     ev.close()
     best = min(rows, key=lambda r: r["seconds"])
     return {
@@ -532,6 +541,9 @@ def ns_leg(cfg: int, nlive: int, batches, eps: float, proposal: str = "gmc", snr
                                f"set for optimal SNR {snr}, {nlive} live points, {proposal} proposals, eps {eps}",
                    "nlive": nlive, "batches": list(batches), "logl_theta0": l0, "injected_mc": float(th0[0])},
         "runs": rows,
+        "importance_sampling_check": {"logz": lz_is, "logz_err": rel_is, "ess": ess_is,
+                                      "proposal": "16-component Gaussian mixture fitted to 20,000 draws from the last "
+                                                  "run's posterior, with copies widened 1.5, 2.5 and 4 times; 8.0e6 draws"},
     }
 
 
@@ -548,7 +560,7 @@ def main():
     ap.add_argument("--nlive", type=int, default=1000)
     ap.add_argument("--ns-batches", default="128,256,512,1024,2048")
     ap.add_argument("--ns-eps", type=float, default=0.1)
-    ap.add_argument("--ns-proposal", default="gmc", choices=["gmc", "ellipsoid", "prior"])
+    ap.add_argument("--ns-proposal", default="slice", choices=["slice", "gmc", "ellipsoid", "prior"])
     ap.add_argument("--retune", metavar="CACHE", default=None,
                     help="measure the tile shapes again (written to CACHE) instead of loading " + TUNE_FILE)
     ap.add_argument("--rb-eps", type=float, default=0.1,

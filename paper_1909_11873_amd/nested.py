@@ -10,7 +10,9 @@ synchronisation (the host reads the stop flag every few iterations):
      ellipsoid of the live points (the "bounding distribution" the algorithm re-evaluates each
      iteration), gradient-guided walks inside the current contour (Galilean Monte Carlo: straight
      steps from live points, reflected off the contour along the likelihood gradient, which the
-     library's adjoint provides for a whole batch at once), or a caller's proposal function.
+     library's adjoint provides for a whole batch at once), slice-sampling walks inside the
+     contour (random directions in the live points' whitened coordinates, stepping out and
+     shrinkage; every chain moves, whatever the local scale), or a caller's proposal function.
   3. Prior transform and ln L of the whole batch (for the GW likelihood: the library's kernels).
   4. Candidates in the cube with L >= L_min are accepted (n' of them).
   5. The paper replaces the worst live point by each accepted candidate in turn. Taken in
@@ -112,19 +114,83 @@ def gw_prior_transform(mc_range=(10.0, 60.0), dl_range=(100.0, 2000.0), tc_half=
     return transform
 
 
+SLICE_MAX_DRAWS = 48     # shrinkage draws per slice move before a chain gives up that move
+SLICE_GROUP = 4          # shrinkage draws evaluated together
+
+
+def slice_move(x, dirn, unif, m, inside):
+    """One slice-sampling move per chain for the uniform distribution on a region (stepping out
+    and shrinkage along a line, Neal 2003, sections 4.1 and 4.2).
+
+    x[n, d]: the chains' points (inside the region); dirn[n, d]: each chain's direction, whose
+    length is the initial interval's; unif[2 + SLICE_MAX_DRAWS, n]: uniform numbers, row 0 the
+    interval's offset, row 1 the split of the m - 1 stepping-out steps between the two ends, the
+    rest the shrinkage draws in order; inside(p[N, d]) -> bool[N].
+    Returns (new points, whether each chain moved).
+
+    The interval [x - r dirn, x + (1 - r) dirn] steps out by whole lengths, at most J times to
+    the left and m - 1 - J times to the right (J = floor(m v)), while its end lies inside; then
+    draws uniformly from it, shrinking it to the draw after every draw outside, until a draw
+    lands inside. The line need not cross the region in one piece: the move leaves the uniform
+    distribution on the region invariant all the same, and never returns its start point.
+
+    The outcome is fixed by the uniform numbers and by which of the points the procedure looks at
+    lie inside, so those points are evaluated ahead, in one batch per stage: the m possible left
+    ends and m possible right ends together, then the shrinkage draws in groups of SLICE_GROUP,
+    each draw from the interval as it would be if the earlier draws of its group had fallen
+    outside. The first draw inside is the one the sequential procedure returns. A chain with no
+    draw inside after SLICE_MAX_DRAWS keeps its point."""
+    n, d = x.shape
+    f64 = dict(dtype=x.dtype, device=x.device)
+    lo, hi = -unif[0], 1.0 - unif[0]
+    if m > 1:
+        jl = torch.floor(m * unif[1])
+        jr = (m - 1) - jl
+        steps = torch.arange(m, **f64)
+        ends = torch.cat([lo[None] - steps[:, None], hi[None] + steps[:, None]])          # [2m, n]
+        ok = inside((x[None] + ends[..., None] * dirn[None]).reshape(-1, d)).reshape(2 * m, n)
+        out_l = torch.where(ok[:m].all(0), m, torch.argmin(ok[:m].to(torch.int8), 0)).to(x.dtype)
+        out_r = torch.where(ok[m:].all(0), m, torch.argmin(ok[m:].to(torch.int8), 0)).to(x.dtype)
+        lo = lo - torch.minimum(out_l, jl)
+        hi = hi + torch.minimum(out_r, jr)
+    done = torch.zeros(n, dtype=torch.bool, device=x.device)
+    xn = x
+    for g0 in range(0, SLICE_MAX_DRAWS, SLICE_GROUP):
+        ts = []
+        a, b = lo, hi
+        for k in range(g0, g0 + SLICE_GROUP):
+            t = a + unif[2 + k] * (b - a)
+            ts.append(t)
+            a = torch.where(t < 0.0, t, a)
+            b = torch.where(t >= 0.0, t, b)
+        tt = torch.stack(ts)                                                              # [group, n]
+        ok = inside((x[None] + tt[..., None] * dirn[None]).reshape(-1, d)).reshape(SLICE_GROUP, n) & ~done[None]
+        hit = ok.any(0)
+        tsel = tt.gather(0, torch.argmax(ok.to(torch.int8), 0)[None])[0]
+        xn = torch.where(hit[:, None], x + tsel[:, None] * dirn, xn)
+        done = done | hit
+        lo, hi = torch.where(done, lo, a), torch.where(done, hi, b)
+        if bool(done.all()):
+            break
+    return xn, done
+
+
 class ParallelNestedSampler:
     """K live points, n candidates per iteration, everything on `device`.
 
     loglike(theta[n, d]) -> ln L[n] (float64 tensors on the device; NaN counts as -inf).
     prior_transform(u[n, d]) -> theta[n, d]; identity if None.
-    proposal: "prior", "ellipsoid", "gmc", or a function (it, live_u, live_l) -> u[n, d].
+    proposal: "prior", "ellipsoid", "gmc", "slice", or a function (it, live_u, live_l) -> u[n, d].
     loglike_grad(theta[n, d]) -> (ln L[n], d ln L / d theta [n, d]): needed for "gmc".
+    slice_steps, slice_width, slice_out: slice moves per candidate, the initial interval length in
+    units of the live points' spread along the direction, and the stepping-out limit m.
     """
 
     def __init__(self, loglike: Callable, ndim: int, nlive: int, batch: int,
                  prior_transform: Optional[Callable] = None, device="cuda:0", seed: int = 0,
                  proposal="ellipsoid", enlarge: float = 1.25, volume: str = "order", check_every: int = 8,
-                 loglike_grad: Optional[Callable] = None, gmc_steps: int = 20):
+                 loglike_grad: Optional[Callable] = None, gmc_steps: int = 20, slice_steps: Optional[int] = None,
+                 slice_width: float = 3.0, slice_out: int = 4):
         if nlive < 2 or batch < 1 or ndim < 1:
             raise ValueError("need nlive >= 2, batch >= 1, ndim >= 1")
         if volume not in ("order", "paper"):
@@ -140,6 +206,10 @@ class ParallelNestedSampler:
             raise ValueError("proposal 'gmc' needs loglike_grad")
         self.loglike_grad, self.gmc_steps = loglike_grad, max(1, int(gmc_steps))
         self.gmc_scale = 0.5            # step length in units of the live points' spread, adapted
+        self.slice_steps = max(1, int(slice_steps)) if slice_steps is not None else 5 * ndim
+        if slice_width <= 0.0 or slice_out < 1:
+            raise ValueError("need slice_width > 0 and slice_out >= 1")
+        self.slice_width, self.slice_out = float(slice_width), int(slice_out)
         self.extra_calls = 0
 
     # ---- proposals -------------------------------------------------------------------------
@@ -230,6 +300,32 @@ class ParallelNestedSampler:
         self._gmc_rate = acc_moves / self.gmc_steps
         return torch.where(moved[:, None], x, torch.full_like(x, 2.0))
 
+    def _in_contour(self, u, lmin):
+        l, inside = self._loglike(u)
+        self.extra_calls += u.shape[0]
+        return inside & (l >= lmin)
+
+    def _slice(self, live_u, live_l):
+        """Slice-sampling walks inside the contour L >= L_min, one chain per candidate: each chain
+        starts at a random live point and makes slice_steps moves of `slice_move`, along random
+        directions isotropic in the coordinates that whiten the live points, each of length
+        slice_width in those coordinates."""
+        n, d, K = self.n, self.d, self.K
+        f64 = dict(dtype=torch.float64, device=self.dev)
+        lmin = live_l[0]
+        start = torch.randint(0, K, (n,), generator=self.gen, device=self.dev)
+        x = live_u[start].clone()
+        xc = live_u - live_u.mean(0)
+        cov = xc.T @ xc / (K - 1) + 1e-14 * torch.eye(d, **f64)
+        chol, _ = torch.linalg.cholesky_ex(cov)
+        inside = lambda p: self._in_contour(p, lmin)
+        for _ in range(self.slice_steps):
+            z = torch.randn(n, d, generator=self.gen, **f64)
+            dirn = self.slice_width * (z / z.norm(dim=1, keepdim=True)) @ chol.T
+            unif = torch.rand(2 + SLICE_MAX_DRAWS, n, generator=self.gen, **f64)
+            x, _ = slice_move(x, dirn, unif, self.slice_out, inside)
+        return x
+
     def _propose(self, it, live_u, live_l):
         if callable(self.proposal):
             return self.proposal(it, live_u, live_l)
@@ -239,6 +335,8 @@ class ParallelNestedSampler:
             return self._ellipsoid(live_u)
         if self.proposal == "gmc":
             return self._gmc(live_u, live_l)
+        if self.proposal == "slice":
+            return self._slice(live_u, live_l)
         raise ValueError(f"unknown proposal {self.proposal!r}")
 
     def _loglike(self, u):
@@ -354,3 +452,45 @@ class ParallelNestedSampler:
                         logz_err=math.sqrt(max(h, 0.0) / K), log_w=log_w, information=h, niter=it,
                         ncall=K + n * it + self.extra_calls, n_accepted=n_acc,
                         seconds=time.perf_counter() - t0, nlive=K)
+
+
+def importance_logz(u_post, loglike, transform, dev, ncomp=16, ndraw=8_000_000, seed=7, scales=(1.0, 1.5, 2.5, 4.0)):
+    """An evidence estimate independent of nested sampling, to check a run against: importance
+    sampling in the unit cube with a Gaussian-mixture proposal fitted to posterior samples
+    u_post[N, d] (ncomp components), mixed in equal parts with copies of it whose covariances
+    are scaled by scales^2, ndraw draws. Returns (ln Z, relative standard error of Z, effective sample size). A mode the
+    posterior samples miss is missed here too."""
+    from sklearn.mixture import GaussianMixture
+    gm = GaussianMixture(ncomp, covariance_type="full", reg_covar=1e-9, random_state=0, max_iter=200).fit(u_post)
+    d = u_post.shape[1]
+    wts = torch.tensor(gm.weights_, device=dev)
+    mus = torch.tensor(gm.means_, device=dev)
+    chol = torch.linalg.cholesky(torch.tensor(gm.covariances_, device=dev))
+    linv = torch.linalg.inv(chol)
+    logdet = torch.log(torch.diagonal(chol, dim1=1, dim2=2)).sum(1)
+    scales = torch.tensor(list(scales), dtype=torch.float64, device=dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+
+    def logq(u):
+        out = []
+        for s in scales.tolist():
+            y = torch.matmul(u[None] - mus[:, None], (linv / s).transpose(1, 2).contiguous())
+            lp = -0.5 * (y * y).sum(-1) - (logdet + d * math.log(s))[:, None] - 0.5 * d * math.log(2 * math.pi)
+            out.append(torch.logsumexp(lp + torch.log(wts)[:, None], 0))
+        return torch.logsumexp(torch.stack(out), 0) - math.log(len(scales))
+
+    lw, B = [], 131072
+    for _ in range((ndraw + B - 1) // B):
+        sc = scales[torch.randint(0, len(scales), (B,), generator=g, device=dev)]
+        ci = torch.multinomial(wts, B, replacement=True, generator=g)
+        z = torch.randn(B, d, generator=g, device=dev, dtype=torch.float64)
+        u = mus[ci] + sc[:, None] * torch.matmul(chol[ci], z[..., None])[..., 0]
+        inside = ((u >= 0) & (u <= 1)).all(1)
+        l = loglike(transform(u.clamp(0.0, 1.0)))
+        l = torch.where(torch.isnan(l) | ~inside, torch.full_like(l, -math.inf), l)
+        lw.append((l - logq(u)).cpu().numpy())
+    lw = np.concatenate(lw)
+    w = np.exp(lw - lw.max())
+    return (lw.max() + math.log(w.mean()), w.std() / w.mean() / math.sqrt(len(w)),
+            w.sum() ** 2 / (w * w).sum())

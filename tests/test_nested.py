@@ -113,6 +113,118 @@ def test_gmc_correlated_gaussian_on_host():
     assert c[0, 1] / math.sqrt(c[0, 0] * c[1, 1]) == pytest.approx(rho, abs=0.02)
 
 
+def two_balls(p):
+    """Membership in a region whose lines need not cross it in one piece: two balls in the cube."""
+    inc = ((p >= 0.0) & (p <= 1.0)).all(-1)
+    return inc & ((((p - 0.3) ** 2).sum(-1) < 0.2 ** 2) | (((p - 0.7) ** 2).sum(-1) < 0.15 ** 2))
+
+
+def neal_slice_move(x0, dirn, unif, m, inside):
+    """Neal's stepping-out and shrinkage, one chain at a time, with the same uniform numbers."""
+    r = unif[0]
+    lo0, hi0 = -r, 1.0 - r
+    sl = sr = 0
+    if m > 1:
+        jl = math.floor(m * unif[1])
+        jr = m - 1 - jl
+        while sl < jl and inside(x0 + (lo0 - sl) * dirn):
+            sl += 1
+        while sr < jr and inside(x0 + (hi0 + sr) * dirn):
+            sr += 1
+    lo, hi = lo0 - sl, hi0 + sr
+    for k in range(nested.SLICE_MAX_DRAWS):
+        t = lo + unif[2 + k] * (hi - lo)
+        p = x0 + t * dirn
+        if inside(p):
+            return p, True
+        if t < 0.0:
+            lo = t
+        else:
+            hi = t
+    return x0, False
+
+
+@pytest.mark.parametrize("m", [1, 4])
+def test_slice_move_is_the_sequential_procedure(m):
+    """The batched slice move (ends and shrinkage draws evaluated ahead, in groups) returns
+    exactly what the sequential procedure returns with the same random numbers."""
+    rng = np.random.default_rng(11 + m)
+    n, d = 400, 3
+    x = np.where(rng.random((3 * n, 1)) < 0.5, 0.3, 0.7) + 0.05 * rng.standard_normal((3 * n, d))
+    x = x[two_balls(torch.tensor(x)).numpy()][:n]
+    assert len(x) == n
+    dirn = rng.standard_normal((n, d)) + np.where(rng.random((n, 1)) < 0.5, 3.0, 0.0)   # half near the diagonal
+    dirn *= (0.02 + 0.8 * rng.random((n, 1))) / np.linalg.norm(dirn, axis=1, keepdims=True)
+    unif = rng.random((2 + nested.SLICE_MAX_DRAWS, n))
+    got, moved = nested.slice_move(torch.tensor(x), torch.tensor(dirn), torch.tensor(unif), m, two_balls)
+    inside_np = lambda p: bool(two_balls(torch.tensor(p)))
+    for i in range(n):
+        ref, ok = neal_slice_move(x[i], dirn[i], unif[:, i], m, inside_np)
+        assert bool(moved[i]) == ok
+        np.testing.assert_array_equal(got[i].numpy(), ref)
+    assert bool(moved.all())
+    assert (np.linalg.norm(got.numpy() - x, axis=1) > 0).all()
+    # some lines left one ball for the other
+    assert ((np.linalg.norm(x - 0.3, axis=1) < 0.2) != (np.linalg.norm(got.numpy() - 0.3, axis=1) < 0.2)).any()
+
+
+def test_slice_moves_keep_the_region_uniform():
+    """Uniform points in a ball stay uniform under slice moves: (r / R)^3 stays U(0, 1) and the
+    direction stays isotropic."""
+    from scipy import stats
+    rng = np.random.default_rng(5)
+    n, d, R = 20000, 3, 0.3
+    v = rng.standard_normal((n, d))
+    x = 0.5 + R * v / np.linalg.norm(v, axis=1, keepdims=True) * rng.random((n, 1)) ** (1.0 / d)
+    inside = lambda p: ((p - 0.5) ** 2).sum(-1) < R * R
+    xt = torch.tensor(x)
+    for step in range(3):
+        dirn = torch.tensor(rng.standard_normal((n, d)))
+        dirn = 0.25 * dirn / dirn.norm(dim=1, keepdim=True)
+        xt, moved = nested.slice_move(xt, dirn, torch.tensor(rng.random((2 + nested.SLICE_MAX_DRAWS, n))), 4, inside)
+        assert bool(moved.all())
+    y = xt.numpy() - 0.5
+    r = np.linalg.norm(y, axis=1)
+    assert r.max() < R
+    assert stats.kstest((r / R) ** 3, "uniform").pvalue > 1e-3
+    np.testing.assert_allclose(y.mean(0), 0.0, atol=4 * R / math.sqrt(5 * n))
+    assert stats.kstest(y[:, 2] / r, "uniform", args=(-1, 2)).pvalue > 1e-3
+
+
+def test_slice_proposal_on_host():
+    """Slice-sampling walks as the proposal: the normalised correlated Gaussian (ln Z = 0) and its
+    correlation; every candidate lies inside the contour, so every candidate is accepted."""
+    s, rho = 0.05, 0.98
+    cov = s * s * torch.tensor([[1.0, rho, 0.0], [rho, 1.0, 0.0], [0.0, 0.0, 1.0]], dtype=torch.float64)
+    prec = torch.linalg.inv(cov)
+    norm = -0.5 * math.log((2 * math.pi) ** 3 * float(torch.linalg.det(cov)))
+
+    def ll(th):
+        x = th - 0.5
+        return norm - 0.5 * ((x @ prec) * x).sum(1)
+
+    res = nested.ParallelNestedSampler(ll, 3, 300, 128, device="cpu", seed=9, proposal="slice").run(eps=0.01)
+    assert abs(res.logz) < 4 * res.logz_err + 0.1, (res.logz, res.logz_err)
+    assert np.all(res.n_accepted == 128)
+    w = np.exp(res.log_w)
+    m = np.sum(w[:, None] * res.u, 0)
+    c = np.einsum("i,ij,ik->jk", w, res.u - m, res.u - m)
+    assert c[0, 1] / math.sqrt(c[0, 0] * c[1, 1]) == pytest.approx(rho, abs=0.02)
+
+
+def test_importance_logz_on_a_normalised_gaussian():
+    """The importance-sampling check itself: ln Z = 0 for a normalised Gaussian inside the cube."""
+    s = 0.05
+    cov = s * s * np.array([[1.0, 0.9, 0.0], [0.9, 1.0, 0.0], [0.0, 0.0, 1.0]])
+    prec = torch.tensor(np.linalg.inv(cov))
+    norm = -0.5 * math.log((2 * math.pi) ** 3 * np.linalg.det(cov))
+    ll = lambda th: norm - 0.5 * (((th - 0.5) @ prec) * (th - 0.5)).sum(1)
+    post = np.random.default_rng(1).multivariate_normal(np.full(3, 0.5), cov, size=4000)
+    lz, rel, ess = nested.importance_logz(post, ll, lambda u: u, torch.device("cpu"), ncomp=2, ndraw=262144,
+                                          scales=(1.0, 1.5))
+    assert abs(lz) < 5 * rel + 1e-3 and rel < 0.01 and ess > 1e4
+
+
 def test_speedup_law():
     assert nested.speedup_law(1, 2000) == pytest.approx(1.0, rel=3e-4)
     # the values quoted beside the paper's scaling test (K = 2000)
@@ -197,3 +309,45 @@ def test_gw_nested_sampling_recovers_the_injection(batch):
 
 
 RESULTS = {}
+
+
+@pytest.mark.gpu
+def test_gw_slice_nested_sampling_matches_importance_sampling():
+    """Three detectors, 8 s, aligned spins (11 parameters), the injection moved to optimal SNR 20,
+    the library's mixed-precision kernels, slice walks (5 d moves per candidate): the run keeps
+    the injected sky position, reaches the injection's likelihood, and its evidence agrees with
+    an importance-sampling estimate whose proposal is fitted to the run's own posterior. The
+    tolerance of 1.5 nats covers the run-to-run scatter of this posterior's evidence (standard
+    deviation 0.6 over eight runs at K = 1000 and 2000; the sqrt(H/K) error, 0.17, leaves out
+    posterior mass drifting between the modes of the mass-ratio/spin degeneracy)."""
+    from oracle import gw_oracle as o
+    from paper_1909_11873_amd import gwlike as gw
+    from paper_1909_11873_amd import synth
+
+    spec = synth.event_spec(1)
+    f, psd, nz, dets = synth.event_arrays(spec)
+    th0 = spec.theta0.copy()
+    h = o.strain_all(th0, dets, f)
+    snr0 = math.sqrt(sum(float(o.inner(h[i], h[i], torch.tensor(psd[i]), spec.df)) for i in range(len(dets))))
+    th0[4] *= snr0 / 20.0
+    data = nz + o.strain_all(th0, dets, f).numpy()
+    l0 = float(o.logl(th0[None], data, psd, dets, f, spec.df)[0])
+    ev = gw.Event(torch.tensor(data, device=DEV), torch.tensor(psd, device=DEV), dets,
+                  torch.tensor(f, device=DEV), spec.df)
+    ll = lambda th: gw.logl(th, ev, "mixed")
+    tr = nested.gw_prior_transform(mc_range=spec.mc_range, spins=spec.spins)
+    res = nested.ParallelNestedSampler(ll, 11, 1000, 1024, device=DEV, seed=2, prior_transform=tr,
+                                       proposal="slice").run(eps=0.1, max_iter=2000)
+    w = np.exp(res.log_w)
+    w /= w.sum()
+    sky = np.hypot(np.angle(np.exp(1j * (res.theta[:, 5] - th0[5]))), res.theta[:, 6] - th0[6]) < 0.3
+    post = res.u[np.random.default_rng(0).choice(len(w), size=20000, p=w)]
+    lz_is, rel, ess = nested.importance_logz(post, ll, tr, DEV)
+    print(f"GW NS slice c1: {res.niter} iterations, {res.ncall} calls, {res.seconds:.1f} s, lnZ {res.logz:.2f} "
+          f"+- {res.logz_err:.2f}; importance sampling {lz_is:.3f} +- {rel:.3f} (ESS {ess:.0f}); "
+          f"logL(theta0) {l0:.2f}, max logL {res.logl.max():.2f}, injected sky mass {w[sky].sum():.3f}")
+    assert w[sky].sum() > 0.9
+    assert res.logl.max() > l0 - 1.0
+    assert rel < 0.1 and ess > 100
+    assert abs(res.logz - lz_is) < 1.5
+    ev.close()
