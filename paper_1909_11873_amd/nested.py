@@ -75,22 +75,24 @@ def gw_prior_transform(mc_range=(10.0, 60.0), dl_range=(100.0, 2000.0), tc_half=
     density ~ d^2, isotropic sky and orientation, uniform angles and coalescence time."""
     lo3, hi3 = dl_range[0] ** 3, dl_range[1] ** 3
 
+    sw = 1.8 if spins else 0.0
+    # the columns that are affine in u: theta = offset + scale u
+    offset = [mc_range[0], 0.2, -sw / 2, -sw / 2, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, -tc_half]
+    scale = [mc_range[1] - mc_range[0], 0.8, sw, sw, 0.0, 2.0 * math.pi, 0.0, 0.0, math.pi, 2.0 * math.pi,
+             2.0 * tc_half]
+    consts = {}
+
     def transform(u: torch.Tensor) -> torch.Tensor:
-        th = torch.empty_like(u)
-        th[:, 0] = mc_range[0] + (mc_range[1] - mc_range[0]) * u[:, 0]
-        th[:, 1] = 0.2 + 0.8 * u[:, 1]
-        if spins:
-            th[:, 2] = -0.9 + 1.8 * u[:, 2]
-            th[:, 3] = -0.9 + 1.8 * u[:, 3]
-        else:
-            th[:, 2:4] = 0.0
+        key = (u.device, u.dtype)
+        if key not in consts:
+            consts[key] = (torch.tensor(offset, device=u.device, dtype=u.dtype),
+                           torch.tensor(scale, device=u.device, dtype=u.dtype))
+        off, sc = consts[key]
+        th = torch.addcmul(off, u, sc)
         th[:, 4] = torch.pow(lo3 + u[:, 4] * (hi3 - lo3), 1.0 / 3.0)
-        th[:, 5] = 2.0 * math.pi * u[:, 5]
-        th[:, 6] = torch.asin(2.0 * u[:, 6] - 1.0)
-        th[:, 7] = torch.acos(2.0 * u[:, 7] - 1.0)
-        th[:, 8] = math.pi * u[:, 8]
-        th[:, 9] = 2.0 * math.pi * u[:, 9]
-        th[:, 10] = -tc_half + 2.0 * tc_half * u[:, 10]
+        s67 = 2.0 * u[:, 6:8] - 1.0
+        th[:, 6] = torch.asin(s67[:, 0])
+        th[:, 7] = torch.acos(s67[:, 1])
         return th
 
     def jacobian(u: torch.Tensor) -> torch.Tensor:
@@ -115,7 +117,7 @@ def gw_prior_transform(mc_range=(10.0, 60.0), dl_range=(100.0, 2000.0), tc_half=
 
 
 SLICE_MAX_DRAWS = 48     # shrinkage draws per slice move before a chain gives up that move
-SLICE_GROUP = 4          # shrinkage draws evaluated together
+SLICE_GROUP = 8          # shrinkage draws evaluated together
 
 
 def slice_move(x, dirn, unif, m, inside):
@@ -161,8 +163,8 @@ def slice_move(x, dirn, unif, m, inside):
         for k in range(g0, g0 + SLICE_GROUP):
             t = a + unif[2 + k] * (b - a)
             ts.append(t)
-            a = torch.where(t < 0.0, t, a)
-            b = torch.where(t >= 0.0, t, b)
+            left = t < 0.0
+            a, b = torch.where(left, t, a), torch.where(left, b, t)
         tt = torch.stack(ts)                                                              # [group, n]
         ok = inside((x[None] + tt[..., None] * dirn[None]).reshape(-1, d)).reshape(SLICE_GROUP, n) & ~done[None]
         hit = ok.any(0)
