@@ -12,10 +12,15 @@ namespace gwl {
 
 constexpr int NB = 8;  // bins per float32 block before the float64 flush (mixed precision)
 
-// Float64 phasor by table and short polynomials: t = n/N + y with n = rint(N t), |y| <= 1/(2N),
-// e^{2 pi i t} = T[n mod N] e^{2 pi i y}; T holds (cos, sin) of 2 pi k / N in LDS and the
-// Taylor series of e^{2 pi i y} is cut where the next term is below 1e-17 (|2 pi y| <= 0.0123).
-constexpr int PH_TBL = 256;
+// Float64 phasor by table and short polynomials. The float64 kernels carry the phase in table
+// units, 1/N of a cycle (their per-point phase coefficients are scaled by N, a power of two, so
+// every product and sum rounds exactly as in cycles): tu = n + y with n = rint(tu), |y| <= 1/2,
+// and e^{2 pi i tu / N} = T[n mod N] e^{2 pi i y / N}. T holds (cos, sin) of 2 pi k / N in LDS
+// (16 KB per workgroup). With N = 1024, |2 pi y / N| <= 3.1e-3, and the Taylor series of
+// sin(2 pi y / N) and cos(2 pi y / N) stop after their y^5 and y^4 terms: the first omitted
+// terms are below 2e-19 and 2e-18 of the result. The series' coefficients are those of
+// sin(2 pi y) and cos(2 pi y) divided by powers of N (exact).
+constexpr int PH_TBL = 1024;
 __device__ __forceinline__ void fill_phasor_table(double2* tbl) {
   for (int k = threadIdx.x; k < PH_TBL; k += blockDim.x) {
     double s, c;
@@ -23,17 +28,23 @@ __device__ __forceinline__ void fill_phasor_table(double2* tbl) {
     tbl[k] = make_double2(c, s);
   }
 }
-__device__ __forceinline__ void sincos_cycles_tbl(double t, const double2* __restrict__ tbl, double& s, double& c) {
-  const double n = rint(t * (double)PH_TBL);
-  const double y = fma(n, -1.0 / PH_TBL, t);                // exact, |y| <= 1/512
+template <int ND>
+__device__ __forceinline__ void to_table_units(double (&a)[NBASIS], double (&T)[ND]) {
+#pragma unroll
+  for (int m = 0; m < NBASIS; ++m) a[m] *= (double)PH_TBL;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) T[d] *= (double)PH_TBL;
+}
+__device__ __forceinline__ void sincos_tbl(double tu, const double2* __restrict__ tbl, double& s, double& c) {
+  constexpr double N = PH_TBL;
+  const double n = rint(tu);
+  const double y = tu - n;                       // exact
   const double2 e = tbl[(int)n & (PH_TBL - 1)];  // v_cvt_i32_f64 clamps; the mask keeps the index in range
   const double z = y * y;
-  double ps = fma(z, 81.60524927607506, -41.34170224039976);                               // sin(2 pi y) / y
-  ps = fma(ps, z, 6.283185307179586);
+  double ps = fma(z, 81.60524927607506 / (N * N * N * N * N), -41.34170224039976 / (N * N * N));  // sin(2 pi y / N) / y
+  ps = fma(ps, z, 6.283185307179586 / N);
   const double sv = ps * y;
-  double pc = fma(z, -85.45681720669373, 64.9393940226683);                               // cos(2 pi y)
-  pc = fma(pc, z, -19.739208802178716);
-  pc = fma(pc, z, 1.0);
+  const double pc = fma(fma(z, 64.9393940226683 / (N * N * N * N), -19.739208802178716 / (N * N)), z, 1.0);
   c = fma(e.x, pc, -(e.y * sv));
   s = fma(e.y, pc, e.x * sv);
 }
@@ -130,7 +141,7 @@ __device__ __forceinline__ void f64_bin(const RowF64<ND> r, GradP gt, int k,
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
     double sn, cs;
-    sincos_cycles_tbl(fma(r.f, T[d], psi), tbl, sn, cs);
+    sincos_tbl(fma(r.f, T[d], psi), tbl, sn, cs);  // phase in table units
     const double ur = r.u[2 * d], ui = r.u[2 * d + 1];
     if (!GRAD) {
       z[2 * d] = fma(ur, cs, fma(ui, sn, z[2 * d]));

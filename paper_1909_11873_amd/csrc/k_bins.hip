@@ -84,6 +84,7 @@ __global__ __launch_bounds__(BLOCK) void k_bins_f64(const RowF64<ND>* __restrict
   const int64_t pc = p < B ? p : B - 1;
   double a[NBASIS], T[ND], cr[ND], ci[ND];
   load_coef<ND, double>(coef, Bp, pc, GRAD, a, T, cr, ci);
+  to_table_units<ND>(a, T);
   double z[NZ];
   bin_loop_f64<ND, GRAD>(tab, gtab, k0, k1, a, T, cr, ci, tbl, z);
 #pragma unroll

@@ -84,14 +84,16 @@ __device__ __forceinline__ void cal_bin(const Row r, const CalRow cw, GradP gt, 
     }
     // q = u p exp(i dphi) = u exp(-2 pi i (phi - dphi / 2 pi)): the calibration phase joins the
     // model phase before the reduction, so one phasor (with its gain correction) serves both
-    const double ph = fma((double)dp, -0.15915494309189535, fma(r.f, T[d], psi));
+    // (the float64 variant's phase is in table units: dphi / 2 pi scaled by PH_TBL as well)
+    constexpr double inv2pi = MIXED ? -0.15915494309189535 : -0.15915494309189535 * PH_TBL;
+    const double ph = fma((double)dp, inv2pi, fma(r.f, T[d], psi));
     T_ cs, sn;
     if constexpr (MIXED) {
       const float rr = (float)__builtin_amdgcn_fract(ph);
       cs = __builtin_amdgcn_cosf(rr);
       sn = __builtin_amdgcn_sinf(rr);
     } else {
-      sincos_cycles_tbl(ph, tbl, sn, cs);
+      sincos_tbl(ph, tbl, sn, cs);
     }
     const T_ ur = r.u[2 * d], ui = r.u[2 * d + 1];
     const T_ qr = fma(ur, cs, ui * sn);
@@ -140,7 +142,7 @@ __global__ __launch_bounds__(BLOCK) void k_bins_cal(const void* __restrict__ tab
                                                     CalShape sh, double* __restrict__ part) {
   typedef typename std::conditional<MIXED, float, double>::type T_;
   constexpr int NZ = nz_cal(ND, GRAD);
-  __shared__ double2 tbl[PH_TBL];
+  __shared__ double2 tbl[MIXED ? 1 : PH_TBL];  // the float64 phasor table
   if constexpr (!MIXED) {
     fill_phasor_table(tbl);
     __syncthreads();
@@ -153,6 +155,7 @@ __global__ __launch_bounds__(BLOCK) void k_bins_cal(const void* __restrict__ tab
   double a[NBASIS], T[ND];
   T_ cr[ND], ci[ND];
   load_coef<ND, T_>(coef, Bp, pc, GRAD, a, T, cr, ci);
+  if constexpr (!MIXED) to_table_units<ND>(a, T);  // the float64 phase runs in 1/PH_TBL cycles
   T_ ca[ND][4], cp[ND][4];
   const int n = sh.nnode, j0 = sh.j0[j];
 #pragma unroll

@@ -99,8 +99,8 @@ __global__ __launch_bounds__(BLOCK, (ND <= 3 ? (GRAD && MIXED ? 5 : 4) : 3)) voi
                                                       unsigned int* __restrict__ done,
                                                       unsigned long long* __restrict__ tev) {
   constexpr int NZ = nz_of(ND, GRAD);
-  __shared__ double2 tbl[PH_TBL];
-  fill_phasor_table(tbl);
+  __shared__ double2 tbl[MIXED ? 1 : PH_TBL];  // the float64 phasor table
+  if constexpr (!MIXED) fill_phasor_table(tbl);
   __syncthreads();
   const int lane = threadIdx.x % WAVE;
   for (;;) {
@@ -134,6 +134,7 @@ __global__ __launch_bounds__(BLOCK, (ND <= 3 ? (GRAD && MIXED ? 5 : 4) : 3)) voi
     } else {
       double cr[ND], ci[ND];
       load_coef<ND, double>(ev.coef, ev.Bp, pc, GRAD, a, T, cr, ci);
+      to_table_units<ND>(a, T);
       bin_loop_f64<ND, GRAD>((const_as_ptr<RowF64<ND>>)ev.tab, (const_as_ptr<RowGradF64>)ev.gtab, k0, k1, a, T, cr,
                              ci, tbl, tot);
     }
