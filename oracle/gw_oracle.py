@@ -33,8 +33,10 @@ Parity status of each part (what pins it, in the tests):
     <h|h> under a flat PSD.
   * Newtonian, 1PN, 1.5PN (with beta) and 2PN (with sigma) phase terms: pinned
     by the published 2PN time-frequency relation t(f) through dPsi/df = 2 pi t(f).
-  * 2.5PN, 3PN and 3.5PN phase coefficients: parity unpinned (the publications
-    they come from are not available here; only their O(v^5) size is checked).
+  * every non-spinning phase coefficient, 2.5PN, 3PN and 3.5PN included: pinned
+    by the stationary-phase integral of the PN energy balance (binding energy to
+    3PN, gravitational-wave flux to 3.5PN with its logarithm), which gives the
+    same series by an independent route. The spin terms beyond 2PN are absent.
   * antenna patterns: pinned by the detector-frame closed form of F+^2 + Fx^2,
     the polarisation-rotation law and the 4/25 sky/orientation average.
   * time delays: pinned by zenith, nadir and horizon special cases.

@@ -89,6 +89,18 @@ MUTATIONS = [
      [lambda: pins.test_phase_derivative_matches_2pn_time_frequency_relation(-0.85, 0.9)]),
     ("phi4 dropped", "pn_coefficients", lambda: _wrap_pn(3, lambda p, e, a, b: 0.0 * p),
      [lambda: pins.test_phase_derivative_matches_2pn_time_frequency_relation(0.0, 0.0)]),
+    ("phi5 eta term mistyped", "pn_coefficients",
+     lambda: _wrap_pn(4, lambda p, e, a, b: p * (38645.0 / 756.0 - 56.0 * e / 9.0) / (38645.0 / 756.0 - 65.0 * e / 9.0)),
+     [lambda: pins.test_phase_coefficients_follow_from_pn_energy_and_flux(0.5)]),
+    ("phi6 gamma_E term dropped", "pn_coefficients",
+     lambda: _wrap_pn(5, lambda p, e, a, b: p + 6848.0 * 0.5772156649015329 / 21.0),
+     [lambda: pins.test_phase_coefficients_follow_from_pn_energy_and_flux(1.0)]),
+    ("phi6 eta^3 sign", "pn_coefficients",
+     lambda: _wrap_pn(5, lambda p, e, a, b: p + 2.0 * 127825.0 * e ** 3 / 1296.0),
+     [lambda: pins.test_phase_coefficients_follow_from_pn_energy_and_flux(1.0)]),
+    ("phi7 eta^2 sign", "pn_coefficients",
+     lambda: _wrap_pn(6, lambda p, e, a, b: p + 2.0 * math.pi * 74045.0 * e ** 2 / 756.0),
+     [lambda: pins.test_phase_coefficients_follow_from_pn_energy_and_flux(0.2)]),
     ("tc sign", "phase", _phase_tc_sign, [pins.test_phase_constant_terms]),
     ("amplitude mass power", "amplitude", _amp_power, [pins.test_amplitude_matches_spa_of_quadrupole_chirp]),
     ("amplitude f exponent", "polarizations", lambda: _pol("fexp"), [pins.test_flat_psd_hurwitz_zeta_closed_form]),

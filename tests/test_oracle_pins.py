@@ -149,6 +149,57 @@ def test_phase_derivative_matches_2pn_time_frequency_relation(chi1, chi2):
     assert ratios[1] / ratios[2] == pytest.approx(32.0, rel=0.12)
 
 
+def stationary_phase_coefficients(eta, v):
+    """phi_k of the TaylorF2 series derived from the PN binding energy E(v) (to 3PN) and the GW
+    energy flux F(v) (to 3.5PN, with its 3PN logarithm) of a circular, non-spinning binary.
+
+    With E = -(eta M v^2 / 2) E^(v) and F = (32/5) eta^2 v^10 F^(v), the balance dE/dt = -F gives
+    dt/dv = (5M / (32 eta)) v^-9 R(v), R = (E^ + v E^'/2) / F^ = sum_k r_k v^k + r_6l v^6 ln v, and
+    the orbital phase obeys dphi/dv = (v^3 / M) dt/dv. The stationary-phase Fourier phase of the
+    dominant harmonic, Psi = 2 pi f t(v) - 2 phi(v) - pi/4 with pi M f = v^3, then is
+    2 pi f t_c - phi_c - pi/4 + 3 / (128 eta v^5) sum_k phi_k v^k, where integrating term by term
+      phi_k = 40 r_k / ((k - 8)(k - 5))           (k != 5),
+      phi_5 = -(40/9) r_5 (1 + 3 ln v)            (k = 5 integrates to a logarithm; the constant
+                                                  1 is the conventional split with phi_c),
+      phi_6 = -20 r_6 + 10 r_6l - 20 r_6l ln v    (the v^6 ln v term of R)."""
+    pi, ge = math.pi, 0.5772156649015329
+    e2 = -3.0 / 4.0 - eta / 12.0
+    e4 = -27.0 / 8.0 + 19.0 * eta / 8.0 - eta ** 2 / 24.0
+    e6 = (-675.0 / 64.0 + (34445.0 / 576.0 - 205.0 * pi ** 2 / 96.0) * eta - 155.0 * eta ** 2 / 96.0
+          - 35.0 * eta ** 3 / 5184.0)
+    f = [1.0, 0.0,
+         -1247.0 / 336.0 - 35.0 * eta / 12.0,
+         4.0 * pi,
+         -44711.0 / 9072.0 + 9271.0 * eta / 504.0 + 65.0 * eta ** 2 / 18.0,
+         -(8191.0 / 672.0 + 583.0 * eta / 24.0) * pi,
+         (6643739519.0 / 69854400.0 + 16.0 * pi ** 2 / 3.0 - 1712.0 * ge / 105.0 - 856.0 / 105.0 * math.log(16.0)
+          + (-134543.0 / 7776.0 + 41.0 * pi ** 2 / 48.0) * eta - 94403.0 * eta ** 2 / 3024.0
+          - 775.0 * eta ** 3 / 324.0),
+         (-16285.0 / 504.0 + 214745.0 * eta / 1728.0 + 193385.0 * eta ** 2 / 3024.0) * pi]
+    f6l = -2.0 * 856.0 / 105.0                       # the flux's -856/105 ln(16 v^2)
+    num = [1.0, 0.0, 2.0 * e2, 0.0, 3.0 * e4, 0.0, 4.0 * e6, 0.0]
+    r = [0.0] * 8                                    # power-series division num / F^
+    for k in range(8):
+        r[k] = num[k] - sum(f[j] * r[k - j] for j in range(1, k + 1))
+    r6l = -f6l                                       # the only v^6 ln v term below v^8
+    lv = math.log(v)
+    return {0: r[0], 2: 40.0 * r[2] / 18.0, 3: 40.0 * r[3] / 10.0, 4: 40.0 * r[4] / 4.0,
+            5: -40.0 / 9.0 * r[5] * (1.0 + 3.0 * lv), 6: -20.0 * r[6] + 10.0 * r6l - 20.0 * r6l * lv,
+            7: 40.0 * r[7] / -2.0}
+
+
+@pytest.mark.parametrize("q", [1.0, 0.5, 0.2])
+def test_phase_coefficients_follow_from_pn_energy_and_flux(q):
+    """Every non-spinning phase coefficient, the 2.5PN, 3PN and 3.5PN ones included, equals the
+    stationary-phase integral of the PN energy balance (an independent route to the same series)."""
+    for v in (0.05, 0.2, 0.4):
+        eta, _, phis = o.pn_coefficients(torch.tensor(30.0, dtype=DT), torch.tensor(q, dtype=DT), 0.0, 0.0,
+                                         torch.tensor(v, dtype=DT))
+        ref = stationary_phase_coefficients(float(eta), v)
+        for k, got in zip((0, 2, 3, 4, 5, 6, 7), phis):
+            assert float(got) == pytest.approx(ref[k], rel=1e-12, abs=1e-12), (k, q, v)
+
+
 def test_phase_constant_terms():
     """Psi carries 2 pi f tc - phic - pi/4: shifting tc by tau adds 2 pi f tau; shifting phic subtracts."""
     f = torch.tensor([25.0, 80.0, 700.0], dtype=DT)
