@@ -142,39 +142,119 @@ def slice_move(x, dirn, unif, m, inside):
     each draw from the interval as it would be if the earlier draws of its group had fallen
     outside. The first draw inside is the one the sequential procedure returns. A chain with no
     draw inside after SLICE_MAX_DRAWS keeps its point."""
+    lo, hi = _slice_stepping(x, dirn, unif[0], unif[1], m, inside)
+    done = torch.zeros(x.shape[0], dtype=torch.bool, device=x.device)
+    xn = x
+    for g0 in range(0, SLICE_MAX_DRAWS, SLICE_GROUP):
+        xn, done, lo, hi = _slice_group(x, dirn, lo, hi, done, xn, unif[2 + g0:2 + g0 + SLICE_GROUP], inside)
+        if bool(done.all()):
+            break
+    return xn, done
+
+
+def _slice_stepping(x, dirn, u0, u1, m, inside):
+    """The interval of a slice move after stepping out: (lo, hi) in units of dirn."""
     n, d = x.shape
-    f64 = dict(dtype=x.dtype, device=x.device)
-    lo, hi = -unif[0], 1.0 - unif[0]
+    lo, hi = -u0, 1.0 - u0
     if m > 1:
-        jl = torch.floor(m * unif[1])
+        jl = torch.floor(m * u1)
         jr = (m - 1) - jl
-        steps = torch.arange(m, **f64)
+        steps = torch.arange(m, dtype=x.dtype, device=x.device)
         ends = torch.cat([lo[None] - steps[:, None], hi[None] + steps[:, None]])          # [2m, n]
         ok = inside((x[None] + ends[..., None] * dirn[None]).reshape(-1, d)).reshape(2 * m, n)
         out_l = torch.where(ok[:m].all(0), m, torch.argmin(ok[:m].to(torch.int8), 0)).to(x.dtype)
         out_r = torch.where(ok[m:].all(0), m, torch.argmin(ok[m:].to(torch.int8), 0)).to(x.dtype)
         lo = lo - torch.minimum(out_l, jl)
         hi = hi + torch.minimum(out_r, jr)
-    done = torch.zeros(n, dtype=torch.bool, device=x.device)
-    xn = x
-    for g0 in range(0, SLICE_MAX_DRAWS, SLICE_GROUP):
-        ts = []
-        a, b = lo, hi
-        for k in range(g0, g0 + SLICE_GROUP):
-            t = a + unif[2 + k] * (b - a)
-            ts.append(t)
-            left = t < 0.0
-            a, b = torch.where(left, t, a), torch.where(left, b, t)
-        tt = torch.stack(ts)                                                              # [group, n]
-        ok = inside((x[None] + tt[..., None] * dirn[None]).reshape(-1, d)).reshape(SLICE_GROUP, n) & ~done[None]
-        hit = ok.any(0)
-        tsel = tt.gather(0, torch.argmax(ok.to(torch.int8), 0)[None])[0]
-        xn = torch.where(hit[:, None], x + tsel[:, None] * dirn, xn)
-        done = done | hit
-        lo, hi = torch.where(done, lo, a), torch.where(done, hi, b)
-        if bool(done.all()):
-            break
-    return xn, done
+    return lo, hi
+
+
+def _slice_group(x, dirn, lo, hi, done, xn, ug, inside):
+    """One group of shrinkage draws (ug[G, n], in order) for the chains not done yet."""
+    n, d = x.shape
+    ts = []
+    a, b = lo, hi
+    for k in range(ug.shape[0]):
+        t = a + ug[k] * (b - a)
+        ts.append(t)
+        left = t < 0.0
+        a, b = torch.where(left, t, a), torch.where(left, b, t)
+    tt = torch.stack(ts)                                                                  # [G, n]
+    ok = inside((x[None] + tt[..., None] * dirn[None]).reshape(-1, d)).reshape(ug.shape[0], n) & ~done[None]
+    hit = ok.any(0)
+    tsel = tt.gather(0, torch.argmax(ok.to(torch.int8), 0)[None])[0]
+    xn = torch.where(hit[:, None], x + tsel[:, None] * dirn, xn)
+    done = done | hit
+    return xn, done, torch.where(done, lo, a), torch.where(done, hi, b)
+
+
+class _SliceGraphs:
+    """The slice moves of one batch shape captured as two HIP graphs on the device: (A) a move's
+    direction, stepping out and first group of shrinkage draws; (B) one further group. The host
+    draws each move's random numbers into static buffers (the same calls, in the same order, as
+    the eager path, so both paths give the same chains bit for bit), replays A, and replays B
+    until every chain is done; the likelihood calls inside (prior transform, the library's
+    kernels) are part of the graphs."""
+
+    def __init__(self, smp, inside_raw):
+        n, d, m, G = smp.n, smp.d, smp.slice_out, SLICE_GROUP
+        f64 = dict(dtype=torch.float64, device=smp.dev)
+        self.smp = smp
+        # placeholders for the warm-up and the capture: points at the cube's centre, unit directions
+        self.x, self.z, self.dirn, self.xn = (torch.full((n, d), 0.5, **f64) for _ in range(4))
+        self.unif = torch.full((2 + SLICE_MAX_DRAWS, n), 0.5, **f64)
+        self.ub = torch.full((G, n), 0.5, **f64)
+        self.chol = torch.eye(d, **f64)
+        self.lmin = torch.full((), -math.inf, **f64)
+        self.lo, self.hi = torch.zeros(n, **f64), torch.zeros(n, **f64)
+        self.done = torch.zeros(n, dtype=torch.bool, device=smp.dev)
+        inside = lambda p: inside_raw(p, self.lmin)
+
+        def stage_a():
+            dirn = smp.slice_width * (self.z / self.z.norm(dim=1, keepdim=True)) @ self.chol.T
+            lo, hi = _slice_stepping(self.x, dirn, self.unif[0], self.unif[1], m, inside)
+            xn, done, lo, hi = _slice_group(self.x, dirn, lo, hi, torch.zeros_like(self.done), self.x,
+                                            self.unif[2:2 + G], inside)
+            for dst, src in ((self.dirn, dirn), (self.xn, xn), (self.done, done), (self.lo, lo), (self.hi, hi)):
+                dst.copy_(src)
+
+        def stage_b():
+            xn, done, lo, hi = _slice_group(self.x, self.dirn, self.lo, self.hi, self.done, self.xn, self.ub, inside)
+            for dst, src in ((self.xn, xn), (self.done, done), (self.lo, lo), (self.hi, hi)):
+                dst.copy_(src)
+
+        side = torch.cuda.Stream(device=smp.dev)
+        side.wait_stream(torch.cuda.current_stream(smp.dev))
+        with torch.cuda.stream(side):            # warm-up outside capture (allocator, kernels)
+            stage_a()
+            stage_b()
+        torch.cuda.current_stream(smp.dev).wait_stream(side)
+        torch.cuda.synchronize(smp.dev)
+        self.ga, self.gb = torch.cuda.CUDAGraph(), torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.ga):
+            stage_a()
+        with torch.cuda.graph(self.gb, pool=self.ga.pool()):
+            stage_b()
+        self.calls_a, self.calls_b = (2 * m + G) * n if m > 1 else G * n, G * n
+
+    def walk(self, x0, chol, lmin, steps):
+        smp, n, d = self.smp, self.smp.n, self.smp.d
+        self.x.copy_(x0)
+        self.chol.copy_(chol)
+        self.lmin.copy_(lmin)
+        for _ in range(steps):
+            torch.randn(n, d, generator=smp.gen, out=self.z)
+            torch.rand(2 + SLICE_MAX_DRAWS, n, generator=smp.gen, out=self.unif)
+            self.ga.replay()
+            smp.extra_calls += self.calls_a
+            for g0 in range(SLICE_GROUP, SLICE_MAX_DRAWS, SLICE_GROUP):
+                if bool(self.done.all()):
+                    break
+                self.ub.copy_(self.unif[2 + g0:2 + g0 + SLICE_GROUP])
+                self.gb.replay()
+                smp.extra_calls += self.calls_b
+            self.x.copy_(self.xn)
+        return self.x.clone()
 
 
 class ParallelNestedSampler:
@@ -192,7 +272,7 @@ class ParallelNestedSampler:
                  prior_transform: Optional[Callable] = None, device="cuda:0", seed: int = 0,
                  proposal="ellipsoid", enlarge: float = 1.25, volume: str = "order", check_every: int = 8,
                  loglike_grad: Optional[Callable] = None, gmc_steps: int = 20, slice_steps: Optional[int] = None,
-                 slice_width: float = 3.0, slice_out: int = 4):
+                 slice_width: float = 3.0, slice_out: int = 4, slice_graphs: bool = True):
         if nlive < 2 or batch < 1 or ndim < 1:
             raise ValueError("need nlive >= 2, batch >= 1, ndim >= 1")
         if volume not in ("order", "paper"):
@@ -212,6 +292,9 @@ class ParallelNestedSampler:
         if slice_width <= 0.0 or slice_out < 1:
             raise ValueError("need slice_width > 0 and slice_out >= 1")
         self.slice_width, self.slice_out = float(slice_width), int(slice_out)
+        # slice moves replayed from captured graphs on a CUDA device (None: not built yet)
+        self.slice_graphs = bool(slice_graphs) and self.dev.type == "cuda"
+        self._graphs = None
         self.extra_calls = 0
 
     # ---- proposals -------------------------------------------------------------------------
@@ -302,10 +385,13 @@ class ParallelNestedSampler:
         self._gmc_rate = acc_moves / self.gmc_steps
         return torch.where(moved[:, None], x, torch.full_like(x, 2.0))
 
-    def _in_contour(self, u, lmin):
+    def _inside_raw(self, u, lmin):
         l, inside = self._loglike(u)
-        self.extra_calls += u.shape[0]
         return inside & (l >= lmin)
+
+    def _in_contour(self, u, lmin):
+        self.extra_calls += u.shape[0]
+        return self._inside_raw(u, lmin)
 
     def _slice(self, live_u, live_l):
         """Slice-sampling walks inside the contour L >= L_min, one chain per candidate: each chain
@@ -320,6 +406,10 @@ class ParallelNestedSampler:
         xc = live_u - live_u.mean(0)
         cov = xc.T @ xc / (K - 1) + 1e-14 * torch.eye(d, **f64)
         chol, _ = torch.linalg.cholesky_ex(cov)
+        if self.slice_graphs:
+            if self._graphs is None:
+                self._graphs = _SliceGraphs(self, self._inside_raw)
+            return self._graphs.walk(x, chol, lmin, self.slice_steps)
         inside = lambda p: self._in_contour(p, lmin)
         for _ in range(self.slice_steps):
             z = torch.randn(n, d, generator=self.gen, **f64)

@@ -351,3 +351,27 @@ def test_gw_slice_nested_sampling_matches_importance_sampling():
     assert rel < 0.1 and ess > 100
     assert abs(res.logz - lz_is) < 1.5
     ev.close()
+
+
+@pytest.mark.gpu
+def test_slice_graphs_replay_the_eager_moves():
+    """The slice moves replayed from captured graphs give the eager moves bit for bit: the same
+    dead points, likelihoods and call counts over a few iterations of a GW run."""
+    from paper_1909_11873_amd import gwlike as gw
+
+    spec, th0, f, psd, data, dets, l0 = quiet_c0_event()
+    ev = gw.Event(torch.tensor(data, device=DEV), torch.tensor(psd, device=DEV), dets,
+                  torch.tensor(f, device=DEV), spec.df)
+    runs = []
+    for graphs in (True, False):
+        smp = nested.ParallelNestedSampler(lambda th: gw.logl(th, ev, "mixed"), 11, 200, 256, proposal="slice",
+                                           slice_steps=6, slice_graphs=graphs, device=DEV, seed=12,
+                                           prior_transform=nested.gw_prior_transform(spins=False))
+        runs.append(smp.run(eps=0.1, max_iter=12))
+    a, b = runs
+    assert a.niter == b.niter == 12
+    np.testing.assert_array_equal(a.u, b.u)
+    np.testing.assert_array_equal(a.logl, b.logl)
+    assert a.ncall == b.ncall
+    ev.close()
+
