@@ -3,7 +3,8 @@
 This is the paper's section 3 ("Parallel Nested Sampling") and its algorithm "Static Parallel
 Nested Sampling" with the pool of workers replaced by one batch of candidates per iteration.
 Everything stays on the device; one iteration is a fixed sequence of launches with no host
-synchronisation (the host reads the stop flag every few iterations):
+synchronisation (the host reads the stop flag every few iterations; the slice-sampling proposal
+also asks, after each group of shrinkage draws, whether every chain has finished):
 
   1. L_min is the first live log-likelihood (the live set is kept sorted ascending).
   2. n candidates in the unit cube: prior draws (the paper's proposal), draws from the bounding
