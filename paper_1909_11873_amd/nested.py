@@ -195,7 +195,9 @@ class _SliceGraphs:
     draws each move's random numbers into static buffers (the same calls, in the same order, as
     the eager path, so both paths give the same chains bit for bit), replays A, and replays B
     until every chain is done; the likelihood calls inside (prior transform, the library's
-    kernels) are part of the graphs."""
+    kernels) are part of the graphs, with the device addresses they had at capture: the sampler
+    captures again at the start of every run, and the likelihood's data (an event's tables) must
+    stay alive while a run lasts."""
 
     def __init__(self, smp, inside_raw):
         n, d, m, G = smp.n, smp.d, smp.slice_out, SLICE_GROUP
@@ -444,6 +446,9 @@ class ParallelNestedSampler:
         f64 = dict(dtype=torch.float64, device=dev)
         t0 = time.perf_counter()
         self.extra_calls = 0
+        # captured slice moves hold the device pointers of the likelihood they were captured with
+        # (for the GW likelihood: the event's tables), so every run captures them again
+        self._graphs = None
         if live_u is None:
             live_u = torch.rand(K, d, generator=self.gen, **f64)
         live_u = live_u.to(**f64).contiguous()
