@@ -91,6 +91,31 @@ __device__ inline double epilogue_value(const double (&acc)[NZ], const double (&
   return out;
 }
 
+// The same value from the point's set-up rows (A, Q_det and c0 as the point model gave them; a
+// point outside the model's domain has NaN rows and gets NaN), so the forward epilogue does not
+// evaluate the point model a second time.
+template <int ND, int NZ>
+__device__ inline double epilogue_value_rows(const double (&acc)[NZ], const double* __restrict__ coef, int64_t Bp,
+                                             int64_t p, const EventConst& ec, double uref) {
+  const double amp = coef[CO_AMP * Bp + p];
+  const double c0f = coef[CO_C0 * Bp + p];
+  const double c0 = c0f - rint(c0f);
+  double es, ecs;
+  sincos_cycles_f64(c0, es, ecs);
+  const double er = ecs, ei = -es;
+  double out = 0.0;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    const double qr = coef[(CO_QR + d) * Bp + p], qi = coef[(CO_QI + d) * Bp + p];
+    const double xr = amp * (er * qr - ei * qi);
+    const double xi = amp * (er * qi + ei * qr);
+    const double dh = uref * (xr * acc[2 * d] - xi * acc[2 * d + 1]);
+    const double hh = amp * amp * (qr * qr + qi * qi) * ec.K[d];
+    out += dh - 0.5 * hh;
+  }
+  return out;
+}
+
 // Gradient. With w_det = u p, p = exp(-2 pi i (psi_k + f_k T_det)) and y_det = Im(c_det w_det),
 // the bin loop accumulated per point
 //   Z_det = sum_k w_det,  Z1_det = sum_k f_k y_det,  Y_m = sum_k g_m(f_k) sum_det y_det.

@@ -37,11 +37,12 @@ hipError_t launch_bins(int nd, bool mixed, bool grad, const void* tab, const voi
                        const double* coef, int64_t B, int64_t Bp, int64_t M, const LoopShape& sh, double* part,
                        hipStream_t s);
 
-// epilogue: partial sums -> logL[B] (and grad[B][11])
+// epilogue: partial sums -> logL[B] (and grad[B][11]); the value alone reads the set-up rows
+// `coef`, the gradient evaluates the point model from theta
 // `scaled`: the partial sums came from the float32 tables, which hold u / uref
 hipError_t launch_epilogue(int nd, bool grad, bool scaled, const EventGeom& g, const EventConst* ec,
-                           const double* theta, int64_t B, int64_t Bp, int nchunk, const double* part, double* logl,
-                           double* gradout, hipStream_t s);
+                           const double* theta, const double* coef, int64_t B, int64_t Bp, int nchunk,
+                           const double* part, double* logl, double* gradout, hipStream_t s);
 
 // float32 rows from float64 rows: tab32 = (basis, u / ec->uref)
 hipError_t launch_prep_mixed(int nd, const void* tab64, int64_t M, const EventConst* ec, void* tab32, hipStream_t s);

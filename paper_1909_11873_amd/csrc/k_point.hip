@@ -47,8 +47,8 @@ hipError_t launch_setup(int nd, const EventGeom& g, const EventConst* ec, bool s
 }
 
 template <int ND>
-__global__ __launch_bounds__(PT_BLOCK) void k_epilogue(EventGeom g, const EventConst* __restrict__ ec,
-                                                       const double* __restrict__ theta, int64_t B, int64_t Bp,
+__global__ __launch_bounds__(PT_BLOCK) void k_epilogue(const EventConst* __restrict__ ec,
+                                                       const double* __restrict__ coef, int64_t B, int64_t Bp,
                                                        int nchunk, bool scaled, const double* __restrict__ part,
                                                        double* __restrict__ logl) {
   const int64_t p = (int64_t)blockIdx.x * PT_BLOCK + threadIdx.x;
@@ -58,12 +58,7 @@ __global__ __launch_bounds__(PT_BLOCK) void k_epilogue(EventGeom g, const EventC
   double acc[NZ];
   gather<NZ>(part, nchunk, Bp, p, acc);
   if (scaled) apply_gain<ND>(e, acc);
-  double th[NPARAM];
-#pragma unroll
-  for (int i = 0; i < NPARAM; ++i) th[i] = theta[p * NPARAM + i];
-  bool valid;
-  const double v = epilogue_value<ND, NZ>(acc, th, g, e, scaled ? e.uref : 1.0, valid);
-  logl[p] = valid ? v : __builtin_nan("");
+  logl[p] = epilogue_value_rows<ND, NZ>(acc, coef, Bp, p, e, scaled ? e.uref : 1.0);
 }
 
 template <int ND>
@@ -90,8 +85,8 @@ __global__ __launch_bounds__(PT_BLOCK) void k_epilogue_grad(EventGeom g, const E
 }
 
 hipError_t launch_epilogue(int nd, bool grad, bool scaled, const EventGeom& g, const EventConst* ec, const double* theta,
-                           int64_t B, int64_t Bp, int nchunk, const double* part, double* logl, double* gradout,
-                           hipStream_t s) {
+                           const double* coef, int64_t B, int64_t Bp, int nchunk, const double* part, double* logl,
+                           double* gradout, hipStream_t s) {
   dim3 grid((unsigned)((B + PT_BLOCK - 1) / PT_BLOCK));
 #define GWL_EPI(N)                                                                                                  \
   case N:                                                                                                           \
@@ -99,8 +94,7 @@ hipError_t launch_epilogue(int nd, bool grad, bool scaled, const EventGeom& g, c
       hipLaunchKernelGGL(k_epilogue_grad<N>, grid, dim3(PT_BLOCK), 0, s, g, ec, theta, B, Bp, nchunk, scaled, part, \
                          logl, gradout);                                                                            \
     else                                                                                                            \
-      hipLaunchKernelGGL(k_epilogue<N>, grid, dim3(PT_BLOCK), 0, s, g, ec, theta, B, Bp, nchunk, scaled, part, \
-                         logl);                                                                                     \
+      hipLaunchKernelGGL(k_epilogue<N>, grid, dim3(PT_BLOCK), 0, s, ec, coef, B, Bp, nchunk, scaled, part, logl);   \
     break;
   switch (nd) {
     GWL_EPI(1)

@@ -164,20 +164,19 @@ __global__ __launch_bounds__(MULTI_PT_BLOCK) void k_multi_epilogue(const MultiEv
     double acc[NZ];
     gather<NZ>(ev.part, ev.nchunk, ev.Bp, p, acc);
     if (scaled) apply_gain<ND>(ec, acc);
-    double th[NPARAM];
-#pragma unroll
-    for (int i = 0; i < NPARAM; ++i) th[i] = o.theta[p * NPARAM + i];
-    const double nan = __builtin_nan("");
-    bool valid;
     if constexpr (GRAD) {
+      double th[NPARAM];
+#pragma unroll
+      for (int i = 0; i < NPARAM; ++i) th[i] = o.theta[p * NPARAM + i];
+      const double nan = __builtin_nan("");
+      bool valid;
       double gout[NPARAM];
       const double v = epilogue_gradient<ND>(acc, th, geoms[e], ec, scaled ? ec.uref : 1.0, valid, gout);
       o.logl[p] = valid ? v : nan;
 #pragma unroll
       for (int j = 0; j < NPARAM; ++j) o.grad[p * NPARAM + j] = valid ? gout[j] : nan;
     } else {
-      const double v = epilogue_value<ND, NZ>(acc, th, geoms[e], ec, scaled ? ec.uref : 1.0, valid);
-      o.logl[p] = valid ? v : nan;
+      o.logl[p] = epilogue_value_rows<ND, NZ>(acc, ev.coef, ev.Bp, p, ec, scaled ? ec.uref : 1.0);
     }
   }
   if (threadIdx.x == 0) atomicMax(&ctl->tend, wall_clock64());

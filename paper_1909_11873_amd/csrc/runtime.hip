@@ -565,7 +565,8 @@ hipError_t enqueue_logl(gwl_event ev, const double* theta, int64_t B, bool mixed
                     part, s);
   if (prof) prof_end(s, pa, pb);
   if (e == hipSuccess)
-    e = launch_epilogue(ev->ndet, grad, mixed, ev->geom, ev->ec, theta, B, Bp, sh.nchunk, part, logl, gradout, s);
+    e = launch_epilogue(ev->ndet, grad, mixed, ev->geom, ev->ec, theta, coef, B, Bp, sh.nchunk, part, logl, gradout,
+                        s);
   return e;
 }
 
