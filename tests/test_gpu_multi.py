@@ -178,3 +178,41 @@ def test_c4_full_workload_sampled():
     plan.close()
     for ev in evs:
         ev.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_multi_with_relative_binning_events(events, prec):
+    """A plan may mix relative-binning events (rows on the edges, the fiducial's phase subtracted
+    at set-up) with full-grid events: each event's results equal its single-event calls."""
+    mixed_events = []
+    for i, e in enumerate(events):
+        if i % 2 == 0:
+            fid = synth.event_spec(4, i).theta0
+            ev = gw.Event(torch.tensor(e["data"], device=DEV), torch.tensor(e["psd"], device=DEV), e["dets"],
+                          torch.tensor(e["f"], device=DEV), e["df"], fiducial=fid, rb_eps=0.2)
+            assert 0 < ev.rb_edges < len(e["f"])
+            mixed_events.append(ev)
+        else:
+            mixed_events.append(e["ev"])
+    # points near each event's fiducial, where relative binning is meant to be used
+    rng = np.random.default_rng(5)
+    step = np.array([0.05, 0.01, 0.02, 0.02, 10.0, 0.01, 0.01, 0.02, 0.02, 0.05, 1e-4]) * 0.3
+    thetas = [torch.tensor(synth.event_spec(4, i).theta0 + step * rng.standard_normal((b, 11)), device=DEV)
+              for i, b in enumerate(BATCHES)]
+    for grad in (False, True):
+        plan = gw.MultiPlan(mixed_events, BATCHES, prec, with_grad=grad)
+        logls, grads, _ = plan.launch(thetas)
+        for ev, t, l, g in zip(mixed_events, thetas, logls, grads if grad else [None] * len(thetas)):
+            if t.shape[0] == 0:
+                continue
+            if grad:
+                sv, sg = gw.logl_grad(t, ev, prec)
+                tol = 1e-8 if prec == "fp64" else 2e-4
+                assert np.abs(g.cpu().numpy() - sg.cpu().numpy()).max() <= tol * max(1.0, float(sg.abs().max()))
+            else:
+                sv = gw.logl(t, ev, prec)
+            assert np.abs(l.cpu().numpy() - sv.cpu().numpy()).max() <= (1e-8 if prec == "fp64" else 2e-4)
+        plan.close()
+    for i, ev in enumerate(mixed_events):
+        if i % 2 == 0:
+            ev.close()
