@@ -35,6 +35,7 @@ from __future__ import annotations
 import dataclasses
 import math
 import time
+import warnings
 from typing import Callable, Optional
 
 import numpy as np
@@ -296,7 +297,8 @@ class ParallelNestedSampler:
             raise ValueError("need slice_width > 0 and slice_out >= 1")
         self.slice_width, self.slice_out = float(slice_width), int(slice_out)
         # slice moves replayed from captured graphs on a CUDA device (None: not built yet)
-        self.slice_graphs = bool(slice_graphs) and self.dev.type == "cuda"
+        self.slice_graphs_requested = bool(slice_graphs) and self.dev.type == "cuda"
+        self.slice_graphs = self.slice_graphs_requested
         self._graphs = None
         self.extra_calls = 0
 
@@ -409,9 +411,13 @@ class ParallelNestedSampler:
         xc = live_u - live_u.mean(0)
         cov = xc.T @ xc / (K - 1) + 1e-14 * torch.eye(d, **f64)
         chol, _ = torch.linalg.cholesky_ex(cov)
-        if self.slice_graphs:
-            if self._graphs is None:
+        if self.slice_graphs and self._graphs is None:
+            try:
                 self._graphs = _SliceGraphs(self, self._inside_raw)
+            except Exception as exc:      # a likelihood that cannot be captured: eager moves
+                warnings.warn(f"slice moves run eagerly: capturing them failed ({exc})")
+                self.slice_graphs = False
+        if self.slice_graphs:
             return self._graphs.walk(x, chol, lmin, self.slice_steps)
         inside = lambda p: self._in_contour(p, lmin)
         for _ in range(self.slice_steps):
@@ -449,6 +455,7 @@ class ParallelNestedSampler:
         # captured slice moves hold the device pointers of the likelihood they were captured with
         # (for the GW likelihood: the event's tables), so every run captures them again
         self._graphs = None
+        self.slice_graphs = self.slice_graphs_requested
         if live_u is None:
             live_u = torch.rand(K, d, generator=self.gen, **f64)
         live_u = live_u.to(**f64).contiguous()

@@ -375,3 +375,33 @@ def test_slice_graphs_replay_the_eager_moves():
     assert a.ncall == b.ncall
     ev.close()
 
+
+@pytest.mark.gpu
+def test_slice_moves_fall_back_to_eager_when_capture_fails():
+    """A likelihood that cannot run under graph capture (here: one that refuses to) makes the
+    sampler warn and move eagerly, with the same result as asking for eager moves."""
+    from paper_1909_11873_amd import gwlike as gw
+
+    spec, th0, f, psd, data, dets, l0 = quiet_c0_event()
+    ev = gw.Event(torch.tensor(data, device=DEV), torch.tensor(psd, device=DEV), dets,
+                  torch.tensor(f, device=DEV), spec.df)
+
+    def refusing(th):
+        if torch.cuda.is_current_stream_capturing():
+            raise RuntimeError("this likelihood does not run under capture")
+        return gw.logl(th, ev, "mixed")
+
+    runs = []
+    for graphs in (True, False):
+        smp = nested.ParallelNestedSampler(refusing, 11, 100, 128, proposal="slice", slice_steps=3,
+                                           slice_graphs=graphs, device=DEV, seed=8,
+                                           prior_transform=nested.gw_prior_transform(spins=False))
+        if graphs:
+            with pytest.warns(UserWarning, match="eagerly"):
+                runs.append(smp.run(eps=0.1, max_iter=5))
+        else:
+            runs.append(smp.run(eps=0.1, max_iter=5))
+    np.testing.assert_array_equal(runs[0].u, runs[1].u)
+    assert runs[0].ncall == runs[1].ncall
+    ev.close()
+
