@@ -241,6 +241,48 @@ gwl_status gwl_autotune_load(const char* cache_path);
 gwl_status gwl_profile_enable(int on);
 gwl_status gwl_profile_read(int64_t* launches, double* total_ms);
 
+/*
+ * Slice-sampling support for a sampler above the likelihood (the walks that propose the
+ * candidates of the paper's section 3 algorithm; procedure: Neal 2003, "Slice sampling",
+ * sections 4.1 and 4.2). One slice move of n chains in d dimensions is: place an interval
+ * [x - u0 dirn, x + (1 - u0) dirn] on each chain's line, step its ends out by whole lengths while
+ * they lie inside the region (at most jl = floor(m u1) steps to the left and jr = m - 1 - jl to
+ * the right), then draw t uniformly from [lo, hi], shrinking the interval to the draw after
+ * every draw outside, until a draw lands inside. These calls do the bookkeeping; the caller
+ * evaluates ln L at the points they write and passes the values back. The region is {p in the
+ * unit cube, ln L(p) >= lmin}; a NaN ln L counts as outside.
+ *
+ * All arrays are float64 device memory, row-major, owned by the caller; `lmin` points to one
+ * device double; `done` is one byte per chain (0 or 1). Every product and sum is rounded on its
+ * own, in the order written above (no fused multiply-add), so the results equal those of the
+ * same steps taken one array operation at a time. Calls are stream-ordered on `stream`;
+ * GWL_E_SHAPE for n < 1, d < 1, m < 1 or G < 1, GWL_E_INVALID for a null pointer.
+ *
+ * gwl_slice_ends: lo = -u0, hi = 1 - u0, jl, jr as above, and the 2m candidate ends of every
+ *   chain, pts[(j n + i) d ..] = x_i + (lo_i - j) dirn_i and pts[((m + j) n + i) d ..] =
+ *   x_i + (hi_i + j) dirn_i for j = 0..m-1.
+ * gwl_slice_ends_select: with logl[2m n] the values at those ends: lo -= min(steps left, jl),
+ *   hi += min(steps right, jr), where the steps on a side are the index of its first end outside
+ *   the region (m if none).
+ * gwl_slice_draws: G shrinkage draws per chain, each from the interval as it would be if the
+ *   earlier draws had fallen outside: t_k = a + u_k (b - a) from (a, b) = (lo, hi), then a = t_k
+ *   if t_k < 0 else b = t_k; writes t[k n + i], the points pts[(k n + i) d ..] = x_i + t_k dirn_i,
+ *   and the final (a, b).
+ * gwl_slice_select: with logl[G n] the values at those points, for every chain not yet done:
+ *   the first draw inside the region (if any) gives xn = x + t dirn and done = 1; a chain still
+ *   not done takes (lo, hi) = (a, b).
+ */
+gwl_status gwl_slice_ends(int64_t n, int d, int m, const double* x, const double* dirn, const double* u0,
+                          const double* u1, double* pts, double* lo, double* hi, double* jl, double* jr, void* stream);
+gwl_status gwl_slice_ends_select(int64_t n, int d, int m, const double* pts, const double* logl, const double* lmin,
+                                 double* lo, double* hi, const double* jl, const double* jr, void* stream);
+gwl_status gwl_slice_draws(int64_t n, int d, int G, const double* x, const double* dirn, const double* lo,
+                           const double* hi, const double* u, double* t, double* pts, double* a, double* b,
+                           void* stream);
+gwl_status gwl_slice_select(int64_t n, int d, int G, const double* x, const double* dirn, const double* t,
+                            const double* pts, const double* logl, const double* lmin, const double* a,
+                            const double* b, double* xn, unsigned char* done, double* lo, double* hi, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

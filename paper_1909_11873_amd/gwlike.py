@@ -77,6 +77,10 @@ def lib() -> ctypes.CDLL:
         "gwl_launch_shape": ([vp, i64, cint, cint, ctypes.POINTER(cint), ctypes.POINTER(cint)], cint),
         "gwl_profile_enable": ([cint], cint),
         "gwl_profile_read": ([ctypes.POINTER(i64), ctypes.POINTER(dbl)], cint),
+        "gwl_slice_ends": ([i64, cint, cint] + [vp] * 9 + [vp], cint),
+        "gwl_slice_ends_select": ([i64, cint, cint] + [vp] * 7 + [vp], cint),
+        "gwl_slice_draws": ([i64, cint, cint] + [vp] * 9 + [vp], cint),
+        "gwl_slice_select": ([i64, cint, cint] + [vp] * 12 + [vp], cint),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -395,3 +399,73 @@ def profile_read():
 
 def version() -> str:
     return lib().gwl_version().decode()
+
+
+# ---- slice-sampling bookkeeping (gwl_slice_*): n chains in d dimensions -----------------------
+def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _f64(t: torch.Tensor, name: str, shape) -> torch.Tensor:
+    t = _dev(t, name, torch.float64)
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, not {tuple(t.shape)}")
+    return t
+
+
+def slice_ends(x: torch.Tensor, dirn: torch.Tensor, u0: torch.Tensor, u1: torch.Tensor, m: int):
+    """(pts[2m n, d], lo, hi, jl, jr): the initial interval of every chain and its 2m candidate ends."""
+    n, d = x.shape
+    x, dirn = _f64(x, "x", (n, d)), _f64(dirn, "dirn", (n, d))
+    u0, u1 = _f64(u0, "u0", (n,)), _f64(u1, "u1", (n,))
+    pts = torch.empty(2 * m * n, d, dtype=torch.float64, device=x.device)
+    lo, hi, jl, jr = (torch.empty(n, dtype=torch.float64, device=x.device) for _ in range(4))
+    _check("gwl_slice_ends", lib().gwl_slice_ends(n, d, m, _ptr(x), _ptr(dirn), _ptr(u0), _ptr(u1), _ptr(pts),
+                                                  _ptr(lo), _ptr(hi), _ptr(jl), _ptr(jr), _stream(x)))
+    return pts, lo, hi, jl, jr
+
+
+def slice_ends_select(pts, logl, lmin, lo, hi, jl, jr, m: int) -> None:
+    """Steps the interval ends out (in place on lo, hi) given ln L at the candidate ends."""
+    n = lo.shape[0]
+    d = pts.shape[1]
+    for t, name in ((lo, "lo"), (hi, "hi")):
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.shape == (n,)):
+            raise ValueError(f"{name} must be a contiguous float64 CUDA tensor of shape ({n},)")
+    pts, logl = _f64(pts, "pts", (2 * m * n, d)), _f64(logl, "logl", (2 * m * n,))
+    lmin, jl, jr = _f64(lmin, "lmin", ()), _f64(jl, "jl", (n,)), _f64(jr, "jr", (n,))
+    _check("gwl_slice_ends_select", lib().gwl_slice_ends_select(n, d, m, _ptr(pts), _ptr(logl), _ptr(lmin), _ptr(lo),
+                                                                _ptr(hi), _ptr(jl), _ptr(jr), _stream(pts)))
+
+
+def slice_draws(x, dirn, lo, hi, u):
+    """(t[G, n], pts[G n, d], a, b): G shrinkage draws per chain and the interval after them,
+    each draw taken as if the earlier ones had fallen outside."""
+    n, d = x.shape
+    G = u.shape[0]
+    x, dirn = _f64(x, "x", (n, d)), _f64(dirn, "dirn", (n, d))
+    lo, hi, u = _f64(lo, "lo", (n,)), _f64(hi, "hi", (n,)), _f64(u, "u", (G, n))
+    t = torch.empty(G, n, dtype=torch.float64, device=x.device)
+    pts = torch.empty(G * n, d, dtype=torch.float64, device=x.device)
+    a, b = torch.empty_like(lo), torch.empty_like(lo)
+    _check("gwl_slice_draws", lib().gwl_slice_draws(n, d, G, _ptr(x), _ptr(dirn), _ptr(lo), _ptr(hi), _ptr(u), _ptr(t),
+                                                    _ptr(pts), _ptr(a), _ptr(b), _stream(x)))
+    return t, pts, a, b
+
+
+def slice_select(x, dirn, t, pts, logl, lmin, a, b, xn, done, lo, hi) -> None:
+    """For every chain not done: the first draw inside the region becomes its point (xn, done);
+    otherwise its interval becomes (a, b). In place on xn, done, lo, hi."""
+    n, d = x.shape
+    G = t.shape[0]
+    for v, name, shape, dt in ((xn, "xn", (n, d), torch.float64), (done, "done", (n,), torch.bool),
+                               (lo, "lo", (n,), torch.float64), (hi, "hi", (n,), torch.float64)):
+        if not (v.is_cuda and v.dtype == dt and v.is_contiguous() and tuple(v.shape) == shape):
+            raise ValueError(f"{name} must be a contiguous {dt} CUDA tensor of shape {shape}")
+    x, dirn, t = _f64(x, "x", (n, d)), _f64(dirn, "dirn", (n, d)), _f64(t, "t", (G, n))
+    pts, logl, lmin = _f64(pts, "pts", (G * n, d)), _f64(logl, "logl", (G * n,)), _f64(lmin, "lmin", ())
+    a, b = _f64(a, "a", (n,)), _f64(b, "b", (n,))
+    _check("gwl_slice_select", lib().gwl_slice_select(n, d, G, _ptr(x), _ptr(dirn), _ptr(t), _ptr(pts), _ptr(logl),
+                                                      _ptr(lmin), _ptr(a), _ptr(b), _ptr(xn), _ptr(done), _ptr(lo),
+                                                      _ptr(hi), _stream(x)))
+

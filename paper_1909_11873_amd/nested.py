@@ -190,6 +190,41 @@ def _slice_group(x, dirn, lo, hi, done, xn, ug, inside):
     return xn, done, torch.where(done, lo, a), torch.where(done, hi, b)
 
 
+def _slice_stepping_dev(x, dirn, u0, u1, m, raw, lmin):
+    """_slice_stepping with the library's kernels (gwl_slice_ends / _ends_select); raw(p) is
+    ln L at the points p (NaN allowed), lmin a device scalar. Same arithmetic, same results."""
+    if m <= 1:
+        return -u0, 1.0 - u0
+    from . import gwlike as gw
+    pts, lo, hi, jl, jr = gw.slice_ends(x, dirn, u0, u1, m)
+    gw.slice_ends_select(pts, raw(pts), lmin, lo, hi, jl, jr, m)
+    return lo, hi
+
+
+def _slice_group_dev(x, dirn, lo, hi, done, xn, ug, raw, lmin):
+    """_slice_group with the library's kernels (gwl_slice_draws / _select), in place on xn, done,
+    lo and hi."""
+    from . import gwlike as gw
+    t, pts, a, b = gw.slice_draws(x, dirn, lo, hi, ug)
+    gw.slice_select(x, dirn, t, pts, raw(pts), lmin, a, b, xn, done, lo, hi)
+    return xn, done, lo, hi
+
+
+def slice_move_dev(x, dirn, unif, m, raw, lmin):
+    """slice_move with the bookkeeping in the library's kernels: the candidate ends and draws
+    are written by one kernel per stage and judged by another, between them one call of raw(p)
+    (ln L at the points, NaN allowed); the region is {p in the cube, ln L(p) >= lmin}."""
+    lo, hi = _slice_stepping_dev(x, dirn, unif[0], unif[1], m, raw, lmin)
+    lo, hi = lo.contiguous(), hi.contiguous()
+    done = torch.zeros(x.shape[0], dtype=torch.bool, device=x.device)
+    xn = x.clone()
+    for g0 in range(0, SLICE_MAX_DRAWS, SLICE_GROUP):
+        _slice_group_dev(x, dirn, lo, hi, done, xn, unif[2 + g0:2 + g0 + SLICE_GROUP], raw, lmin)
+        if bool(done.all()):
+            break
+    return xn, done
+
+
 class _SliceGraphs:
     """The slice moves of one batch shape captured as two HIP graphs on the device: (A) a move's
     direction, stepping out and first group of shrinkage draws; (B) one further group. The host
@@ -200,7 +235,7 @@ class _SliceGraphs:
     captures again at the start of every run, and the likelihood's data (an event's tables) must
     stay alive while a run lasts."""
 
-    def __init__(self, smp, inside_raw):
+    def __init__(self, smp):
         n, d, m, G = smp.n, smp.d, smp.slice_out, SLICE_GROUP
         f64 = dict(dtype=torch.float64, device=smp.dev)
         self.smp = smp
@@ -212,33 +247,35 @@ class _SliceGraphs:
         self.lmin = torch.full((), -math.inf, **f64)
         self.lo, self.hi = torch.zeros(n, **f64), torch.zeros(n, **f64)
         self.done = torch.zeros(n, dtype=torch.bool, device=smp.dev)
-        inside = lambda p: inside_raw(p, self.lmin)
+        stepping, group = smp._slice_stages(self.lmin, count=False)
 
         def stage_a():
-            dirn = smp.slice_width * (self.z / self.z.norm(dim=1, keepdim=True)) @ self.chol.T
-            lo, hi = _slice_stepping(self.x, dirn, self.unif[0], self.unif[1], m, inside)
-            xn, done, lo, hi = _slice_group(self.x, dirn, lo, hi, torch.zeros_like(self.done), self.x,
-                                            self.unif[2:2 + G], inside)
-            for dst, src in ((self.dirn, dirn), (self.xn, xn), (self.done, done), (self.lo, lo), (self.hi, hi)):
-                dst.copy_(src)
+            self.dirn.copy_(smp.slice_width * (self.z / self.z.norm(dim=1, keepdim=True)) @ self.chol.T)
+            lo, hi = stepping(self.x, self.dirn, self.unif[0], self.unif[1])
+            self.lo.copy_(lo)
+            self.hi.copy_(hi)
+            self.done.zero_()
+            self.xn.copy_(self.x)
+            stage_b(self.unif[2:2 + G])
 
-        def stage_b():
-            xn, done, lo, hi = _slice_group(self.x, self.dirn, self.lo, self.hi, self.done, self.xn, self.ub, inside)
+        def stage_b(ug):
+            xn, done, lo, hi = group(self.x, self.dirn, self.lo, self.hi, self.done, self.xn, ug)
             for dst, src in ((self.xn, xn), (self.done, done), (self.lo, lo), (self.hi, hi)):
-                dst.copy_(src)
+                if dst is not src:
+                    dst.copy_(src)
 
         side = torch.cuda.Stream(device=smp.dev)
         side.wait_stream(torch.cuda.current_stream(smp.dev))
         with torch.cuda.stream(side):            # warm-up outside capture (allocator, kernels)
             stage_a()
-            stage_b()
+            stage_b(self.ub)
         torch.cuda.current_stream(smp.dev).wait_stream(side)
         torch.cuda.synchronize(smp.dev)
         self.ga, self.gb = torch.cuda.CUDAGraph(), torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.ga):
             stage_a()
         with torch.cuda.graph(self.gb, pool=self.ga.pool()):
-            stage_b()
+            stage_b(self.ub)
         self.calls_a, self.calls_b = (2 * m + G) * n if m > 1 else G * n, G * n
 
     def walk(self, x0, chol, lmin, steps):
@@ -276,7 +313,8 @@ class ParallelNestedSampler:
                  prior_transform: Optional[Callable] = None, device="cuda:0", seed: int = 0,
                  proposal="ellipsoid", enlarge: float = 1.25, volume: str = "order", check_every: int = 8,
                  loglike_grad: Optional[Callable] = None, gmc_steps: int = 20, slice_steps: Optional[int] = None,
-                 slice_width: float = 3.0, slice_out: int = 4, slice_graphs: bool = True):
+                 slice_width: float = 3.0, slice_out: int = 4, slice_graphs: bool = True,
+                 slice_kernels: Optional[bool] = None):
         if nlive < 2 or batch < 1 or ndim < 1:
             raise ValueError("need nlive >= 2, batch >= 1, ndim >= 1")
         if volume not in ("order", "paper"):
@@ -298,6 +336,11 @@ class ParallelNestedSampler:
         self.slice_width, self.slice_out = float(slice_width), int(slice_out)
         # slice moves replayed from captured graphs on a CUDA device (None: not built yet)
         self.slice_graphs_requested = bool(slice_graphs) and self.dev.type == "cuda"
+        # slice-move bookkeeping in the library's kernels (default on a CUDA device), else in
+        # torch array operations; both give the same chains
+        self.slice_kernels = (self.dev.type == "cuda") if slice_kernels is None else bool(slice_kernels)
+        if self.slice_kernels and self.dev.type != "cuda":
+            raise ValueError("slice_kernels needs a CUDA device")
         self.slice_graphs = self.slice_graphs_requested
         self._graphs = None
         self.extra_calls = 0
@@ -398,6 +441,26 @@ class ParallelNestedSampler:
         self.extra_calls += u.shape[0]
         return self._inside_raw(u, lmin)
 
+    def _raw(self, u):
+        """ln L at the points u (clamped into the cube), NaN kept: the slice kernels judge the
+        cube and the contour themselves."""
+        return self.loglike(self.transform(u.clamp(0.0, 1.0)))
+
+    def _slice_stages(self, lmin, count=True):
+        """(stepping(x, dirn, u0, u1) -> (lo, hi), group(x, dirn, lo, hi, done, xn, ug) ->
+        (xn, done, lo, hi)) for the contour ln L >= lmin, in the library's kernels or in torch."""
+        m = self.slice_out
+        if self.slice_kernels:
+            def raw(p):
+                if count:
+                    self.extra_calls += p.shape[0]
+                return self._raw(p)
+            return (lambda x, dirn, u0, u1: _slice_stepping_dev(x, dirn, u0, u1, m, raw, lmin),
+                    lambda x, dirn, lo, hi, done, xn, ug: _slice_group_dev(x, dirn, lo, hi, done, xn, ug, raw, lmin))
+        inside = (lambda p: self._in_contour(p, lmin)) if count else (lambda p: self._inside_raw(p, lmin))
+        return (lambda x, dirn, u0, u1: _slice_stepping(x, dirn, u0, u1, m, inside),
+                lambda x, dirn, lo, hi, done, xn, ug: _slice_group(x, dirn, lo, hi, done, xn, ug, inside))
+
     def _slice(self, live_u, live_l):
         """Slice-sampling walks inside the contour L >= L_min, one chain per candidate: each chain
         starts at a random live point and makes slice_steps moves of `slice_move`, along random
@@ -413,18 +476,25 @@ class ParallelNestedSampler:
         chol, _ = torch.linalg.cholesky_ex(cov)
         if self.slice_graphs and self._graphs is None:
             try:
-                self._graphs = _SliceGraphs(self, self._inside_raw)
+                self._graphs = _SliceGraphs(self)
             except Exception as exc:      # a likelihood that cannot be captured: eager moves
                 warnings.warn(f"slice moves run eagerly: capturing them failed ({exc})")
                 self.slice_graphs = False
         if self.slice_graphs:
             return self._graphs.walk(x, chol, lmin, self.slice_steps)
         inside = lambda p: self._in_contour(p, lmin)
+
+        def raw(p):
+            self.extra_calls += p.shape[0]
+            return self._raw(p)
         for _ in range(self.slice_steps):
             z = torch.randn(n, d, generator=self.gen, **f64)
             dirn = self.slice_width * (z / z.norm(dim=1, keepdim=True)) @ chol.T
             unif = torch.rand(2 + SLICE_MAX_DRAWS, n, generator=self.gen, **f64)
-            x, _ = slice_move(x, dirn, unif, self.slice_out, inside)
+            if self.slice_kernels:
+                x, _ = slice_move_dev(x, dirn, unif, self.slice_out, raw, lmin)
+            else:
+                x, _ = slice_move(x, dirn, unif, self.slice_out, inside)
         return x
 
     def _propose(self, it, live_u, live_l):

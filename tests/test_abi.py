@@ -73,3 +73,18 @@ def test_python_binding_rejects_cpu_tensors():
                  [(0.1, 0.2, 0.3, 0.4)], torch.ones(10, dtype=torch.float64), 0.25)
     with pytest.raises(ValueError):
         gw._prec("half")
+
+
+def test_slice_entry_points_check_arguments_without_device_work():
+    L = gw.lib()
+    fake = ctypes.c_void_p(0x1000)
+    ptrs9 = [fake] * 9
+    assert L.gwl_slice_ends(0, 3, 4, *ptrs9, None) == -2
+    assert L.gwl_slice_ends(10, 0, 4, *ptrs9, None) == -2
+    assert L.gwl_slice_ends(10, 3, 0, *ptrs9, None) == -2
+    assert L.gwl_slice_ends(10, 3, 4, None, *ptrs9[1:], None) == -1
+    assert L.gwl_slice_ends_select(10, 3, 4, *([fake] * 6), None, None) == -1
+    assert L.gwl_slice_draws(10, 3, 0, *ptrs9, None) == -2
+    assert L.gwl_slice_draws(1 << 30, 3, 8, *ptrs9, None) == -2     # 2 G n points beyond 2^30
+    assert L.gwl_slice_select(10, 3, 8, *([fake] * 11), None, None) == -1
+    assert b"null pointer" in L.gwl_last_error()

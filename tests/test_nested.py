@@ -354,26 +354,61 @@ def test_gw_slice_nested_sampling_matches_importance_sampling():
 
 
 @pytest.mark.gpu
-def test_slice_graphs_replay_the_eager_moves():
-    """The slice moves replayed from captured graphs give the eager moves bit for bit: the same
-    dead points, likelihoods and call counts over a few iterations of a GW run."""
+def test_slice_graphs_and_kernels_replay_the_eager_moves():
+    """The slice moves replayed from captured graphs, and with their bookkeeping in the library's
+    kernels (gwl_slice_*), give the eager torch moves bit for bit: the same dead points,
+    likelihoods and call counts over a few iterations of a GW run."""
     from paper_1909_11873_amd import gwlike as gw
 
     spec, th0, f, psd, data, dets, l0 = quiet_c0_event()
     ev = gw.Event(torch.tensor(data, device=DEV), torch.tensor(psd, device=DEV), dets,
                   torch.tensor(f, device=DEV), spec.df)
     runs = []
-    for graphs in (True, False):
+    for graphs, kernels in ((False, False), (True, True), (False, True), (True, False)):
         smp = nested.ParallelNestedSampler(lambda th: gw.logl(th, ev, "mixed"), 11, 200, 256, proposal="slice",
-                                           slice_steps=6, slice_graphs=graphs, device=DEV, seed=12,
-                                           prior_transform=nested.gw_prior_transform(spins=False))
+                                           slice_steps=6, slice_graphs=graphs, slice_kernels=kernels, device=DEV,
+                                           seed=12, prior_transform=nested.gw_prior_transform(spins=False))
         runs.append(smp.run(eps=0.1, max_iter=12))
-    a, b = runs
-    assert a.niter == b.niter == 12
-    np.testing.assert_array_equal(a.u, b.u)
-    np.testing.assert_array_equal(a.logl, b.logl)
-    assert a.ncall == b.ncall
+    ref = runs[0]
+    assert ref.niter == 12
+    for r in runs[1:]:
+        assert r.niter == ref.niter
+        np.testing.assert_array_equal(r.u, ref.u)
+        np.testing.assert_array_equal(r.logl, ref.logl)
+        assert r.ncall == ref.ncall
     ev.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("m", [1, 4])
+def test_slice_kernels_are_the_sequential_procedure(m):
+    """The library's slice kernels against the one-chain-at-a-time procedure with the same
+    random numbers, on a region made of two balls (ln L = 0 inside, -inf outside)."""
+    from paper_1909_11873_amd import gwlike as gw
+
+    rng = np.random.default_rng(21 + m)
+    n, d = 500, 3
+    x = np.where(rng.random((3 * n, 1)) < 0.5, 0.3, 0.7) + 0.05 * rng.standard_normal((3 * n, d))
+    x = x[two_balls(torch.tensor(x)).numpy()][:n]
+    dirn = rng.standard_normal((n, d)) + np.where(rng.random((n, 1)) < 0.5, 3.0, 0.0)
+    dirn *= (0.02 + 0.8 * rng.random((n, 1))) / np.linalg.norm(dirn, axis=1, keepdims=True)
+    unif = rng.random((2 + nested.SLICE_MAX_DRAWS, n))
+    raw = lambda p: torch.where(two_balls(p), 0.0, -math.inf).to(torch.float64)
+    lmin = torch.zeros((), dtype=torch.float64, device=DEV)
+    got, moved = nested.slice_move_dev(torch.tensor(x, device=DEV), torch.tensor(dirn, device=DEV),
+                                       torch.tensor(unif, device=DEV), m, raw, lmin)
+    got, moved = got.cpu().numpy(), moved.cpu().numpy()
+    inside_np = lambda p: bool(two_balls(torch.tensor(p)))
+    for i in range(n):
+        ref, ok = neal_slice_move(x[i], dirn[i], unif[:, i], m, inside_np)
+        assert bool(moved[i]) == ok
+        np.testing.assert_array_equal(got[i], ref)
+    assert moved.all()
+    with pytest.raises(gw.GWLError):
+        gw.slice_draws(torch.zeros(0, 3, dtype=torch.float64, device=DEV), torch.zeros(0, 3, dtype=torch.float64,
+                       device=DEV), torch.zeros(0, dtype=torch.float64, device=DEV),
+                       torch.zeros(0, dtype=torch.float64, device=DEV),
+                       torch.zeros(8, 0, dtype=torch.float64, device=DEV))
 
 
 @pytest.mark.gpu
