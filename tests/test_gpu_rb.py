@@ -24,6 +24,18 @@ def rb_event(cfg, eps, f_hi=None):
     return spec, f, psd, data, dets, ev, full, summ
 
 
+# Mixed precision on relative-binning rows: each edge's term V_e r_e is large (a few hundred
+# bins' worth), few terms are summed and nothing averages. Every term carries about four float32
+# relative roundings (V / uref stored in float32, the product, the block sum, the hardware phasor
+# with its 1.25e-7 maximum error): |error| <= 2.5e-7 sum_e |V_e| (|r_e| ~ 1 near the fiducial),
+# and never less than the full path's 1e-3.
+RB_MIXED_REL = 2.5e-7
+
+
+def rb_mixed_tolerance(summ):
+    return max(1e-3, RB_MIXED_REL * float(np.abs(summ["V"]).sum()))
+
+
 @pytest.mark.parametrize("cfg,eps", [(1, 0.1), (1, 0.5), (2, 0.1)])
 def test_rb_matches_the_rb_oracle(cfg, eps):
     spec, f, psd, data, dets, ev, full, summ = rb_event(cfg, eps)
@@ -32,11 +44,13 @@ def test_rb_matches_the_rb_oracle(cfg, eps):
     th = np.concatenate([near(spec.theta0, 6, seed=cfg, scale=0.3), synth.theta_batch(spec, 2)])
     th[0] = spec.theta0
     ref = rb.logl(th, summ, psd, dets, f, spec.df).numpy()
-    for prec, tol in (("fp64", 1e-9), ("mixed", 1e-3)):
+    for prec in ("fp64", "mixed"):
         got = gw.logl(torch.tensor(th, device=DEV), ev, prec).cpu().numpy()
         err = np.abs(got - ref)
-        print(f"RB c{cfg} eps {eps} ({ne} edges of {nb} bins) {prec}: max |dlogL| vs RB oracle {err.max():.3e}")
-        assert np.all(err <= tol * np.maximum(1.0, np.abs(ref) if prec == "fp64" else 1.0))
+        tol = 1e-9 * np.maximum(1.0, np.abs(ref)) if prec == "fp64" else rb_mixed_tolerance(summ)
+        print(f"RB c{cfg} eps {eps} ({ne} edges of {nb} bins) {prec}: max |dlogL| vs RB oracle {err.max():.3e} "
+              f"(tolerance {np.max(tol):.2e})")
+        assert np.all(err <= tol)
 
 
 def test_rb_gradient_matches_the_rb_oracle():
