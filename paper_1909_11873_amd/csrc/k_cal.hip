@@ -76,33 +76,35 @@ __device__ __forceinline__ void cal_bin(const Row r, const CalRow cw, GradP gt, 
   }
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
-    T_ da = cw.w[0] * ca[d][0], dp = cw.w[0] * cp[d][0];
+    // g1 = 1 + dA and dphi at this bin, from the four nearest nodes
+    T_ g1 = fma(cw.w[0], ca[d][0], (T_)1), dp = cw.w[0] * cp[d][0];
 #pragma unroll
     for (int i = 1; i < 4; ++i) {
-      da = fma(cw.w[i], ca[d][i], da);
+      g1 = fma(cw.w[i], ca[d][i], g1);
       dp = fma(cw.w[i], cp[d][i], dp);
     }
     // q = u p exp(i dphi) = u exp(-2 pi i (phi - dphi / 2 pi)): the calibration phase joins the
-    // model phase before the reduction, so one phasor (with its gain correction) serves both
-    // (the float64 variant's phase is in table units: dphi / 2 pi scaled by PH_TBL as well)
-    constexpr double inv2pi = MIXED ? -0.15915494309189535 : -0.15915494309189535 * PH_TBL;
-    const double ph = fma((double)dp, inv2pi, fma(r.f, T[d], psi));
+    // model phase before the phasor, so one phasor (with its gain correction) serves both. The
+    // mixed variant subtracts dphi / 2 pi (at most a few hundredths of a cycle) in float32 from
+    // the reduced phase; the float64 variant adds it in table units before the reduction.
     T_ cs, sn;
     if constexpr (MIXED) {
-      const float rr = (float)__builtin_amdgcn_fract(ph);
+      const float rr = fmaf(dp, -0.15915494f, (float)__builtin_amdgcn_fract(fma(r.f, T[d], psi)));
       cs = __builtin_amdgcn_cosf(rr);
       sn = __builtin_amdgcn_sinf(rr);
     } else {
-      sincos_tbl(ph, tbl, sn, cs);
+      sincos_tbl(fma(dp, -0.15915494309189535 * PH_TBL, fma(r.f, T[d], psi)), tbl, sn, cs);
     }
     const T_ ur = r.u[2 * d], ui = r.u[2 * d + 1];
     const T_ qr = fma(ur, cs, ui * sn);
     const T_ qi = fma(ui, cs, -(ur * sn));
-    const T_ g1 = (T_)1 + da;
-    const T_ vr = g1 * qr, vi = g1 * qi;            // calibrated product
-    z[2 * d] += vr;
-    z[2 * d + 1] += vi;
-    if constexpr (GRAD) {
+    if constexpr (!GRAD) {
+      z[2 * d] = fma(g1, qr, z[2 * d]);            // calibrated product g1 q
+      z[2 * d + 1] = fma(g1, qi, z[2 * d + 1]);
+    } else {
+      const T_ vr = g1 * qr, vi = g1 * qi;          // calibrated product
+      z[2 * d] += vr;
+      z[2 * d + 1] += vi;
       const T_ yd = fma(cr[d], vi, ci[d] * vr);     // Im(c w_cal)
       const T_ ya = fma(cr[d], qr, -(ci[d] * qi));  // Re(c q)
       z[2 * ND + d] = fma(fk, yd, z[2 * ND + d]);
