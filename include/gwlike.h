@@ -58,7 +58,7 @@ typedef enum {
   GWL_E_SHAPE = -2,       /* sizes inconsistent with each other or beyond the supported range    */
   GWL_E_DEVICE = -3,      /* a HIP runtime call failed (message names it)                      */
   GWL_E_NOMEM = -4,       /* device allocation failed                                          */
-  GWL_E_UNSUPPORTED = -5, /* valid request this build does not implement                       */
+  GWL_E_UNSUPPORTED = -5, /* valid request the library does not implement                      */
   GWL_E_INTERNAL = -6
 } gwl_status;
 
