@@ -212,6 +212,23 @@ def test_slice_proposal_on_host():
     assert c[0, 1] / math.sqrt(c[0, 0] * c[1, 1]) == pytest.approx(rho, abs=0.02)
 
 
+def test_slice_evidence_scatter_matches_its_quoted_error():
+    """Ten independent slice-walk runs on a normalised 4-D Gaussian (ln Z = 0): their mean is
+    within three standard errors of 0, and their scatter agrees with the sqrt(H/K) error each run
+    quotes (within the spread a sample of ten allows)."""
+    d, s = 4, 0.05
+    norm = -d * math.log(math.sqrt(2 * math.pi) * s)
+    ll = lambda th: norm - ((th - 0.5) ** 2).sum(1) / (2 * s * s)
+    zs, es = [], []
+    for seed in range(10):
+        res = nested.ParallelNestedSampler(ll, d, 150, 64, device="cpu", seed=seed, proposal="slice").run(eps=0.01)
+        zs.append(res.logz)
+        es.append(res.logz_err)
+    err = float(np.median(es))
+    assert abs(np.mean(zs)) < 3 * err / math.sqrt(len(zs)) + 0.01, zs
+    assert 0.5 * err < np.std(zs, ddof=1) < 1.6 * err, (np.std(zs, ddof=1), err)
+
+
 def test_importance_logz_on_a_normalised_gaussian():
     """The importance-sampling check itself: ln Z = 0 for a normalised Gaussian inside the cube."""
     s = 0.05
