@@ -1,0 +1,63 @@
+"""The largest shapes the path is meant for: a batch of 2^22 points and a grid of 2^22 + 1 bins
+(a 2048 s segment, 20-2068 Hz), each against the FP64 oracle on sampled points."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import gw_oracle as o
+from paper_1909_11873_amd import gwlike as gw
+from paper_1909_11873_amd import synth
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def event(f_lo, f_hi, df, theta0, seed):
+    f = synth.freq_grid(f_lo, f_hi, df)
+    s = synth.psd_fit(f)
+    names = ["D1", "D2", "D3"]
+    dets = np.array([synth.detector_rad(n) for n in names])
+    psd = np.stack([s] * 3)
+    data = np.stack([synth.noise(seed + i, s, df) for i in range(3)]) + o.strain_all(theta0, dets, f).numpy()
+    ev = gw.Event(torch.tensor(data, device=DEV), torch.tensor(psd, device=DEV), dets, torch.tensor(f, device=DEV), df)
+    return ev, f, psd, data, dets
+
+
+def test_batch_of_2_to_the_22_points():
+    spec = synth.event_spec(1)
+    ev, f, psd, data, dets = event(20.0, 52.0, 0.25, spec.theta0, 9100)   # 129 bins
+    B = 1 << 22
+    rng = np.random.default_rng(9101)
+    theta = synth.prior_draw(rng, B)
+    th = torch.tensor(theta, device=DEV)
+    pick = np.array([0, 1, 777777, B // 2 + 3, B - 2, B - 1])
+    ref = o.logl(theta[pick], data, psd, dets, f, 0.25).numpy()
+    for prec, tol in (("fp64", 1e-6), ("mixed", 1e-3)):
+        got = gw.logl(th, ev, prec)
+        assert got.shape == (B,)
+        assert bool(torch.isfinite(got).all())
+        err = np.abs(got.cpu().numpy()[pick] - ref)
+        print(f"B = 2^22, {len(f)} bins, {prec}: max |dlogL| on {len(pick)} sampled points {err.max():.2e}")
+        assert err.max() <= tol
+        # the same points in a small batch (another launch shape) agree
+        small = gw.logl(th[pick], ev, prec).cpu().numpy()
+        assert np.abs(small - got.cpu().numpy()[pick]).max() <= (1e-9 if prec == "fp64" else 2e-4)
+    ev.close()
+
+
+def test_grid_of_2_to_the_22_bins():
+    spec = synth.event_spec(2)                                              # a long low-mass signal
+    df = 1.0 / 2048.0
+    ev, f, psd, data, dets = event(20.0, 20.0 + (1 << 22) * df, df, spec.theta0, 9200)
+    assert len(f) == (1 << 22) + 1
+    theta = synth.theta_batch(spec, 70)
+    theta[0] = spec.theta0
+    th = torch.tensor(theta, device=DEV)
+    ref = o.logl(theta[[0, 69]], data, psd, dets, f, df).numpy()
+    for prec, tol in (("fp64", 1e-6), ("mixed", 1e-3)):
+        got = gw.logl(th, ev, prec).cpu().numpy()
+        assert np.all(np.isfinite(got))
+        err = np.abs(got[[0, 69]] - ref)
+        print(f"M = 2^22 + 1 bins, {prec}: |dlogL| {err.max():.2e} (logL(theta0) {ref[0]:.2f})")
+        assert err.max() <= tol * max(1.0, abs(ref[0]) if prec == "fp64" else 1.0)
+    ev.close()
