@@ -37,8 +37,9 @@
  *     opaque handles and the device tables inside them.
  *   - `stream` is a hipStream_t passed as void* (NULL = the default stream). Calls that take a
  *     stream are asynchronous and stream-ordered: outputs are valid once the stream has
- *     reached the call. Handles are immutable after creation and may be used concurrently
- *     from several streams.
+ *     reached the call. Event handles are immutable after creation and may be used
+ *     concurrently from several streams. A multi-event plan owns one workspace: launches of
+ *     the same plan must not overlap (issue them on one stream, or wait between them).
  *   - Argument errors are detected on the host before any launch and return GWL_E_INVALID or
  *     GWL_E_SHAPE with a message in gwl_last_error(); a failing HIP call returns
  *     GWL_E_DEVICE. No C++ exception crosses this interface. Nothing is written on error.
