@@ -138,6 +138,13 @@ def test_multi_plan_argument_errors(events):
     with pytest.raises(ValueError):
         plan.launch([torch.zeros(3, 11, dtype=torch.float64, device=DEV)])
     plan.close()
+    # events of one plan share their detector count
+    e = events[0]
+    one = gw.Event(torch.tensor(e["data"][:1], device=DEV), torch.tensor(e["psd"][:1], device=DEV), e["dets"][:1],
+                   torch.tensor(e["f"], device=DEV), e["df"])
+    with pytest.raises(gw.GWLError, match="detector count"):
+        gw.MultiPlan([e["ev"], one], [70, 5], "mixed")
+    one.close()
 
 
 def test_c4_full_workload_sampled():
