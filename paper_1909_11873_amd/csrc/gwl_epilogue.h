@@ -56,11 +56,14 @@ __device__ inline void apply_gain(const EventConst& ec, double (&acc)[NZ]) {
   }
 }
 
-// Sum the per-chunk partials of one point in chunk order (deterministic).
+// Sum the per-chunk partials of one point in chunk order (deterministic). The chunk loop is
+// unrolled so that several chunks' loads are in flight before their adds, which still run in
+// chunk order; with one thread per point this loop is latency-bound otherwise.
 template <int NZ>
 __device__ inline void gather(const double* __restrict__ part, int nchunk, int64_t Bp, int64_t p, double (&acc)[NZ]) {
 #pragma unroll
   for (int z = 0; z < NZ; ++z) acc[z] = 0.0;
+#pragma unroll 8
   for (int c = 0; c < nchunk; ++c) {
 #pragma unroll
     for (int z = 0; z < NZ; ++z) acc[z] += part[((int64_t)c * NZ + z) * Bp + p];

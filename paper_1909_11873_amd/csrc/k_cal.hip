@@ -246,10 +246,14 @@ __global__ __launch_bounds__(CAL_PT_BLOCK) void k_epilogue_cal(EventGeom g, cons
 #pragma unroll
   for (int d = 0; d < ND; ++d)
     for (int i = 0; i < MAXNODE; ++i) mA[d][i] = mB[d][i] = 0.0;
+  // chunk-order sums; the value sums' loop is unrolled to keep several chunks' loads in flight
+#pragma unroll 8
   for (int c = 0; c < nchunk; ++c) {
 #pragma unroll
     for (int zz = 0; zz < NZU; ++zz) acc[zz] += part[((int64_t)c * NZ + zz) * Bp + p];
-    if constexpr (GRAD) {
+  }
+  if constexpr (GRAD) {
+    for (int c = 0; c < nchunk; ++c) {
       const int j0 = sh.j0[sh.cj[c]];
 #pragma unroll
       for (int d = 0; d < ND; ++d)
