@@ -271,7 +271,8 @@ gwl_status gwl_profile_read(int64_t* launches, double* total_ms);
  *   and the final (a, b).
  * gwl_slice_select: with logl[G n] the values at those points, for every chain not yet done:
  *   the first draw inside the region (if any) gives xn = x + t dirn and done = 1; a chain still
- *   not done takes (lo, hi) = (a, b).
+ *   not done takes (lo, hi) = (a, b). The cube test recomputes x + t dirn with the same rounding
+ *   as the points gwl_slice_draws wrote, so those points are not read again.
  */
 gwl_status gwl_slice_ends(int64_t n, int d, int m, const double* x, const double* dirn, const double* u0,
                           const double* u1, double* pts, double* lo, double* hi, double* jl, double* jr, void* stream);
@@ -281,8 +282,29 @@ gwl_status gwl_slice_draws(int64_t n, int d, int G, const double* x, const doubl
                            const double* hi, const double* u, double* t, double* pts, double* a, double* b,
                            void* stream);
 gwl_status gwl_slice_select(int64_t n, int d, int G, const double* x, const double* dirn, const double* t,
-                            const double* pts, const double* logl, const double* lmin, const double* a,
-                            const double* b, double* xn, unsigned char* done, double* lo, double* hi, void* stream);
+                            const double* logl, const double* lmin, const double* a, const double* b, double* xn,
+                            unsigned char* done, double* lo, double* hi, void* stream);
+
+/*
+ * Prior transform for a sampler above the likelihood (the prior-sampling step of the paper's
+ * section 2: nested sampling draws points uniformly in the unit cube and maps them to parameters
+ * through the prior's inverse CDF). Columns are independent; column j maps u to
+ *   theta = g_j(c0_j + c1_j clamp(u, 0, 1))   (the argument in one fused multiply-add)
+ * with g_j the identity (a uniform prior on [c0, c0 + c1]), the cube root (density ~ x^2 on
+ * [a, b]: c0 = a^3, c1 = b^3 - a^3), asin (density ~ cos x, e.g. declination on [-pi/2, pi/2]:
+ * c0 = -1, c1 = 2) or acos (density ~ sin x, e.g. inclination on [0, pi]: c0 = -1, c1 = 2, which
+ * maps u = 0 to pi). asin and acos arguments are clamped to [-1, 1]. Points outside the cube
+ * are clamped into it first, so a sampler may pass candidates it will judge itself.
+ *
+ * u and theta: n x d float64 row-major device arrays owned by the caller (they must not
+ * overlap); map, c0, c1: host arrays of d entries, copied at the call. Stream-ordered on
+ * `stream`. GWL_E_SHAPE for n < 1 or d outside [1, GWL_PRIOR_MAX_DIM]; GWL_E_INVALID for a null
+ * pointer or an unknown map code.
+ */
+#define GWL_PRIOR_MAX_DIM 64
+typedef enum { GWL_MAP_LINEAR = 0, GWL_MAP_CBRT = 1, GWL_MAP_ASIN = 2, GWL_MAP_ACOS = 3 } gwl_prior_map;
+gwl_status gwl_prior_transform(int64_t n, int d, const int* map, const double* c0, const double* c1, const double* u,
+                               double* theta, void* stream);
 
 #ifdef __cplusplus
 }

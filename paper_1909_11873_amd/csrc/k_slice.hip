@@ -23,31 +23,34 @@ __device__ __forceinline__ bool in_region(const double* __restrict__ p, int d, d
   return ok;
 }
 
-__global__ __launch_bounds__(SLICE_BLOCK) void k_slice_ends(int64_t n, int d, int m, const double* __restrict__ x,
-                                                            const double* __restrict__ dirn,
-                                                            const double* __restrict__ u0,
-                                                            const double* __restrict__ u1, double* __restrict__ pts,
-                                                            double* __restrict__ lo, double* __restrict__ hi,
-                                                            double* __restrict__ jl, double* __restrict__ jr) {
+__global__ __launch_bounds__(SLICE_BLOCK) void k_slice_ends(int64_t n, int m, const double* __restrict__ u0,
+                                                            const double* __restrict__ u1, double* __restrict__ lo,
+                                                            double* __restrict__ hi, double* __restrict__ jl,
+                                                            double* __restrict__ jr) {
   const int64_t i = (int64_t)blockIdx.x * SLICE_BLOCK + threadIdx.x;
   if (i >= n) return;
-  const double l0 = -u0[i], h0 = 1.0 - u0[i];
   const double sl = floor((double)m * u1[i]);
-  lo[i] = l0;
-  hi[i] = h0;
+  lo[i] = -u0[i];
+  hi[i] = 1.0 - u0[i];
   jl[i] = sl;
   jr[i] = (double)(m - 1) - sl;
-  const double* xi = x + i * d;
-  const double* di = dirn + i * d;
-  for (int j = 0; j < m; ++j) {
-    const double el = l0 - (double)j, er = h0 + (double)j;
-    double* pl = pts + ((int64_t)j * n + i) * d;
-    double* pr = pts + ((int64_t)(m + j) * n + i) * d;
-    for (int c = 0; c < d; ++c) {
-      pl[c] = xi[c] + el * di[c];
-      pr[c] = xi[c] + er * di[c];
-    }
-  }
+}
+
+// One thread per coordinate of a candidate end: row r = j n + i is chain i's left end j
+// (lo - j) for j < m and its right end j - m (hi + j - m) above.
+__global__ __launch_bounds__(SLICE_BLOCK) void k_slice_end_points(int64_t n, int d, int m,
+                                                                  const double* __restrict__ x,
+                                                                  const double* __restrict__ dirn,
+                                                                  const double* __restrict__ lo,
+                                                                  const double* __restrict__ hi,
+                                                                  double* __restrict__ pts) {
+  const int64_t e = (int64_t)blockIdx.x * SLICE_BLOCK + threadIdx.x;
+  if (e >= 2 * (int64_t)m * n * d) return;
+  const int64_t r = e / d, c = e - r * d;
+  const int j = (int)(r / n);
+  const int64_t i = r - (int64_t)j * n;
+  const double t = j < m ? lo[i] - (double)j : hi[i] + (double)(j - m);
+  pts[e] = x[i * d + c] + t * dirn[i * d + c];
 }
 
 __global__ __launch_bounds__(SLICE_BLOCK) void k_slice_ends_select(int64_t n, int d, int m,
@@ -70,24 +73,17 @@ __global__ __launch_bounds__(SLICE_BLOCK) void k_slice_ends_select(int64_t n, in
   hi[i] = hi[i] + fmin((double)out_r, jr[i]);
 }
 
-__global__ __launch_bounds__(SLICE_BLOCK) void k_slice_draws(int64_t n, int d, int G, const double* __restrict__ x,
-                                                             const double* __restrict__ dirn,
-                                                             const double* __restrict__ lo,
+__global__ __launch_bounds__(SLICE_BLOCK) void k_slice_draws(int64_t n, int G, const double* __restrict__ lo,
                                                              const double* __restrict__ hi,
                                                              const double* __restrict__ u, double* __restrict__ t,
-                                                             double* __restrict__ pts, double* __restrict__ a,
-                                                             double* __restrict__ b) {
+                                                             double* __restrict__ a, double* __restrict__ b) {
   const int64_t i = (int64_t)blockIdx.x * SLICE_BLOCK + threadIdx.x;
   if (i >= n) return;
   double ai = lo[i], bi = hi[i];
-  const double* xi = x + i * d;
-  const double* di = dirn + i * d;
   for (int k = 0; k < G; ++k) {
     const int64_t r = (int64_t)k * n + i;
     const double tk = ai + u[r] * (bi - ai);
     t[r] = tk;
-    double* p = pts + r * d;
-    for (int c = 0; c < d; ++c) p[c] = xi[c] + tk * di[c];
     if (tk < 0.0)
       ai = tk;
     else
@@ -97,7 +93,26 @@ __global__ __launch_bounds__(SLICE_BLOCK) void k_slice_draws(int64_t n, int d, i
   b[i] = bi;
 }
 
-__global__ __launch_bounds__(SLICE_BLOCK) void k_slice_select(int64_t n, int d, int G, const double* __restrict__ pts,
+// One thread per coordinate of a draw: pts[r d + c] = x_i + t_r dirn_i, r = k n + i.
+__global__ __launch_bounds__(SLICE_BLOCK) void k_slice_draw_points(int64_t n, int d, int G,
+                                                                   const double* __restrict__ x,
+                                                                   const double* __restrict__ dirn,
+                                                                   const double* __restrict__ t,
+                                                                   double* __restrict__ pts) {
+  const int64_t e = (int64_t)blockIdx.x * SLICE_BLOCK + threadIdx.x;
+  if (e >= (int64_t)G * n * d) return;
+  const int64_t r = e / d, c = e - r * d;
+  const int64_t i = r % n;
+  pts[e] = x[i * d + c] + t[r] * dirn[i * d + c];
+}
+
+// The cube test recomputes the draw's coordinates (the same products and sums as the points
+// the likelihood saw), so the chain reads its own x and direction instead of G point rows. The
+// draws are judged without an early exit (the first one inside wins), which leaves their loads
+// independent of one another.
+__global__ __launch_bounds__(SLICE_BLOCK) void k_slice_select(int64_t n, int d, int G, const double* __restrict__ x,
+                                                              const double* __restrict__ dirn,
+                                                              const double* __restrict__ t,
                                                               const double* __restrict__ logl,
                                                               const double* __restrict__ lmin,
                                                               const double* __restrict__ a,
@@ -108,16 +123,30 @@ __global__ __launch_bounds__(SLICE_BLOCK) void k_slice_select(int64_t n, int d, 
   if (i >= n) return;
   if (done[i]) return;
   const double lm = *lmin;
-  for (int k = 0; k < G; ++k) {
+  const double* xi = x + i * d;
+  const double* di = dirn + i * d;
+  int first = G;
+  double tf = 0.0;
+  for (int k = G - 1; k >= 0; --k) {
     const int64_t r = (int64_t)k * n + i;
-    if (in_region(pts + r * d, d, logl[r], lm)) {
-      for (int c = 0; c < d; ++c) xn[i * d + c] = pts[r * d + c];
-      done[i] = 1;
-      return;
+    const double tk = t[r];
+    bool ok = logl[r] >= lm;
+    for (int c = 0; c < d; ++c) {
+      const double p = xi[c] + tk * di[c];
+      ok = ok && p >= 0.0 && p <= 1.0;
+    }
+    if (ok) {
+      first = k;
+      tf = tk;
     }
   }
-  lo[i] = a[i];
-  hi[i] = b[i];
+  if (first < G) {
+    for (int c = 0; c < d; ++c) xn[i * d + c] = xi[c] + tf * di[c];
+    done[i] = 1;
+  } else {
+    lo[i] = a[i];
+    hi[i] = b[i];
+  }
 }
 
 static unsigned grid_of(int64_t n) { return (unsigned)((n + SLICE_BLOCK - 1) / SLICE_BLOCK); }
@@ -148,8 +177,10 @@ gwl_status gwl_slice_ends(int64_t n, int d, int m, const double* x, const double
   if (st != GWL_OK) return st;
   if (!x || !dirn || !u0 || !u1 || !pts || !lo || !hi || !jl || !jr)
     return fail(GWL_E_INVALID, "gwl_slice_ends: null pointer");
-  hipLaunchKernelGGL(k_slice_ends, dim3(grid_of(n)), dim3(SLICE_BLOCK), 0, (hipStream_t)stream, n, d, m, x, dirn,
-                     u0, u1, pts, lo, hi, jl, jr);
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_slice_ends, dim3(grid_of(n)), dim3(SLICE_BLOCK), 0, s, n, m, u0, u1, lo, hi, jl, jr);
+  hipLaunchKernelGGL(k_slice_end_points, dim3(grid_of(2 * (int64_t)m * n * d)), dim3(SLICE_BLOCK), 0, s, n, d, m, x,
+                     dirn, (const double*)lo, (const double*)hi, pts);
   return launched("gwl_slice_ends");
 }
 
@@ -173,21 +204,23 @@ gwl_status gwl_slice_draws(int64_t n, int d, int G, const double* x, const doubl
   if (st != GWL_OK) return st;
   if (!x || !dirn || !lo || !hi || !u || !t || !pts || !a || !b)
     return fail(GWL_E_INVALID, "gwl_slice_draws: null pointer");
-  hipLaunchKernelGGL(k_slice_draws, dim3(grid_of(n)), dim3(SLICE_BLOCK), 0, (hipStream_t)stream, n, d, G, x, dirn,
-                     lo, hi, u, t, pts, a, b);
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_slice_draws, dim3(grid_of(n)), dim3(SLICE_BLOCK), 0, s, n, G, lo, hi, u, t, a, b);
+  hipLaunchKernelGGL(k_slice_draw_points, dim3(grid_of((int64_t)G * n * d)), dim3(SLICE_BLOCK), 0, s, n, d, G, x,
+                     dirn, (const double*)t, pts);
   return launched("gwl_slice_draws");
 }
 
 gwl_status gwl_slice_select(int64_t n, int d, int G, const double* x, const double* dirn, const double* t,
-                            const double* pts, const double* logl, const double* lmin, const double* a,
-                            const double* b, double* xn, unsigned char* done, double* lo, double* hi, void* stream) {
+                            const double* logl, const double* lmin, const double* a, const double* b, double* xn,
+                            unsigned char* done, double* lo, double* hi, void* stream) {
   clear_error();
   gwl_status st = check_shape(n, d, G);
   if (st != GWL_OK) return st;
-  if (!x || !dirn || !t || !pts || !logl || !lmin || !a || !b || !xn || !done || !lo || !hi)
+  if (!x || !dirn || !t || !logl || !lmin || !a || !b || !xn || !done || !lo || !hi)
     return fail(GWL_E_INVALID, "gwl_slice_select: null pointer");
-  hipLaunchKernelGGL(k_slice_select, dim3(grid_of(n)), dim3(SLICE_BLOCK), 0, (hipStream_t)stream, n, d, G, pts, logl,
-                     lmin, a, b, xn, done, lo, hi);
+  hipLaunchKernelGGL(k_slice_select, dim3(grid_of(n)), dim3(SLICE_BLOCK), 0, (hipStream_t)stream, n, d, G, x, dirn, t,
+                     logl, lmin, a, b, xn, done, lo, hi);
   return launched("gwl_slice_select");
 }
 

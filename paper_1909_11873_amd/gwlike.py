@@ -80,7 +80,8 @@ def lib() -> ctypes.CDLL:
         "gwl_slice_ends": ([i64, cint, cint] + [vp] * 9 + [vp], cint),
         "gwl_slice_ends_select": ([i64, cint, cint] + [vp] * 7 + [vp], cint),
         "gwl_slice_draws": ([i64, cint, cint] + [vp] * 9 + [vp], cint),
-        "gwl_slice_select": ([i64, cint, cint] + [vp] * 12 + [vp], cint),
+        "gwl_slice_select": ([i64, cint, cint] + [vp] * 11 + [vp], cint),
+        "gwl_prior_transform": ([i64, cint] + [vp] * 5 + [vp], cint),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -453,7 +454,7 @@ def slice_draws(x, dirn, lo, hi, u):
     return t, pts, a, b
 
 
-def slice_select(x, dirn, t, pts, logl, lmin, a, b, xn, done, lo, hi) -> None:
+def slice_select(x, dirn, t, logl, lmin, a, b, xn, done, lo, hi) -> None:
     """For every chain not done: the first draw inside the region becomes its point (xn, done);
     otherwise its interval becomes (a, b). In place on xn, done, lo, hi."""
     n, d = x.shape
@@ -463,9 +464,39 @@ def slice_select(x, dirn, t, pts, logl, lmin, a, b, xn, done, lo, hi) -> None:
         if not (v.is_cuda and v.dtype == dt and v.is_contiguous() and tuple(v.shape) == shape):
             raise ValueError(f"{name} must be a contiguous {dt} CUDA tensor of shape {shape}")
     x, dirn, t = _f64(x, "x", (n, d)), _f64(dirn, "dirn", (n, d)), _f64(t, "t", (G, n))
-    pts, logl, lmin = _f64(pts, "pts", (G * n, d)), _f64(logl, "logl", (G * n,)), _f64(lmin, "lmin", ())
+    logl, lmin = _f64(logl, "logl", (G * n,)), _f64(lmin, "lmin", ())
     a, b = _f64(a, "a", (n,)), _f64(b, "b", (n,))
-    _check("gwl_slice_select", lib().gwl_slice_select(n, d, G, _ptr(x), _ptr(dirn), _ptr(t), _ptr(pts), _ptr(logl),
-                                                      _ptr(lmin), _ptr(a), _ptr(b), _ptr(xn), _ptr(done), _ptr(lo),
-                                                      _ptr(hi), _stream(x)))
+    _check("gwl_slice_select", lib().gwl_slice_select(n, d, G, _ptr(x), _ptr(dirn), _ptr(t), _ptr(logl), _ptr(lmin),
+                                                      _ptr(a), _ptr(b), _ptr(xn), _ptr(done), _ptr(lo), _ptr(hi),
+                                                      _stream(x)))
 
+
+MAP_LINEAR, MAP_CBRT, MAP_ASIN, MAP_ACOS = 0, 1, 2, 3
+
+
+class PriorColumns:
+    """The per-column maps and coefficients of gwl_prior_transform, held as the host arrays the
+    call copies (built once, reused by every call)."""
+
+    def __init__(self, maps, c0, c1):
+        d = len(maps)
+        if not (len(c0) == len(c1) == d) or not 1 <= d <= 64:
+            raise ValueError("maps, c0 and c1 must have the same length, 1 to 64")
+        if any(int(m) not in (MAP_LINEAR, MAP_CBRT, MAP_ASIN, MAP_ACOS) for m in maps):
+            raise ValueError(f"unknown map code in {list(maps)}")
+        self.d = d
+        self.maps = (ctypes.c_int * d)(*[int(m) for m in maps])
+        self.c0 = (ctypes.c_double * d)(*[float(x) for x in c0])
+        self.c1 = (ctypes.c_double * d)(*[float(x) for x in c1])
+        self.ptrs = tuple(ctypes.cast(a, ctypes.c_void_p) for a in (self.maps, self.c0, self.c1))
+
+
+def prior_transform(u: torch.Tensor, cols: PriorColumns) -> torch.Tensor:
+    """theta[n, d] = g_j(c0_j + c1_j clamp(u, 0, 1)) column by column (gwl_prior_transform)."""
+    if u.dim() != 2 or u.shape[1] != cols.d:
+        raise ValueError(f"u must have shape (n, {cols.d}), not {tuple(u.shape)}")
+    u = _dev(u, "u", torch.float64)
+    theta = torch.empty_like(u)
+    _check("gwl_prior_transform", lib().gwl_prior_transform(u.shape[0], cols.d, *cols.ptrs, _ptr(u), _ptr(theta),
+                                                            _stream(u)))
+    return theta

@@ -74,25 +74,33 @@ def speedup_law(n: float, nlive: float) -> float:
 def gw_prior_transform(mc_range=(10.0, 60.0), dl_range=(100.0, 2000.0), tc_half=0.1, spins=True):
     """Unit cube -> the 11 parameters (mc, q, chi1, chi2, dl, ra, dec, iota, psi, phic, tc) by the
     inverse CDFs of the prior: uniform mc, q in [0.2, 1], spins in [-0.9, 0.9], distance with
-    density ~ d^2, isotropic sky and orientation, uniform angles and coalescence time."""
+    density ~ d^2, isotropic sky and orientation, uniform angles and coalescence time. Each column
+    is g(c0 + c1 u) with g the identity, the cube root (distance), asin (declination) or acos
+    (inclination); points outside the cube are clamped into it first. On a CUDA tensor the
+    library's gwl_prior_transform does the whole map in one launch."""
     lo3, hi3 = dl_range[0] ** 3, dl_range[1] ** 3
-
     sw = 1.8 if spins else 0.0
-    # the columns that are affine in u: theta = offset + scale u
-    offset = [mc_range[0], 0.2, -sw / 2, -sw / 2, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, -tc_half]
-    scale = [mc_range[1] - mc_range[0], 0.8, sw, sw, 0.0, 2.0 * math.pi, 0.0, 0.0, math.pi, 2.0 * math.pi,
-             2.0 * tc_half]
+    c0 = [mc_range[0], 0.2, -sw / 2, -sw / 2, lo3, 0.0, -1.0, -1.0, 0.0, 0.0, -tc_half]
+    c1 = [mc_range[1] - mc_range[0], 0.8, sw, sw, hi3 - lo3, 2.0 * math.pi, 2.0, 2.0, math.pi, 2.0 * math.pi,
+          2.0 * tc_half]
+    maps = [0, 0, 0, 0, 1, 0, 2, 3, 0, 0, 0]       # identity, cube root (4), asin (6), acos (7)
     consts = {}
 
     def transform(u: torch.Tensor) -> torch.Tensor:
+        if u.is_cuda and u.dtype == torch.float64 and not u.requires_grad:
+            from . import gwlike as gw
+            if "cols" not in consts:
+                consts["cols"] = gw.PriorColumns(maps, c0, c1)
+            return gw.prior_transform(u, consts["cols"])
         key = (u.device, u.dtype)
         if key not in consts:
-            consts[key] = (torch.tensor(offset, device=u.device, dtype=u.dtype),
-                           torch.tensor(scale, device=u.device, dtype=u.dtype))
-        off, sc = consts[key]
-        th = torch.addcmul(off, u, sc)
-        th[:, 4] = torch.pow(lo3 + u[:, 4] * (hi3 - lo3), 1.0 / 3.0)
-        s67 = 2.0 * u[:, 6:8] - 1.0
+            consts[key] = (torch.tensor(c0, device=u.device, dtype=u.dtype),
+                           torch.tensor(c1, device=u.device, dtype=u.dtype))
+        a, b = consts[key]
+        x = torch.addcmul(a, u.clamp(0.0, 1.0), b)
+        th = x.clone()
+        th[:, 4] = torch.pow(x[:, 4], 1.0 / 3.0)
+        s67 = x[:, 6:8].clamp(-1.0, 1.0)
         th[:, 6] = torch.asin(s67[:, 0])
         th[:, 7] = torch.acos(s67[:, 1])
         return th
@@ -115,6 +123,7 @@ def gw_prior_transform(mc_range=(10.0, 60.0), dl_range=(100.0, 2000.0), tc_half=
         return j
 
     transform.jacobian = jacobian
+    transform.clamps = True
     return transform
 
 
@@ -206,7 +215,7 @@ def _slice_group_dev(x, dirn, lo, hi, done, xn, ug, raw, lmin):
     lo and hi."""
     from . import gwlike as gw
     t, pts, a, b = gw.slice_draws(x, dirn, lo, hi, ug)
-    gw.slice_select(x, dirn, t, pts, raw(pts), lmin, a, b, xn, done, lo, hi)
+    gw.slice_select(x, dirn, t, raw(pts), lmin, a, b, xn, done, lo, hi)
     return xn, done, lo, hi
 
 
@@ -444,6 +453,8 @@ class ParallelNestedSampler:
     def _raw(self, u):
         """ln L at the points u (clamped into the cube), NaN kept: the slice kernels judge the
         cube and the contour themselves."""
+        if getattr(self.transform, "clamps", False):
+            return self.loglike(self.transform(u))
         return self.loglike(self.transform(u.clamp(0.0, 1.0)))
 
     def _slice_stages(self, lmin, count=True):

@@ -86,5 +86,21 @@ def test_slice_entry_points_check_arguments_without_device_work():
     assert L.gwl_slice_ends_select(10, 3, 4, *([fake] * 6), None, None) == -1
     assert L.gwl_slice_draws(10, 3, 0, *ptrs9, None) == -2
     assert L.gwl_slice_draws(1 << 30, 3, 8, *ptrs9, None) == -2     # 2 G n points beyond 2^30
-    assert L.gwl_slice_select(10, 3, 8, *([fake] * 11), None, None) == -1
+    assert L.gwl_slice_select(10, 3, 8, *([fake] * 10), None, None) == -1
     assert b"null pointer" in L.gwl_last_error()
+
+
+def test_prior_transform_checks_arguments_without_device_work():
+    L = gw.lib()
+    fake = ctypes.c_void_p(0x1000)
+    maps = (ctypes.c_int * 3)(0, 1, 7)
+    coef = (ctypes.c_double * 3)(0.0, 1.0, 2.0)
+    pm, pc = ctypes.cast(maps, ctypes.c_void_p), ctypes.cast(coef, ctypes.c_void_p)
+    assert L.gwl_prior_transform(0, 3, pm, pc, pc, fake, fake, None) == -2
+    assert L.gwl_prior_transform(10, 0, pm, pc, pc, fake, fake, None) == -2
+    assert L.gwl_prior_transform(10, 65, pm, pc, pc, fake, fake, None) == -2
+    assert L.gwl_prior_transform(10, 3, pm, pc, pc, None, fake, None) == -1
+    assert L.gwl_prior_transform(10, 3, pm, pc, pc, fake, fake, None) == -1     # map code 7
+    assert b"unknown map 7" in L.gwl_last_error()
+    with pytest.raises(ValueError):
+        gw.PriorColumns([0, 5], [0.0, 0.0], [1.0, 1.0])

@@ -267,7 +267,61 @@ def test_gw_prior_transform_matches_synthetic_prior_draws():
     np.testing.assert_allclose(th, ref, rtol=1e-12, atol=1e-12)
 
 
+def test_gw_prior_transform_is_the_inverse_cdf():
+    """Each column's CDF, written from its density, at the transformed point returns u: uniform
+    columns (x - a)/(b - a), distance (x^3 - a^3)/(b^3 - a^3) for density ~ x^2, declination
+    (1 + sin x)/2 for density ~ cos x, inclination (1 + cos x)/2 for density ~ sin x with the
+    orientation that maps u = 0 to pi. Points outside the cube land on its faces."""
+    lo, hi = 100.0, 2000.0
+    tr = nested.gw_prior_transform(mc_range=(10.0, 60.0), dl_range=(lo, hi), tc_half=0.1)
+    u = np.random.default_rng(17).random((400, 11))
+    th = tr(torch.tensor(u)).numpy()
+    cdf = np.empty_like(th)
+    for j, (a, b) in {0: (10.0, 60.0), 1: (0.2, 1.0), 2: (-0.9, 0.9), 3: (-0.9, 0.9), 5: (0.0, 2 * np.pi),
+                      8: (0.0, np.pi), 9: (0.0, 2 * np.pi), 10: (-0.1, 0.1)}.items():
+        cdf[:, j] = (th[:, j] - a) / (b - a)
+    cdf[:, 4] = (th[:, 4] ** 3 - lo ** 3) / (hi ** 3 - lo ** 3)
+    cdf[:, 6] = (1.0 + np.sin(th[:, 6])) / 2.0
+    cdf[:, 7] = (1.0 + np.cos(th[:, 7])) / 2.0
+    np.testing.assert_allclose(cdf, u, atol=1e-12)
+    assert np.all((th[:, 6] >= -np.pi / 2) & (th[:, 6] <= np.pi / 2) & (th[:, 7] >= 0) & (th[:, 7] <= np.pi))
+    out = tr(torch.tensor([[-0.5] * 11, [1.5] * 11])).numpy()
+    np.testing.assert_array_equal(out, tr(torch.tensor([[0.0] * 11, [1.0] * 11])).numpy())
+
+
 DEV = torch.device("cuda:0")
+
+
+@pytest.mark.gpu
+def test_prior_transform_kernel_matches_the_definitions():
+    """gwl_prior_transform against the maps written out in float64 numpy, on the GW prior and on
+    random columns of every kind, with points inside, on the faces of and outside the cube."""
+    from paper_1909_11873_amd import gwlike as gw
+    rng = np.random.default_rng(23)
+    u = rng.uniform(-0.2, 1.2, (70001, 11))
+    u[:5] = 0.0
+    u[5:10] = 1.0
+    tr = nested.gw_prior_transform()
+    got = tr(torch.tensor(u, device=DEV)).cpu().numpy()
+    ref = tr(torch.tensor(u)).numpy()
+    np.testing.assert_allclose(got, ref, rtol=1e-14, atol=1e-15)
+    d = 40
+    maps = rng.integers(0, 4, d)
+    c0 = rng.uniform(-1.0, 1.0, d)
+    c1 = rng.uniform(-2.0, 2.0, d)
+    c0[maps == 1] = rng.uniform(1.0, 1e9, (maps == 1).sum())
+    c1[maps == 1] = rng.uniform(1.0, 1e9, (maps == 1).sum())
+    v = rng.uniform(-0.1, 1.1, (3333, d))
+    got = gw.prior_transform(torch.tensor(v, device=DEV), gw.PriorColumns(maps, c0, c1)).cpu().numpy()
+    x = c0 + c1 * np.clip(v, 0.0, 1.0)
+    ref = np.where(maps == 1, np.cbrt(x), np.where(maps == 2, np.arcsin(np.clip(x, -1, 1)),
+                                                  np.where(maps == 3, np.arccos(np.clip(x, -1, 1)), x)))
+    # the kernel forms the argument in one fused multiply-add, numpy in two roundings; asin and
+    # acos amplify that near +-1, where their slope grows, so compare through the maps' inverses
+    np.testing.assert_allclose(np.where(maps == 1, got ** 3, np.where(maps == 2, np.sin(got),
+                                        np.where(maps == 3, np.cos(got), got))),
+                               np.where(maps == 1, ref ** 3, np.where(maps == 2, np.sin(ref),
+                                        np.where(maps == 3, np.cos(ref), ref))), rtol=1e-13, atol=1e-14)
 
 
 @pytest.mark.gpu
