@@ -149,6 +149,93 @@ __global__ __launch_bounds__(SLICE_BLOCK) void k_slice_select(int64_t n, int d, 
   }
 }
 
+// Lane-parallel forms for groups of at most one wavefront: a chain's L candidates sit on L
+// consecutive lanes of one wavefront (64 / L chains per wavefront, spare lanes idle), each lane
+// judges its own candidate with loads independent of the others, and a ballot gives each chain
+// the index of its first candidate inside (or outside). Same decisions, same arithmetic.
+__device__ __forceinline__ uint64_t group_bits(uint64_t mask, int c, int L) {
+  const uint64_t gm = L == 64 ? ~0ull : ((1ull << L) - 1);
+  return (mask >> (c * L)) & gm;
+}
+
+__global__ __launch_bounds__(SLICE_BLOCK) void k_slice_ends_select_lanes(int64_t n, int d, int m,
+                                                                         const double* __restrict__ pts,
+                                                                         const double* __restrict__ logl,
+                                                                         const double* __restrict__ lmin,
+                                                                         double* __restrict__ lo,
+                                                                         double* __restrict__ hi,
+                                                                         const double* __restrict__ jl,
+                                                                         const double* __restrict__ jr) {
+  const int L = 2 * m, cpw = WAVE / L;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int64_t wave = ((int64_t)blockIdx.x * SLICE_BLOCK + threadIdx.x) / WAVE;
+  const int c = lane / L, j = lane - c * L;
+  const int64_t i = wave * cpw + c;
+  const bool active = c < cpw && i < n;
+  bool in = false;
+  if (active) {
+    const int64_t r = (int64_t)j * n + i;   // left end j for j < m, right end j - m above
+    in = in_region(pts + r * d, d, logl[r], *lmin);
+  }
+  const uint64_t mask = __ballot(in);
+  if (!active || j != 0) return;
+  const uint64_t bits = group_bits(mask, c, L), side = (1ull << m) - 1;
+  const uint64_t out_l = ~bits & side, out_r = ~(bits >> m) & side;
+  const int sl = out_l ? __builtin_ctzll(out_l) : m;
+  const int sr = out_r ? __builtin_ctzll(out_r) : m;
+  lo[i] = lo[i] - fmin((double)sl, jl[i]);
+  hi[i] = hi[i] + fmin((double)sr, jr[i]);
+}
+
+__global__ __launch_bounds__(SLICE_BLOCK) void k_slice_select_lanes(int64_t n, int d, int G,
+                                                                    const double* __restrict__ x,
+                                                                    const double* __restrict__ dirn,
+                                                                    const double* __restrict__ t,
+                                                                    const double* __restrict__ logl,
+                                                                    const double* __restrict__ lmin,
+                                                                    const double* __restrict__ a,
+                                                                    const double* __restrict__ b,
+                                                                    double* __restrict__ xn,
+                                                                    unsigned char* __restrict__ done,
+                                                                    double* __restrict__ lo, double* __restrict__ hi) {
+  const int cpw = WAVE / G;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int64_t wave = ((int64_t)blockIdx.x * SLICE_BLOCK + threadIdx.x) / WAVE;
+  const int c = lane / G, k = lane - c * G;
+  const int64_t i = wave * cpw + c;
+  const bool active = c < cpw && i < n;
+  const bool was_done = active && done[i] != 0;
+  bool ok = false;
+  if (active && !was_done) {
+    const int64_t r = (int64_t)k * n + i;
+    const double tk = t[r];
+    ok = logl[r] >= *lmin;
+    for (int q = 0; q < d; ++q) {
+      const double p = x[i * d + q] + tk * dirn[i * d + q];
+      ok = ok && p >= 0.0 && p <= 1.0;
+    }
+  }
+  const uint64_t mask = __ballot(ok);
+  if (!active || was_done) return;
+  const uint64_t bits = group_bits(mask, c, G);
+  if (bits == 0) {
+    if (k == 0) {
+      lo[i] = a[i];
+      hi[i] = b[i];
+    }
+    return;
+  }
+  // the first draw inside: the chain's lanes write its coordinates together
+  const double tf = t[(int64_t)__builtin_ctzll(bits) * n + i];
+  for (int q = k; q < d; q += G) xn[i * d + q] = x[i * d + q] + tf * dirn[i * d + q];
+  if (k == 0) done[i] = 1;
+}
+
+static unsigned lane_grid(int64_t n, int L) {
+  const int64_t waves = (n + WAVE / L - 1) / (WAVE / L);
+  return (unsigned)((waves * WAVE + SLICE_BLOCK - 1) / SLICE_BLOCK);
+}
+
 static unsigned grid_of(int64_t n) { return (unsigned)((n + SLICE_BLOCK - 1) / SLICE_BLOCK); }
 
 static gwl_status check_shape(int64_t n, int d, int k) {
@@ -191,8 +278,12 @@ gwl_status gwl_slice_ends_select(int64_t n, int d, int m, const double* pts, con
   if (st != GWL_OK) return st;
   if (!pts || !logl || !lmin || !lo || !hi || !jl || !jr)
     return fail(GWL_E_INVALID, "gwl_slice_ends_select: null pointer");
-  hipLaunchKernelGGL(k_slice_ends_select, dim3(grid_of(n)), dim3(SLICE_BLOCK), 0, (hipStream_t)stream, n, d, m, pts,
-                     logl, lmin, lo, hi, jl, jr);
+  if (2 * m <= WAVE)
+    hipLaunchKernelGGL(k_slice_ends_select_lanes, dim3(lane_grid(n, 2 * m)), dim3(SLICE_BLOCK), 0, (hipStream_t)stream,
+                       n, d, m, pts, logl, lmin, lo, hi, jl, jr);
+  else
+    hipLaunchKernelGGL(k_slice_ends_select, dim3(grid_of(n)), dim3(SLICE_BLOCK), 0, (hipStream_t)stream, n, d, m, pts,
+                       logl, lmin, lo, hi, jl, jr);
   return launched("gwl_slice_ends_select");
 }
 
@@ -219,8 +310,12 @@ gwl_status gwl_slice_select(int64_t n, int d, int G, const double* x, const doub
   if (st != GWL_OK) return st;
   if (!x || !dirn || !t || !logl || !lmin || !a || !b || !xn || !done || !lo || !hi)
     return fail(GWL_E_INVALID, "gwl_slice_select: null pointer");
-  hipLaunchKernelGGL(k_slice_select, dim3(grid_of(n)), dim3(SLICE_BLOCK), 0, (hipStream_t)stream, n, d, G, x, dirn, t,
-                     logl, lmin, a, b, xn, done, lo, hi);
+  if (G <= WAVE)
+    hipLaunchKernelGGL(k_slice_select_lanes, dim3(lane_grid(n, G)), dim3(SLICE_BLOCK), 0, (hipStream_t)stream, n, d, G,
+                       x, dirn, t, logl, lmin, a, b, xn, done, lo, hi);
+  else
+    hipLaunchKernelGGL(k_slice_select, dim3(grid_of(n)), dim3(SLICE_BLOCK), 0, (hipStream_t)stream, n, d, G, x, dirn,
+                       t, logl, lmin, a, b, xn, done, lo, hi);
   return launched("gwl_slice_select");
 }
 

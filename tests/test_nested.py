@@ -483,6 +483,47 @@ def test_slice_kernels_are_the_sequential_procedure(m):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("m,G,d", [(2, 1, 3), (3, 3, 13), (4, 8, 11), (5, 7, 2), (32, 64, 5), (33, 65, 4)])
+def test_slice_stage_kernels_match_the_torch_stages(m, G, d):
+    """Each stage kernel against the torch stage it replaces, bit for bit, over stepping-out
+    limits and group sizes that fill a wavefront unevenly, exactly, or not at all (the per-chain
+    fallback above 64 lanes), with more coordinates than lanes, chains already done, NaN ln L and
+    candidates outside the cube."""
+    from paper_1909_11873_amd import gwlike as gw
+
+    rng = np.random.default_rng(100 * m + G)
+    n = 777
+    x = torch.tensor(0.25 + 0.5 * rng.random((n, d)), device=DEV)
+    dirn = torch.tensor(rng.standard_normal((n, d)) * rng.uniform(0.01, 0.6, (n, 1)), device=DEV)
+
+    def raw(p):                        # a ball, NaN in a slab, -inf elsewhere
+        r2 = ((p - 0.5) ** 2).sum(1)
+        out = torch.where(r2 < 0.025 * d, -r2, -math.inf)
+        return torch.where((p[:, 0] > 0.6) & (p[:, 0] < 0.62), math.nan, out)
+
+    lmin = torch.tensor(-0.02 * d, dtype=torch.float64, device=DEV)
+    inside = lambda p: ((p >= 0.0) & (p <= 1.0)).all(1) & (raw(p) >= lmin)
+    u0, u1 = (torch.tensor(rng.random(n), device=DEV) for _ in range(2))
+    lo_t, hi_t = nested._slice_stepping(x, dirn, u0, u1, m, inside)
+    pts, lo, hi, jl, jr = gw.slice_ends(x, dirn, u0, u1, m)
+    gw.slice_ends_select(pts, raw(pts), lmin, lo, hi, jl, jr, m)
+    assert torch.equal(lo, lo_t) and torch.equal(hi, hi_t)
+    assert bool((lo_t < -u0).any()) and bool((hi_t > 1.0 - u0).any())            # some ends stepped out
+
+    done = torch.tensor(rng.random(n) < 0.2, device=DEV)
+    xn = torch.tensor(rng.random((n, d)), device=DEV)
+    ug = torch.tensor(rng.random((G, n)), device=DEV)
+    xn_t, done_t, lo2_t, hi2_t = nested._slice_group(x, dirn, lo, hi, done, xn, ug, inside)
+    t, gpts, a, b = gw.slice_draws(x, dirn, lo, hi, ug)
+    done_k = done.clone()
+    gw.slice_select(x, dirn, t, raw(gpts), lmin, a, b, xn, done_k, lo, hi)
+    assert torch.equal(xn, xn_t) and torch.equal(done_k, done_t)
+    assert torch.equal(lo, lo2_t) and torch.equal(hi, hi2_t)
+    hit = done_k & ~done
+    assert 0 < int(hit.sum()) < int((~done).sum())                               # both outcomes occur
+
+
+@pytest.mark.gpu
 def test_slice_moves_fall_back_to_eager_when_capture_fails():
     """A likelihood that cannot run under graph capture (here: one that refuses to) makes the
     sampler warn and move eagerly, with the same result as asking for eager moves."""
