@@ -46,17 +46,22 @@ hipError_t launch_setup(int nd, const EventGeom& g, const EventConst* ec, bool s
   return hipGetLastError();
 }
 
+// The value epilogue takes EPI_SPLIT lanes per point for the chunk sums: with one thread per
+// point a batch of a few thousand points fills a few dozen CUs, each thread walking every chunk.
+constexpr int EPI_SPLIT = 4;
+
 template <int ND>
 __global__ __launch_bounds__(PT_BLOCK) void k_epilogue(const EventConst* __restrict__ ec,
                                                        const double* __restrict__ coef, int64_t B, int64_t Bp,
                                                        int nchunk, bool scaled, const double* __restrict__ part,
                                                        double* __restrict__ logl) {
-  const int64_t p = (int64_t)blockIdx.x * PT_BLOCK + threadIdx.x;
-  if (p >= B) return;
+  const int64_t p = ((int64_t)blockIdx.x * PT_BLOCK + threadIdx.x) / EPI_SPLIT;
+  const int sub = threadIdx.x & (EPI_SPLIT - 1);
   constexpr int NZ = nz_of(ND, false);
-  const EventConst e = *ec;
   double acc[NZ];
-  gather<NZ>(part, nchunk, Bp, p, acc);
+  gather_split<NZ, EPI_SPLIT>(part, nchunk, Bp, p, sub, p < B, acc);
+  if (p >= B || sub != 0) return;
+  const EventConst e = *ec;
   if (scaled) apply_gain<ND>(e, acc);
   logl[p] = epilogue_value_rows<ND, NZ>(acc, coef, Bp, p, e, scaled ? e.uref : 1.0);
 }
@@ -88,13 +93,15 @@ hipError_t launch_epilogue(int nd, bool grad, bool scaled, const EventGeom& g, c
                            const double* coef, int64_t B, int64_t Bp, int nchunk, const double* part, double* logl,
                            double* gradout, hipStream_t s) {
   dim3 grid((unsigned)((B + PT_BLOCK - 1) / PT_BLOCK));
+  dim3 grid_split((unsigned)((B * EPI_SPLIT + PT_BLOCK - 1) / PT_BLOCK));
 #define GWL_EPI(N)                                                                                                  \
   case N:                                                                                                           \
     if (grad)                                                                                                       \
       hipLaunchKernelGGL(k_epilogue_grad<N>, grid, dim3(PT_BLOCK), 0, s, g, ec, theta, B, Bp, nchunk, scaled, part, \
                          logl, gradout);                                                                            \
     else                                                                                                            \
-      hipLaunchKernelGGL(k_epilogue<N>, grid, dim3(PT_BLOCK), 0, s, ec, coef, B, Bp, nchunk, scaled, part, logl);   \
+      hipLaunchKernelGGL(k_epilogue<N>, grid_split, dim3(PT_BLOCK), 0, s, ec, coef, B, Bp, nchunk, scaled, part,    \
+                         logl);                                                                                     \
     break;
   switch (nd) {
     GWL_EPI(1)
