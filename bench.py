@@ -483,7 +483,8 @@ def scaled_grad_error(g, gref):
     return np.abs(gs - rs) / scale
 
 
-def ns_leg(cfg: int, nlive: int, batches, eps: float, proposal: str = "slice", snr: float = 20.0, seed: int = 1):
+def ns_leg(cfg: int, nlive: int, batches, eps: float, proposal: str = "slice", snr: float = 20.0, seed: int = 1,
+           tune_out=None):
     """Static parallel nested sampling on one event through the mixed-precision kernels, once per
     batch size. The injection sits at the event's theta0 moved in distance to an optimal SNR of
     `snr`. Reports iterations, accepted candidates per iteration, the paper's speed-up
@@ -510,6 +511,13 @@ def ns_leg(cfg: int, nlive: int, batches, eps: float, proposal: str = "slice", s
     ev = gw.Event(data, pt, dets, ft, spec.df)
     l0 = float(gw.logl(torch.tensor(th0[None], device=dev), ev, "fp64")[0])
     transform = nested.gw_prior_transform(mc_range=spec.mc_range, spins=spec.spins)
+    if load_or_tune(tune_out):
+        # the likelihood batches a slice-sampling run makes: the live points, then per move the
+        # 2m stepping-out ends and the groups of shrinkage draws of every chain
+        m = 4                                              # the sampler's default stepping-out limit
+        shapes = {nlive} | {k * n for n in batches for k in (2 * m, nested.SLICE_GROUP)}
+        for b in sorted(shapes):
+            gw.autotune(ev, b, "mixed", cache_path=tune_out)
     rows = []
     for n in batches:
         kw = dict(device=dev, seed=seed, prior_transform=transform, proposal=proposal)
@@ -587,7 +595,7 @@ def main():
     if args.ns:
         batches = [int(x) for x in args.ns_batches.split(",") if x]
         print(json.dumps(ns_leg(args.config if args.config != 4 else 1, args.nlive, batches, args.ns_eps,
-                                args.ns_proposal)))
+                                args.ns_proposal, tune_out=args.retune)))
         return
 
     if args.config == 4:
