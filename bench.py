@@ -48,8 +48,8 @@ def work_per_point_bin(ndet: int, mixed: bool, grad: bool = False):
     the f T_det shift (1 FMA), the reduction to one cycle (1 op), the phasor (sin + cos) and the
     complex multiply-accumulate u (cos - i sin) (4 FMA). In the float64 kernel sin and cos have
     no hardware instruction; their work is the table-and-polynomial evaluation, with the phase
-    in units of 1/1024 cycle (the table index n = rint of it is the reduction, 1 op; y = phase - n,
-    y^2, 4 FMA + 1 MUL for the two short series, 2 FMA + 2 MUL to rotate: 18 flops in all).
+    in units of 1/2048 cycle (the table index n = rint of it is the reduction, 1 op; y = phase - n,
+    y^2, 3 FMA + 1 MUL for the two short series, 2 FMA + 2 MUL to rotate: 16 flops in all).
     The adjoint replaces the multiply-accumulate by the explicit product w = u p (2 MUL + 2 FMA),
     its sum (2 ADD), y_det = Im(c_det w) (MUL + FMA), the f-weighted sum of y_det (FMA) and the
     sum over detectors (ADD, one fewer than detectors): 14 flops per detector - 1; then the 8
@@ -59,10 +59,10 @@ def work_per_point_bin(ndet: int, mixed: bool, grad: bool = False):
         moments = 14 * ndet - 1 + 16
         if mixed:
             return 16 + ndet * (2 + 1), moments, ndet * 2
-        return 16 + ndet * (2 + 18) + moments, 0, 0
+        return 16 + ndet * (2 + 16) + moments, 0, 0
     if mixed:
         return 16 + ndet * (2 + 1), ndet * 8, ndet * 2
-    return 16 + ndet * (2 + 18 + 8), 0, 0
+    return 16 + ndet * (2 + 16 + 8), 0, 0
 
 
 def roofline(ndet: int, mixed: bool, nbins: float, npoints: float, seconds: float, grad: bool = False):

@@ -7,6 +7,7 @@
 
 #include "gwl_common.h"
 #include "gwl_device.h"
+#include "gwl_phasor.h"
 
 namespace gwl {
 
@@ -16,17 +17,15 @@ constexpr int NB = 8;  // bins per float32 block before the float64 flush (mixed
 // units, 1/N of a cycle (their per-point phase coefficients are scaled by N, a power of two, so
 // every product and sum rounds exactly as in cycles): tu = n + y with n = rint(tu), |y| <= 1/2,
 // and e^{2 pi i tu / N} = T[n mod N] e^{2 pi i y / N}. T holds (cos, sin) of 2 pi k / N in LDS
-// (16 KB per workgroup). With N = 1024, |2 pi y / N| <= 3.1e-3, and the Taylor series of
-// sin(2 pi y / N) and cos(2 pi y / N) stop after their y^5 and y^4 terms: the first omitted
-// terms are below 2e-19 and 2e-18 of the result. The series' coefficients are those of
-// sin(2 pi y) and cos(2 pi y) divided by powers of N (exact).
-constexpr int PH_TBL = 1024;
+// (32 KB per workgroup), copied from a table the compiler builds. With N = 2048,
+// |2 pi y / N| <= 1.6e-3, and the Taylor series of sin(2 pi y / N) and cos(2 pi y / N) stop after
+// their y^3 and y^4 terms: the first omitted terms are below 7.2e-17 and 2e-20 in absolute value
+// (under half a unit in the last place of a result near 1). The series' coefficients are those
+// of sin(2 pi y) and cos(2 pi y) divided by powers of N (exact).
+constexpr int PH_TBL = 2048;
+static __device__ const PhasorTable<PH_TBL> kPhasorTable = make_phasor_table<PH_TBL>();
 __device__ __forceinline__ void fill_phasor_table(double2* tbl) {
-  for (int k = threadIdx.x; k < PH_TBL; k += blockDim.x) {
-    double s, c;
-    sincos_cycles_f64((double)k / PH_TBL, s, c);
-    tbl[k] = make_double2(c, s);
-  }
+  for (int k = threadIdx.x; k < PH_TBL; k += blockDim.x) tbl[k] = make_double2(kPhasorTable.e[k].c, kPhasorTable.e[k].s);
 }
 template <int ND>
 __device__ __forceinline__ void to_table_units(double (&a)[NBASIS], double (&T)[ND]) {
@@ -41,8 +40,7 @@ __device__ __forceinline__ void sincos_tbl(double tu, const double2* __restrict_
   const double y = tu - n;                       // exact
   const double2 e = tbl[(int)n & (PH_TBL - 1)];  // v_cvt_i32_f64 clamps; the mask keeps the index in range
   const double z = y * y;
-  double ps = fma(z, 81.60524927607506 / (N * N * N * N * N), -41.34170224039976 / (N * N * N));  // sin(2 pi y / N) / y
-  ps = fma(ps, z, 6.283185307179586 / N);
+  const double ps = fma(z, -41.34170224039976 / (N * N * N), 6.283185307179586 / N);  // sin(2 pi y / N) / y
   const double sv = ps * y;
   const double pc = fma(fma(z, 64.9393940226683 / (N * N * N * N), -19.739208802178716 / (N * N)), z, 1.0);
   c = fma(e.x, pc, -(e.y * sv));
