@@ -57,9 +57,9 @@ hipError_t launch_rb(int nd, const void* fine64, const RowGradF32* fine32g, cons
 // calibrated model: set-up, bin loop and epilogue for theta[B][P], P = 11 + 2 nnode nd;
 // kcal per detector K1 [nnode], K2 [nnode][nnode]; calc is scratch [2 nnode nd][Bp]
 hipError_t launch_cal(int nd, bool mixed, bool grad, const EventGeom& g, const EventConst* ec, const double* kcal,
-                      const void* tab, const void* gtab, const void* calw, const double* theta, int P, int64_t B,
-                      int64_t Bp, const CalShape& sh, double* coef, double* calc, double* part, double* logl,
-                      double* gradout, hipStream_t s);
+                      const void* tab, const void* gtab, const void* calw, const void* calt, const double* calB,
+                      const double* theta, int P, int64_t B, int64_t Bp, const CalShape& sh, double* coef,
+                      double* calc, double* part, double* logl, double* gradout, hipStream_t s);
 
 // model strain on a grid: out[B][nd][M][2]
 hipError_t launch_waveform(int nd, const EventGeom& g, const double* coef, int64_t B, int64_t Bp,

@@ -16,6 +16,9 @@ struct gwl_event_s {
   int ncal = 0;
   gwl::RowCal32* cal32 = nullptr;    // [M] window weights
   gwl::RowCal64* cal64 = nullptr;
+  float* calt32 = nullptr;           // [M] position t in [0, 1] of each bin in its node interval
+  double* calt64 = nullptr;
+  double* calB = nullptr;            // per interval: the window's weights as cubics in t [n-1][4][4]
   double* kcal = nullptr;            // per detector: K1 [ncal], K2 [ncal][ncal]
   int cal_j0[gwl::MAXNODE] = {};
   int64_t cal_kb[gwl::MAXNODE] = {};

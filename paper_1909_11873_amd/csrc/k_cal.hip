@@ -52,11 +52,14 @@ __global__ __launch_bounds__(CAL_PT_BLOCK) void k_setup_cal(EventGeom g, const E
 
 // One bin of the calibrated loop. T_ is float (mixed: hardware phasors, float32 products) or
 // double (float64: table phasor).
+// 1 + dA and dphi come from their cubics in the bin's position t in the node interval (kA, kP:
+// coefficients of t^0 .. t^3 for this chunk's interval, 1 included in kA[.][0]); the window
+// weights cw (the same cubics' parts per node) serve only the adjoint's node moments.
 template <int ND, bool GRAD, class T_, class Row, class CalRow, class GradP>
-__device__ __forceinline__ void cal_bin(const Row r, const CalRow cw, GradP gt, int k, const double (&a)[NBASIS],
-                                        const double (&T)[ND], const T_ (&cr)[ND], const T_ (&ci)[ND],
-                                        const T_ (&ca)[ND][4], const T_ (&cp)[ND][4], const double2* tbl,
-                                        T_ (&z)[nz_cal(ND, GRAD)]) {
+__device__ __forceinline__ void cal_bin(const Row r, const CalRow cw, T_ t, GradP gt, int k,
+                                        const double (&a)[NBASIS], const double (&T)[ND], const T_ (&cr)[ND],
+                                        const T_ (&ci)[ND], const T_ (&kA)[ND][4], const T_ (&kP)[ND][4],
+                                        const double2* tbl, T_ (&z)[nz_cal(ND, GRAD)]) {
   constexpr bool MIXED = sizeof(T_) == 4;
   constexpr int MA = 3 * ND + NBASIS, MB = MA + 4 * ND;
   const double psi = phase_poly(a, r.x, r.w, r.w2, r.lnf);
@@ -76,13 +79,9 @@ __device__ __forceinline__ void cal_bin(const Row r, const CalRow cw, GradP gt, 
   }
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
-    // g1 = 1 + dA and dphi at this bin, from the four nearest nodes
-    T_ g1 = fma(cw.w[0], ca[d][0], (T_)1), dp = cw.w[0] * cp[d][0];
-#pragma unroll
-    for (int i = 1; i < 4; ++i) {
-      g1 = fma(cw.w[i], ca[d][i], g1);
-      dp = fma(cw.w[i], cp[d][i], dp);
-    }
+    // g1 = 1 + dA and dphi at this bin (Horner in t)
+    const T_ g1 = fma(fma(fma(kA[d][3], t, kA[d][2]), t, kA[d][1]), t, kA[d][0]);
+    const T_ dp = fma(fma(fma(kP[d][3], t, kP[d][2]), t, kP[d][1]), t, kP[d][0]);
     // q = u p exp(i dphi) = u exp(-2 pi i (phi - dphi / 2 pi)): the calibration phase joins the
     // model phase before the phasor, so one phasor (with its gain correction) serves both. The
     // mixed variant subtracts dphi / 2 pi (at most a few hundredths of a cycle) in float32 from
@@ -139,7 +138,8 @@ __device__ __forceinline__ bool locate_cal(const CalShape& sh, int& c, int& j, i
 
 template <int ND, bool MIXED, bool GRAD>
 __global__ __launch_bounds__(BLOCK) void k_bins_cal(const void* __restrict__ tabv, const void* __restrict__ gtabv,
-                                                    const void* __restrict__ calwv, const double* __restrict__ coef,
+                                                    const void* __restrict__ calwv, const void* __restrict__ caltv,
+                                                    const double* __restrict__ calB, const double* __restrict__ coef,
                                                     const double* __restrict__ calc, int64_t B, int64_t Bp,
                                                     CalShape sh, double* __restrict__ part) {
   typedef typename std::conditional<MIXED, float, double>::type T_;
@@ -158,14 +158,31 @@ __global__ __launch_bounds__(BLOCK) void k_bins_cal(const void* __restrict__ tab
   T_ cr[ND], ci[ND];
   load_coef<ND, T_>(coef, Bp, pc, GRAD, a, T, cr, ci);
   if constexpr (!MIXED) to_table_units<ND>(a, T);  // the float64 phase runs in 1/PH_TBL cycles
-  T_ ca[ND][4], cp[ND][4];
-  const int n = sh.nnode, j0 = sh.j0[j];
+  // this point's amplitude and phase node values in the window of the chunk's interval, turned
+  // into the cubics' coefficients: k[p] = sum_i v_i B[i][p] (1 added to the amplitude's k[0])
+  T_ kA[ND][4], kP[ND][4];
+  {
+    const int n = sh.nnode, j0 = sh.j0[j];
+    const double* Bj = calB + (int64_t)j * 16;
 #pragma unroll
-  for (int d = 0; d < ND; ++d) {
+    for (int d = 0; d < ND; ++d) {
+      T_ va[4], vp[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      ca[d][i] = (T_)calc[(int64_t)(2 * n * d + j0 + i) * Bp + pc];
-      cp[d][i] = (T_)calc[(int64_t)(2 * n * d + n + j0 + i) * Bp + pc];
+      for (int i = 0; i < 4; ++i) {
+        va[i] = (T_)calc[(int64_t)(2 * n * d + j0 + i) * Bp + pc];
+        vp[i] = (T_)calc[(int64_t)(2 * n * d + n + j0 + i) * Bp + pc];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        T_ sa = q == 0 ? (T_)1 : (T_)0, sp = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          sa = fma(va[i], (T_)Bj[i * 4 + q], sa);
+          sp = fma(vp[i], (T_)Bj[i * 4 + q], sp);
+        }
+        kA[d][q] = sa;
+        kP[d][q] = sp;
+      }
     }
   }
   double tot[NZ];
@@ -175,13 +192,16 @@ __global__ __launch_bounds__(BLOCK) void k_bins_cal(const void* __restrict__ tab
     const RowMixed<ND>* tab = (const RowMixed<ND>*)tabv;
     const RowGradF32* gt = (const RowGradF32*)gtabv;
     const RowCal32* cw = (const RowCal32*)calwv;
+    const float* ct = (const float*)caltv;
     // float32 blocks of NB bins added into float64; each bin's rows are requested one bin ahead
-    // (the tables carry zero padding rows past the last bin)
+    // (the tables carry zero padding rows past the last bin). Only the adjoint reads the weights.
     int k = (int)k0;
     const int kend = (int)k1;
     if (k < kend) {
       RowMixed<ND> cur = load_row_mixed<ND>(tab, k);
-      RowCal32 cwc = cw[k];
+      RowCal32 cwc;
+      if constexpr (GRAD) cwc = cw[k];
+      float tc = ct[k];
       for (; k + NB <= kend; k += NB) {
         float z[NZ];
 #pragma unroll
@@ -189,10 +209,13 @@ __global__ __launch_bounds__(BLOCK) void k_bins_cal(const void* __restrict__ tab
 #pragma unroll 2
         for (int jj = 0; jj < NB; ++jj) {
           const RowMixed<ND> nxt = load_row_mixed<ND>(tab, k + jj + 1);
-          const RowCal32 cwn = cw[k + jj + 1];
-          cal_bin<ND, GRAD, float>(cur, cwc, gt, k + jj, a, T, cr, ci, ca, cp, tbl, z);
+          RowCal32 cwn;
+          if constexpr (GRAD) cwn = cw[k + jj + 1];
+          const float tn = ct[k + jj + 1];
+          cal_bin<ND, GRAD, float>(cur, cwc, tc, gt, k + jj, a, T, cr, ci, kA, kP, tbl, z);
           cur = nxt;
-          cwc = cwn;
+          if constexpr (GRAD) cwc = cwn;
+          tc = tn;
         }
 #pragma unroll
         for (int zz = 0; zz < NZ; ++zz) tot[zz] += (double)z[zz];
@@ -201,7 +224,8 @@ __global__ __launch_bounds__(BLOCK) void k_bins_cal(const void* __restrict__ tab
         float z[NZ];
 #pragma unroll
         for (int zz = 0; zz < NZ; ++zz) z[zz] = 0.0f;
-        for (; k < kend; ++k) cal_bin<ND, GRAD, float>(load_row_mixed<ND>(tab, k), cw[k], gt, k, a, T, cr, ci, ca, cp, tbl, z);
+        for (; k < kend; ++k)
+          cal_bin<ND, GRAD, float>(load_row_mixed<ND>(tab, k), cw[k], ct[k], gt, k, a, T, cr, ci, kA, kP, tbl, z);
 #pragma unroll
         for (int zz = 0; zz < NZ; ++zz) tot[zz] += (double)z[zz];
       }
@@ -210,15 +234,21 @@ __global__ __launch_bounds__(BLOCK) void k_bins_cal(const void* __restrict__ tab
     const RowF64<ND>* tab = (const RowF64<ND>*)tabv;
     const RowGradF64* gt = (const RowGradF64*)gtabv;
     const RowCal64* cw = (const RowCal64*)calwv;
+    const double* ct = (const double*)caltv;
     if (k0 < k1) {
       RowF64<ND> cur = load_row_f64<ND>(tab, (int)k0);
-      RowCal64 cwc = cw[k0];
+      RowCal64 cwc;
+      if constexpr (GRAD) cwc = cw[k0];
+      double tc = ct[k0];
       for (int k = (int)k0; k < (int)k1; ++k) {
         const RowF64<ND> nxt = load_row_f64<ND>(tab, k + 1);
-        const RowCal64 cwn = cw[k + 1];
-        cal_bin<ND, GRAD, double>(cur, cwc, gt, k, a, T, cr, ci, ca, cp, tbl, tot);
+        RowCal64 cwn;
+        if constexpr (GRAD) cwn = cw[k + 1];
+        const double tn = ct[k + 1];
+        cal_bin<ND, GRAD, double>(cur, cwc, tc, gt, k, a, T, cr, ci, kA, kP, tbl, tot);
         cur = nxt;
-        cwc = cwn;
+        if constexpr (GRAD) cwc = cwn;
+        tc = tn;
       }
     }
   }
@@ -315,15 +345,15 @@ __global__ __launch_bounds__(CAL_PT_BLOCK) void k_epilogue_cal(EventGeom g, cons
 
 template <int ND>
 static hipError_t cal_nd(bool mixed, bool grad, const EventGeom& g, const EventConst* ec, const double* kcal,
-                         const void* tab, const void* gtab, const void* calw, const double* theta, int P, int64_t B,
-                         int64_t Bp, const CalShape& sh, double* coef, double* calc, double* part, double* logl,
-                         double* gradout, hipStream_t s) {
+                         const void* tab, const void* gtab, const void* calw, const void* calt, const double* calB,
+                         const double* theta, int P, int64_t B, int64_t Bp, const CalShape& sh, double* coef,
+                         double* calc, double* part, double* logl, double* gradout, hipStream_t s) {
   const int ncal = 2 * sh.nnode * ND;
   hipLaunchKernelGGL(k_setup_cal<ND>, dim3((unsigned)((Bp + CAL_PT_BLOCK - 1) / CAL_PT_BLOCK)), dim3(CAL_PT_BLOCK), 0,
                      s, g, ec, mixed, theta, P, ncal, B, Bp, coef, calc);
   const dim3 grid((unsigned)(sh.gper * NXCD)), block(BLOCK);
 #define GWL_CB(MX, GR) \
-  hipLaunchKernelGGL((k_bins_cal<ND, MX, GR>), grid, block, 0, s, tab, gtab, calw, (const double*)coef, \
+  hipLaunchKernelGGL((k_bins_cal<ND, MX, GR>), grid, block, 0, s, tab, gtab, calw, calt, calB, (const double*)coef, \
                      (const double*)calc, B, Bp, sh, part)
   if (mixed) {
     if (grad) GWL_CB(true, true); else GWL_CB(true, false);
@@ -342,13 +372,14 @@ static hipError_t cal_nd(bool mixed, bool grad, const EventGeom& g, const EventC
 }
 
 hipError_t launch_cal(int nd, bool mixed, bool grad, const EventGeom& g, const EventConst* ec, const double* kcal,
-                      const void* tab, const void* gtab, const void* calw, const double* theta, int P, int64_t B,
-                      int64_t Bp, const CalShape& sh, double* coef, double* calc, double* part, double* logl,
-                      double* gradout, hipStream_t s) {
+                      const void* tab, const void* gtab, const void* calw, const void* calt, const double* calB,
+                      const double* theta, int P, int64_t B, int64_t Bp, const CalShape& sh, double* coef,
+                      double* calc, double* part, double* logl, double* gradout, hipStream_t s) {
   switch (nd) {
-#define GWL_CN(N)                                                                                                      \
-  case N:                                                                                                              \
-    return cal_nd<N>(mixed, grad, g, ec, kcal, tab, gtab, calw, theta, P, B, Bp, sh, coef, calc, part, logl, gradout, s);
+#define GWL_CN(N)                                                                                                   \
+  case N:                                                                                                           \
+    return cal_nd<N>(mixed, grad, g, ec, kcal, tab, gtab, calw, calt, calB, theta, P, B, Bp, sh, coef, calc, part, \
+                     logl, gradout, s);
     GWL_CN(1)
     GWL_CN(2)
     GWL_CN(3)

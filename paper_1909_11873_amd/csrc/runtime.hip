@@ -275,12 +275,35 @@ gwl_status gwl_event_create_rb(const double* data, const double* psd, const gwl_
 // the real end nodes, expressed over the interval's window of four real nodes; the interval
 // starts; and per detector K1_j = sum_k K_k w_kj, K2_jl = sum_k K_k w_kj w_kl, K_k = 4 df
 // f_k^-7/3 / S_k.
+// Catmull-Rom weights of nodes j-1 .. j+2 on interval j as polynomials in t (coefficients of
+// t^0 .. t^3), and the ghost nodes at both ends (-1 = 2 v0 - v1, n = 2 v_{n-1} - v_{n-2}) folded
+// into the window of four nodes j0[j] .. j0[j] + 3: B[(j * 4 + i) * 4 + p].
+static void cal_basis(int n, const int* j0, std::vector<double>& B) {
+  const double C[4][4] = {{0.0, -0.5, 1.0, -0.5}, {1.0, 0.0, -2.5, 1.5}, {0.0, 0.5, 2.0, -1.5}, {0.0, 0.0, -0.5, 0.5}};
+  B.assign((size_t)(n - 1) * 16, 0.0);
+  for (int j = 0; j < n - 1; ++j) {
+    double wn[MAXNODE + 2][4] = {};  // over nodes -1 .. n
+    for (int i = 0; i < 4; ++i)
+      for (int q = 0; q < 4; ++q) wn[j + i][q] += C[i][q];
+    for (int q = 0; q < 4; ++q) {
+      wn[1][q] += 2.0 * wn[0][q];
+      wn[2][q] -= wn[0][q];
+      wn[n][q] += 2.0 * wn[n + 1][q];
+      wn[n - 1][q] -= wn[n + 1][q];
+    }
+    for (int i = 0; i < 4; ++i)
+      for (int q = 0; q < 4; ++q) B[((size_t)j * 4 + i) * 4 + q] = wn[j0[j] + i + 1][q];
+  }
+}
+
 static void cal_tables(const std::vector<double>& f, const std::vector<double>& psd, int nd, double df, int n,
-                       std::vector<double>& w, int* j0, int64_t* kb, std::vector<double>& kcal) {
+                       std::vector<double>& w, std::vector<double>& tloc, int* j0, int64_t* kb,
+                       std::vector<double>& kcal) {
   const int64_t M = (int64_t)f.size();
   const double x0 = log(f.front()), x1 = log(f.back());
   const double h = n > 1 ? (x1 - x0) / (n - 1) : 1.0;
   w.assign((size_t)M * 4, 0.0);
+  tloc.assign((size_t)M, 0.0);
   std::vector<double> W((size_t)M * n, 0.0);  // weights over all nodes (for K1, K2)
   std::vector<int> jk((size_t)M);
   for (int j = 0; j < n - 1; ++j) j0[j] = std::min(std::max(j - 1, 0), n - 4);
@@ -289,6 +312,7 @@ static void cal_tables(const std::vector<double>& f, const std::vector<double>& 
     s = std::min(std::max(s, 0.0), (double)(n - 1));
     const int j = std::min(std::max((int)floor(s), 0), n - 2);
     const double t = s - j;
+    tloc[(size_t)k] = t;
     double cw[4] = {0.5 * (-t + 2 * t * t - t * t * t), 0.5 * (2 - 5 * t * t + 3 * t * t * t),
                     0.5 * (t + 4 * t * t - 3 * t * t * t), 0.5 * (-t * t + t * t * t)};  // nodes j-1 .. j+2
     double wn[MAXNODE + 2] = {};  // over nodes -1 .. n
@@ -341,8 +365,9 @@ gwl_status gwl_event_create_cal(const double* data, const double* psd, const gwl
     gwl_event_destroy(ev);
     return hip_fail(e, "grid read-back");
   }
-  std::vector<double> w, kc;
-  cal_tables(fh, ph, ndet, df, nnode, w, ev->cal_j0, ev->cal_kb, kc);
+  std::vector<double> w, tl, kc, basis;
+  cal_tables(fh, ph, ndet, df, nnode, w, tl, ev->cal_j0, ev->cal_kb, kc);
+  cal_basis(nnode, ev->cal_j0, basis);
   std::vector<RowCal32> w32((size_t)M);
   for (int64_t k = 0; k < M; ++k)
     for (int i = 0; i < 4; ++i) w32[(size_t)k].w[i] = (float)w[(size_t)k * 4 + i];
@@ -351,11 +376,19 @@ gwl_status gwl_event_create_cal(const double* data, const double* psd, const gwl
   for (int64_t k = M; k < M + TAB_PAD; ++k)
     for (int i = 0; i < 4; ++i) w32[(size_t)k].w[i] = 0.0f;
   w.resize((size_t)(M + TAB_PAD) * 4, 0.0);
+  tl.resize((size_t)(M + TAB_PAD), 0.0);
+  std::vector<float> t32(tl.begin(), tl.end());
   e = hipMalloc((void**)&ev->cal32, sizeof(RowCal32) * (M + TAB_PAD));
   if (e == hipSuccess) e = hipMalloc((void**)&ev->cal64, sizeof(RowCal64) * (M + TAB_PAD));
+  if (e == hipSuccess) e = hipMalloc((void**)&ev->calt32, sizeof(float) * (M + TAB_PAD));
+  if (e == hipSuccess) e = hipMalloc((void**)&ev->calt64, sizeof(double) * (M + TAB_PAD));
+  if (e == hipSuccess) e = hipMalloc((void**)&ev->calB, sizeof(double) * basis.size());
   if (e == hipSuccess) e = hipMalloc((void**)&ev->kcal, sizeof(double) * kc.size());
   if (e == hipSuccess) e = hipMemcpy(ev->cal32, w32.data(), sizeof(RowCal32) * (M + TAB_PAD), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(ev->cal64, w.data(), sizeof(RowCal64) * (M + TAB_PAD), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ev->calt32, t32.data(), sizeof(float) * (M + TAB_PAD), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ev->calt64, tl.data(), sizeof(double) * (M + TAB_PAD), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ev->calB, basis.data(), sizeof(double) * basis.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(ev->kcal, kc.data(), sizeof(double) * kc.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     gwl_event_destroy(ev);
@@ -370,6 +403,9 @@ gwl_status gwl_event_destroy(gwl_event ev) {
   if (!ev) return GWL_OK;
   if (ev->cal32) (void)hipFree(ev->cal32);
   if (ev->cal64) (void)hipFree(ev->cal64);
+  if (ev->calt32) (void)hipFree(ev->calt32);
+  if (ev->calt64) (void)hipFree(ev->calt64);
+  if (ev->calB) (void)hipFree(ev->calB);
   if (ev->kcal) (void)hipFree(ev->kcal);
   if (ev->tab64) (void)hipFree(ev->tab64);
   if (ev->tab32) (void)hipFree(ev->tab32);
@@ -436,7 +472,8 @@ static gwl_status run_logl_cal(gwl_event ev, const double* theta, int64_t B, boo
   double* part = calc + (size_t)ncal * Bp;
   e = launch_cal(nd, mixed, grad, ev->geom, ev->ec, ev->kcal, mixed ? ev->tab32 : ev->tab64,
                  mixed ? (const void*)ev->g32 : (const void*)ev->g64, mixed ? (const void*)ev->cal32 : (const void*)ev->cal64,
-                 theta, NPARAM + ncal, B, Bp, sh, coef, calc, part, logl, gradout, s);
+                 mixed ? (const void*)ev->calt32 : (const void*)ev->calt64, ev->calB, theta, NPARAM + ncal, B, Bp, sh,
+                 coef, calc, part, logl, gradout, s);
   hipError_t e2 = hipFreeAsync(ws, s);
   if (e != hipSuccess) return hip_fail(e, "launch");
   if (e2 != hipSuccess) return hip_fail(e2, "workspace release");
