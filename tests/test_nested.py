@@ -7,6 +7,7 @@ points' coordinates must agree too. The CPU cases run the driver on host tensors
 run the same comparison on the device and a full run on the GW likelihood.
 """
 import math
+import warnings
 
 import numpy as np
 import pytest
@@ -439,7 +440,12 @@ def test_slice_graphs_and_kernels_replay_the_eager_moves():
         smp = nested.ParallelNestedSampler(lambda th: gw.logl(th, ev, "mixed"), 11, 200, 256, proposal="slice",
                                            slice_steps=6, slice_graphs=graphs, slice_kernels=kernels, device=DEV,
                                            seed=12, prior_transform=nested.gw_prior_transform(spins=False))
-        runs.append(smp.run(eps=0.1, max_iter=12))
+        with warnings.catch_warnings(record=True) as caught:
+            warnings.simplefilter("always")
+            runs.append(smp.run(eps=0.1, max_iter=12))
+        # the graph runs really replayed graphs (a failed capture warns and moves eagerly)
+        assert not [w for w in caught if "eagerly" in str(w.message)]
+        assert smp.slice_graphs == graphs
     ref = runs[0]
     assert ref.niter == 12
     for r in runs[1:]:
