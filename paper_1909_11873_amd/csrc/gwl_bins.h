@@ -174,18 +174,27 @@ __device__ __forceinline__ void bin_loop_mixed(TabP tab, GradP gtab,
   for (int z = 0; z < NZ; ++z) tot[z] = 0.0;
   int k = k0;
   if (k + NB <= k1) {
-    // each bin's row is requested one bin ahead of its use; the tables carry TAB_PAD zero rows
-    // after the last bin, so the look-ahead read past a chunk's end stays in bounds
-    RowMixed<ND> cur = load_row_mixed<ND>(tab, k);
+    // each bin's row is requested ahead of its use, two bins ahead in the forward loop and one
+    // in the adjoint (whose registers would lose it a wavefront per SIMD); the tables carry
+    // TAB_PAD zero rows after the last bin, so the look-ahead read past a chunk's end stays in
+    // bounds
+    RowMixed<ND> cur = load_row_mixed<ND>(tab, k), nx1 = load_row_mixed<ND>(tab, k + (GRAD ? 0 : 1));
     for (; k + NB <= k1; k += NB) {
       float z[NZ];
 #pragma unroll
       for (int j = 0; j < NZ; ++j) z[j] = 0.0f;
 #pragma unroll 2
       for (int j = 0; j < NB; ++j) {
-        const RowMixed<ND> nxt = load_row_mixed<ND>(tab, k + j + 1);
-        mixed_bin<ND, GRAD, GradP>(cur, gtab, k + j, a, T, cr, ci, z);
-        cur = nxt;
+        if constexpr (GRAD) {
+          const RowMixed<ND> nxt = load_row_mixed<ND>(tab, k + j + 1);
+          mixed_bin<ND, GRAD, GradP>(cur, gtab, k + j, a, T, cr, ci, z);
+          cur = nxt;
+        } else {
+          const RowMixed<ND> nx2 = load_row_mixed<ND>(tab, k + j + 2);
+          mixed_bin<ND, GRAD, GradP>(cur, gtab, k + j, a, T, cr, ci, z);
+          cur = nx1;
+          nx1 = nx2;
+        }
       }
 #pragma unroll
       for (int j = 0; j < NZ; ++j) tot[j] += (double)z[j];
@@ -211,7 +220,8 @@ __device__ __forceinline__ void bin_loop_f64(TabP tab, GradP gtab,
 #pragma unroll
   for (int j = 0; j < NZ; ++j) z[j] = 0.0;
   if (k0 >= k1) return;
-  RowF64<ND> cur = load_row_f64<ND>(tab, k0);  // rows requested one bin ahead (see bin_loop_mixed)
+  // rows requested one bin ahead (two ahead measured no faster here and cost registers)
+  RowF64<ND> cur = load_row_f64<ND>(tab, k0);
 #pragma unroll 2
   for (int k = k0; k < k1; ++k) {
     const RowF64<ND> nxt = load_row_f64<ND>(tab, k + 1);
