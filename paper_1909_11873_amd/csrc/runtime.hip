@@ -371,7 +371,7 @@ gwl_status gwl_event_create_cal(const double* data, const double* psd, const gwl
   std::vector<RowCal32> w32((size_t)M);
   for (int64_t k = 0; k < M; ++k)
     for (int i = 0; i < 4; ++i) w32[(size_t)k].w[i] = (float)w[(size_t)k * 4 + i];
-  // TAB_PAD zero rows past the last bin: the bin loop requests each row one bin ahead
+  // TAB_PAD zero rows past the last bin: the bin loops request rows ahead of their bin
   w32.resize((size_t)(M + TAB_PAD));
   for (int64_t k = M; k < M + TAB_PAD; ++k)
     for (int i = 0; i < 4; ++i) w32[(size_t)k].w[i] = 0.0f;
