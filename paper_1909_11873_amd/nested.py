@@ -644,11 +644,20 @@ def importance_logz(u_post, loglike, transform, dev, ncomp=16, ndraw=8_000_000, 
     """An evidence estimate independent of nested sampling, to check a run against: importance
     sampling in the unit cube with a Gaussian-mixture proposal fitted to posterior samples
     u_post[N, d] (ncomp components), mixed in equal parts with copies of it whose covariances
-    are scaled by scales^2, ndraw draws. Returns (ln Z, relative standard error of Z, effective sample size). A mode the
-    posterior samples miss is missed here too."""
+    are scaled by scales^2, ndraw draws. Coordinates whose posterior spread is that of a uniform
+    draw (standard deviation above 0.27; a uniform one has 0.289, e.g. a parameter the likelihood
+    ignores) are drawn uniformly instead, the mixture covering the others. Returns (ln Z,
+    relative standard error of Z, effective sample size). A mode the posterior samples miss is
+    missed here too."""
     from sklearn.mixture import GaussianMixture
-    gm = GaussianMixture(ncomp, covariance_type="full", reg_covar=1e-9, random_state=0, max_iter=200).fit(u_post)
-    d = u_post.shape[1]
+    d_all = u_post.shape[1]
+    flat = u_post.std(0) > 0.27
+    keep = np.flatnonzero(~flat)
+    gm = GaussianMixture(ncomp, covariance_type="full", reg_covar=1e-9, random_state=0,
+                         max_iter=200).fit(u_post[:, keep])
+    d = len(keep)
+    keep_t = torch.tensor(keep, device=dev)
+    flat_t = torch.tensor(np.flatnonzero(flat), device=dev)
     wts = torch.tensor(gm.weights_, device=dev)
     mus = torch.tensor(gm.means_, device=dev)
     chol = torch.linalg.cholesky(torch.tensor(gm.covariances_, device=dev))
@@ -658,10 +667,11 @@ def importance_logz(u_post, loglike, transform, dev, ncomp=16, ndraw=8_000_000, 
     g = torch.Generator(device=dev)
     g.manual_seed(seed)
 
-    def logq(u):
+    def logq(v):
+        """log density of the mixture part at v[B, d] (the uniform coordinates add 0)"""
         out = []
         for s in scales.tolist():
-            y = torch.matmul(u[None] - mus[:, None], (linv / s).transpose(1, 2).contiguous())
+            y = torch.matmul(v[None] - mus[:, None], (linv / s).transpose(1, 2).contiguous())
             lp = -0.5 * (y * y).sum(-1) - (logdet + d * math.log(s))[:, None] - 0.5 * d * math.log(2 * math.pi)
             out.append(torch.logsumexp(lp + torch.log(wts)[:, None], 0))
         return torch.logsumexp(torch.stack(out), 0) - math.log(len(scales))
@@ -671,11 +681,15 @@ def importance_logz(u_post, loglike, transform, dev, ncomp=16, ndraw=8_000_000, 
         sc = scales[torch.randint(0, len(scales), (B,), generator=g, device=dev)]
         ci = torch.multinomial(wts, B, replacement=True, generator=g)
         z = torch.randn(B, d, generator=g, device=dev, dtype=torch.float64)
-        u = mus[ci] + sc[:, None] * torch.matmul(chol[ci], z[..., None])[..., 0]
+        v = mus[ci] + sc[:, None] * torch.matmul(chol[ci], z[..., None])[..., 0]
+        u = torch.empty(B, d_all, dtype=torch.float64, device=dev)
+        u[:, keep_t] = v
+        if len(flat_t):
+            u[:, flat_t] = torch.rand(B, len(flat_t), generator=g, device=dev, dtype=torch.float64)
         inside = ((u >= 0) & (u <= 1)).all(1)
         l = loglike(transform(u.clamp(0.0, 1.0)))
         l = torch.where(torch.isnan(l) | ~inside, torch.full_like(l, -math.inf), l)
-        lw.append((l - logq(u)).cpu().numpy())
+        lw.append((l - logq(v)).cpu().numpy())
     lw = np.concatenate(lw)
     w = np.exp(lw - lw.max())
     return (lw.max() + math.log(w.mean()), w.std() / w.mean() / math.sqrt(len(w)),

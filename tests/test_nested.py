@@ -243,6 +243,22 @@ def test_importance_logz_on_a_normalised_gaussian():
     assert abs(lz) < 5 * rel + 1e-3 and rel < 0.01 and ess > 1e4
 
 
+def test_importance_logz_with_a_coordinate_the_likelihood_ignores():
+    """A parameter the likelihood ignores has a uniform posterior; its coordinate is drawn
+    uniformly, the mixture covering the rest. ln Z = 0 again (normalised Gaussian in the other
+    two coordinates), with most draws useful."""
+    s = 0.05
+    cov = s * s * np.array([[1.0, 0.6], [0.6, 1.0]])
+    prec = torch.tensor(np.linalg.inv(cov))
+    norm = -0.5 * math.log((2 * math.pi) ** 2 * np.linalg.det(cov))
+    ll = lambda th: norm - 0.5 * (((th[:, :2] - 0.5) @ prec) * (th[:, :2] - 0.5)).sum(1)
+    rng = np.random.default_rng(2)
+    post = np.column_stack([rng.multivariate_normal(np.full(2, 0.5), cov, size=4000), rng.random(4000)])
+    lz, rel, ess = nested.importance_logz(post, ll, lambda u: u, torch.device("cpu"), ncomp=2, ndraw=262144,
+                                          scales=(1.0, 1.5))
+    assert abs(lz) < 5 * rel + 1e-3 and rel < 0.01 and ess > 5e4
+
+
 def test_speedup_law():
     assert nested.speedup_law(1, 2000) == pytest.approx(1.0, rel=3e-4)
     # the values quoted beside the paper's scaling test (K = 2000)
