@@ -546,6 +546,42 @@ def test_slice_stage_kernels_match_the_torch_stages(m, G, d):
 
 
 @pytest.mark.gpu
+def test_slice_kernels_on_one_chain_in_one_dimension():
+    """The smallest shapes: one chain, one coordinate, against the sequential procedure."""
+    inside = lambda p: ((p - 0.4).abs() < 0.25).all(-1)
+    raw = lambda p: torch.where(inside(p), 0.0, -math.inf).to(torch.float64)
+    lmin = torch.zeros((), dtype=torch.float64, device=DEV)
+    rng = np.random.default_rng(5)
+    for trial in range(20):
+        x = np.array([[0.2 + 0.4 * rng.random()]])
+        dirn = np.array([[rng.uniform(-0.5, 0.5)]])
+        unif = rng.random((2 + nested.SLICE_MAX_DRAWS, 1))
+        got, moved = nested.slice_move_dev(torch.tensor(x, device=DEV), torch.tensor(dirn, device=DEV),
+                                           torch.tensor(unif, device=DEV), 4, raw, lmin)
+        ref, ok = neal_slice_move(x[0], dirn[0], unif[:, 0], 4, lambda p: bool(inside(torch.tensor(p))))
+        assert bool(moved[0]) == ok
+        np.testing.assert_array_equal(got.cpu().numpy()[0], ref)
+
+
+@pytest.mark.gpu
+def test_prior_transform_at_its_largest_width_and_one_point():
+    from paper_1909_11873_amd import gwlike as gw
+    rng = np.random.default_rng(29)
+    d = 64
+    maps = np.arange(d) % 4
+    c0 = np.where(maps == 1, 8.0, -1.0)
+    c1 = np.where(maps == 1, 19.0, 2.0)
+    u = rng.random((1, d))
+    got = gw.prior_transform(torch.tensor(u, device=DEV), gw.PriorColumns(maps, c0, c1)).cpu().numpy()
+    x = c0 + c1 * u
+    xc = np.clip(x, -1.0, 1.0)                          # np.where evaluates every branch
+    ref = np.where(maps == 1, np.cbrt(x), np.where(maps == 2, np.arcsin(xc), np.where(maps == 3, np.arccos(xc), x)))
+    np.testing.assert_allclose(got, ref, rtol=1e-13, atol=1e-13)
+    with pytest.raises(ValueError):
+        gw.PriorColumns([0] * 65, [0.0] * 65, [1.0] * 65)
+
+
+@pytest.mark.gpu
 def test_slice_moves_fall_back_to_eager_when_capture_fails():
     """A likelihood that cannot run under graph capture (here: one that refuses to) makes the
     sampler warn and move eagerly, with the same result as asking for eager moves."""
