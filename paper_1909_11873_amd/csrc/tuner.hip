@@ -10,6 +10,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -200,7 +201,9 @@ gwl_status gwl_autotune(const char* cache_path, gwl_event ev, int64_t B, gwl_pre
   if (cache_path) load_cache(cache_path);  // keep entries of other shapes
   const bool mixed = prec == GWL_MIXED, grad = with_grad != 0;
 
-  // candidate chunk counts around the heuristic, each distinct after rounding
+  // candidate chunk counts: powers of two around the heuristic, then a second pass around the
+  // best of those (3/4 .. 3/2 of it), each launch shape timed once (the chunk count a shape really
+  // uses can differ from the request)
   const int h = heuristic_nchunk(B, ev->M);
   std::vector<int> cand;
   const int mult[] = {1, 2, 4, 8, 16};
@@ -208,19 +211,27 @@ gwl_status gwl_autotune(const char* cache_path, gwl_event ev, int64_t B, gwl_pre
     cand.push_back(h / m);
     cand.push_back(h * m);
   }
-  // distinct launch shapes (the chunk count a shape really uses can differ from the request)
   std::vector<LoopShape> shapes;
-  for (int c : cand) {
-    if (c < 1 || (int64_t)c > ev->M) continue;
-    const LoopShape sh = make_shape(B, ev->M, c);
-    bool seen = false;
-    for (const LoopShape& u : shapes) seen |= (u.nchunk == sh.nchunk);
-    if (!seen) shapes.push_back(sh);
-  }
+  auto add_shapes = [&](const std::vector<int>& cs) {
+    std::vector<LoopShape> out;
+    for (int c : cs) {
+      if (c < 1 || (int64_t)c > ev->M) continue;
+      const LoopShape sh = make_shape(B, ev->M, c);
+      bool seen = false;
+      for (const LoopShape& u : shapes) seen |= (u.nchunk == sh.nchunk);
+      if (!seen) {
+        shapes.push_back(sh);
+        out.push_back(sh);
+      }
+    }
+    return out;
+  };
+  const std::vector<LoopShape> first = add_shapes(cand);
 
   const int64_t Bp = (B + WAVE - 1) / WAVE * WAVE;
   int maxc = 1;
-  for (const LoopShape& u : shapes) maxc = u.nchunk > maxc ? u.nchunk : maxc;
+  for (const LoopShape& u : first) maxc = u.nchunk > maxc ? u.nchunk : maxc;
+  maxc = (int)std::min<int64_t>(ev->M, 3 * (int64_t)maxc / 2 + 1);  // room for the second pass
   double *theta = nullptr, *logl = nullptr, *grad_out = nullptr, *ws = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipMalloc((void**)&theta, sizeof(double) * NPARAM * (size_t)B);
@@ -235,24 +246,34 @@ gwl_status gwl_autotune(const char* cache_path, gwl_event ev, int64_t B, gwl_pre
   }
   int best = h;
   double best_ms = 1e300;
-  for (size_t i = 0; e == hipSuccess && i < shapes.size(); ++i) {
-    const LoopShape& sh = shapes[i];
-    double* coef = ws;
-    double* part = ws + (size_t)NCOEF * Bp;
-    float ms_min = 1e30f;
-    for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
-      e = hipEventRecord(e0, 0);
-      if (e == hipSuccess) e = enqueue_logl(ev, theta, B, mixed, grad, sh, coef, part, logl, grad_out, 0);
-      if (e == hipSuccess) e = hipEventRecord(e1, 0);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      float ms = 0.0f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (rep > 0 && ms < ms_min) ms_min = ms;  // first run is a warm-up
+  auto time_shapes = [&](const std::vector<LoopShape>& list) {
+    for (size_t i = 0; e == hipSuccess && i < list.size(); ++i) {
+      const LoopShape& sh = list[i];
+      if (sh.nchunk > maxc) continue;  // beyond the workspace (not reached: maxc bounds the second pass)
+      double* coef = ws;
+      double* part = ws + (size_t)NCOEF * Bp;
+      float ms_min = 1e30f;
+      for (int rep = 0; rep < 6 && e == hipSuccess; ++rep) {
+        e = hipEventRecord(e0, 0);
+        if (e == hipSuccess) e = enqueue_logl(ev, theta, B, mixed, grad, sh, coef, part, logl, grad_out, 0);
+        if (e == hipSuccess) e = hipEventRecord(e1, 0);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (rep > 0 && ms < ms_min) ms_min = ms;  // first run is a warm-up
+      }
+      if (e == hipSuccess && ms_min < best_ms) {
+        best_ms = ms_min;
+        best = sh.nchunk;
+      }
     }
-    if (e == hipSuccess && ms_min < best_ms) {
-      best_ms = ms_min;
-      best = sh.nchunk;
-    }
+  };
+  time_shapes(first);
+  if (e == hipSuccess) {
+    std::vector<int> fine;
+    const int num[] = {6, 7, 9, 10, 11, 12};  // eighths of the best count
+    for (int q : num) fine.push_back((int)(((int64_t)best * q + 4) / 8));
+    time_shapes(add_shapes(fine));
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
