@@ -332,32 +332,40 @@ gwl_status gwl_multi_autotune(const char* cache_path, const gwl_event* evs, int 
   }
   int best_chunk = 0, best_desc = 0;
   double best_ms = 1e300;
-  for (int chunk = 1024; err == hipSuccess && chunk <= 16384; chunk <<= 1) {
-    for (int desc = 0; desc < 2 && err == hipSuccess; ++desc) {
-      gwl_plan pl = nullptr;
-      if (build_plan(evs, E, B_e, prec, with_grad, chunk, desc != 0, &pl) != GWL_OK) {
-        clear_error();  // this candidate does not fit (too many items): skip it
-        continue;
-      }
-      float ms_min = 1e30f;
-      for (int rep = 0; rep < 4 && err == hipSuccess; ++rep) {
-        err = hipEventRecord(e0, 0);
-        if (err == hipSuccess &&
-            gwl_multi_launch(pl, tp.data(), lp.data(), grad ? gp.data() : nullptr, nullptr, nullptr) != GWL_OK)
-          err = hipErrorLaunchFailure;
-        if (err == hipSuccess) err = hipEventRecord(e1, 0);
-        if (err == hipSuccess) err = hipEventSynchronize(e1);
-        float ms = 0.0f;
-        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-        if (rep > 0 && ms < ms_min) ms_min = ms;  // the first launch is a warm-up
-      }
-      gwl_plan_destroy(pl);
-      if (err == hipSuccess && ms_min < best_ms) {
-        best_ms = ms_min;
-        best_chunk = chunk;
-        best_desc = desc;
-      }
+  auto try_plan = [&](int chunk, int desc) {
+    gwl_plan pl = nullptr;
+    if (build_plan(evs, E, B_e, prec, with_grad, chunk, desc != 0, &pl) != GWL_OK) {
+      clear_error();  // this candidate does not fit (too many items): skip it
+      return;
     }
+    float ms_min = 1e30f;
+    for (int rep = 0; rep < 4 && err == hipSuccess; ++rep) {
+      err = hipEventRecord(e0, 0);
+      if (err == hipSuccess &&
+          gwl_multi_launch(pl, tp.data(), lp.data(), grad ? gp.data() : nullptr, nullptr, nullptr) != GWL_OK)
+        err = hipErrorLaunchFailure;
+      if (err == hipSuccess) err = hipEventRecord(e1, 0);
+      if (err == hipSuccess) err = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+      if (rep > 0 && ms < ms_min) ms_min = ms;  // the first launch is a warm-up
+    }
+    gwl_plan_destroy(pl);
+    if (err == hipSuccess && ms_min < best_ms) {
+      best_ms = ms_min;
+      best_chunk = chunk;
+      best_desc = desc;
+    }
+  };
+  // chunk lengths in powers of two, both queue orders; then 3/4 to 3/2 of the best length, in
+  // eighths, in the best order
+  for (int chunk = 1024; err == hipSuccess && chunk <= 16384; chunk <<= 1)
+    for (int desc = 0; desc < 2 && err == hipSuccess; ++desc) try_plan(chunk, desc);
+  if (err == hipSuccess && best_chunk > 0) {
+    const int c0 = best_chunk, d0 = best_desc;
+    const int num[] = {6, 7, 9, 10, 11, 12};
+    for (int q : num)
+      if (err == hipSuccess) try_plan((int)(((int64_t)c0 * q + 4) / 8), d0);
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
