@@ -443,7 +443,11 @@ static gwl_status run_logl_cal(gwl_event ev, const double* theta, int64_t B, boo
   sh.npg = (int)((B + WAVE - 1) / WAVE);
   // chunks of about M / want bins, none crossing a node interval (intervals in ln f hold very
   // different numbers of bins, so each is cut into its own number of pieces)
-  const int want = std::min(heuristic_nchunk(B, ev->M), MAXCALCHUNK - (n - 1));
+  // forward: the plain loop's tuned chunk count (the calibrated loop differs only by its per-bin
+  // spline); adjoint: the heuristic, since each of its chunks writes 11 N_det + 8 partial sums per
+  // point and more chunks measured slower
+  const int tuned = grad ? heuristic_nchunk(B, ev->M) : choose_nchunk(ev, B, mixed, false);
+  const int want = std::min(tuned, MAXCALCHUNK - (n - 1));
   const int64_t target = std::max<int64_t>(1, (ev->M + want - 1) / want);
   int nc = 0;
   for (int j = 0; j < n - 1; ++j) {
