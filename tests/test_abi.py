@@ -104,3 +104,14 @@ def test_prior_transform_checks_arguments_without_device_work():
     assert b"unknown map 7" in L.gwl_last_error()
     with pytest.raises(ValueError):
         gw.PriorColumns([0, 5], [0.0, 0.0], [1.0, 1.0])
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the built library every entry into the binding raises; nothing falls back to
+    a CPU implementation."""
+    monkeypatch.setattr(gw, "_lib", None)
+    monkeypatch.setattr(gw, "LIB_PATH", str(tmp_path / "libgwlike.so"))
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        gw.lib()
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        gw.version()
