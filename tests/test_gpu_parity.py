@@ -4,7 +4,9 @@ Tolerances: |logL_gpu - logL_oracle| <= 1e-3 absolute for the mixed-precision ke
 accuracy target of this library) and <= 1e-6 for the float64 kernels; gradients compare
 width-scaled components to 1e-4 relative (see helpers.scaled_grad_error).
 """
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -48,6 +50,18 @@ def test_c0_every_point(c0, prec):
     assert err.max() <= TOL[prec]
 
 
+def use_bench_shapes(spec, ev, batch, prec, grad):
+    """Load the committed tile shapes, as the benchmark does, and check that a call of this
+    shape launches with the tuned chunk count."""
+    cache = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                         "paper_1909_11873_amd", "tuning_gfx950.json")
+    gw.autotune_load(cache)
+    want = [e["nchunk"] for e in json.load(open(cache))["entries"]
+            if tuple(e.get(k) for k in ("ndet", "M", "mixed", "grad", "npg_bucket")) ==
+            (spec.ndet, spec.nbins, int(prec == "mixed"), int(grad), batch // 64)]
+    assert len(want) == 1 and gw.launch_shape(ev, batch, prec, grad)[0] == want[0]
+
+
 @pytest.fixture(scope="module")
 def c1():
     spec, f, psd, data, dets = event_inputs(1)
@@ -65,8 +79,10 @@ def c1():
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_c1_full_batch_sampled(c1, prec):
-    """Full 65536-point launch (the benchmark's launch), compared on sampled points."""
+    """Full 65536-point launch with the committed tile shapes (the benchmark's launch), compared
+    on sampled points."""
     spec, ev, th, sample, ref = c1
+    use_bench_shapes(spec, ev, len(th), prec, False)
     got = gw.logl(torch.tensor(th, device=DEV), ev, prec).cpu().numpy()
     assert np.all(np.isfinite(got))
     err = np.abs(got[sample] - ref)
@@ -252,6 +268,7 @@ def c3():
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_c3_gradient_against_oracle_autograd(c3, prec):
     spec, ev, th, sample, vref, gref = c3
+    use_bench_shapes(spec, ev, len(th), prec, True)
     val, g = gw.logl_grad(torch.tensor(th, device=DEV), ev, prec)
     val, g = val.cpu().numpy(), g.cpu().numpy()
     assert np.abs(val[sample] - vref).max() <= TOL[prec]
