@@ -110,6 +110,7 @@ def test_c2_long_signal_sampled():
     sample = np.array([0, 1, 2, 1000, 2047, 4095])
     ref = oracle_logl(th[sample], f, psd, data, dets, spec.df)
     for prec in ("mixed", "fp64"):
+        use_bench_shapes(spec, ev, len(th), prec, False)
         got = gw.logl(torch.tensor(th, device=DEV), ev, prec).cpu().numpy()
         err = np.abs(got[sample] - ref)
         print(f"c2 {prec}: max |dlogL| {err.max():.3e} (M={len(f)}), logL(theta0)={ref[0]:.4f}")
