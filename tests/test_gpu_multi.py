@@ -162,7 +162,16 @@ def test_c4_full_workload_sampled():
         ths.append(th)
         inputs.append((f, psd, data, dets, spec.df))
     batches = [len(t) for t in ths]
+    # the committed plan shape, loaded as the benchmark loads it
+    import json
+    import os
+    cache = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                         "paper_1909_11873_amd", "tuning_gfx950.json")
+    gw.autotune_load(cache)
+    tuned = [(e["chunk"], bool(e["descending"])) for e in json.load(open(cache))["entries"]
+             if e.get("multi") and e["events"] == 64 and e["mixed"] == 1 and e["grad"] == 1]
     plan = gw.MultiPlan(evs, batches, "mixed", with_grad=True)
+    assert len(tuned) == 1 and plan.info()[:2] == tuned[0]
     logls, grads, lat = plan.launch([torch.tensor(t, device=DEV) for t in ths], latency=True)
     worst, worst_g = 0.0, 0.0
     for e, (th, l, g, inp) in enumerate(zip(ths, logls, grads, inputs)):
