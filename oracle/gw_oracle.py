@@ -39,7 +39,15 @@ Parity status of each part (what pins it, in the tests):
     same series by an independent route. The spin terms beyond 2PN are absent.
   * antenna patterns: pinned by the detector-frame closed form of F+^2 + Fx^2,
     the polarisation-rotation law and the 4/25 sky/orientation average.
-  * time delays: pinned by zenith, nadir and horizon special cases.
+  * time delays: pinned by zenith, nadir and horizon special cases; the sign of
+    the delay factor exp(-2 pi i f dt) by the time-shift theorem (the detector
+    strain equals the geocentre strain of a source with t_c + dt).
+  * the sidereal angle: pinned by the zenith delay at right ascension
+    gmst + longitude and by logL(ra, gmst) = logL(ra - gmst, 0).
+  * the sum over bins: pinned by its convergence to the continuous inner
+    product (composite Gauss-Legendre quadrature) at first, then, with the
+    Euler-Maclaurin end term, second order in df; the float64 rounding by a
+    50-digit evaluation of the per-bin definition (agreement to ~1e-15).
   * the sign of i in h_x and of the phase exponent are conventions of this
     build (FT with exp(-2 pi i f t)); they are checked for internal consistency
     by the time-shift and phase invariances only.

@@ -79,6 +79,35 @@ def _logl_half():
     return bad
 
 
+def _strain_delay_exponent_sign():
+    def bad(f, theta, det, gmst=0.0):
+        r, d = o.detector_geometry(*det)
+        fp, fx = o.antenna(d, theta[5], theta[6], theta[8], gmst)
+        dt = o.time_delay(r, theta[5], theta[6], gmst)
+        hp, hc = o.polarizations(f, theta)
+        return (fp * hp + fx * hc) * torch.exp(2j * math.pi * f * dt)
+    return bad
+
+
+def _strain_delay_ignores_gmst():
+    def bad(f, theta, det, gmst=0.0):
+        r, d = o.detector_geometry(*det)
+        fp, fx = o.antenna(d, theta[5], theta[6], theta[8], gmst)
+        dt = o.time_delay(r, theta[5], theta[6])
+        hp, hc = o.polarizations(f, theta)
+        return (fp * hp + fx * hc) * torch.exp(-2j * math.pi * f * dt)
+    return bad
+
+
+def _gmst_sign():
+    orig = o.source_frame
+    return lambda ra, dec, psi, gmst=0.0: orig(ra, dec, psi, -gmst)
+
+
+def _inner_drops_last_bin():
+    return lambda a, b, psd, df: 4.0 * df * torch.sum((torch.real(torch.conj(a) * b) / psd)[..., :-1])
+
+
 MUTATIONS = [
     ("phi2 mistyped", "pn_coefficients", lambda: _wrap_pn(1, lambda p, e, a, b: p + 0.01),
      [lambda: pins.test_phase_derivative_matches_2pn_time_frequency_relation(0.0, 0.0)]),
@@ -113,6 +142,13 @@ MUTATIONS = [
     ("time delay sign", "time_delay", _delay_sign, [pins.test_time_delay_special_cases]),
     ("inner product factor", "inner", _inner_factor, [pins.test_eq2_exponent_ratio]),
     ("missing 1/2 on <h|h>", "logl_point", _logl_half, [pins.test_eq2_exponent_ratio]),
+    ("detector delay exponent sign", "detector_strain", _strain_delay_exponent_sign,
+     [pins.test_detector_delay_is_a_time_shift_of_the_geocentre_signal]),
+    ("detector delay at GMST 0", "detector_strain", _strain_delay_ignores_gmst,
+     [pins.test_sidereal_angle_turns_the_sky_with_the_earth]),
+    ("GMST sign", "source_frame", _gmst_sign, [pins.test_sidereal_angle_turns_the_sky_with_the_earth]),
+    ("inner product drops the last bin", "inner", _inner_drops_last_bin,
+     [pins.test_discrete_likelihood_converges_to_the_frequency_integral]),
 ]
 
 

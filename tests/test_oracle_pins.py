@@ -480,3 +480,173 @@ def test_prior_ranges_and_seeding():
     specs = [synth.event_spec(4, e) for e in range(64)]
     assert all(4 <= s.duration <= 128 and 256 <= s.batch <= 8192 for s in specs)
     assert len({s.seed_base for s in specs}) == 64
+
+
+# ------------------------------------------------------------------------------------------
+# Time shift at the detector and the sidereal angle (section 2, Eq. 2 summed over detectors)
+# ------------------------------------------------------------------------------------------
+def test_detector_delay_is_a_time_shift_of_the_geocentre_signal():
+    """Time-shift theorem: a detector that sees the wave Delta t after the geocentre records the
+    geocentre strain of a source whose coalescence time is t_c + Delta t. At the detector's zenith
+    (Delta t = -R/c) and nadir (+R/c), with psi chosen so that F_+ = 1 and F_x = 0, the detector
+    strain must equal h_+ of that shifted source exactly."""
+    f = torch.tensor([20.0, 33.3, 150.0, 900.0], dtype=DT)
+    for name in ["D1", "D3"]:
+        lat, lon, ax, ay = synth.detector_rad(name)
+        _, d = o.detector_geometry(lat, lon, ax, ay)
+        for ra, dec, dt in [(lon, lat, -RE / C), (lon + math.pi, -lat, RE / C)]:
+            fp0, fx0 = o.antenna(d, torch.tensor(ra, dtype=DT), torch.tensor(dec, dtype=DT), torch.tensor(0.0, dtype=DT))
+            psi = 0.5 * math.atan2(float(fx0), float(fp0))        # F_x(psi) = 0 and F_+(psi) = 1 overhead
+            fp, fx = o.antenna(d, torch.tensor(ra, dtype=DT), torch.tensor(dec, dtype=DT), torch.tensor(psi, dtype=DT))
+            assert float(fp) == pytest.approx(1.0, abs=1e-13) and abs(float(fx)) < 1e-13
+            th = torch.tensor([22.0, 0.7, 0.3, -0.1, 600.0, ra, dec, 0.6, psi, 1.1, 0.013], dtype=DT)
+            got = o.detector_strain(f, th, (lat, lon, ax, ay)).numpy()
+            shifted = th.clone()
+            shifted[10] += dt
+            want = o.polarizations(f, shifted)[0].numpy()
+            np.testing.assert_allclose(got, want, rtol=1e-9, atol=0)
+
+
+def test_sidereal_angle_turns_the_sky_with_the_earth():
+    """GMST is the right ascension of the Greenwich meridian: a detector at east longitude lon has
+    right ascension gmst + lon overhead, so the zenith delay -R/c moves there. And the likelihood
+    depends on right ascension and GMST only through their difference."""
+    g = 1.3
+    for name in ["D1", "D2", "D3"]:
+        lat, lon, ax, ay = synth.detector_rad(name)
+        r, _ = o.detector_geometry(lat, lon, ax, ay)
+        zen = float(o.time_delay(r, torch.tensor(lon + g, dtype=DT), torch.tensor(lat, dtype=DT), g))
+        assert zen == pytest.approx(-RE / C, rel=1e-14)
+    f, psd, data, dets, df = small_event()
+    th = draw(3, seed=31)
+    shifted = th.copy()
+    shifted[:, 5] -= g
+    a = o.logl(th, data, psd, dets, f, df, gmst=g).numpy()
+    b = o.logl(shifted, data, psd, dets, f, df, gmst=0.0).numpy()
+    np.testing.assert_allclose(a, b, rtol=1e-11, atol=1e-9)
+    # and it does change the likelihood (GMST is not ignored)
+    c = o.logl(th, data, psd, dets, f, df, gmst=0.0).numpy()
+    assert np.abs(a - c).max() > 1e-3
+
+
+# ------------------------------------------------------------------------------------------
+# Brute force: continuum quadrature and a 50-digit evaluation of the per-bin definition
+# ------------------------------------------------------------------------------------------
+def _gauss_legendre(fn, a, b, panels, nodes=32):
+    """Composite Gauss-Legendre quadrature of a vectorised fn over [a, b]."""
+    x, w = np.polynomial.legendre.leggauss(nodes)
+    edges = np.linspace(a, b, panels + 1)
+    lo, hi = edges[:-1, None], edges[1:, None]
+    pts = (0.5 * (hi - lo) * x[None, :] + 0.5 * (hi + lo)).ravel()
+    wts = (0.5 * (hi - lo) * w[None, :]).ravel()
+    return float(np.sum(wts * fn(pts)))
+
+
+def test_discrete_likelihood_converges_to_the_frequency_integral():
+    """Eq. 2's sum over bins is a Riemann sum (both band edges included) of the continuous
+    noise-weighted inner product: for noiseless data d = h(theta1) and a smooth PSD, the oracle's
+    logL(theta2) approaches sum_det int [4 Re(conj(d) h)/S - 2 |h|^2/S] df with the trapezoid
+    rule's first Euler-Maclaurin term, (df/2) (g(f_lo) + g(f_hi)), then at second order in df."""
+    f_lo, f_hi = 20.0, 60.0
+    dets = np.array([synth.detector_rad(n) for n in ["D1", "D2"]])
+    th1 = np.array([24.0, 0.7, 0.2, -0.1, 500.0, 1.0, 0.3, 0.8, 0.4, 1.2, 0.002])
+    th2 = th1 + np.array([0.02, 0.01, 0.0, 0.05, 30.0, 0.01, -0.01, 0.05, 0.02, 0.1, 0.0002])
+
+    def integrand(fv):
+        fv = np.asarray(fv, dtype=np.float64)
+        ft = torch.tensor(fv)
+        s = synth.psd_fit(fv)
+        d = o.strain_all(th1, dets, ft).numpy()
+        h = o.strain_all(th2, dets, ft).numpy()
+        return np.sum(4.0 * np.real(np.conj(d) * h) / s - 2.0 * np.abs(h) ** 2 / s, axis=0)
+
+    exact = _gauss_legendre(integrand, f_lo, f_hi, 256)
+    assert _gauss_legendre(integrand, f_lo, f_hi, 512) == pytest.approx(exact, rel=1e-13)
+    edge = integrand(np.array([f_lo, f_hi]))
+    errs, corrected = [], []
+    for df in (0.5, 0.25, 0.125):
+        f = synth.freq_grid(f_lo, f_hi, df)
+        psd = np.stack([synth.psd_fit(f)] * 2)
+        data = o.strain_all(th1, dets, f).numpy()
+        got = float(o.logl(th2[None], data, psd, dets, f, df)[0])
+        errs.append(got - exact)
+        corrected.append(got - 0.5 * df * edge.sum() - exact)
+    assert abs(errs[0]) < 0.05 * abs(exact)
+    for j in range(2):
+        assert errs[j] / errs[j + 1] == pytest.approx(2.0, rel=0.02)          # first order in df
+        assert corrected[j] / corrected[j + 1] == pytest.approx(4.0, rel=0.05)  # then second order
+    assert abs(corrected[-1]) < 1e-3 * abs(errs[-1])
+
+
+def _mp_model_strain(th, det, fk, gmst):
+    """h_det(f_k) at 50 digits, from the signal model's definitions written out with mpmath: the
+    TaylorF2 series in v, the Newtonian amplitude, and the antenna response as dot products of the
+    arm directions with the polarisation axes."""
+    import mpmath as mp
+    mc, q, x1, x2, dl, ra, dec, inc, psi, phic, tc = (mp.mpf(float(v)) for v in th)
+    lat, lon, azx, azy = (mp.mpf(float(v)) for v in det)
+    pi = mp.pi
+    c, tsun, mpc, re = mp.mpf(299792458), mp.mpf("4.925490947641267e-6"), mp.mpf("3.0856775814913673e22"), mp.mpf(6371000)
+    eta = q / (1 + q) ** 2
+    mt = mc * eta ** mp.mpf(-0.6)
+    m1, m2 = 1 / (1 + q), q / (1 + q)
+    beta = (mp.mpf(113) / 12 * m1 ** 2 + mp.mpf(25) / 4 * eta) * x1 + (mp.mpf(113) / 12 * m2 ** 2 + mp.mpf(25) / 4 * eta) * x2
+    sigma = mp.mpf(79) / 8 * eta * x1 * x2
+    ge = mp.euler
+    amp = mp.sqrt(mp.mpf(5) / 24) * pi ** (mp.mpf(-2) / 3) * (tsun * mc) ** (mp.mpf(5) / 6) * c / (dl * mpc)
+    # source direction, polarisation axes and arms in Earth-fixed coordinates
+    h = ra - mp.mpf(float(gmst))
+    k = [mp.cos(dec) * mp.cos(h), mp.cos(dec) * mp.sin(h), mp.sin(dec)]
+    uu = [-mp.sin(dec) * mp.cos(h), -mp.sin(dec) * mp.sin(h), mp.cos(dec)]
+    vv = [-mp.sin(h), mp.cos(h), mp.mpf(0)]
+    X = [mp.cos(psi) * a + mp.sin(psi) * b for a, b in zip(uu, vv)]
+    Y = [-mp.sin(psi) * a + mp.cos(psi) * b for a, b in zip(uu, vv)]
+    north = [-mp.sin(lat) * mp.cos(lon), -mp.sin(lat) * mp.sin(lon), mp.cos(lat)]
+    east = [-mp.sin(lon), mp.cos(lon), mp.mpf(0)]
+    xa = [mp.cos(azx) * a + mp.sin(azx) * b for a, b in zip(north, east)]
+    ya = [mp.cos(azy) * a + mp.sin(azy) * b for a, b in zip(north, east)]
+    dot = lambda a, b: sum(p * r for p, r in zip(a, b))
+    Xx, Xy, Yx, Yy = dot(X, xa), dot(X, ya), dot(Y, xa), dot(Y, ya)
+    fp = (Xx ** 2 - Xy ** 2 - Yx ** 2 + Yy ** 2) / 2
+    fx = Xx * Yx - Xy * Yy
+    dt = -re * dot([mp.cos(lat) * mp.cos(lon), mp.cos(lat) * mp.sin(lon), mp.sin(lat)], k) / c
+    out = []
+    for fv in fk:
+        fm = mp.mpf(float(fv))
+        v = (pi * tsun * mt * fm) ** (mp.mpf(1) / 3)
+        ser = (1 + (mp.mpf(3715) / 756 + mp.mpf(55) / 9 * eta) * v ** 2 + (-16 * pi + 4 * beta) * v ** 3
+               + (mp.mpf(15293365) / 508032 + mp.mpf(27145) / 504 * eta + mp.mpf(3085) / 72 * eta ** 2 - 10 * sigma) * v ** 4
+               + pi * (mp.mpf(38645) / 756 - mp.mpf(65) / 9 * eta) * (1 + 3 * mp.log(v)) * v ** 5
+               + (mp.mpf(11583231236531) / 4694215680 - mp.mpf(640) / 3 * pi ** 2 - mp.mpf(6848) / 21 * ge
+                  - mp.mpf(6848) / 21 * mp.log(4 * v)
+                  + (mp.mpf(-15737765635) / 3048192 + mp.mpf(2255) / 12 * pi ** 2) * eta
+                  + mp.mpf(76055) / 1728 * eta ** 2 - mp.mpf(127825) / 1296 * eta ** 3) * v ** 6
+               + pi * (mp.mpf(77096675) / 254016 + mp.mpf(378515) / 1512 * eta - mp.mpf(74045) / 756 * eta ** 2) * v ** 7)
+        phase = 2 * pi * fm * (tc + dt) - phic - pi / 4 + 3 / (128 * eta * v ** 5) * ser
+        a = amp * fm ** (mp.mpf(-7) / 6)
+        out.append(a * (fp * (1 + mp.cos(inc) ** 2) / 2 - 1j * fx * mp.cos(inc)) * mp.exp(-1j * phase))
+    return out
+
+
+def test_oracle_matches_50_digit_per_bin_evaluation():
+    """The FP64 oracle against the per-bin definition of Eq. 2's ratio evaluated at 50 digits
+    (tiny inputs: 48 bins, 3 detectors, 5 points, one of them at a non-zero sidereal angle): the
+    oracle's rounding stays at the 1e-12 level relative to the sum of the magnitudes it adds."""
+    import mpmath as mp
+    mp.mp.dps = 50
+    f, psd, data, dets, df = small_event(m=48)
+    th = draw(4, seed=41)
+    th = np.concatenate([synth.THETA0_BBH[None], th])
+    for b, gmst in enumerate([0.0, 0.0, 0.0, 0.0, 2.1]):
+        got = float(o.logl(th[b:b + 1], data, psd, dets, f, df, gmst=gmst)[0])
+        tot, mag = mp.mpf(0), mp.mpf(0)
+        for i in range(3):
+            hk = _mp_model_strain(th[b], dets[i], f, gmst)
+            for k in range(len(f)):
+                dk = mp.mpc(float(data[i, k].real), float(data[i, k].imag))
+                s = mp.mpf(float(psd[i, k]))
+                dh = 4 * mp.mpf(df) * mp.re(mp.conj(dk) * hk[k]) / s
+                hh = 2 * mp.mpf(df) * abs(hk[k]) ** 2 / s
+                tot += dh - hh
+                mag += abs(dh) + hh
+        assert abs(got - float(tot)) <= 1e-12 * float(mag), (b, got, float(tot))
