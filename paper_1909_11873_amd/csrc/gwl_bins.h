@@ -34,11 +34,18 @@ __device__ __forceinline__ void to_table_units(double (&a)[NBASIS], double (&T)[
 #pragma unroll
   for (int d = 0; d < ND; ++d) T[d] *= (double)PH_TBL;
 }
+// The integer n comes from adding and subtracting 1.5 * 2^52: for |tu| < 2^51 the sum lies in
+// [2^52, 2^53), where the float64 spacing is 1, so it is rounded to the nearest integer (ties to
+// even), and its low mantissa bits are n modulo 2^52 in two's complement; the low 11 bits are
+// the table index for negative n too. (A float64 -> int32 conversion would clamp beyond 2^31.)
+// The set-up keeps |tu| below 2048 * PHASE_LIMIT = 2^50 or marks the point invalid.
 __device__ __forceinline__ void sincos_tbl(double tu, const double2* __restrict__ tbl, double& s, double& c) {
   constexpr double N = PH_TBL;
-  const double n = rint(tu);
-  const double y = tu - n;                       // exact
-  const double2 e = tbl[(int)n & (PH_TBL - 1)];  // v_cvt_i32_f64 clamps; the mask keeps the index in range
+  constexpr double RND = 6755399441055744.0;     // 1.5 * 2^52
+  const double t = tu + RND;
+  const double n = t - RND;                      // rint(tu), exact
+  const double y = tu - n;                       // exact, |y| <= 1/2
+  const double2 e = tbl[(unsigned)__double2loint(t) & (PH_TBL - 1)];
   const double z = y * y;
   const double ps = fma(z, -41.34170224039976 / (N * N * N), 6.283185307179586 / N);  // sin(2 pi y / N) / y
   const double sv = ps * y;
@@ -90,18 +97,19 @@ __device__ __forceinline__ double phase_poly(const double (&a)[NBASIS], double x
   return fma(w2, t, w * a[0]);
 }
 
+// One bin of the mixed-precision loop. The complex sums Z_det go into the float32 block sums z;
+// the adjoint's moments (f y_det per detector, g_m y for the eight basis functions) go straight
+// into float64 (tot[2 ND ..]), with the basis values in float64: the gradient combines these
+// moments with coefficients of both signs that nearly cancel for the mass and spin directions,
+// so a float32 rounding on each moment would be magnified there. On this chip a float64 FMA
+// issues at the rate of an unpacked float32 one, so this costs about what the float32 block sums
+// and their flushes did.
 template <int ND, bool GRAD, class GradP>
 __device__ __forceinline__ void mixed_bin(const RowMixed<ND> r, GradP gt, int k,
                                           const double (&a)[NBASIS], const double (&T)[ND], const float (&cr)[ND],
-                                          const float (&ci)[ND], float (&z)[nz_of(ND, GRAD)]) {
+                                          const float (&ci)[ND], float (&z)[2 * ND], double (&tot)[nz_of(ND, GRAD)]) {
   const double psi = phase_poly(a, r.x, r.w, r.w2, r.lnf);
-  float y = 0.0f;
-  float fk = 0.0f;
-  RowGradF32 g;
-  if (GRAD) {
-    g = load_grad_f32(gt, k);
-    fk = g.f;
-  }
+  double y = 0.0;
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
     const double ph = fma(r.f, T[d], psi);
@@ -118,14 +126,16 @@ __device__ __forceinline__ void mixed_bin(const RowMixed<ND> r, GradP gt, int k,
       const float wi = fmaf(ui, cs, -(ur * sn));
       z[2 * d] += wr;
       z[2 * d + 1] += wi;
-      const float yd = fmaf(cr[d], wi, ci[d] * wr);  // Im(c_det w)
-      z[2 * ND + d] = fmaf(fk, yd, z[2 * ND + d]);
+      const double yd = (double)fmaf(cr[d], wi, ci[d] * wr);  // Im(c_det w)
+      tot[2 * ND + d] = fma(r.f, yd, tot[2 * ND + d]);
       y = d == 0 ? yd : y + yd;
     }
   }
   if (GRAD) {
+    const RowGradF64 g = load_grad_f64(gt, k);
+    const double gm[NBASIS] = {r.w, r.w2, g.g2, g.g3, r.lnf, r.x, g.g6, g.g7};
 #pragma unroll
-    for (int m = 0; m < NBASIS; ++m) z[3 * ND + m] = fmaf(g.g[m], y, z[3 * ND + m]);
+    for (int m = 0; m < NBASIS; ++m) tot[3 * ND + m] = fma(gm[m], y, tot[3 * ND + m]);
   }
 }
 
@@ -163,13 +173,15 @@ __device__ __forceinline__ void f64_bin(const RowF64<ND> r, GradP gt, int k,
 }
 
 // The bin loop of one wavefront: points in lanes, bins [k0, k1) of one event.
-// Mixed precision: float32 sums over blocks of NB bins, each block added into float64.
+// Mixed precision: the complex sums in float32 over blocks of NB bins, each block added into
+// float64; the adjoint moments in float64 throughout (see mixed_bin).
 template <int ND, bool GRAD, class TabP, class GradP>
 __device__ __forceinline__ void bin_loop_mixed(TabP tab, GradP gtab,
                                                int k0, int k1, const double (&a)[NBASIS], const double (&T)[ND],
                                                const float (&cr)[ND], const float (&ci)[ND],
                                                double (&tot)[nz_of(ND, GRAD)]) {
   constexpr int NZ = nz_of(ND, GRAD);
+  constexpr int NF = 2 * ND;  // float32 block sums
 #pragma unroll
   for (int z = 0; z < NZ; ++z) tot[z] = 0.0;
   int k = k0;
@@ -180,33 +192,33 @@ __device__ __forceinline__ void bin_loop_mixed(TabP tab, GradP gtab,
     // bounds
     RowMixed<ND> cur = load_row_mixed<ND>(tab, k), nx1 = load_row_mixed<ND>(tab, k + (GRAD ? 0 : 1));
     for (; k + NB <= k1; k += NB) {
-      float z[NZ];
+      float z[NF];
 #pragma unroll
-      for (int j = 0; j < NZ; ++j) z[j] = 0.0f;
+      for (int j = 0; j < NF; ++j) z[j] = 0.0f;
 #pragma unroll 2
       for (int j = 0; j < NB; ++j) {
         if constexpr (GRAD) {
           const RowMixed<ND> nxt = load_row_mixed<ND>(tab, k + j + 1);
-          mixed_bin<ND, GRAD, GradP>(cur, gtab, k + j, a, T, cr, ci, z);
+          mixed_bin<ND, GRAD, GradP>(cur, gtab, k + j, a, T, cr, ci, z, tot);
           cur = nxt;
         } else {
           const RowMixed<ND> nx2 = load_row_mixed<ND>(tab, k + j + 2);
-          mixed_bin<ND, GRAD, GradP>(cur, gtab, k + j, a, T, cr, ci, z);
+          mixed_bin<ND, GRAD, GradP>(cur, gtab, k + j, a, T, cr, ci, z, tot);
           cur = nx1;
           nx1 = nx2;
         }
       }
 #pragma unroll
-      for (int j = 0; j < NZ; ++j) tot[j] += (double)z[j];
+      for (int j = 0; j < NF; ++j) tot[j] += (double)z[j];
     }
   }
   if (k < k1) {
-    float z[NZ];
+    float z[NF];
 #pragma unroll
-    for (int j = 0; j < NZ; ++j) z[j] = 0.0f;
-    for (; k < k1; ++k) mixed_bin<ND, GRAD, GradP>(load_row_mixed<ND>(tab, k), gtab, k, a, T, cr, ci, z);
+    for (int j = 0; j < NF; ++j) z[j] = 0.0f;
+    for (; k < k1; ++k) mixed_bin<ND, GRAD, GradP>(load_row_mixed<ND>(tab, k), gtab, k, a, T, cr, ci, z, tot);
 #pragma unroll
-    for (int j = 0; j < NZ; ++j) tot[j] += (double)z[j];
+    for (int j = 0; j < NF; ++j) tot[j] += (double)z[j];
   }
 }
 

@@ -31,11 +31,18 @@ struct EventConst {
   double gain_i;      //   complex gain of the hardware float32 phasor out of the float32 sums
   int bad;            // nonzero if an input value was rejected
   int pad;
+  double fmin, fmax;  // lowest and highest grid frequency
+  double gmax[NBASIS];// max over [fmin, fmax] of |g_m(f)|: bounds the phase range of a point
   // Relative binning: the fiducial waveform's phase coefficients and detector shifts. The set-up
   // subtracts them, so the bin loop evaluates the phase of h / h0 on the edges. Zero otherwise.
   double fa[NBASIS];
   double fT[MAXDET];
 };
+
+// Largest phase, in cycles, that a point may reach on the grid: the float64 bin loops split
+// 2048 times the phase into an integer and a remainder in float64, exactly for magnitudes below
+// 2^51; a point whose phase bound exceeds PHASE_LIMIT is outside the supported domain (NaN).
+constexpr double PHASE_LIMIT = 549755813888.0;  // 2^39
 
 // Phases sampled to measure the hardware phasor gain: NGAIN_BLK workgroups x 256 threads x
 // NGAIN_PER phases, uniform on [0, 1) cycles.

@@ -10,7 +10,8 @@
 
 namespace gwl {
 
-// Set-up rows (layout CO_*) of one point; false if the point is outside the model's domain.
+// Set-up rows (layout CO_*) of one point; false if the point is outside the model's domain or,
+// given the event (ec), its phase could exceed PHASE_LIMIT cycles somewhere on the grid.
 // With `scaled` (float32 tables) the event's (gain_r, gain_i) undoes the mean gain of the bin
 // loop's phasor (1 for float64 tables). It enters the adjoint projection factors
 // c_det = E G Q_det, E = exp(-2 pi i c0), through which the adjoint bin loop keeps only the one
@@ -40,7 +41,17 @@ __device__ inline bool setup_rows(const double (&th)[NPARAM], const EventGeom& g
   }
   rows[CO_C0] = pm.c0;
   rows[CO_AMP] = pm.amp;
-  return pm.valid;
+  bool in_range = true;
+  if (ec) {
+    // bound on |sum_m a_m g_m(f) + f T_det| over the grid
+    double bound = 0.0, tmax = 0.0;
+#pragma unroll
+    for (int m = 0; m < NBASIS; ++m) bound = fma(fabs(rows[CO_A + m]), ec->gmax[m], bound);
+#pragma unroll
+    for (int d = 0; d < ND; ++d) tmax = fmax(tmax, fabs(rows[CO_T + d]));
+    in_range = fma(tmax, ec->fmax, bound) < PHASE_LIMIT;
+  }
+  return pm.valid && in_range;
 }
 
 // Divide the measured mean gain of the float32 hardware phasor out of the complex sums Z_det

@@ -38,6 +38,12 @@ namespace gwl {
 
 constexpr int64_t kMaxBatch = (int64_t)1 << 30;
 
+// Whether a call in precision p runs the mixed-precision bin loop on this event. A
+// relative-binning event always runs the float64 loop: its few hundred edge terms are each the
+// sum of hundreds of bins, and float32 roundings on them (the stored V_e, the hardware phasor,
+// the products) do not average down below the 1e-3 bound on loud events.
+inline bool use_mixed(const gwl_event_s* ev, gwl_precision p) { return p == GWL_MIXED && ev->M_full == 0; }
+
 gwl_status fail(gwl_status st, const char* fmt, ...);
 gwl_status hip_fail(hipError_t e, const char* what);
 void clear_error();

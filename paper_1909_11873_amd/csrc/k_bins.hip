@@ -14,7 +14,7 @@
 // [0, 1) cycles (v_fract_f64); float32 for the phasor (hardware sin/cos, which take cycles)
 // and the complex multiply-accumulate. The float32 sums run over blocks of NB bins and are
 // then added into float64 accumulators (cascaded summation), so float32 rounding never acts
-// on more than NB terms at once.
+// on more than NB terms at once. The adjoint's moments are accumulated in float64.
 #include <hip/hip_runtime.h>
 
 #include "gwl_bins.h"
@@ -52,7 +52,7 @@ __device__ __forceinline__ bool locate(const LoopShape& sh, int64_t M, int& c, i
 
 template <int ND, bool GRAD>
 __global__ __launch_bounds__(BLOCK) void k_bins_mixed(const RowMixed<ND>* __restrict__ tab,
-                                                      const RowGradF32* __restrict__ gtab,
+                                                      const RowGradF64* __restrict__ gtab,
                                                       const double* __restrict__ coef, int64_t B, int64_t Bp, int64_t M,
                                                       LoopShape sh, double* __restrict__ part) {
   constexpr int NZ = nz_of(ND, GRAD);
@@ -99,10 +99,10 @@ static hipError_t bins_nd(bool mixed, bool grad, const void* tab, const void* gt
   if (mixed) {
     if (grad)
       hipLaunchKernelGGL((k_bins_mixed<ND, true>), grid, block, 0, s, (const RowMixed<ND>*)tab,
-                         (const RowGradF32*)gtab, coef, B, Bp, M, sh, part);
+                         (const RowGradF64*)gtab64, coef, B, Bp, M, sh, part);
     else
       hipLaunchKernelGGL((k_bins_mixed<ND, false>), grid, block, 0, s, (const RowMixed<ND>*)tab,
-                         (const RowGradF32*)gtab, coef, B, Bp, M, sh, part);
+                         (const RowGradF64*)gtab64, coef, B, Bp, M, sh, part);
   } else {
     if (grad)
       hipLaunchKernelGGL((k_bins_f64<ND, true>), grid, block, 0, s, (const RowF64<ND>*)tab,

@@ -18,23 +18,31 @@ constexpr int PREP_BLOCK = 256;
 
 int prep_blocks(int64_t M) { return (int)((M + PREP_BLOCK - 1) / PREP_BLOCK); }
 
-size_t prep_scratch_doubles(int nd, int64_t M) { return (size_t)prep_blocks(M) * (nd + 2) + (size_t)NGAIN_BLK * 2; }
+// per block: ND K_det terms, max |u|, rejected count, lowest and highest frequency
+constexpr int prep_part(int nd) { return nd + 4; }
+
+size_t prep_scratch_doubles(int nd, int64_t M) {
+  return (size_t)prep_blocks(M) * prep_part(nd) + (size_t)NGAIN_BLK * 2;
+}
 
 // One thread per bin. Writes the float64 row, the adjoint basis rows, and per-block partial
-// sums (K_det terms, max |u|, count of rejected inputs) reduced in a fixed tree order.
+// sums (K_det terms, max |u|, count of rejected inputs, frequency range) reduced in a fixed
+// tree order.
 template <int ND>
 __global__ __launch_bounds__(PREP_BLOCK) void k_prep_bins(const double* __restrict__ data, const double* __restrict__ psd,
                                                           const double* __restrict__ fgrid, int64_t M, double df,
                                                           RowF64<ND>* __restrict__ tab64, RowGradF32* __restrict__ g32,
                                                           RowGradF64* __restrict__ g64, double* __restrict__ blockpart) {
-  __shared__ double red[ND + 2][PREP_BLOCK];
+  __shared__ double red[ND + 4][PREP_BLOCK];
   const int64_t k = (int64_t)blockIdx.x * PREP_BLOCK + threadIdx.x;
-  double kt[ND], umax = 0.0, bad = 0.0;
+  double kt[ND], umax = 0.0, bad = 0.0, flo = __builtin_inf(), fhi = 0.0;
 #pragma unroll
   for (int d = 0; d < ND; ++d) kt[d] = 0.0;
   if (k < M) {
     const double f = fgrid[k];
     if (!(f > 0.0) || !isfinite(f)) bad += 1.0;
+    flo = f;
+    fhi = f;
     const double x = cbrt(f);
     const double w2 = 1.0 / f;
     const double w = w2 / (x * x);
@@ -70,6 +78,8 @@ __global__ __launch_bounds__(PREP_BLOCK) void k_prep_bins(const double* __restri
   for (int d = 0; d < ND; ++d) red[d][threadIdx.x] = kt[d];
   red[ND][threadIdx.x] = umax;
   red[ND + 1][threadIdx.x] = bad;
+  red[ND + 2][threadIdx.x] = flo;
+  red[ND + 3][threadIdx.x] = fhi;
   __syncthreads();
   for (int off = PREP_BLOCK / 2; off > 0; off >>= 1) {
     if (threadIdx.x < off) {
@@ -77,10 +87,12 @@ __global__ __launch_bounds__(PREP_BLOCK) void k_prep_bins(const double* __restri
       for (int d = 0; d < ND; ++d) red[d][threadIdx.x] += red[d][threadIdx.x + off];
       red[ND][threadIdx.x] = fmax(red[ND][threadIdx.x], red[ND][threadIdx.x + off]);
       red[ND + 1][threadIdx.x] += red[ND + 1][threadIdx.x + off];
+      red[ND + 2][threadIdx.x] = fmin(red[ND + 2][threadIdx.x], red[ND + 2][threadIdx.x + off]);
+      red[ND + 3][threadIdx.x] = fmax(red[ND + 3][threadIdx.x], red[ND + 3][threadIdx.x + off]);
     }
     __syncthreads();
   }
-  if (threadIdx.x < ND + 2) blockpart[(int64_t)blockIdx.x * (ND + 2) + threadIdx.x] = red[threadIdx.x][0];
+  if (threadIdx.x < ND + 4) blockpart[(int64_t)blockIdx.x * prep_part(ND) + threadIdx.x] = red[threadIdx.x][0];
 }
 
 // Mean complex gain of the float32 hardware phasor (v_cos_f32, v_sin_f32 take cycles) against
@@ -117,22 +129,27 @@ template <int ND>
 __global__ __launch_bounds__(PREP_BLOCK) void k_prep_final(const double* __restrict__ blockpart, int nblk,
                                                            const double* __restrict__ gainpart,
                                                            EventConst* __restrict__ ec) {
-  __shared__ double red[ND + 4][PREP_BLOCK];
-  double acc[ND + 4];
+  constexpr int NP = prep_part(ND);
+  __shared__ double red[NP + 2][PREP_BLOCK];
+  double acc[NP + 2];
 #pragma unroll
-  for (int j = 0; j < ND + 4; ++j) acc[j] = 0.0;
+  for (int j = 0; j < NP + 2; ++j) acc[j] = 0.0;
+  acc[ND + 2] = __builtin_inf();
   for (int b = threadIdx.x; b < nblk; b += PREP_BLOCK) {
+    const double* bp = blockpart + (int64_t)b * NP;
 #pragma unroll
-    for (int d = 0; d < ND; ++d) acc[d] += blockpart[(int64_t)b * (ND + 2) + d];
-    acc[ND] = fmax(acc[ND], blockpart[(int64_t)b * (ND + 2) + ND]);
-    acc[ND + 1] += blockpart[(int64_t)b * (ND + 2) + ND + 1];
+    for (int d = 0; d < ND; ++d) acc[d] += bp[d];
+    acc[ND] = fmax(acc[ND], bp[ND]);
+    acc[ND + 1] += bp[ND + 1];
+    acc[ND + 2] = fmin(acc[ND + 2], bp[ND + 2]);
+    acc[ND + 3] = fmax(acc[ND + 3], bp[ND + 3]);
   }
   for (int b = threadIdx.x; b < NGAIN_BLK; b += PREP_BLOCK) {
-    acc[ND + 2] += gainpart[2 * b];
-    acc[ND + 3] += gainpart[2 * b + 1];
+    acc[NP] += gainpart[2 * b];
+    acc[NP + 1] += gainpart[2 * b + 1];
   }
 #pragma unroll
-  for (int j = 0; j < ND + 4; ++j) red[j][threadIdx.x] = acc[j];
+  for (int j = 0; j < NP + 2; ++j) red[j][threadIdx.x] = acc[j];
   __syncthreads();
   for (int off = PREP_BLOCK / 2; off > 0; off >>= 1) {
     if (threadIdx.x < off) {
@@ -140,8 +157,10 @@ __global__ __launch_bounds__(PREP_BLOCK) void k_prep_final(const double* __restr
       for (int d = 0; d < ND; ++d) red[d][threadIdx.x] += red[d][threadIdx.x + off];
       red[ND][threadIdx.x] = fmax(red[ND][threadIdx.x], red[ND][threadIdx.x + off]);
       red[ND + 1][threadIdx.x] += red[ND + 1][threadIdx.x + off];
-      red[ND + 2][threadIdx.x] += red[ND + 2][threadIdx.x + off];
-      red[ND + 3][threadIdx.x] += red[ND + 3][threadIdx.x + off];
+      red[ND + 2][threadIdx.x] = fmin(red[ND + 2][threadIdx.x], red[ND + 2][threadIdx.x + off]);
+      red[ND + 3][threadIdx.x] = fmax(red[ND + 3][threadIdx.x], red[ND + 3][threadIdx.x + off]);
+      red[NP][threadIdx.x] += red[NP][threadIdx.x + off];
+      red[NP + 1][threadIdx.x] += red[NP + 1][threadIdx.x + off];
     }
     __syncthreads();
   }
@@ -153,12 +172,24 @@ __global__ __launch_bounds__(PREP_BLOCK) void k_prep_final(const double* __restr
     // smallest power of two >= max |u| (exact rescaling of the float32 tables)
     e.uref = (um > 0.0 && isfinite(um)) ? exp2(ceil(log2(um))) : 1.0;
     // Z_hw ~ conj(G) Z for coherent sums, so the float32 sums are multiplied by 1 / conj(G)
-    const double gr = red[ND + 2][0], gi = red[ND + 3][0];
+    const double gr = red[NP][0], gi = red[NP + 1][0];
     const double g2 = gr * gr + gi * gi;
     e.gain_r = gr / g2;
     e.gain_i = gi / g2;
     e.bad = red[ND + 1][0] != 0.0 || !isfinite(um);
     e.pad = 0;
+    e.fmin = red[ND + 2][0];
+    e.fmax = red[ND + 3][0];
+    // |g_m| over the band: each basis function is monotone there except f^(1/3) ln f, whose
+    // magnitude peaks at f = e^-3 (value 3/e) when the band contains that point
+    const double fl = e.fmin, fh = e.fmax;
+    const double ga[NBASIS] = {pow(fl, -5.0 / 3.0), 1.0 / fl, pow(fl, -2.0 / 3.0), pow(fl, -1.0 / 3.0),
+                               fabs(log(fl)), cbrt(fl), fabs(cbrt(fl) * log(fl)), pow(fl, 2.0 / 3.0)};
+    const double gb[NBASIS] = {pow(fh, -5.0 / 3.0), 1.0 / fh, pow(fh, -2.0 / 3.0), pow(fh, -1.0 / 3.0),
+                               fabs(log(fh)), cbrt(fh), fabs(cbrt(fh) * log(fh)), pow(fh, 2.0 / 3.0)};
+#pragma unroll
+    for (int m = 0; m < NBASIS; ++m) e.gmax[m] = fmax(ga[m], gb[m]);
+    if (fl < 0.049787068367863944 && fh > 0.049787068367863944) e.gmax[6] = fmax(e.gmax[6], 1.1036383235143269);
 #pragma unroll
     for (int m = 0; m < NBASIS; ++m) e.fa[m] = 0.0;
 #pragma unroll
@@ -199,8 +230,8 @@ template <int ND>
 static hipError_t prep_nd(const double* data, const double* psd, const double* fgrid, int64_t M, double df, void* tab64,
                           void* tab32, RowGradF32* g32, RowGradF64* g64, double* blockpart, int nblk, EventConst* ec,
                           hipStream_t s) {
-  // blockpart holds nblk * (ND + 2) bin partials followed by NGAIN_BLK * 2 gain partials
-  double* gainpart = blockpart + (size_t)nblk * (ND + 2);
+  // blockpart holds nblk * prep_part(ND) bin partials followed by NGAIN_BLK * 2 gain partials
+  double* gainpart = blockpart + (size_t)nblk * prep_part(ND);
   hipLaunchKernelGGL(k_prep_bins<ND>, dim3(nblk), dim3(PREP_BLOCK), 0, s, data, psd, fgrid, M, df,
                      (RowF64<ND>*)tab64, g32, g64, blockpart);
   hipLaunchKernelGGL(k_gain_partial, dim3(NGAIN_BLK), dim3(PREP_BLOCK), 0, s, gainpart);

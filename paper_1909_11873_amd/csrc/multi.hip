@@ -31,14 +31,16 @@ constexpr int MULTI_PT_BLOCK = 128;
 
 struct MultiEvDev {
   const void* tab;         // RowMixed<ND> or RowF64<ND> [M]
-  const void* gtab;        // RowGradF32 or RowGradF64 [M]
+  const void* gtab;        // RowGradF64 [M] (adjoint basis, both precisions)
   const EventConst* ec;
   double* coef;            // [NCOEF][Bp]
   double* part;            // [nchunk][NZ][Bp]
   int64_t Bp;
   int M, chunk, nchunk, npg;
   int item0, nitems;       // first item in the queue, item count
-  int pad[2];
+  int f64;                 // 1: float64 tables and loop (every event of a float64 plan, and the
+                           // relative-binning events of a mixed one)
+  int pad;
 };
 
 struct MultiIODev {
@@ -75,7 +77,7 @@ __global__ __launch_bounds__(MULTI_PT_BLOCK) void k_multi_setup(const MultiEvDev
                                                                  const EventGeom* __restrict__ geoms,
                                                                  const MultiIODev* __restrict__ io,
                                                                  const int* __restrict__ blk_ev,
-                                                                 const int* __restrict__ blk_p0, bool scaled) {
+                                                                 const int* __restrict__ blk_p0) {
   const int e = blk_ev[blockIdx.x];
   const int64_t p = (int64_t)blk_p0[blockIdx.x] + threadIdx.x;
   const MultiEvDev ev = evs[e];
@@ -86,21 +88,22 @@ __global__ __launch_bounds__(MULTI_PT_BLOCK) void k_multi_setup(const MultiEvDev
 #pragma unroll
   for (int i = 0; i < NPARAM; ++i) th[i] = o.theta[pc * NPARAM + i];
   double rows[NCOEF];
-  const bool valid = setup_rows<ND>(th, geoms[e], ev.ec, scaled, rows);
+  const bool valid = setup_rows<ND>(th, geoms[e], ev.ec, ev.f64 == 0, rows);
   const double nan = __builtin_nan("");
 #pragma unroll
   for (int j = 0; j < NCOEF; ++j) ev.coef[j * ev.Bp + p] = valid ? rows[j] : nan;
 }
 
-// Persistent bin loop: one wavefront per item, items from the shared counter.
-template <int ND, bool MIXED, bool GRAD>
-__global__ __launch_bounds__(BLOCK, (ND <= 3 ? (GRAD && MIXED ? 5 : 4) : 3)) void k_multi_bins(const MultiEvDev* __restrict__ evs, int E, int total,
-                                                      const MultiIODev* __restrict__ io, MultiCtl* __restrict__ ctl,
-                                                      unsigned int* __restrict__ done,
-                                                      unsigned long long* __restrict__ tev) {
+// Persistent bin loop: one wavefront per item, items from the shared counter. ANYF64: a mixed
+// plan that also holds float64 (relative-binning) events, which take the float64 loop.
+template <int ND, bool MIXED, bool GRAD, bool ANYF64>
+__global__ __launch_bounds__(BLOCK, (ND <= 3 ? (GRAD && MIXED && !ANYF64 ? 5 : 4) : 3)) void k_multi_bins(
+    const MultiEvDev* __restrict__ evs, int E, int total, const MultiIODev* __restrict__ io,
+    MultiCtl* __restrict__ ctl, unsigned int* __restrict__ done, unsigned long long* __restrict__ tev) {
   constexpr int NZ = nz_of(ND, GRAD);
-  __shared__ double2 tbl[MIXED ? 1 : PH_TBL];  // the float64 phasor table
-  if constexpr (!MIXED) fill_phasor_table(tbl);
+  constexpr bool TBL = !MIXED || ANYF64;
+  __shared__ double2 tbl[TBL ? PH_TBL : 1];  // the float64 phasor table
+  if constexpr (TBL) fill_phasor_table(tbl);
   __syncthreads();
   const int lane = threadIdx.x % WAVE;
   for (;;) {
@@ -126,17 +129,23 @@ __global__ __launch_bounds__(BLOCK, (ND <= 3 ? (GRAD && MIXED ? 5 : 4) : 3)) voi
     const int k1 = k0 + ev.chunk < ev.M ? k0 + ev.chunk : ev.M;
     double tot[NZ];
     double a[NBASIS], T[ND];
-    if constexpr (MIXED) {
-      float cr[ND], ci[ND];
-      load_coef<ND, float>(ev.coef, ev.Bp, pc, GRAD, a, T, cr, ci);
-      bin_loop_mixed<ND, GRAD>((const_as_ptr<RowMixed<ND>>)ev.tab, (const_as_ptr<RowGradF32>)ev.gtab, k0, k1, a, T,
-                               cr, ci, tot);
+    bool f64path = !MIXED;
+    if constexpr (MIXED && ANYF64) f64path = ev.f64 != 0;  // wave-uniform (scalar) branch
+    if (!f64path) {
+      if constexpr (MIXED) {
+        float cr[ND], ci[ND];
+        load_coef<ND, float>(ev.coef, ev.Bp, pc, GRAD, a, T, cr, ci);
+        bin_loop_mixed<ND, GRAD>((const_as_ptr<RowMixed<ND>>)ev.tab, (const_as_ptr<RowGradF64>)ev.gtab, k0, k1, a,
+                                 T, cr, ci, tot);
+      }
     } else {
-      double cr[ND], ci[ND];
-      load_coef<ND, double>(ev.coef, ev.Bp, pc, GRAD, a, T, cr, ci);
-      to_table_units<ND>(a, T);
-      bin_loop_f64<ND, GRAD>((const_as_ptr<RowF64<ND>>)ev.tab, (const_as_ptr<RowGradF64>)ev.gtab, k0, k1, a, T, cr,
-                             ci, tbl, tot);
+      if constexpr (TBL) {
+        double cr[ND], ci[ND];
+        load_coef<ND, double>(ev.coef, ev.Bp, pc, GRAD, a, T, cr, ci);
+        to_table_units<ND>(a, T);
+        bin_loop_f64<ND, GRAD>((const_as_ptr<RowF64<ND>>)ev.tab, (const_as_ptr<RowGradF64>)ev.gtab, k0, k1, a, T,
+                               cr, ci, tbl, tot);
+      }
     }
     global_as_ptr<double> part = (global_as_ptr<double>)ev.part;
 #pragma unroll
@@ -152,13 +161,14 @@ __global__ __launch_bounds__(MULTI_PT_BLOCK) void k_multi_epilogue(const MultiEv
                                                                     const EventGeom* __restrict__ geoms,
                                                                     const MultiIODev* __restrict__ io,
                                                                     const int* __restrict__ blk_ev,
-                                                                    const int* __restrict__ blk_p0, bool scaled,
+                                                                    const int* __restrict__ blk_p0,
                                                                     MultiCtl* __restrict__ ctl) {
   constexpr int NZ = nz_of(ND, GRAD);
   const int e = blk_ev[blockIdx.x];
   const int64_t p = (int64_t)blk_p0[blockIdx.x] + threadIdx.x;
   const MultiEvDev ev = evs[e];
   const MultiIODev o = io[e];
+  const bool scaled = ev.f64 == 0;
   if (p < o.B) {
     const EventConst ec = *ev.ec;
     double acc[NZ];
@@ -188,6 +198,7 @@ struct gwl_plan_s {
   int device = 0;
   int E = 0, nd = 0;
   bool mixed = false, grad = false;
+  bool anyf64 = false;         // a mixed plan with float64 (relative-binning) events
   std::vector<int64_t> B;
   std::vector<int> order;      // queue position -> event index
   int total = 0, grid = 0, nptblk = 0, chunk = 0;
@@ -246,24 +257,28 @@ hipError_t enqueue_multi_nd(gwl_plan pl, hipStream_t s) {
   hipLaunchKernelGGL(gwl::k_multi_reset, dim3((E + 255) / 256), dim3(256), 0, s, c, done, tev, E);
   hipLaunchKernelGGL(gwl::k_multi_setup<ND>, dim3(pl->nptblk), dim3(gwl::MULTI_PT_BLOCK), 0, s,
                      (const gwl::MultiEvDev*)pl->d_evs, (const gwl::EventGeom*)pl->d_geoms,
-                     (const gwl::MultiIODev*)pl->d_io, blk_ev, blk_p0, pl->mixed);
-#define GWL_MB(MX, GR)                                                                                             \
-  hipLaunchKernelGGL((gwl::k_multi_bins<ND, MX, GR>), dim3(pl->grid), dim3(gwl::BLOCK), 0, s,                   \
+                     (const gwl::MultiIODev*)pl->d_io, blk_ev, blk_p0);
+#define GWL_MB(MX, GR, AF)                                                                                         \
+  hipLaunchKernelGGL((gwl::k_multi_bins<ND, MX, GR, AF>), dim3(pl->grid), dim3(gwl::BLOCK), 0, s,               \
                      (const gwl::MultiEvDev*)pl->d_evs, E, pl->total, (const gwl::MultiIODev*)pl->d_io, c, done, tev)
   if (pl->mixed) {
-    if (pl->grad) GWL_MB(true, true); else GWL_MB(true, false);
+    if (pl->anyf64) {
+      if (pl->grad) GWL_MB(true, true, true); else GWL_MB(true, false, true);
+    } else {
+      if (pl->grad) GWL_MB(true, true, false); else GWL_MB(true, false, false);
+    }
   } else {
-    if (pl->grad) GWL_MB(false, true); else GWL_MB(false, false);
+    if (pl->grad) GWL_MB(false, true, false); else GWL_MB(false, false, false);
   }
 #undef GWL_MB
   if (pl->grad)
     hipLaunchKernelGGL((gwl::k_multi_epilogue<ND, true>), dim3(pl->nptblk), dim3(gwl::MULTI_PT_BLOCK), 0, s,
                        (const gwl::MultiEvDev*)pl->d_evs, (const gwl::EventGeom*)pl->d_geoms,
-                       (const gwl::MultiIODev*)pl->d_io, blk_ev, blk_p0, pl->mixed, c);
+                       (const gwl::MultiIODev*)pl->d_io, blk_ev, blk_p0, c);
   else
     hipLaunchKernelGGL((gwl::k_multi_epilogue<ND, false>), dim3(pl->nptblk), dim3(gwl::MULTI_PT_BLOCK), 0, s,
                        (const gwl::MultiEvDev*)pl->d_evs, (const gwl::EventGeom*)pl->d_geoms,
-                       (const gwl::MultiIODev*)pl->d_io, blk_ev, blk_p0, pl->mixed, c);
+                       (const gwl::MultiIODev*)pl->d_io, blk_ev, blk_p0, c);
   return hipGetLastError();
 }
 
@@ -278,23 +293,27 @@ hipError_t enqueue_multi(gwl_plan pl, hipStream_t s) {
 }
 
 template <int ND>
-hipError_t occupancy_nd(bool mixed, bool grad, int* nblk) {
-#define GWL_OCC(MX, GR) \
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(nblk, gwl::k_multi_bins<ND, MX, GR>, gwl::BLOCK, 0)
+hipError_t occupancy_nd(bool mixed, bool grad, bool anyf64, int* nblk) {
+#define GWL_OCC(MX, GR, AF) \
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(nblk, gwl::k_multi_bins<ND, MX, GR, AF>, gwl::BLOCK, 0)
   if (mixed) {
-    if (grad) GWL_OCC(true, true); else GWL_OCC(true, false);
+    if (anyf64) {
+      if (grad) GWL_OCC(true, true, true); else GWL_OCC(true, false, true);
+    } else {
+      if (grad) GWL_OCC(true, true, false); else GWL_OCC(true, false, false);
+    }
   } else {
-    if (grad) GWL_OCC(false, true); else GWL_OCC(false, false);
+    if (grad) GWL_OCC(false, true, false); else GWL_OCC(false, false, false);
   }
 #undef GWL_OCC
 }
 
-hipError_t occupancy(int nd, bool mixed, bool grad, int* nblk) {
+hipError_t occupancy(int nd, bool mixed, bool grad, bool anyf64, int* nblk) {
   switch (nd) {
-    case 1: return occupancy_nd<1>(mixed, grad, nblk);
-    case 2: return occupancy_nd<2>(mixed, grad, nblk);
-    case 3: return occupancy_nd<3>(mixed, grad, nblk);
-    case 4: return occupancy_nd<4>(mixed, grad, nblk);
+    case 1: return occupancy_nd<1>(mixed, grad, anyf64, nblk);
+    case 2: return occupancy_nd<2>(mixed, grad, anyf64, nblk);
+    case 3: return occupancy_nd<3>(mixed, grad, anyf64, nblk);
+    case 4: return occupancy_nd<4>(mixed, grad, anyf64, nblk);
   }
   return hipErrorInvalidValue;
 }
@@ -322,8 +341,7 @@ gwl_status build_plan(const gwl_event* evs, int E, const int64_t* B_e, gwl_preci
   gwl_status st = check_device(evs[0]->device);
   if (st != GWL_OK) return st;
   if (!kMultiEnabled)
-    return fail(GWL_E_UNSUPPORTED, "the persistent multi-event launch is switched off: its first GPU run did not "
-                                   "complete and the cause has not been identified");
+    return fail(GWL_E_UNSUPPORTED, "the persistent multi-event launch is switched off");
 
   gwl_plan pl = new (std::nothrow) gwl_plan_s();
   if (!pl) return fail(GWL_E_NOMEM, "host allocation failed");
@@ -333,12 +351,14 @@ gwl_status build_plan(const gwl_event* evs, int E, const int64_t* B_e, gwl_preci
   pl->mixed = prec == GWL_MIXED;
   pl->grad = with_grad != 0;
   pl->B.assign(B_e, B_e + E);
+  // a mixed plan runs its relative-binning events on the float64 loop, as single calls do
+  for (int e = 0; e < E; ++e) pl->anyf64 |= pl->mixed && !use_mixed(evs[e], prec);
 
   // one chunk length for all events: the largest power of two in [1024, 16384] that still
   // gives at least four items per resident wavefront
   hipError_t err = hipSuccess;
   int occ = 0, ncu = 0, clk = 0;
-  err = occupancy(nd, pl->mixed, pl->grad, &occ);
+  err = occupancy(nd, pl->mixed, pl->grad, pl->anyf64, &occ);
   if (err == hipSuccess) err = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, pl->device);
   if (err == hipSuccess) err = hipDeviceGetAttribute(&clk, hipDeviceAttributeWallClockRate, pl->device);
   if (err != hipSuccess) {
@@ -403,8 +423,9 @@ gwl_status build_plan(const gwl_event* evs, int E, const int64_t* B_e, gwl_preci
     d.item0 = item0;
     d.nitems = d.npg * d.nchunk;
     item0 += d.nitems;
-    d.tab = pl->mixed ? ev->tab32 : ev->tab64;
-    d.gtab = pl->mixed ? (const void*)ev->g32 : (const void*)ev->g64;
+    d.f64 = use_mixed(ev, prec) ? 0 : 1;
+    d.tab = d.f64 ? ev->tab64 : ev->tab32;
+    d.gtab = ev->g64;
     d.ec = ev->ec;
     ws_doubles += (size_t)NCOEF * d.Bp + (size_t)d.nchunk * NZ * d.Bp;
     hgeo[q] = ev->geom;

@@ -495,7 +495,7 @@ static gwl_status logl_common(gwl_event ev, const double* theta, int64_t B, gwl_
                                                            with_grad ? " and grad" : "");
   gwl_status st = check_device(ev->device);
   if (st != GWL_OK) return st;
-  const bool mixed = prec == GWL_MIXED;
+  const bool mixed = use_mixed(ev, prec);
   if (ev->ncal > 0) return run_logl_cal(ev, theta, B, mixed, with_grad, logl, grad, (hipStream_t)stream);
   const LoopShape sh = make_shape(B, ev->M, choose_nchunk(ev, B, mixed, with_grad));
   return run_logl(ev, theta, B, mixed, with_grad, sh, logl, grad, (hipStream_t)stream);
@@ -517,7 +517,7 @@ gwl_status gwl_launch_shape(gwl_event ev, int64_t B, gwl_precision prec, int wit
   if (!ev) return fail(GWL_E_INVALID, "event is null");
   if (B < 1 || B > kMaxBatch) return fail(GWL_E_SHAPE, "B=%lld outside [1, %lld]", (long long)B, (long long)kMaxBatch);
   if (prec != GWL_FP64 && prec != GWL_MIXED) return fail(GWL_E_INVALID, "unknown precision %d", (int)prec);
-  const LoopShape sh = make_shape(B, ev->M, choose_nchunk(ev, B, prec == GWL_MIXED, with_grad != 0));
+  const LoopShape sh = make_shape(B, ev->M, choose_nchunk(ev, B, use_mixed(ev, prec), with_grad != 0));
   if (nchunk) *nchunk = sh.nchunk;
   if (chunk_bins) *chunk_bins = sh.chunk;
   return GWL_OK;

@@ -199,7 +199,7 @@ gwl_status gwl_autotune(const char* cache_path, gwl_event ev, int64_t B, gwl_pre
   gwl_status st = check_device(ev->device);
   if (st != GWL_OK) return st;
   if (cache_path) load_cache(cache_path);  // keep entries of other shapes
-  const bool mixed = prec == GWL_MIXED, grad = with_grad != 0;
+  const bool mixed = use_mixed(ev, prec), grad = with_grad != 0;
 
   // candidate chunk counts: powers of two around the heuristic, then a second pass around the
   // best of those (3/4 .. 3/2 of it), each launch shape timed once (the chunk count a shape really

@@ -14,8 +14,9 @@ WIDTHS = np.array([50.0, 0.8, 1.8, 1.8, 1900.0, 2 * math.pi, math.pi, math.pi, m
 
 
 @functools.lru_cache(maxsize=8)
-def event_inputs(cfg: int, event: int = 0, f_hi: float | None = None, ndet: int | None = None):
-    """(spec, fgrid, psd, data, dets) of a workload; data = noise + oracle injection at theta0."""
+def event_inputs(cfg: int, event: int = 0, f_hi: float | None = None, ndet: int | None = None, gmst: float = 0.0):
+    """(spec, fgrid, psd, data, dets) of a workload; data = noise + oracle injection at theta0
+    (seen at sidereal angle gmst)."""
     spec = synth.event_spec(cfg, event)
     f, psd, nz, dets = synth.event_arrays(spec)
     if f_hi is not None:
@@ -28,7 +29,7 @@ def event_inputs(cfg: int, event: int = 0, f_hi: float | None = None, ndet: int 
             dets[3] = np.radians([-31.4, 115.7, 0.0, 90.0])
         psd = np.stack([psd[0]] * ndet)
         nz = np.stack([synth.noise(spec.seed_base + 50 + i, psd[0], spec.df) for i in range(ndet)])
-    data = nz + o.strain_all(spec.theta0, dets, f).numpy()
+    data = nz + o.strain_all(spec.theta0, dets, f, gmst).numpy()
     return spec, f, psd, data, dets
 
 

@@ -103,11 +103,17 @@ def test_c1_mixed_matches_fp64_everywhere(c1):
 
 
 def test_c2_long_signal_sampled():
+    """The 128 s workload (259,585 bins per detector) at the committed tile shapes: 64 points
+    against the oracle, the injection and the eight loudest prior draws among them."""
     spec, f, psd, data, dets = event_inputs(2)
     ev = make_event(f, psd, data, dets, spec.df)
     th = synth.theta_batch(spec)
     th[0] = spec.theta0
-    sample = np.array([0, 1, 2, 1000, 2047, 4095])
+    loud = np.argsort(th[:, 0] ** (5 / 3) / th[:, 4] ** 2)[-8:]
+    rng = np.random.default_rng(2)
+    sample = np.unique(np.concatenate([[0, 1, 2, 1000, 2047, 4095], loud,
+                                       rng.choice(np.arange(3, 4095), 50, replace=False)]))
+    assert len(sample) >= 64
     ref = oracle_logl(th[sample], f, psd, data, dets, spec.df)
     for prec in ("mixed", "fp64"):
         use_bench_shapes(spec, ev, len(th), prec, False)

@@ -24,16 +24,9 @@ def rb_event(cfg, eps, f_hi=None):
     return spec, f, psd, data, dets, ev, full, summ
 
 
-# Mixed precision on relative-binning rows: each edge's term V_e r_e is large (a few hundred
-# bins' worth), few terms are summed and nothing averages. Every term carries about four float32
-# relative roundings (V / uref stored in float32, the product, the block sum, the hardware phasor
-# with its 1.25e-7 maximum error): |error| <= 2.5e-7 sum_e |V_e| (|r_e| ~ 1 near the fiducial),
-# and never less than the full path's 1e-3.
-RB_MIXED_REL = 2.5e-7
-
-
-def rb_mixed_tolerance(summ):
-    return max(1e-3, RB_MIXED_REL * float(np.abs(summ["V"]).sum()))
+# GWL_MIXED on a relative-binning event runs the float64 edge loop (float32 roundings on a few
+# hundred large edge terms do not average down below 1e-3 on loud events), so both precisions are
+# held to the full path's mixed bound of 1e-3 absolute, and the float64 one to 1e-9 relative.
 
 
 @pytest.mark.parametrize("cfg,eps", [(1, 0.1), (1, 0.5), (2, 0.1)])
@@ -47,7 +40,7 @@ def test_rb_matches_the_rb_oracle(cfg, eps):
     for prec in ("fp64", "mixed"):
         got = gw.logl(torch.tensor(th, device=DEV), ev, prec).cpu().numpy()
         err = np.abs(got - ref)
-        tol = 1e-9 * np.maximum(1.0, np.abs(ref)) if prec == "fp64" else rb_mixed_tolerance(summ)
+        tol = 1e-9 * np.maximum(1.0, np.abs(ref)) if prec == "fp64" else 1e-3
         print(f"RB c{cfg} eps {eps} ({ne} edges of {nb} bins) {prec}: max |dlogL| vs RB oracle {err.max():.3e} "
               f"(tolerance {np.max(tol):.2e})")
         assert np.all(err <= tol)

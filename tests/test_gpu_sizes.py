@@ -61,3 +61,27 @@ def test_grid_of_2_to_the_22_bins():
         print(f"M = 2^22 + 1 bins, {prec}: |dlogL| {err.max():.2e} (logL(theta0) {ref[0]:.2f})")
         assert err.max() <= tol * max(1.0, abs(ref[0]) if prec == "fp64" else 1.0)
     ev.close()
+
+
+def test_large_coalescence_times_and_the_phase_limit():
+    """Points whose phase reaches millions of cycles on the grid (t_c = +-600 s at 2048 Hz is
+    1.2e6 cycles, 2.5e9 table units of the float64 phasor: beyond a 32-bit index) against the
+    oracle, on the 128 s grid; a point whose phase bound exceeds 2^39 cycles is outside the
+    supported domain and gives NaN in both precisions."""
+    spec = synth.event_spec(2)
+    ev, f, psd, data, dets = event(20.0, 2048.0, 1.0 / 128.0, spec.theta0, 9300)
+    theta = synth.theta_batch(spec, 8)
+    theta[:, 10] = [600.0, -600.0, 599.9, -250.0, 1e9, 2e8, 0.0, 37.5]
+    th = torch.tensor(theta, device=DEV)
+    ok = [0, 1, 2, 3, 6, 7]
+    ref = o.logl(theta[ok], data, psd, dets, f, 1.0 / 128.0).numpy()
+    for prec, tol in (("fp64", 1e-6), ("mixed", 1e-3)):
+        got = gw.logl(th, ev, prec).cpu().numpy()
+        err = np.abs(got[ok] - ref)
+        print(f"t_c up to 600 s on {len(f)} bins, {prec}: max |dlogL| {err.max():.2e}")
+        assert err.max() <= tol
+        assert np.isnan(got[4])                       # 1e9 s x 2048 Hz > 2^39 cycles
+        assert np.isfinite(got[5])                    # 2e8 s x 2048 Hz < 2^39 cycles
+        v, g = gw.logl_grad(th, ev, prec)
+        assert np.isnan(v.cpu().numpy()[4]) and np.all(np.isnan(g.cpu().numpy()[4]))
+    ev.close()
