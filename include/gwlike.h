@@ -29,7 +29,11 @@
  *   7 inclination (rad)                      8 polarisation psi (rad) 9 coalescence phase (rad)
  *   10 geocentre coalescence time t_c (s)
  * A row with a non-finite value, q outside (0, 1], Mc <= 0, D_L <= 0 or |chi| >= 1 yields
- * logL = NaN (and a NaN gradient row); the call still returns GWL_OK.
+ * logL = NaN (and a NaN gradient row); the call still returns GWL_OK. So does a row whose phase
+ * could exceed 2^39 cycles somewhere on the event's grid (bounded at set-up by
+ * sum_m |a_m| max|g_m(f)| + max_det |t_c + dt_det| f_max over the post-Newtonian terms a_m g_m(f)
+ * of the phase in cycles; e.g. |t_c| f_max >= 2^39): beyond that a float64 phase no longer
+ * resolves a cycle finely enough, and the float64 kernels' table index would not be exact.
  *
  * Conventions for every call:
  *   - Device pointers are HIP device (HBM) addresses on the current device; host pointers are
@@ -153,10 +157,26 @@ gwl_status gwl_event_info(gwl_event ev, int* ndet, int64_t* M, double* df);
  *          GWL_MIXED: float64 for the post-Newtonian phase, the time-shift term and its
  *          reduction modulo one cycle, and for every per-point scalar and reduction; float32
  *          for the per-bin phasor, complex multiply-accumulate over short blocks of bins.
- * B = 0 is a no-op. Workspace is taken from the stream-ordered device memory pool.
+ * B = 0 is a no-op. The call allocates nothing once the event's workspace on `stream` is large
+ * enough: the event keeps one workspace per stream, grown (outside graph capture only) by the
+ * first call that needs more. On a stream that is capturing a graph a call that would need to
+ * grow it returns GWL_E_INVALID: reserve it first with gwl_event_reserve (or one ordinary call of
+ * the same size on that stream).
+ * GWL_MIXED on a relative-binning event runs the float64 edge loop: its few hundred edge terms are
+ * each a sum over hundreds of bins, and float32 roundings on them would not stay within the
+ * accuracy the mixed path keeps elsewhere (1e-3 absolute on logL).
  */
 gwl_status gwl_logl_batch(gwl_event ev, const double* theta, int64_t B, gwl_precision prec, double* logl,
                           void* stream);
+
+/*
+ * Grow the event's workspace on `stream` to what a gwl_logl_batch (with_grad = 0) or
+ * gwl_logl_grad (with_grad = 1) call with these arguments needs, so that such calls allocate
+ * nothing, also under graph capture. Must not be called while `stream` is capturing (it may
+ * allocate, and then returns GWL_E_INVALID there). Growing synchronises `stream` before the old
+ * buffer is freed. The workspace lives until the event is destroyed.
+ */
+gwl_status gwl_event_reserve(gwl_event ev, int64_t B, gwl_precision prec, int with_grad, void* stream);
 
 /*
  * logL and its gradient with respect to all 11 parameters (adjoint of the same evaluation,

@@ -3,11 +3,24 @@
 
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+#include <vector>
+
 #include "../../include/gwlike.h"
 #include "gwl_common.h"
 #include "gwl_launch.h"
 
+// Device workspace of an event on one stream: grown (never shrunk) outside graph capture, reused
+// by every later call on that stream; calls on one stream are ordered, so they can share it.
+struct gwl_workspace {
+  hipStream_t stream = nullptr;
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
 struct gwl_event_s {
+  std::mutex ws_mu;                  // guards ws
+  std::vector<gwl_workspace> ws;     // one per stream that has called on this event
   int device = 0;
   int ndet = 0;
   int64_t M = 0;                     // rows the bin loop walks (bins, or edges for relative binning)
@@ -68,6 +81,13 @@ hipError_t fill_theta(double* theta, int64_t B, hipStream_t s);
 
 gwl_status run_logl(gwl_event ev, const double* theta, int64_t B, bool mixed, bool grad, const LoopShape& sh,
                     double* logl, double* gradout, hipStream_t s);
+
+// The event's workspace on stream s, grown to at least `bytes` if needed (zero-filled when it
+// grows). Growing is refused while s is capturing a graph (GWL_E_INVALID): the caller reserves it
+// beforehand with gwl_event_reserve or an ordinary call of the same size.
+gwl_status event_workspace(gwl_event ev, hipStream_t s, size_t bytes, void** out);
+// Workspace bytes a single-event call of this kind needs.
+size_t call_workspace_bytes(const gwl_event_s* ev, int64_t B, bool mixed, bool grad);
 hipError_t enqueue_logl(gwl_event ev, const double* theta, int64_t B, bool mixed, bool grad, const LoopShape& sh,
                         double* coef, double* part, double* logl, double* gradout, hipStream_t s);
 

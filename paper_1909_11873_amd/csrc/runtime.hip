@@ -401,6 +401,9 @@ gwl_status gwl_event_create_cal(const double* data, const double* psd, const gwl
 
 gwl_status gwl_event_destroy(gwl_event ev) {
   if (!ev) return GWL_OK;
+  for (gwl_workspace& w : ev->ws)
+    if (w.ptr) (void)hipFree(w.ptr);
+  ev->ws.clear();
   if (ev->cal32) (void)hipFree(ev->cal32);
   if (ev->cal64) (void)hipFree(ev->cal64);
   if (ev->calt32) (void)hipFree(ev->calt32);
@@ -469,18 +472,16 @@ static gwl_status run_logl_cal(gwl_event ev, const double* theta, int64_t B, boo
   const int nchunk = sh.nchunk, ncal = 2 * n * nd;
   const size_t bytes = sizeof(double) * ((size_t)NCOEF * Bp + (size_t)ncal * Bp + (size_t)nchunk * nz_cal(nd, grad) * Bp);
   void* ws = nullptr;
-  hipError_t e = hipMallocAsync(&ws, bytes, s);
-  if (e != hipSuccess) return hip_fail(e, "workspace");
+  gwl_status st = event_workspace(ev, s, bytes, &ws);
+  if (st != GWL_OK) return st;
   double* coef = (double*)ws;
   double* calc = coef + (size_t)NCOEF * Bp;
   double* part = calc + (size_t)ncal * Bp;
-  e = launch_cal(nd, mixed, grad, ev->geom, ev->ec, ev->kcal, mixed ? ev->tab32 : ev->tab64,
+  hipError_t e = launch_cal(nd, mixed, grad, ev->geom, ev->ec, ev->kcal, mixed ? ev->tab32 : ev->tab64,
                  mixed ? (const void*)ev->g32 : (const void*)ev->g64, mixed ? (const void*)ev->cal32 : (const void*)ev->cal64,
                  mixed ? (const void*)ev->calt32 : (const void*)ev->calt64, ev->calB, theta, NPARAM + ncal, B, Bp, sh,
                  coef, calc, part, logl, gradout, s);
-  hipError_t e2 = hipFreeAsync(ws, s);
   if (e != hipSuccess) return hip_fail(e, "launch");
-  if (e2 != hipSuccess) return hip_fail(e2, "workspace release");
   return GWL_OK;
 }
 
@@ -509,6 +510,19 @@ gwl_status gwl_logl_batch(gwl_event ev, const double* theta, int64_t B, gwl_prec
 gwl_status gwl_logl_grad(gwl_event ev, const double* theta, int64_t B, gwl_precision prec, double* logl, double* grad,
                          void* stream) {
   return logl_common(ev, theta, B, prec, logl, grad, true, stream);
+}
+
+gwl_status gwl_event_reserve(gwl_event ev, int64_t B, gwl_precision prec, int with_grad, void* stream) {
+  clear_error();
+  if (!ev) return fail(GWL_E_INVALID, "event is null");
+  if (B < 0 || B > kMaxBatch) return fail(GWL_E_SHAPE, "B=%lld outside [0, %lld]", (long long)B, (long long)kMaxBatch);
+  if (prec != GWL_FP64 && prec != GWL_MIXED) return fail(GWL_E_INVALID, "unknown precision %d", (int)prec);
+  if (B == 0) return GWL_OK;
+  gwl_status st = check_device(ev->device);
+  if (st != GWL_OK) return st;
+  void* ws = nullptr;
+  return event_workspace(ev, (hipStream_t)stream, call_workspace_bytes(ev, B, use_mixed(ev, prec), with_grad != 0),
+                         &ws);
 }
 
 gwl_status gwl_launch_shape(gwl_event ev, int64_t B, gwl_precision prec, int with_grad, int* nchunk,
@@ -554,20 +568,74 @@ size_t workspace_bytes(int64_t Bp, int nchunk, int nd, bool grad) {
   return sizeof(double) * ((size_t)NCOEF * Bp + (size_t)nchunk * nz_of(nd, grad) * Bp);
 }
 
-// Set-up, bin loop and epilogue on `s`, with workspace from the stream-ordered pool.
+// Set-up, bin loop and epilogue on `s`, in the event's workspace for `s`.
 gwl_status run_logl(gwl_event ev, const double* theta, int64_t B, bool mixed, bool grad, const LoopShape& sh,
                     double* logl, double* gradout, hipStream_t s) {
   const int64_t Bp = (int64_t)sh.npg * WAVE;
   void* ws = nullptr;
-  hipError_t e = hipMallocAsync(&ws, workspace_bytes(Bp, sh.nchunk, ev->ndet, grad), s);
-  if (e != hipSuccess) return hip_fail(e, "workspace");
+  gwl_status st = event_workspace(ev, s, workspace_bytes(Bp, sh.nchunk, ev->ndet, grad), &ws);
+  if (st != GWL_OK) return st;
   double* coef = (double*)ws;
   double* part = coef + (size_t)NCOEF * Bp;
-  e = enqueue_logl(ev, theta, B, mixed, grad, sh, coef, part, logl, gradout, s);
-  hipError_t e2 = hipFreeAsync(ws, s);
+  hipError_t e = enqueue_logl(ev, theta, B, mixed, grad, sh, coef, part, logl, gradout, s);
   if (e != hipSuccess) return hip_fail(e, "launch");
-  if (e2 != hipSuccess) return hip_fail(e2, "workspace release");
   return GWL_OK;
+}
+
+gwl_status event_workspace(gwl_event ev, hipStream_t s, size_t bytes, void** out) {
+  *out = nullptr;
+  std::lock_guard<std::mutex> lk(ev->ws_mu);
+  gwl_workspace* w = nullptr;
+  for (gwl_workspace& x : ev->ws)
+    if (x.stream == s) w = &x;
+  if (w && w->bytes >= bytes) {
+    *out = w->ptr;
+    return GWL_OK;
+  }
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(s, &cs);
+  if (e != hipSuccess) return hip_fail(e, "stream capture status");
+  if (cs != hipStreamCaptureStatusNone)
+    return fail(GWL_E_INVALID, "the call needs %zu bytes of workspace on a stream that is capturing a graph and has %zu: "
+                               "reserve it first (gwl_event_reserve, or one call of this size on that stream outside "
+                               "capture)", bytes, w ? w->bytes : (size_t)0);
+  const size_t grain = (size_t)2 << 20;
+  const size_t nb = (bytes + grain - 1) / grain * grain;
+  void* p = nullptr;
+  e = hipMalloc(&p, nb);
+  if (e != hipSuccess) return hip_fail(e, "workspace");
+  e = hipMemsetAsync(p, 0, nb, s);
+  if (e == hipSuccess && w && w->ptr) {
+    // the old buffer may still be in use by work queued on s
+    e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipFree(w->ptr);
+    w->ptr = nullptr;
+    w->bytes = 0;
+  }
+  if (e != hipSuccess) {
+    (void)hipFree(p);
+    return hip_fail(e, "workspace");
+  }
+  if (!w) {
+    ev->ws.push_back(gwl_workspace{});
+    w = &ev->ws.back();
+    w->stream = s;
+  }
+  w->ptr = p;
+  w->bytes = nb;
+  *out = p;
+  return GWL_OK;
+}
+
+size_t call_workspace_bytes(const gwl_event_s* ev, int64_t B, bool mixed, bool grad) {
+  const int64_t Bp = (B + WAVE - 1) / WAVE * WAVE;
+  if (ev->ncal > 0) {
+    // the calibrated loop uses at most MAXCALCHUNK chunks and 2 nnode nd calibration rows
+    return sizeof(double) * ((size_t)NCOEF * Bp + (size_t)2 * ev->ncal * ev->ndet * Bp +
+                             (size_t)MAXCALCHUNK * nz_cal(ev->ndet, grad) * Bp);
+  }
+  const LoopShape sh = make_shape(B, ev->M, choose_nchunk(ev, B, mixed, grad));
+  return workspace_bytes(Bp, sh.nchunk, ev->ndet, grad);
 }
 
 // ---- bin-loop timing (gwl_profile_*) ----

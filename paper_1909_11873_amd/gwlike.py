@@ -75,6 +75,7 @@ def lib() -> ctypes.CDLL:
         "gwl_autotune": ([ctypes.c_char_p, vp, i64, cint, cint], cint),
         "gwl_autotune_load": ([ctypes.c_char_p], cint),
         "gwl_launch_shape": ([vp, i64, cint, cint, ctypes.POINTER(cint), ctypes.POINTER(cint)], cint),
+        "gwl_event_reserve": ([vp, i64, cint, cint, vp], cint),
         "gwl_profile_enable": ([cint], cint),
         "gwl_profile_read": ([ctypes.POINTER(i64), ctypes.POINTER(dbl)], cint),
         "gwl_slice_ends": ([i64, cint, cint] + [vp] * 9 + [vp], cint),
@@ -379,6 +380,15 @@ def launch_shape(ev: Event, batch: int, precision="mixed", with_grad: bool = Fal
     _check("gwl_launch_shape", lib().gwl_launch_shape(ev.handle, int(batch), _prec(precision), int(bool(with_grad)),
                                                       ctypes.byref(n), ctypes.byref(c)))
     return n.value, c.value
+
+
+def reserve(ev: Event, batch: int, precision="mixed", with_grad: bool = False, stream=None) -> None:
+    """Grow the event's workspace on `stream` (default: the current stream) for calls of this size,
+    so that they allocate nothing, also under graph capture (gwl_event_reserve)."""
+    if stream is None:
+        stream = torch.cuda.current_stream(ev.device)
+    _check("gwl_event_reserve", lib().gwl_event_reserve(ev.handle, int(batch), _prec(precision), int(bool(with_grad)),
+                                                        ctypes.c_void_p(stream.cuda_stream)))
 
 
 def autotune_load(cache_path: str) -> None:

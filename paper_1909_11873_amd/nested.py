@@ -280,18 +280,22 @@ class _SliceGraphs:
             stage_b(self.ub)
         torch.cuda.current_stream(smp.dev).wait_stream(side)
         torch.cuda.synchronize(smp.dev)
+        # captured on the warm-up's stream: the library keeps its workspace per stream and grows it
+        # only outside capture, so the warm-up has reserved what the captured calls use
         self.ga, self.gb = torch.cuda.CUDAGraph(), torch.cuda.CUDAGraph()
-        with torch.cuda.graph(self.ga):
+        with torch.cuda.graph(self.ga, stream=side):
             stage_a()
-        with torch.cuda.graph(self.gb, pool=self.ga.pool()):
+        with torch.cuda.graph(self.gb, pool=self.ga.pool(), stream=side):
             stage_b(self.ub)
         self.calls_a, self.calls_b = (2 * m + G) * n if m > 1 else G * n, G * n
 
     def walk(self, x0, chol, lmin, steps):
+        """(points, whether each chain moved at least once)."""
         smp, n, d = self.smp, self.smp.n, self.smp.d
         self.x.copy_(x0)
         self.chol.copy_(chol)
         self.lmin.copy_(lmin)
+        moved = torch.zeros(n, dtype=torch.bool, device=smp.dev)
         for _ in range(steps):
             torch.randn(n, d, generator=smp.gen, out=self.z)
             torch.rand(2 + SLICE_MAX_DRAWS, n, generator=smp.gen, out=self.unif)
@@ -303,8 +307,9 @@ class _SliceGraphs:
                 self.ub.copy_(self.unif[2 + g0:2 + g0 + SLICE_GROUP])
                 self.gb.replay()
                 smp.extra_calls += self.calls_b
+            moved |= self.done
             self.x.copy_(self.xn)
-        return self.x.clone()
+        return self.x.clone(), moved
 
 
 class ParallelNestedSampler:
@@ -476,7 +481,9 @@ class ParallelNestedSampler:
         """Slice-sampling walks inside the contour L >= L_min, one chain per candidate: each chain
         starts at a random live point and makes slice_steps moves of `slice_move`, along random
         directions isotropic in the coordinates that whiten the live points, each of length
-        slice_width in those coordinates."""
+        slice_width in those coordinates. A chain whose every move gave up (no shrinkage draw
+        inside) is still at its live point: it is returned outside the cube, so it is rejected
+        instead of duplicating that point."""
         n, d, K = self.n, self.d, self.K
         f64 = dict(dtype=torch.float64, device=self.dev)
         lmin = live_l[0]
@@ -492,8 +499,10 @@ class ParallelNestedSampler:
                 warnings.warn(f"slice moves run eagerly: capturing them failed ({exc})")
                 self.slice_graphs = False
         if self.slice_graphs:
-            return self._graphs.walk(x, chol, lmin, self.slice_steps)
+            x, moved = self._graphs.walk(x, chol, lmin, self.slice_steps)
+            return torch.where(moved[:, None], x, torch.full_like(x, 2.0))
         inside = lambda p: self._in_contour(p, lmin)
+        moved = torch.zeros(n, dtype=torch.bool, device=self.dev)
 
         def raw(p):
             self.extra_calls += p.shape[0]
@@ -503,10 +512,11 @@ class ParallelNestedSampler:
             dirn = self.slice_width * (z / z.norm(dim=1, keepdim=True)) @ chol.T
             unif = torch.rand(2 + SLICE_MAX_DRAWS, n, generator=self.gen, **f64)
             if self.slice_kernels:
-                x, _ = slice_move_dev(x, dirn, unif, self.slice_out, raw, lmin)
+                x, done = slice_move_dev(x, dirn, unif, self.slice_out, raw, lmin)
             else:
-                x, _ = slice_move(x, dirn, unif, self.slice_out, inside)
-        return x
+                x, done = slice_move(x, dirn, unif, self.slice_out, inside)
+            moved |= done
+        return torch.where(moved[:, None], x, torch.full_like(x, 2.0))
 
     def _propose(self, it, live_u, live_l):
         if callable(self.proposal):

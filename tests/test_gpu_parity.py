@@ -111,9 +111,10 @@ def test_c2_long_signal_sampled():
     th[0] = spec.theta0
     loud = np.argsort(th[:, 0] ** (5 / 3) / th[:, 4] ** 2)[-8:]
     rng = np.random.default_rng(2)
-    sample = np.unique(np.concatenate([[0, 1, 2, 1000, 2047, 4095], loud,
-                                       rng.choice(np.arange(3, 4095), 50, replace=False)]))
-    assert len(sample) >= 64
+    fixed = np.unique(np.concatenate([[0, 1, 2, 1000, 2047, 4095], loud]))
+    rest = rng.choice(np.setdiff1d(np.arange(4096), fixed), 64 - len(fixed), replace=False)
+    sample = np.unique(np.concatenate([fixed, rest]))
+    assert len(sample) == 64
     ref = oracle_logl(th[sample], f, psd, data, dets, spec.df)
     for prec in ("mixed", "fp64"):
         use_bench_shapes(spec, ev, len(th), prec, False)

@@ -213,6 +213,33 @@ def test_slice_proposal_on_host():
     assert c[0, 1] / math.sqrt(c[0, 0] * c[1, 1]) == pytest.approx(rho, abs=0.02)
 
 
+def test_slice_chains_that_never_move_are_rejected():
+    """A contour that no shrinkage draw can hit (the likelihood is finite only at the live points
+    themselves): every move of every chain gives up, so each chain still sits on the live point
+    it started from. Such chains come back outside the unit cube (rejected), not as copies of
+    live points; with a likelihood that chains can move in, none is."""
+    d, K, n = 2, 40, 64
+    live = torch.rand(K, d, dtype=torch.float64, generator=torch.Generator().manual_seed(3))
+
+    def needle(th):
+        hit = (th[:, None, :] == live[None]).all(-1).any(-1)
+        return torch.where(hit, torch.zeros(th.shape[0], dtype=torch.float64),
+                           torch.full((th.shape[0],), -math.inf, dtype=torch.float64))
+
+    smp = nested.ParallelNestedSampler(needle, d, K, n, device="cpu", seed=4, proposal="slice", slice_steps=2)
+    cand = smp._slice(live, torch.zeros(K, dtype=torch.float64))
+    assert cand.shape == (n, d)
+    assert bool(((cand < 0.0) | (cand > 1.0)).any(1).all())          # all outside the cube
+    # an ordinary contour: every chain moves and stays inside the cube
+    smp2 = nested.ParallelNestedSampler(lambda th: -((th - 0.5) ** 2).sum(1), d, K, n, device="cpu", seed=4,
+                                        proposal="slice", slice_steps=2)
+    lv = 0.5 + 0.1 * (live - 0.5)
+    ll = -((lv - 0.5) ** 2).sum(1)
+    order = torch.argsort(ll)
+    cand2 = smp2._slice(lv[order], ll[order])
+    assert bool(((cand2 >= 0.0) & (cand2 <= 1.0)).all())
+
+
 def test_slice_evidence_scatter_matches_its_quoted_error():
     """Ten independent slice-walk runs on a normalised 4-D Gaussian (ln Z = 0): their mean is
     within three standard errors of 0, and their scatter agrees with the sqrt(H/K) error each run
