@@ -80,6 +80,9 @@ typedef struct {
   double lat, lon, xarm_az, yarm_az;
 } gwl_detector;
 
+/* gwl_event_create flags */
+#define GWL_F_ISCO_CUTOFF 1u
+
 typedef struct gwl_event_s* gwl_event;
 typedef struct gwl_plan_s* gwl_plan;
 
@@ -97,7 +100,13 @@ const char* gwl_version(void);
  *   dets   host,   gwl_detector [ndet]
  *   df     frequency spacing = 1/T (s^-1); the 4 df of the inner product uses it
  *   gmst   Greenwich sidereal angle (rad) of the segment, held fixed across the segment
- *   flags  0 (reserved)
+ *   flags  0, or GWL_F_ISCO_CUTOFF: the model is zero above the gravitational-wave frequency of
+ *          the innermost stable circular orbit of the point's total mass M,
+ *          f_isco = c^3 / (6^(3/2) pi G M) (twice the orbital frequency at r = 6 G M / c^2): both
+ *          inner products keep only the bins with f_k <= f_isco. The grid must then increase
+ *          (GWL_E_INVALID otherwise). Not available with relative binning, the calibration model
+ *          or multi-event plans (GWL_E_UNSUPPORTED). The cut moves with the masses in whole bins,
+ *          so gwl_logl_grad returns the derivative with the point's bins held fixed.
  * The call prepares the per-bin tables of the factored likelihood on the device (event
  * preparation, section 2 Eq. 2 rearranged: u_k = 4 df f_k^(-7/6) conj(d_k)/S_k and
  * K_det = 4 df sum_k f_k^(-7/3)/S_k) and synchronises `stream` before returning, so the
@@ -134,11 +143,25 @@ gwl_status gwl_event_create_rb(const double* data, const double* psd, const gwl_
  * On such an event gwl_logl_batch and gwl_logl_grad take theta [B][11 + 2 nnode ndet]: the 11
  * signal parameters, then per detector its nnode amplitude values followed by its nnode phase
  * values (radians); grad has the same shape. <h|h> stays exact (per-event spline moments).
- * Not usable in multi-event plans (GWL_E_UNSUPPORTED).
+ * With relative binning: gwl_event_create_rb_cal.
  */
 gwl_status gwl_event_create_cal(const double* data, const double* psd, const gwl_detector* dets, int ndet,
                                 const double* fgrid, int64_t M, double df, double gmst, int nnode, unsigned flags,
                                 void* stream, gwl_event* out);
+
+/*
+ * Relative binning and the calibration model together: the event of gwl_event_create_rb (same
+ * edges and summary data against theta_fid) whose model carries the calibration factor of
+ * gwl_event_create_cal (nnode nodes per detector, spanning the grid from its first to its last
+ * bin). The factor is smooth in f, so its product with h / h0 is interpolated between edges like
+ * h / h0 itself: <d|h_cal> = Re sum_e V_e rho(f_e) (1 + dA(f_e)) exp(i dphi(f_e)), on the edges
+ * only; <h_cal|h_cal> stays exact, its spline moments taken over every grid bin. theta and grad
+ * have 11 + 2 nnode ndet columns, as on a calibrated event. Both precisions run the float64 edge
+ * loop.
+ */
+gwl_status gwl_event_create_rb_cal(const double* data, const double* psd, const gwl_detector* dets, int ndet,
+                                   const double* fgrid, int64_t M, double df, double gmst, const double* theta_fid,
+                                   double eps, int nnode, unsigned flags, void* stream, gwl_event* out);
 
 /* Relative-binning sizes: number of edges (0 for an ordinary event) and of grid bins. */
 gwl_status gwl_event_rb_info(gwl_event ev, int64_t* nedge, int64_t* nbins);
@@ -201,7 +224,10 @@ gwl_status gwl_waveform(const double* theta, int64_t B, const gwl_detector* dets
  * gwl_multi_plan_create builds the work list (event, point group, bin range), sizes the
  * workspace for the given per-event batch sizes B_e, picks tile shapes, and captures the whole
  * evaluation (queue reset, per-point set-up, persistent kernel, per-event finalisation) in a
- * HIP graph bound to the events. The events must outlive the plan.
+ * HIP graph bound to the events. The events must outlive the plan. Calibrated events (of
+ * gwl_event_create_cal or gwl_event_create_rb_cal) are not in the persistent queue: each launch
+ * runs their own set-up, bin-loop and epilogue kernels on the same stream after the graph, with
+ * theta and grad of 11 + 2 nnode ndet columns; the ISCO cut-off is not supported in plans.
  *   evs       host [E] event handles;  B_e host int64 [E] (each >= 0)
  *   with_grad 0: logL only; 1: logL and gradient
  */
@@ -209,7 +235,8 @@ gwl_status gwl_multi_plan_create(const gwl_event* evs, int E, const int64_t* B_e
                                  int with_grad, gwl_plan* out);
 
 /*
- * Run a plan. theta[e], logl[e], grad[e] are device pointers ([B_e][11], [B_e], [B_e][11]);
+ * Run a plan. theta[e], logl[e], grad[e] are device pointers ([B_e][P_e], [B_e], [B_e][P_e], P_e = 11
+ * or 11 + 2 nnode ndet on a calibrated event);
  * grad may be null when the plan has no gradient. The pointer tables are host arrays of E
  * entries. If event_latency_us is non-null it receives, per event, the time from the start of
  * the launch to the completion of that event's results (device clock), and the call then
@@ -249,13 +276,21 @@ gwl_status gwl_autotune(const char* cache_path, gwl_event ev, int64_t B, gwl_pre
 gwl_status gwl_launch_shape(gwl_event ev, int64_t B, gwl_precision prec, int with_grad, int* nchunk,
                             int* chunk_bins);
 
+/* The evaluation kernel's layout for such a call: wavefronts per workgroup (each takes one chunk
+ * of bins for the workgroup's 64 points; the chunks are added in LDS), workgroups per group of 64
+ * points (nchunk = waves x groups), and whether the per-point set-up runs inside that kernel (1)
+ * or in a set-up kernel before it (0). Any output pointer may be null. */
+gwl_status gwl_launch_layout(gwl_event ev, int64_t B, gwl_precision prec, int with_grad, int* waves, int* groups,
+                             int* setup);
+
 /* Load tile choices from a JSON cache written by gwl_autotune (missing file = GWL_E_INVALID). */
 gwl_status gwl_autotune_load(const char* cache_path);
 
 /*
- * Kernel timing for measurement. While enabled, every bin-loop launch made by gwl_logl_batch
- * and gwl_logl_grad is bracketed by two HIP events recorded on the caller's stream (the
- * stream the kernel runs on). gwl_profile_read waits for those events and returns the number
+ * Kernel timing for measurement. While enabled, every launch of the evaluation kernel (the bin
+ * loop with its reduction and, for the value, the epilogue) made by gwl_logl_batch and
+ * gwl_logl_grad is bracketed by two HIP events recorded on the caller's stream (the stream the
+ * kernel runs on). gwl_profile_read waits for those events and returns the number
  * of bracketed launches and their summed duration in milliseconds since the previous read,
  * then forgets them. Either pointer may be null. Disabling keeps unread records.
  */

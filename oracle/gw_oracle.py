@@ -48,6 +48,9 @@ Parity status of each part (what pins it, in the tests):
     product (composite Gauss-Legendre quadrature) at first, then, with the
     Euler-Maclaurin end term, second order in df; the float64 rounding by a
     50-digit evaluation of the per-bin definition (agreement to ~1e-15).
+  * the optional ISCO cut-off: its frequency pinned by Kepler's law at r = 6GM/c^2
+    (twice the orbital frequency), the cut by evaluating on the grid truncated
+    there.
   * the sign of i in h_x and of the phase exponent are conventions of this
     build (FT with exp(-2 pi i f t)); they are checked for internal consistency
     by the time-shift and phase invariances only.
@@ -193,11 +196,23 @@ def inner(a, b, psd, df):
     return 4.0 * df * torch.sum(torch.real(torch.conj(a) * b) / psd)
 
 
-def logl_point(theta, data, psd, dets, fgrid, df, gmst=0.0):
-    """logL for one parameter point; data[ndet, M] complex128, psd[ndet, M], dets[ndet] x 4."""
+def isco_frequency(theta):
+    """Gravitational-wave frequency at the innermost stable circular orbit of a Schwarzschild
+    black hole of the binary's total mass: twice the orbital frequency at r = 6 G M / c^2,
+    f = c^3 / (6^(3/2) pi G M)."""
+    _, mtot, _, _ = masses(theta[0], theta[1])
+    return 1.0 / (6.0 ** 1.5 * math.pi * T_SUN * mtot)
+
+
+def logl_point(theta, data, psd, dets, fgrid, df, gmst=0.0, isco=False):
+    """logL for one parameter point; data[ndet, M] complex128, psd[ndet, M], dets[ndet] x 4.
+    With isco the model is zero above the ISCO frequency (both inner products lose those bins)."""
     total = torch.zeros((), dtype=DT)
+    keep = fgrid <= isco_frequency(theta) if isco else None
     for i in range(len(dets)):
         h = detector_strain(fgrid, theta, tuple(float(v) for v in dets[i]), gmst)
+        if keep is not None:
+            h = torch.where(keep, h, torch.zeros_like(h))
         total = total + inner(data[i], h, psd[i], df) - 0.5 * inner(h, h, psd[i], df)
     return total
 
@@ -209,26 +224,27 @@ def _as_inputs(data, psd, fgrid):
     return data, psd, fgrid
 
 
-def logl(theta, data, psd, dets, fgrid, df, gmst=0.0):
+def logl(theta, data, psd, dets, fgrid, df, gmst=0.0, isco=False):
     """logL for every row of theta[B, 11] (float64 numpy or tensor); returns float64 tensor [B]."""
     data, psd, fgrid = _as_inputs(data, psd, fgrid)
     th = torch.as_tensor(theta, dtype=DT).reshape(-1, 11)
     out = torch.empty(th.shape[0], dtype=DT)
     with torch.no_grad():
         for b in range(th.shape[0]):
-            out[b] = logl_point(th[b], data, psd, dets, fgrid, df, gmst)
+            out[b] = logl_point(th[b], data, psd, dets, fgrid, df, gmst, isco)
     return out
 
 
-def logl_grad(theta, data, psd, dets, fgrid, df, gmst=0.0):
-    """(logL[B], dlogL/dtheta[B, 11]) by reverse-mode autograd through logl_point."""
+def logl_grad(theta, data, psd, dets, fgrid, df, gmst=0.0, isco=False):
+    """(logL[B], dlogL/dtheta[B, 11]) by reverse-mode autograd through logl_point (with isco the
+    cut is a step in theta: its derivative is that of the model on the bins kept)."""
     data, psd, fgrid = _as_inputs(data, psd, fgrid)
     th = torch.as_tensor(theta, dtype=DT).reshape(-1, 11)
     val = torch.empty(th.shape[0], dtype=DT)
     grad = torch.empty(th.shape[0], 11, dtype=DT)
     for b in range(th.shape[0]):
         tb = th[b].clone().requires_grad_(True)
-        lb = logl_point(tb, data, psd, dets, fgrid, df, gmst)
+        lb = logl_point(tb, data, psd, dets, fgrid, df, gmst, isco)
         (g,) = torch.autograd.grad(lb, tb)
         val[b] = lb.detach()
         grad[b] = g

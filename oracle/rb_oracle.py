@@ -25,7 +25,9 @@ formulas; the readings taken here (each one pinned in tests/test_rb_oracle.py):
 logL_RB(theta) = sum_det [ <d|h>_RB - 1/2 <h|h> ].
 
 Parity status: pinned (partition of unity at the fiducial, exactness when every bin is an edge,
-second-order convergence in the edge spacing, the edge rule itself).
+second-order convergence in the edge spacing, the edge rule itself). With the calibration model:
+pinned by reduction to the plain binned likelihood at zero calibration and to the calibrated
+full likelihood when every bin is an edge.
 """
 from __future__ import annotations
 
@@ -34,6 +36,7 @@ import math
 import numpy as np
 import torch
 
+from oracle import cal_oracle as co
 from oracle import gw_oracle as o
 
 GAMMAS = (-5.0 / 3.0, -2.0 / 3.0, 1.0, 5.0 / 3.0, 7.0 / 3.0)
@@ -92,8 +95,11 @@ def summary(data, psd, dets, fgrid, df, theta_fid, eps, gmst=0.0):
     return {"idx": idx, "fe": f[idx], "h0e": h0[:, idx], "V": V, "eps": eps}
 
 
-def logl_point(theta, summ, psd, dets, fgrid, df, gmst=0.0):
-    """logL_RB for one point (torch, differentiable in theta)."""
+def logl_point(theta, summ, psd, dets, fgrid, df, gmst=0.0, nnode=0):
+    """logL_RB for one point (torch, differentiable in theta). With nnode > 0 the model carries
+    the calibration factor of cal_oracle (theta [11 + 2 nnode ndet], columns as there): the
+    ratio at the edges becomes h_cal / h0 (the factor is smooth in f, so its product with h / h0
+    is interpolated like h / h0 itself), and <h_cal|h_cal> is taken over every bin."""
     fe = torch.as_tensor(summ["fe"], dtype=o.DT)
     fgrid = torch.as_tensor(fgrid, dtype=o.DT)
     psd = torch.as_tensor(psd, dtype=o.DT)
@@ -102,32 +108,41 @@ def logl_point(theta, summ, psd, dets, fgrid, df, gmst=0.0):
     total = torch.zeros((), dtype=o.DT)
     for i in range(len(dets)):
         det = tuple(float(v) for v in dets[i])
-        he = o.detector_strain(fe, theta, det, gmst)
+        he = o.detector_strain(fe, theta[:11], det, gmst)
+        h = o.detector_strain(fgrid, theta[:11], det, gmst)
+        if nnode:
+            base = 11 + 2 * nnode * i
+            amp, ph = theta[base:base + nnode], theta[base + nnode:base + 2 * nnode]
+            he = he * co.factor(fe, amp, ph)
+            h = h * co.factor(fgrid, amp, ph)
         r = he / h0e[i]
         dh = torch.sum(torch.real(V[i] * r))
-        h = o.detector_strain(fgrid, theta, det, gmst)
         total = total + dh - 0.5 * o.inner(h, h, psd[i], df)
     return total
 
 
-def logl(theta, summ, psd, dets, fgrid, df, gmst=0.0):
-    """logL_RB for every row of theta[B, 11]; float64 tensor [B]."""
-    th = torch.as_tensor(theta, dtype=o.DT).reshape(-1, 11)
+def _rows(theta, nnode, ndet):
+    return torch.as_tensor(theta, dtype=o.DT).reshape(-1, 11 + 2 * nnode * ndet)
+
+
+def logl(theta, summ, psd, dets, fgrid, df, gmst=0.0, nnode=0):
+    """logL_RB for every row of theta[B, 11 + 2 nnode ndet]; float64 tensor [B]."""
+    th = _rows(theta, nnode, len(dets))
     out = torch.empty(th.shape[0], dtype=o.DT)
     with torch.no_grad():
         for b in range(th.shape[0]):
-            out[b] = logl_point(th[b], summ, psd, dets, fgrid, df, gmst)
+            out[b] = logl_point(th[b], summ, psd, dets, fgrid, df, gmst, nnode)
     return out
 
 
-def logl_grad(theta, summ, psd, dets, fgrid, df, gmst=0.0):
-    """(logL_RB[B], its gradient [B, 11]) by reverse-mode autograd."""
-    th = torch.as_tensor(theta, dtype=o.DT).reshape(-1, 11)
+def logl_grad(theta, summ, psd, dets, fgrid, df, gmst=0.0, nnode=0):
+    """(logL_RB[B], its gradient [B, 11 + 2 nnode ndet]) by reverse-mode autograd."""
+    th = _rows(theta, nnode, len(dets))
     val = torch.empty(th.shape[0], dtype=o.DT)
-    grad = torch.empty(th.shape[0], 11, dtype=o.DT)
+    grad = torch.empty_like(th)
     for b in range(th.shape[0]):
         tb = th[b].clone().requires_grad_(True)
-        lb = logl_point(tb, summ, psd, dets, fgrid, df, gmst)
+        lb = logl_point(tb, summ, psd, dets, fgrid, df, gmst, nnode)
         (g,) = torch.autograd.grad(lb, tb)
         val[b] = lb.detach()
         grad[b] = g

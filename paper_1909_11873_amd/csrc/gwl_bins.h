@@ -172,14 +172,25 @@ __device__ __forceinline__ void f64_bin(const RowF64<ND> r, GradP gt, int k,
   }
 }
 
+// A row with its whitened data zeroed in the lanes whose point is cut off below bin k (the
+// optional ISCO cut-off: kc bins kept), so that the bin adds nothing there.
+template <int ND, class Row>
+__device__ __forceinline__ Row cut_row(Row r, int k, int kc) {
+  const bool keep = k < kc;
+#pragma unroll
+  for (int j = 0; j < 2 * ND; ++j) r.u[j] = keep ? r.u[j] : 0;
+  return r;
+}
+
 // The bin loop of one wavefront: points in lanes, bins [k0, k1) of one event.
 // Mixed precision: the complex sums in float32 over blocks of NB bins, each block added into
-// float64; the adjoint moments in float64 throughout (see mixed_bin).
-template <int ND, bool GRAD, class TabP, class GradP>
+// float64; the adjoint moments in float64 throughout (see mixed_bin). CUT: each lane keeps only
+// its first kc bins.
+template <int ND, bool GRAD, class TabP, class GradP, bool CUT = false>
 __device__ __forceinline__ void bin_loop_mixed(TabP tab, GradP gtab,
                                                int k0, int k1, const double (&a)[NBASIS], const double (&T)[ND],
                                                const float (&cr)[ND], const float (&ci)[ND],
-                                               double (&tot)[nz_of(ND, GRAD)]) {
+                                               double (&tot)[nz_of(ND, GRAD)], int kc = 0) {
   constexpr int NZ = nz_of(ND, GRAD);
   constexpr int NF = 2 * ND;  // float32 block sums
 #pragma unroll
@@ -199,11 +210,11 @@ __device__ __forceinline__ void bin_loop_mixed(TabP tab, GradP gtab,
       for (int j = 0; j < NB; ++j) {
         if constexpr (GRAD) {
           const RowMixed<ND> nxt = load_row_mixed<ND>(tab, k + j + 1);
-          mixed_bin<ND, GRAD, GradP>(cur, gtab, k + j, a, T, cr, ci, z, tot);
+          mixed_bin<ND, GRAD, GradP>(CUT ? cut_row<ND>(cur, k + j, kc) : cur, gtab, k + j, a, T, cr, ci, z, tot);
           cur = nxt;
         } else {
           const RowMixed<ND> nx2 = load_row_mixed<ND>(tab, k + j + 2);
-          mixed_bin<ND, GRAD, GradP>(cur, gtab, k + j, a, T, cr, ci, z, tot);
+          mixed_bin<ND, GRAD, GradP>(CUT ? cut_row<ND>(cur, k + j, kc) : cur, gtab, k + j, a, T, cr, ci, z, tot);
           cur = nx1;
           nx1 = nx2;
         }
@@ -216,18 +227,22 @@ __device__ __forceinline__ void bin_loop_mixed(TabP tab, GradP gtab,
     float z[NF];
 #pragma unroll
     for (int j = 0; j < NF; ++j) z[j] = 0.0f;
-    for (; k < k1; ++k) mixed_bin<ND, GRAD, GradP>(load_row_mixed<ND>(tab, k), gtab, k, a, T, cr, ci, z, tot);
+    for (; k < k1; ++k) {
+      const RowMixed<ND> r = load_row_mixed<ND>(tab, k);
+      mixed_bin<ND, GRAD, GradP>(CUT ? cut_row<ND>(r, k, kc) : r, gtab, k, a, T, cr, ci, z, tot);
+    }
 #pragma unroll
     for (int j = 0; j < NF; ++j) tot[j] += (double)z[j];
   }
 }
 
 // Float64: sums in float64 throughout.
-template <int ND, bool GRAD, class TabP, class GradP>
+template <int ND, bool GRAD, class TabP, class GradP, bool CUT = false>
 __device__ __forceinline__ void bin_loop_f64(TabP tab, GradP gtab,
                                              int k0, int k1, const double (&a)[NBASIS], const double (&T)[ND],
                                              const double (&cr)[ND], const double (&ci)[ND],
-                                             const double2* __restrict__ tbl, double (&z)[nz_of(ND, GRAD)]) {
+                                             const double2* __restrict__ tbl, double (&z)[nz_of(ND, GRAD)],
+                                             int kc = 0) {
   constexpr int NZ = nz_of(ND, GRAD);
 #pragma unroll
   for (int j = 0; j < NZ; ++j) z[j] = 0.0;
@@ -237,7 +252,7 @@ __device__ __forceinline__ void bin_loop_f64(TabP tab, GradP gtab,
 #pragma unroll 2
   for (int k = k0; k < k1; ++k) {
     const RowF64<ND> nxt = load_row_f64<ND>(tab, k + 1);
-    f64_bin<ND, GRAD, GradP>(cur, gtab, k, a, T, cr, ci, tbl, z);
+    f64_bin<ND, GRAD, GradP>(CUT ? cut_row<ND>(cur, k, kc) : cur, gtab, k, a, T, cr, ci, tbl, z);
     cur = nxt;
   }
 }
@@ -262,6 +277,42 @@ __device__ __forceinline__ void load_coef(const double* __restrict__ coef, int64
     cr[d] = grad ? (QT)coef[(CO_CR + d) * Bp + pc] : (QT)0;
     ci[d] = grad ? (QT)coef[(CO_CI + d) * Bp + pc] : (QT)0;
   }
+}
+
+// The optional ISCO cut-off (GWL_F_ISCO_CUTOFF): the number of grid bins at or below the
+// gravitational-wave frequency of the innermost stable circular orbit of the point's total
+// mass, f_isco = 1 / (6^(3/2) pi T_sun M) (twice the orbital frequency at r = 6 G M / c^2). The
+// grid is increasing; a first guess from its mean spacing is corrected by stepping, with a
+// bisection if the guess is far off. Every caller (set-up, evaluation, gradient epilogue) takes
+// the same decision in float64.
+__device__ inline int isco_bins(double mc, double q, const double* __restrict__ fgrid, int64_t M, const EventConst& ec) {
+  const double eta = q / ((1.0 + q) * (1.0 + q));
+  const double mtot = mc * pow(eta, -0.6);
+  const double fi = 1.0 / (14.696938456699067 * kPi * kTsun * mtot);  // 6^(3/2) = 14.696938456699067
+  if (!(fi > 0.0) || !isfinite(fi)) return 0;
+  // first index with f > fi
+  double g = floor((fi - ec.fmin) / ec.grid_df) + 1.0;
+  g = fmin(fmax(g, 0.0), (double)M);
+  int64_t k = (int64_t)g;
+  for (int it = 0; it < 8; ++it) {
+    if (k > 0 && fgrid[k - 1] > fi) --k;
+    else if (k < M && fgrid[k] <= fi) ++k;
+    else return (int)k;
+  }
+  int64_t lo = 0, hi = M;  // bisection: f[k] <= fi for k < lo, f[k] > fi for k >= hi
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo) / 2;
+    if (fgrid[mid] <= fi) lo = mid + 1;
+    else hi = mid;
+  }
+  return (int)lo;
+}
+
+// Largest value of v across the wavefront (every lane gets it, as a scalar).
+__device__ inline int wave_max(int v) {
+#pragma unroll
+  for (int off = WAVE / 2; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
+  return __builtin_amdgcn_readfirstlane(v);
 }
 
 }  // namespace gwl

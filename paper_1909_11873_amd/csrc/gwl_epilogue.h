@@ -81,38 +81,6 @@ __device__ inline void gather(const double* __restrict__ part, int nchunk, int64
   }
 }
 
-// The same sums with S lanes per point (S a power of two, the lanes consecutive): lane `sub`
-// sums chunks sub q .. sub q + q - 1 in chunk order, q = nchunk / S the same for every lane (a
-// wave-uniform trip count keeps several chunks' loads in flight), then chunk S q + sub if that
-// is one of the nchunk - S q left over; a butterfly over the S lanes adds the parts, pairwise by
-// lane distance 1, 2, ...; every lane ends with the same, launch-shape-deterministic total. All
-// S lanes must call it (it shuffles); `valid` false contributes zeros.
-template <int NZ, int S>
-__device__ inline void gather_split(const double* __restrict__ part, int nchunk, int64_t Bp, int64_t p, int sub,
-                                    bool valid, double (&acc)[NZ]) {
-#pragma unroll
-  for (int z = 0; z < NZ; ++z) acc[z] = 0.0;
-  const int q = nchunk / S;
-  if (valid) {
-    const double* src = part + (int64_t)sub * q * NZ * Bp + p;
-#pragma unroll 8
-    for (int c = 0; c < q; ++c) {
-#pragma unroll
-      for (int z = 0; z < NZ; ++z) acc[z] += src[((int64_t)c * NZ + z) * Bp];
-    }
-    if (sub < nchunk - S * q) {
-      const double* tail = part + (int64_t)(S * q + sub) * NZ * Bp + p;
-#pragma unroll
-      for (int z = 0; z < NZ; ++z) acc[z] += tail[(int64_t)z * Bp];
-    }
-  }
-#pragma unroll
-  for (int off = 1; off < S; off <<= 1) {
-#pragma unroll
-    for (int z = 0; z < NZ; ++z) acc[z] += __shfl_xor(acc[z], off, S);
-  }
-}
-
 // logL = sum_det [ uref Re(A E Q_det Z_det) - 1/2 A^2 |Q_det|^2 K_det ],  E = exp(-2 pi i c0).
 // `acc` holds Z_det (re, im) first; uref = 1 for float64 tables.
 template <int ND, int NZ>

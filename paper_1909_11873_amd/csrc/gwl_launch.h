@@ -7,18 +7,24 @@
 
 namespace gwl {
 
-// Shape of one bin-loop launch: points in groups of 64 (one wavefront), bins in `nchunk`
-// chunks of `chunk` bins; items = nchunk * ceil(npg / WAVES_PER_BLOCK) workgroups, dealt so
-// that each accelerator die works through a contiguous range of chunks.
+// Shape of one evaluation launch: points in groups of 64 (one wavefront), a workgroup of W
+// wavefronts per (point group, chunk group), each wavefront one chunk of `chunk` bins, G
+// workgroups per point group (nchunk = W G chunks in all); the items = npg G workgroups are
+// dealt so that each accelerator die works through a contiguous range of chunk groups. `setup`:
+// the per-point set-up runs inside the kernel instead of the set-up kernel.
+constexpr int MAX_EVAL_WAVES = 16;
 struct LoopShape {
   int npg;      // point groups = ceil(B / 64)
-  int nchunk;   // bin chunks
+  int W;        // wavefronts (chunks) per workgroup
+  int G;        // workgroups per point group
+  int nchunk;   // W G
   int chunk;    // bins per chunk
-  int nbpg;     // workgroups per chunk = ceil(npg / WAVES_PER_BLOCK)
-  int items;    // nchunk * nbpg
+  int items;    // workgroups = npg G
   int gper;     // workgroups per die = ceil(items / NXCD)
+  int setup;    // 1: set-up inside the evaluation kernel
 };
-LoopShape make_shape(int64_t B, int64_t M, int nchunk);
+LoopShape make_shape(int64_t B, int64_t M, int W, int G, int setup);
+size_t eval_lds_doubles(bool mixed, const LoopShape& sh);
 
 // event preparation: per-bin tables, K_det and the float32 scale
 hipError_t launch_prep(int nd, const double* data, const double* psd, const double* fgrid, int64_t M, double df,
@@ -32,17 +38,24 @@ size_t prep_scratch_doubles(int nd, int64_t M);  // size of `blockpart`
 hipError_t launch_setup(int nd, const EventGeom& g, const EventConst* ec, bool scaled, const double* theta, int64_t B,
                         int64_t Bp, double* coef, hipStream_t s);
 
-// bin loop: coef -> partial sums [nchunk][nz][Bp]
-hipError_t launch_bins(int nd, bool mixed, bool grad, const void* tab, const void* gtab, const void* gtab64,
-                       const double* coef, int64_t B, int64_t Bp, int64_t M, const LoopShape& sh, double* part,
-                       hipStream_t s);
+// evaluation: set-up rows (coef, unless sh.setup), bin loop, reduction over the W chunks of a
+// workgroup and, for the value, over its G workgroups (part [G][nz][Bp] and cnt [npg], zero
+// between calls, when G > 1) and the float64 epilogue -> logl[B]; for the gradient the
+// workgroup sums go to part [G][nz][Bp] for the gradient epilogue
+// fgrid [M] and kcum [nd][M + 1] (running sums of the K_det terms) for an event with the ISCO
+// cut-off, else both null
+hipError_t launch_eval(int nd, bool mixed, bool grad, const void* tab, const RowGradF64* gtab, const double* theta,
+                       const EventGeom& geo, const EventConst* ec, const double* coef, int64_t B, int64_t Bp,
+                       int64_t M, const LoopShape& sh, double* part, unsigned int* cnt, double* logl,
+                       const double* fgrid, const double* kcum, hipStream_t s);
 
-// epilogue: partial sums -> logL[B] (and grad[B][11]); the value alone reads the set-up rows
-// `coef`, the gradient evaluates the point model from theta
+// epilogue: partial sums [nchunk][nz][Bp] -> logL[B] (and grad[B][11]); the value alone reads the
+// set-up rows `coef`, the gradient evaluates the point model from theta
 // `scaled`: the partial sums came from the float32 tables, which hold u / uref
 hipError_t launch_epilogue(int nd, bool grad, bool scaled, const EventGeom& g, const EventConst* ec,
                            const double* theta, const double* coef, int64_t B, int64_t Bp, int nchunk,
-                           const double* part, double* logl, double* gradout, hipStream_t s);
+                           const double* part, double* logl, double* gradout, hipStream_t s,
+                           const double* fgrid = nullptr, const double* kcum = nullptr, int64_t M = 0);
 
 // float32 rows from float64 rows: tab32 = (basis, u / ec->uref)
 hipError_t launch_prep_mixed(int nd, const void* tab64, int64_t M, const EventConst* ec, void* tab32, hipStream_t s);

@@ -16,6 +16,8 @@ struct gwl_workspace {
   hipStream_t stream = nullptr;
   void* ptr = nullptr;
   size_t bytes = 0;
+  unsigned int* cnt = nullptr;       // completion counters of the evaluation kernel: zero between calls
+  size_t ncnt = 0;
 };
 
 struct gwl_event_s {
@@ -25,6 +27,7 @@ struct gwl_event_s {
   int ndet = 0;
   int64_t M = 0;                     // rows the bin loop walks (bins, or edges for relative binning)
   int64_t M_full = 0;                // bins of the grid (relative binning), else 0
+  std::vector<int64_t> rb_idx;       // the relative-binning edges' bins
   // calibration model (ncal nodes per detector, 0 = none)
   int ncal = 0;
   gwl::RowCal32* cal32 = nullptr;    // [M] window weights
@@ -43,6 +46,8 @@ struct gwl_event_s {
   void* tab32 = nullptr;             // RowMixed<ndet>[M]
   gwl::RowGradF32* g32 = nullptr;    // [M]
   gwl::RowGradF64* g64 = nullptr;    // [M]
+  double* fgrid = nullptr;           // [M] grid frequencies (ISCO cut-off only)
+  double* kcum = nullptr;            // [ndet][M + 1] running sums of the K_det terms (ISCO cut-off only)
   gwl::EventConst* ec = nullptr;     // device copy
   gwl::EventConst ech = {};          // host copy
 };
@@ -64,10 +69,16 @@ gwl_status check_device(int dev);
 gwl_status make_geom(const gwl_detector* dets, int ndet, double gmst, EventGeom& g);
 size_t row64_bytes(int nd);
 size_t row32_bytes(int nd);
-size_t workspace_bytes(int64_t Bp, int nchunk, int nd, bool grad);
+// workspace of an evaluation launch: set-up rows [NCOEF][Bp] unless the kernel does the set-up,
+// then workgroup partial sums [G][nz][Bp] for the gradient or when G > 1 (doubles), and npg
+// completion counters for the value when G > 1
+size_t workspace_bytes(int64_t Bp, const LoopShape& sh, int nd, bool grad);
+size_t workspace_counters(const LoopShape& sh, bool grad);
 
-// number of bin chunks for a launch (autotuner cache, else a heuristic)
-int choose_nchunk(const gwl_event_s* ev, int64_t B, bool mixed, bool grad);
+// launch shape of a call (autotuner cache, else a heuristic)
+LoopShape choose_shape(const gwl_event_s* ev, int64_t B, bool mixed, bool grad);
+LoopShape heuristic_shape(int64_t B, int64_t M, bool mixed, bool grad);
+// number of bin chunks of the calibrated loop's adjoint (a heuristic)
 int heuristic_nchunk(int64_t B, int64_t M);
 
 // multi-event plans: build with an explicit chunk length (0 = heuristic) and queue order; the
@@ -76,19 +87,23 @@ gwl_status build_plan(const gwl_event* evs, int E, const int64_t* B_e, gwl_preci
                       int chunk_req, bool descending, gwl_plan* out);
 void choose_multi_shape(const gwl_event* evs, int E, const int64_t* B_e, bool mixed, bool grad, int* chunk,
                         bool* descending);
-// fill theta[B][11] with valid parameter points (timing inputs)
-hipError_t fill_theta(double* theta, int64_t B, hipStream_t s);
+// fill theta[B][P] with valid parameter points (timing inputs; P >= 11, zeros past column 11)
+hipError_t fill_theta(double* theta, int64_t B, hipStream_t s, int P = NPARAM);
 
 gwl_status run_logl(gwl_event ev, const double* theta, int64_t B, bool mixed, bool grad, const LoopShape& sh,
                     double* logl, double* gradout, hipStream_t s);
+// a call on a calibrated event (its own set-up, bin loop and epilogue kernels)
+gwl_status run_calibrated(gwl_event ev, const double* theta, int64_t B, bool mixed, bool grad, double* logl,
+                          double* gradout, hipStream_t s);
 
 // The event's workspace on stream s, grown to at least `bytes` if needed (zero-filled when it
 // grows). Growing is refused while s is capturing a graph (GWL_E_INVALID): the caller reserves it
 // beforehand with gwl_event_reserve or an ordinary call of the same size.
-gwl_status event_workspace(gwl_event ev, hipStream_t s, size_t bytes, void** out);
+gwl_status event_workspace(gwl_event ev, hipStream_t s, size_t bytes, size_t ncnt, void** out,
+                           unsigned int** cnt = nullptr);
 // Workspace bytes a single-event call of this kind needs.
 size_t call_workspace_bytes(const gwl_event_s* ev, int64_t B, bool mixed, bool grad);
 hipError_t enqueue_logl(gwl_event ev, const double* theta, int64_t B, bool mixed, bool grad, const LoopShape& sh,
-                        double* coef, double* part, double* logl, double* gradout, hipStream_t s);
+                        double* ws, unsigned int* cnt, double* logl, double* gradout, hipStream_t s);
 
 }  // namespace gwl

@@ -1,14 +1,27 @@
 // The bin loop: for every (point, detector, frequency bin) evaluate the post-Newtonian phase,
 // shift it by the detector's arrival time, reduce it modulo one cycle, form the phasor and
-// multiply-accumulate it against the event's whitened data (the sum over bins j of Eq. 2).
+// multiply-accumulate it against the event's whitened data (the sum over bins j of Eq. 2), then
+// reduce over bins and, for the value, apply the float64 epilogue in the same kernel.
 //
 // Mapping to CDNA: one lane per parameter point, one wavefront per 64 points, and all lanes
 // of a wavefront walk the same bins in lock-step. Every per-bin quantity (frequency basis,
 // whitened data) is therefore wave-uniform and arrives through scalar loads into SGPRs,
-// while the per-point coefficients live in VGPRs for the whole chunk. There is no cross-lane
-// reduction: each lane owns its point's sums. Bins are split into chunks only to give the
-// chip enough wavefronts; each chunk writes one partial per point, summed in chunk order by
-// the epilogue.
+// while the per-point coefficients live in VGPRs for the whole chunk.
+//
+// A workgroup holds W wavefronts that share one group of 64 points and take W consecutive
+// chunks of the bins; G workgroups cover a point group's bins. The W partial sums of a
+// workgroup are added in LDS in wavefront order; with G = 1 the first wavefront then applies
+// the epilogue directly, so neither partial sums nor a second kernel are needed. With G > 1 each
+// workgroup writes its partial sums and the last one to finish (a counter per point group, after
+// an agent-scope release/acquire) adds the G of them in workgroup order: every sum is taken in a
+// fixed order, so results are bitwise reproducible for a given shape. The gradient's epilogue
+// (eleven forward-mode passes through the point model, over 250 registers) runs as its own kernel
+// on the G partial sums.
+//
+// The per-point set-up (phase coefficients, shifts, projection factors) either comes from the
+// set-up kernel's rows or is computed here by the first wavefront of each workgroup and handed
+// to the others through LDS (sh.setup): that saves a launch for small calls, at the price of the
+// set-up's registers in this kernel.
 //
 // Mixed precision: float64 for the phase polynomial, the f T_det term and the reduction to
 // [0, 1) cycles (v_fract_f64); float32 for the phasor (hardware sin/cos, which take cycles)
@@ -17,111 +30,295 @@
 // on more than NB terms at once. The adjoint's moments are accumulated in float64.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "gwl_bins.h"
 #include "gwl_common.h"
 #include "gwl_device.h"
+#include "gwl_epilogue.h"
 #include "gwl_launch.h"
 
 namespace gwl {
 
-LoopShape make_shape(int64_t B, int64_t M, int nchunk) {
+LoopShape make_shape(int64_t B, int64_t M, int W, int G, int setup) {
   LoopShape s;
   s.npg = (int)((B + WAVE - 1) / WAVE);
-  if (nchunk < 1) nchunk = 1;
-  if (nchunk > M) nchunk = (int)M;
-  s.chunk = (int)((M + nchunk - 1) / nchunk);
-  s.nchunk = (int)((M + s.chunk - 1) / s.chunk);
-  s.nbpg = (s.npg + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
-  s.items = s.nchunk * s.nbpg;
+  if (W < 1) W = 1;
+  if (W > MAX_EVAL_WAVES) W = MAX_EVAL_WAVES;
+  if (G < 1) G = 1;
+  // no more chunks than bins
+  const int64_t gmax = (M + W - 1) / W;
+  if (G > gmax) G = (int)(gmax > 0 ? gmax : 1);
+  s.W = W;
+  s.G = G;
+  s.nchunk = W * G;
+  s.chunk = (int)((M + s.nchunk - 1) / s.nchunk);
+  s.items = s.npg * G;
   s.gper = (s.items + NXCD - 1) / NXCD;
+  s.setup = setup ? 1 : 0;
   return s;
 }
 
-// Decode the workgroup's (chunk, point group) and the lane's point; false if idle.
-__device__ __forceinline__ bool locate(const LoopShape& sh, int64_t M, int& c, int& k0, int& k1, int& pg) {
-  const int bid = blockIdx.x;
-  const int item = (bid % NXCD) * sh.gper + bid / NXCD;  // dies take contiguous item ranges
-  if (item >= sh.items) return false;
-  c = item / sh.nbpg;
-  pg = (item - c * sh.nbpg) * WAVES_PER_BLOCK + (int)(threadIdx.x / WAVE);
-  if (pg >= sh.npg) return false;
-  k0 = c * sh.chunk;
-  k1 = (int)((int64_t)k0 + sh.chunk < M ? k0 + sh.chunk : M);
-  return true;
+// Dynamic LDS of a workgroup, in doubles: the set-up rows (NCOEF x 64) when the set-up runs here,
+// then the float64 phasor table (PH_TBL double2), which the cross-wavefront reduction reuses, or,
+// for mixed precision, the reduction buffer alone ((W - 1) x RED_Z x 64).
+constexpr int RED_Z = 4;  // sums reduced per LDS pass
+size_t eval_lds_doubles(bool mixed, const LoopShape& sh) {
+  const size_t rows = sh.setup ? (size_t)NCOEF * WAVE : 0;
+  const size_t red = (size_t)(sh.W - 1) * RED_Z * WAVE;
+  const size_t tbl = mixed ? 0 : (size_t)2 * PH_TBL;
+  return rows + (red > tbl ? red : tbl);
 }
 
-template <int ND, bool GRAD>
-__global__ __launch_bounds__(BLOCK) void k_bins_mixed(const RowMixed<ND>* __restrict__ tab,
-                                                      const RowGradF64* __restrict__ gtab,
-                                                      const double* __restrict__ coef, int64_t B, int64_t Bp, int64_t M,
-                                                      LoopShape sh, double* __restrict__ part) {
-  constexpr int NZ = nz_of(ND, GRAD);
-  int c, k0, k1, pg;
-  if (!locate(sh, M, c, k0, k1, pg)) return;
-  const int64_t p = (int64_t)pg * WAVE + (threadIdx.x % WAVE);
-  const int64_t pc = p < B ? p : B - 1;
-  double a[NBASIS], T[ND];
-  float cr[ND], ci[ND];
-  load_coef<ND, float>(coef, Bp, pc, GRAD, a, T, cr, ci);
-  double tot[NZ];
-  bin_loop_mixed<ND, GRAD>(tab, gtab, k0, k1, a, T, cr, ci, tot);
+// logL of one point from its reduced sums and set-up values (A, c0, Q_det):
+//   sum_det [ uref Re(A E Q_det Z_det) - 1/2 A^2 |Q_det|^2 K_det ],  E = exp(-2 pi i c0).
+template <int ND, int NZ>
+__device__ inline double value_from_rows(const double (&acc)[NZ], double amp, double c0f, const double (&qr)[ND],
+                                         const double (&qi)[ND], const EventConst& ec, double uref) {
+  const double c0 = c0f - rint(c0f);
+  double es, ecs;
+  sincos_cycles_f64(c0, es, ecs);
+  const double er = ecs, ei = -es;
+  double out = 0.0;
 #pragma unroll
-  for (int z = 0; z < NZ; ++z) part[((int64_t)c * NZ + z) * Bp + p] = tot[z];
-}
-
-template <int ND, bool GRAD>
-__global__ __launch_bounds__(BLOCK) void k_bins_f64(const RowF64<ND>* __restrict__ tab,
-                                                    const RowGradF64* __restrict__ gtab,
-                                                    const double* __restrict__ coef, int64_t B, int64_t Bp, int64_t M,
-                                                    LoopShape sh, double* __restrict__ part) {
-  constexpr int NZ = nz_of(ND, GRAD);
-  __shared__ double2 tbl[PH_TBL];
-  fill_phasor_table(tbl);  // before any wavefront leaves
-  __syncthreads();
-  int c, k0, k1, pg;
-  if (!locate(sh, M, c, k0, k1, pg)) return;
-  const int64_t p = (int64_t)pg * WAVE + (threadIdx.x % WAVE);
-  const int64_t pc = p < B ? p : B - 1;
-  double a[NBASIS], T[ND], cr[ND], ci[ND];
-  load_coef<ND, double>(coef, Bp, pc, GRAD, a, T, cr, ci);
-  to_table_units<ND>(a, T);
-  double z[NZ];
-  bin_loop_f64<ND, GRAD>(tab, gtab, k0, k1, a, T, cr, ci, tbl, z);
-#pragma unroll
-  for (int j = 0; j < NZ; ++j) part[((int64_t)c * NZ + j) * Bp + p] = z[j];
-}
-
-template <int ND>
-static hipError_t bins_nd(bool mixed, bool grad, const void* tab, const void* gtab, const void* gtab64,
-                          const double* coef, int64_t B, int64_t Bp, int64_t M, const LoopShape& sh, double* part,
-                          hipStream_t s) {
-  const dim3 grid((unsigned)(sh.gper * NXCD)), block(BLOCK);
-  if (mixed) {
-    if (grad)
-      hipLaunchKernelGGL((k_bins_mixed<ND, true>), grid, block, 0, s, (const RowMixed<ND>*)tab,
-                         (const RowGradF64*)gtab64, coef, B, Bp, M, sh, part);
-    else
-      hipLaunchKernelGGL((k_bins_mixed<ND, false>), grid, block, 0, s, (const RowMixed<ND>*)tab,
-                         (const RowGradF64*)gtab64, coef, B, Bp, M, sh, part);
-  } else {
-    if (grad)
-      hipLaunchKernelGGL((k_bins_f64<ND, true>), grid, block, 0, s, (const RowF64<ND>*)tab,
-                         (const RowGradF64*)gtab64, coef, B, Bp, M, sh, part);
-    else
-      hipLaunchKernelGGL((k_bins_f64<ND, false>), grid, block, 0, s, (const RowF64<ND>*)tab,
-                         (const RowGradF64*)gtab64, coef, B, Bp, M, sh, part);
+  for (int d = 0; d < ND; ++d) {
+    const double xr = amp * (er * qr[d] - ei * qi[d]);
+    const double xi = amp * (er * qi[d] + ei * qr[d]);
+    const double dh = uref * (xr * acc[2 * d] - xi * acc[2 * d + 1]);
+    const double hh = amp * amp * (qr[d] * qr[d] + qi[d] * qi[d]) * ec.K[d];
+    out += dh - 0.5 * hh;
   }
+  return out;
+}
+
+template <int ND, bool MIXED>
+using TabRow = typename std::conditional<MIXED, RowMixed<ND>, RowF64<ND>>::type;
+
+// The tables are `const __restrict__` kernel arguments, so the compiler reads their wave-uniform
+// rows with scalar loads.
+// Wavefronts per SIMD that the register budget must allow (as the bin loop alone needs): the
+// reduction and epilogue after the loop would otherwise let the compiler take registers that
+// cost a wavefront per SIMD. The in-kernel set-up needs more and is not bounded.
+template <int ND, bool MIXED, bool GRAD, bool SETUP, bool CUT>
+constexpr int eval_waves_per_eu() {
+  return (SETUP || CUT) ? 1 : (ND > 3 ? 1 : (MIXED ? (GRAD ? 5 : 8) : (GRAD ? 4 : 5)));
+}
+
+// CUT: the optional ISCO cut-off; every lane keeps only the bins at or below its point's ISCO
+// frequency (isco_bins over fgrid), the wavefront stops at the last bin any of its lanes keeps,
+// and <h|h> takes the kept bins' share of K_det from the per-detector running sums kcum
+// [ND][M + 1].
+template <int ND, bool MIXED, bool GRAD, bool SETUP, bool CUT>
+__global__ __launch_bounds__(WAVE * MAX_EVAL_WAVES)
+__attribute__((amdgpu_waves_per_eu(eval_waves_per_eu<ND, MIXED, GRAD, SETUP, CUT>()))) void k_eval(
+    const TabRow<ND, MIXED>* __restrict__ tab, const RowGradF64* __restrict__ gtab, const double* __restrict__ theta,
+    EventGeom geo, const EventConst* __restrict__ ec, const double* __restrict__ coef, int64_t B, int64_t Bp, int64_t M,
+    LoopShape sh, double* __restrict__ part, unsigned int* __restrict__ cnt, double* __restrict__ logl,
+    const double* __restrict__ fgrid, const double* __restrict__ kcum) {
+  constexpr int NZ = nz_of(ND, GRAD);
+  extern __shared__ double lds[];
+  double* rows_s = lds;                                        // [NCOEF][64] when SETUP
+  double* tail = lds + (SETUP ? NCOEF * WAVE : 0);             // table, then the reduction buffer
+  double2* tbl = reinterpret_cast<double2*>(tail);
+
+  const int bid = blockIdx.x;
+  const int item = (bid % NXCD) * sh.gper + bid / NXCD;        // dies take contiguous item ranges
+  if (item >= sh.items) return;                                // whole workgroup
+  const int g = item / sh.npg;
+  const int pg = item - g * sh.npg;
+  // the wavefront index is uniform across the wavefront; readfirstlane tells the compiler so, which
+  // keeps the chunk's bin range, and with it every table row, in scalar registers
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+  const int lane = (int)(threadIdx.x % WAVE);
+  const int64_t p = (int64_t)pg * WAVE + lane;
+  const int64_t pc = p < B ? p : B - 1;                        // padding lanes repeat the last point
+  const int64_t c = (int64_t)g * sh.W + w;
+  const int64_t k0l = c * sh.chunk;
+  const int k0 = (int)(k0l < M ? k0l : M);
+  int k1 = (int)(k0 + sh.chunk < M ? k0 + sh.chunk : M);
+  int kc = 0;
+  if constexpr (CUT) {
+    kc = isco_bins(theta[pc * NPARAM], theta[pc * NPARAM + 1], fgrid, M, *ec);
+    const int kmax = wave_max(kc);
+    k1 = k1 < kmax ? k1 : (kmax > k0 ? kmax : k0);
+  }
+
+  if constexpr (!MIXED) fill_phasor_table(tbl);
+  if constexpr (SETUP) {
+    if (w == 0) {
+      double th[NPARAM];
+#pragma unroll
+      for (int i = 0; i < NPARAM; ++i) th[i] = theta[pc * NPARAM + i];
+      double rows[NCOEF];
+      const bool valid = setup_rows<ND>(th, geo, ec, MIXED, rows);
+      const double nan = __builtin_nan("");
+#pragma unroll
+      for (int j = 0; j < NCOEF; ++j) rows_s[j * WAVE + lane] = valid ? rows[j] : nan;
+    }
+  }
+  if (SETUP || !MIXED) __syncthreads();
+
+  double a[NBASIS], T[ND];
+  double tot[NZ];
+  if constexpr (MIXED) {
+    float cr[ND], ci[ND];
+    if constexpr (SETUP) {
+#pragma unroll
+      for (int m = 0; m < NBASIS; ++m) a[m] = rows_s[(CO_A + m) * WAVE + lane];
+#pragma unroll
+      for (int d = 0; d < ND; ++d) {
+        T[d] = rows_s[(CO_T + d) * WAVE + lane];
+        cr[d] = GRAD ? (float)rows_s[(CO_CR + d) * WAVE + lane] : 0.0f;
+        ci[d] = GRAD ? (float)rows_s[(CO_CI + d) * WAVE + lane] : 0.0f;
+      }
+    } else {
+      load_coef<ND, float>(coef, Bp, pc, GRAD, a, T, cr, ci);
+    }
+    bin_loop_mixed<ND, GRAD, const TabRow<ND, MIXED>*, const RowGradF64*, CUT>(tab, gtab, k0, k1, a, T, cr, ci, tot,
+                                                                                kc);
+  } else {
+    double cr[ND], ci[ND];
+    if constexpr (SETUP) {
+#pragma unroll
+      for (int m = 0; m < NBASIS; ++m) a[m] = rows_s[(CO_A + m) * WAVE + lane];
+#pragma unroll
+      for (int d = 0; d < ND; ++d) {
+        T[d] = rows_s[(CO_T + d) * WAVE + lane];
+        cr[d] = GRAD ? rows_s[(CO_CR + d) * WAVE + lane] : 0.0;
+        ci[d] = GRAD ? rows_s[(CO_CI + d) * WAVE + lane] : 0.0;
+      }
+    } else {
+      load_coef<ND, double>(coef, Bp, pc, GRAD, a, T, cr, ci);
+    }
+    to_table_units<ND>(a, T);
+    bin_loop_f64<ND, GRAD, const TabRow<ND, MIXED>*, const RowGradF64*, CUT>(tab, gtab, k0, k1, a, T, cr, ci, tbl,
+                                                                              tot, kc);
+  }
+
+  // the W chunk sums of this workgroup, added in wavefront order by the first wavefront; the
+  // buffer reuses the phasor table's LDS, so every wavefront must be past its bin loop first
+  double* red = tail;
+  if (sh.W > 1) {
+#pragma unroll
+    for (int z0 = 0; z0 < NZ; z0 += RED_Z) {
+      __syncthreads();
+      if (w > 0) {
+#pragma unroll
+        for (int zz = 0; zz < RED_Z; ++zz)
+          if (z0 + zz < NZ) red[((w - 1) * RED_Z + zz) * WAVE + lane] = tot[z0 + zz];
+      }
+      __syncthreads();
+      if (w == 0) {
+        for (int v = 1; v < sh.W; ++v) {
+#pragma unroll
+          for (int zz = 0; zz < RED_Z; ++zz)
+            if (z0 + zz < NZ) tot[z0 + zz] += red[((v - 1) * RED_Z + zz) * WAVE + lane];
+        }
+      }
+    }
+  }
+  if (w != 0) return;
+
+  if (GRAD || sh.G > 1) {
+#pragma unroll
+    for (int z = 0; z < NZ; ++z) part[((int64_t)g * NZ + z) * Bp + p] = tot[z];
+  }
+  if constexpr (!GRAD) {
+    if (sh.G > 1) {
+      // the last of the point group's G workgroups adds the G partial sums in workgroup order
+      __threadfence();
+      const unsigned int prev = atomicAdd(&cnt[pg], lane == 0 ? 1u : 0u);
+      const unsigned int done = __builtin_amdgcn_readfirstlane(prev);
+      if (done + 1u != (unsigned int)sh.G) return;
+      __threadfence();
+#pragma unroll
+      for (int z = 0; z < NZ; ++z) tot[z] = 0.0;
+      for (int gg = 0; gg < sh.G; ++gg) {
+#pragma unroll
+        for (int z = 0; z < NZ; ++z) tot[z] += part[((int64_t)gg * NZ + z) * Bp + p];
+      }
+      if (lane == 0) cnt[pg] = 0u;                             // ready for the next call
+    }
+    EventConst e = *ec;
+    if constexpr (CUT) {
+#pragma unroll
+      for (int d = 0; d < ND; ++d) e.K[d] = kcum[(int64_t)d * (M + 1) + kc];
+    }
+    if (MIXED) apply_gain<ND>(e, tot);
+    double qr[ND], qi[ND], amp, c0f;
+    if constexpr (SETUP) {
+      amp = rows_s[CO_AMP * WAVE + lane];
+      c0f = rows_s[CO_C0 * WAVE + lane];
+#pragma unroll
+      for (int d = 0; d < ND; ++d) {
+        qr[d] = rows_s[(CO_QR + d) * WAVE + lane];
+        qi[d] = rows_s[(CO_QI + d) * WAVE + lane];
+      }
+    } else {
+      amp = coef[CO_AMP * Bp + pc];
+      c0f = coef[CO_C0 * Bp + pc];
+#pragma unroll
+      for (int d = 0; d < ND; ++d) {
+        qr[d] = coef[(CO_QR + d) * Bp + pc];
+        qi[d] = coef[(CO_QI + d) * Bp + pc];
+      }
+    }
+    if (p < B) logl[p] = value_from_rows<ND, NZ>(tot, amp, c0f, qr, qi, e, MIXED ? e.uref : 1.0);
+  }
+}
+
+template <int ND, bool MIXED, bool GRAD>
+static hipError_t eval_setup(bool setup, bool cut, const void* tab, const RowGradF64* gtab, const double* theta,
+                             const EventGeom& geo, const EventConst* ec, const double* coef, int64_t B, int64_t Bp,
+                             int64_t M, const LoopShape& sh, double* part, unsigned int* cnt, double* logl,
+                             const double* fgrid, const double* kcum, hipStream_t s) {
+  const dim3 grid((unsigned)(sh.gper * NXCD)), block((unsigned)(sh.W * WAVE));
+  const size_t lds = eval_lds_doubles(MIXED, sh) * sizeof(double);
+  const TabRow<ND, MIXED>* t = (const TabRow<ND, MIXED>*)tab;
+#define GWL_EVAL(ST, CU)                                                                                          \
+  hipLaunchKernelGGL((k_eval<ND, MIXED, GRAD, ST, CU>), grid, block, lds, s, t, gtab, theta, geo, ec, coef, B, Bp, M, \
+                     sh, part, cnt, logl, fgrid, kcum)
+  if (cut) {
+    if (setup) GWL_EVAL(true, true); else GWL_EVAL(false, true);
+  } else {
+    if (setup) GWL_EVAL(true, false); else GWL_EVAL(false, false);
+  }
+#undef GWL_EVAL
   return hipGetLastError();
 }
 
-hipError_t launch_bins(int nd, bool mixed, bool grad, const void* tab, const void* gtab, const void* gtab64,
-                       const double* coef, int64_t B, int64_t Bp, int64_t M, const LoopShape& sh, double* part,
-                       hipStream_t s) {
+template <int ND>
+static hipError_t eval_nd(bool mixed, bool grad, bool cut, const void* tab, const RowGradF64* gtab,
+                          const double* theta, const EventGeom& geo, const EventConst* ec, const double* coef,
+                          int64_t B, int64_t Bp, int64_t M, const LoopShape& sh, double* part, unsigned int* cnt,
+                          double* logl, const double* fgrid, const double* kcum, hipStream_t s) {
+  const bool st = sh.setup != 0;
+#define GWL_EV(MX, GR) \
+  return eval_setup<ND, MX, GR>(st, cut, tab, gtab, theta, geo, ec, coef, B, Bp, M, sh, part, cnt, logl, fgrid, kcum, s)
+  if (mixed) {
+    if (grad) GWL_EV(true, true);
+    GWL_EV(true, false);
+  }
+  if (grad) GWL_EV(false, true);
+  GWL_EV(false, false);
+#undef GWL_EV
+}
+
+hipError_t launch_eval(int nd, bool mixed, bool grad, const void* tab, const RowGradF64* gtab, const double* theta,
+                       const EventGeom& geo, const EventConst* ec, const double* coef, int64_t B, int64_t Bp,
+                       int64_t M, const LoopShape& sh, double* part, unsigned int* cnt, double* logl,
+                       const double* fgrid, const double* kcum, hipStream_t s) {
+  if (sh.W < 1 || sh.W > MAX_EVAL_WAVES || sh.G < 1) return hipErrorInvalidValue;
+  if ((grad || sh.G > 1) && !part) return hipErrorInvalidValue;
+  if (!grad && sh.G > 1 && !cnt) return hipErrorInvalidValue;
+  if (!sh.setup && !coef) return hipErrorInvalidValue;
+  const bool cut = fgrid != nullptr;
+  if (cut && !kcum) return hipErrorInvalidValue;
   switch (nd) {
-    case 1: return bins_nd<1>(mixed, grad, tab, gtab, gtab64, coef, B, Bp, M, sh, part, s);
-    case 2: return bins_nd<2>(mixed, grad, tab, gtab, gtab64, coef, B, Bp, M, sh, part, s);
-    case 3: return bins_nd<3>(mixed, grad, tab, gtab, gtab64, coef, B, Bp, M, sh, part, s);
-    case 4: return bins_nd<4>(mixed, grad, tab, gtab, gtab64, coef, B, Bp, M, sh, part, s);
+    case 1: return eval_nd<1>(mixed, grad, cut, tab, gtab, theta, geo, ec, coef, B, Bp, M, sh, part, cnt, logl, fgrid, kcum, s);
+    case 2: return eval_nd<2>(mixed, grad, cut, tab, gtab, theta, geo, ec, coef, B, Bp, M, sh, part, cnt, logl, fgrid, kcum, s);
+    case 3: return eval_nd<3>(mixed, grad, cut, tab, gtab, theta, geo, ec, coef, B, Bp, M, sh, part, cnt, logl, fgrid, kcum, s);
+    case 4: return eval_nd<4>(mixed, grad, cut, tab, gtab, theta, geo, ec, coef, B, Bp, M, sh, part, cnt, logl, fgrid, kcum, s);
   }
   return hipErrorInvalidValue;
 }

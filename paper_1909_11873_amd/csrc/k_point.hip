@@ -1,8 +1,10 @@
 // Per-point kernels: set-up (phase coefficients, time shifts, projection factors) before the
-// bin loop, and the float64 epilogue after it (the log-likelihood ratio of Eq. 2 and, for the
-// adjoint, its gradient with respect to all 11 parameters).
+// evaluation kernel, and the adjoint's float64 epilogue after it (the log-likelihood ratio of
+// Eq. 2 and its gradient with respect to all 11 parameters; the value alone is finished inside
+// the evaluation kernel).
 #include <hip/hip_runtime.h>
 
+#include "gwl_bins.h"
 #include "gwl_common.h"
 #include "gwl_device.h"
 #include "gwl_epilogue.h"
@@ -46,41 +48,30 @@ hipError_t launch_setup(int nd, const EventGeom& g, const EventConst* ec, bool s
   return hipGetLastError();
 }
 
-// The value epilogue takes EPI_SPLIT lanes per point for the chunk sums: with one thread per
-// point a batch of a few thousand points fills a few dozen CUs, each thread walking every chunk.
-constexpr int EPI_SPLIT = 4;
-
-template <int ND>
-__global__ __launch_bounds__(PT_BLOCK) void k_epilogue(const EventConst* __restrict__ ec,
-                                                       const double* __restrict__ coef, int64_t B, int64_t Bp,
-                                                       int nchunk, bool scaled, const double* __restrict__ part,
-                                                       double* __restrict__ logl) {
-  const int64_t p = ((int64_t)blockIdx.x * PT_BLOCK + threadIdx.x) / EPI_SPLIT;
-  const int sub = threadIdx.x & (EPI_SPLIT - 1);
-  constexpr int NZ = nz_of(ND, false);
-  double acc[NZ];
-  gather_split<NZ, EPI_SPLIT>(part, nchunk, Bp, p, sub, p < B, acc);
-  if (p >= B || sub != 0) return;
-  const EventConst e = *ec;
-  if (scaled) apply_gain<ND>(e, acc);
-  logl[p] = epilogue_value_rows<ND, NZ>(acc, coef, Bp, p, e, scaled ? e.uref : 1.0);
-}
-
+// With the ISCO cut-off (fgrid and kcum given), <h|h> takes the kept bins' share of K_det; the
+// cut moves with the masses in steps, so it adds nothing to the derivative.
 template <int ND>
 __global__ __launch_bounds__(PT_BLOCK) void k_epilogue_grad(EventGeom g, const EventConst* __restrict__ ec,
                                                             const double* __restrict__ theta, int64_t B, int64_t Bp,
                                                             int nchunk, bool scaled, const double* __restrict__ part,
-                                                            double* __restrict__ logl, double* __restrict__ grad) {
+                                                            double* __restrict__ logl, double* __restrict__ grad,
+                                                            const double* __restrict__ fgrid,
+                                                            const double* __restrict__ kcum, int64_t M) {
   const int64_t p = (int64_t)blockIdx.x * PT_BLOCK + threadIdx.x;
   if (p >= B) return;
   constexpr int NZ = nz_of(ND, true);
-  const EventConst e = *ec;
+  EventConst e = *ec;
   double acc[NZ];
   gather<NZ>(part, nchunk, Bp, p, acc);
   if (scaled) apply_gain<ND>(e, acc);
   double th[NPARAM], gout[NPARAM];
 #pragma unroll
   for (int i = 0; i < NPARAM; ++i) th[i] = theta[p * NPARAM + i];
+  if (fgrid) {
+    const int kc = isco_bins(th[0], th[1], fgrid, M, e);
+#pragma unroll
+    for (int d = 0; d < ND; ++d) e.K[d] = kcum[(int64_t)d * (M + 1) + kc];
+  }
   bool valid;
   const double v = epilogue_gradient<ND>(acc, th, g, e, scaled ? e.uref : 1.0, valid, gout);
   const double nan = __builtin_nan("");
@@ -90,18 +81,14 @@ __global__ __launch_bounds__(PT_BLOCK) void k_epilogue_grad(EventGeom g, const E
 }
 
 hipError_t launch_epilogue(int nd, bool grad, bool scaled, const EventGeom& g, const EventConst* ec, const double* theta,
-                           const double* coef, int64_t B, int64_t Bp, int nchunk, const double* part, double* logl,
-                           double* gradout, hipStream_t s) {
+                           const double*, int64_t B, int64_t Bp, int nchunk, const double* part, double* logl,
+                           double* gradout, hipStream_t s, const double* fgrid, const double* kcum, int64_t M) {
+  if (!grad) return hipErrorInvalidValue;  // the value's epilogue runs in the evaluation kernel
   dim3 grid((unsigned)((B + PT_BLOCK - 1) / PT_BLOCK));
-  dim3 grid_split((unsigned)((B * EPI_SPLIT + PT_BLOCK - 1) / PT_BLOCK));
 #define GWL_EPI(N)                                                                                                  \
   case N:                                                                                                           \
-    if (grad)                                                                                                       \
-      hipLaunchKernelGGL(k_epilogue_grad<N>, grid, dim3(PT_BLOCK), 0, s, g, ec, theta, B, Bp, nchunk, scaled, part, \
-                         logl, gradout);                                                                            \
-    else                                                                                                            \
-      hipLaunchKernelGGL(k_epilogue<N>, grid_split, dim3(PT_BLOCK), 0, s, ec, coef, B, Bp, nchunk, scaled, part,    \
-                         logl);                                                                                     \
+    hipLaunchKernelGGL(k_epilogue_grad<N>, grid, dim3(PT_BLOCK), 0, s, g, ec, theta, B, Bp, nchunk, scaled, part,   \
+                       logl, gradout, fgrid, kcum, M);                                                              \
     break;
   switch (nd) {
     GWL_EPI(1)

@@ -72,6 +72,9 @@ __global__ void k_multi_reset(MultiCtl* __restrict__ ctl, unsigned int* __restri
   }
 }
 
+// device clock stamp (a calibrated event's completion)
+__global__ void k_multi_stamp(unsigned long long* __restrict__ t) { *t = wall_clock64(); }
+
 template <int ND>
 __global__ __launch_bounds__(MULTI_PT_BLOCK) void k_multi_setup(const MultiEvDev* __restrict__ evs,
                                                                  const EventGeom* __restrict__ geoms,
@@ -200,6 +203,8 @@ struct gwl_plan_s {
   bool mixed = false, grad = false;
   bool anyf64 = false;         // a mixed plan with float64 (relative-binning) events
   std::vector<int64_t> B;
+  std::vector<gwl_event> evs;  // the events (event order)
+  std::vector<int> cal;        // calibrated events (event index): their own kernels, after the graph
   std::vector<int> order;      // queue position -> event index
   int total = 0, grid = 0, nptblk = 0, chunk = 0;
   bool descending = false;     // queue order: events by descending work instead of ascending
@@ -255,9 +260,10 @@ hipError_t enqueue_multi_nd(gwl_plan pl, hipStream_t s) {
   const int* blk_ev = pl->d_blk;
   const int* blk_p0 = pl->d_blk + pl->nptblk;
   hipLaunchKernelGGL(gwl::k_multi_reset, dim3((E + 255) / 256), dim3(256), 0, s, c, done, tev, E);
-  hipLaunchKernelGGL(gwl::k_multi_setup<ND>, dim3(pl->nptblk), dim3(gwl::MULTI_PT_BLOCK), 0, s,
-                     (const gwl::MultiEvDev*)pl->d_evs, (const gwl::EventGeom*)pl->d_geoms,
-                     (const gwl::MultiIODev*)pl->d_io, blk_ev, blk_p0);
+  if (pl->nptblk > 0)   // no point outside calibrated events: only the reset and the (empty) queue
+    hipLaunchKernelGGL(gwl::k_multi_setup<ND>, dim3(pl->nptblk), dim3(gwl::MULTI_PT_BLOCK), 0, s,
+                       (const gwl::MultiEvDev*)pl->d_evs, (const gwl::EventGeom*)pl->d_geoms,
+                       (const gwl::MultiIODev*)pl->d_io, blk_ev, blk_p0);
 #define GWL_MB(MX, GR, AF)                                                                                         \
   hipLaunchKernelGGL((gwl::k_multi_bins<ND, MX, GR, AF>), dim3(pl->grid), dim3(gwl::BLOCK), 0, s,               \
                      (const gwl::MultiEvDev*)pl->d_evs, E, pl->total, (const gwl::MultiIODev*)pl->d_io, c, done, tev)
@@ -271,6 +277,7 @@ hipError_t enqueue_multi_nd(gwl_plan pl, hipStream_t s) {
     if (pl->grad) GWL_MB(false, true, false); else GWL_MB(false, false, false);
   }
 #undef GWL_MB
+  if (pl->nptblk == 0) return hipGetLastError();
   if (pl->grad)
     hipLaunchKernelGGL((gwl::k_multi_epilogue<ND, true>), dim3(pl->nptblk), dim3(gwl::MULTI_PT_BLOCK), 0, s,
                        (const gwl::MultiEvDev*)pl->d_evs, (const gwl::EventGeom*)pl->d_geoms,
@@ -334,7 +341,7 @@ gwl_status build_plan(const gwl_event* evs, int E, const int64_t* B_e, gwl_preci
   for (int e = 0; e < E; ++e) {
     if (!evs[e]) return fail(GWL_E_INVALID, "event %d is null", e);
     if (evs[e]->ndet != nd) return fail(GWL_E_UNSUPPORTED, "events must share one detector count");
-    if (evs[e]->ncal > 0) return fail(GWL_E_UNSUPPORTED, "event %d has a calibration model: not in multi-event plans", e);
+    if (evs[e]->ech.isco) return fail(GWL_E_UNSUPPORTED, "event %d has the ISCO cut-off: not in multi-event plans", e);
     if (evs[e]->device != evs[0]->device) return fail(GWL_E_INVALID, "events must live on one device");
     if (B_e[e] < 0 || B_e[e] > kMaxBatch) return fail(GWL_E_SHAPE, "B_e[%d]=%lld out of range", e, (long long)B_e[e]);
   }
@@ -351,6 +358,9 @@ gwl_status build_plan(const gwl_event* evs, int E, const int64_t* B_e, gwl_preci
   pl->mixed = prec == GWL_MIXED;
   pl->grad = with_grad != 0;
   pl->B.assign(B_e, B_e + E);
+  pl->evs.assign(evs, evs + E);
+  for (int e = 0; e < E; ++e)
+    if (evs[e]->ncal > 0) pl->cal.push_back(e);
   // a mixed plan runs its relative-binning events on the float64 loop, as single calls do
   for (int e = 0; e < E; ++e) pl->anyf64 |= pl->mixed && !use_mixed(evs[e], prec);
 
@@ -372,7 +382,7 @@ gwl_status build_plan(const gwl_event* evs, int E, const int64_t* B_e, gwl_preci
   auto items_for = [&](int chunk) {
     int64_t n = 0;
     for (int e = 0; e < E; ++e) {
-      if (B_e[e] == 0) continue;
+      if (B_e[e] == 0 || evs[e]->ncal > 0) continue;
       n += ((B_e[e] + WAVE - 1) / WAVE) * ((evs[e]->M + chunk - 1) / chunk);
     }
     return n;
@@ -414,7 +424,7 @@ gwl_status build_plan(const gwl_event* evs, int E, const int64_t* B_e, gwl_preci
     const gwl_event ev = evs[e];
     MultiEvDev& d = hev[q];
     memset(&d, 0, sizeof d);
-    const int64_t B = B_e[e];
+    const int64_t B = evs[e]->ncal > 0 ? 0 : B_e[e];   // calibrated events are not in the queue
     d.npg = (int)((B + WAVE - 1) / WAVE);
     d.Bp = (int64_t)d.npg * WAVE;
     d.M = (int)ev->M;
@@ -528,12 +538,27 @@ gwl_status gwl_multi_launch(gwl_plan pl, const double* const* theta, double* con
     pl->h_io[q].theta = theta[e];
     pl->h_io[q].logl = logl[e];
     pl->h_io[q].grad = pl->grad ? grad[e] : nullptr;
-    pl->h_io[q].B = pl->B[e];
+    pl->h_io[q].B = pl->evs[e]->ncal > 0 ? 0 : pl->B[e];
   }
   err = hipMemcpyAsync(pl->d_io, pl->h_io, sizeof(MultiIODev) * pl->E, hipMemcpyHostToDevice, s);
   if (err == hipSuccess) err = hipEventRecord(pl->io_done, s);
   if (err == hipSuccess) err = hipGraphLaunch(pl->exec, s);
   if (err != hipSuccess) return hip_fail(err, "multi-event launch");
+  // calibrated events: their own set-up, bin-loop and epilogue kernels on the same stream, each
+  // followed by a clock stamp in the event's slot
+  unsigned long long* tev_dev = (unsigned long long*)((unsigned char*)pl->d_ctl + sizeof(MultiCtl) +
+                                                      sizeof(unsigned int) * (size_t)((pl->E + 1) & ~1));
+  for (int e : pl->cal) {
+    if (pl->B[e] == 0) continue;
+    st = run_calibrated(pl->evs[e], theta[e], pl->B[e], pl->mixed && use_mixed(pl->evs[e], GWL_MIXED), pl->grad,
+                        logl[e], pl->grad ? grad[e] : nullptr, s);
+    if (st != GWL_OK) return st;
+    int q = 0;
+    while (pl->order[q] != e) ++q;
+    hipLaunchKernelGGL(k_multi_stamp, dim3(1), dim3(1), 0, s, tev_dev + q);
+    err = hipGetLastError();
+    if (err != hipSuccess) return hip_fail(err, "multi-event launch");
+  }
   if (event_latency_us) {
     const unsigned char* ctl = (const unsigned char*)pl->d_ctl;
     const size_t tev_off = sizeof(MultiCtl) + sizeof(unsigned int) * (size_t)((pl->E + 1) & ~1);
@@ -546,13 +571,15 @@ gwl_status gwl_multi_launch(gwl_plan pl, const double* const* theta, double* con
     if (err != hipSuccess) return hip_fail(err, "latency read-back");
     const unsigned long long t0 = pl->h_stamps[0], tend = pl->h_stamps[1];
     unsigned long long tbins = t0;
-    for (int q = 0; q < pl->E; ++q) tbins = std::max(tbins, pl->h_stamps[2 + q]);
+    for (int q = 0; q < pl->E; ++q)
+      if (pl->evs[pl->order[q]]->ncal == 0) tbins = std::max(tbins, pl->h_stamps[2 + q]);
     // an event's results exist once its last item is done and the final epilogue launch has run
     const double epi_us = tend > tbins ? (double)(tend - tbins) * 1e3 / pl->clock_khz : 0.0;
     for (int q = 0; q < pl->E; ++q) {
       const int e = pl->order[q];
       const unsigned long long te = pl->h_stamps[2 + q];
-      event_latency_us[e] = pl->B[e] == 0 ? 0.0 : (double)(te - t0) * 1e3 / pl->clock_khz + epi_us;
+      const double extra = pl->evs[e]->ncal > 0 ? 0.0 : epi_us;   // calibrated: stamped after its epilogue
+      event_latency_us[e] = pl->B[e] == 0 ? 0.0 : (double)(te - t0) * 1e3 / pl->clock_khz + extra;
     }
   }
   return GWL_OK;

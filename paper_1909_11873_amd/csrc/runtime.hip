@@ -89,6 +89,45 @@ gwl_status check_device(int dev) {
 
 }  // namespace gwl
 
+namespace gwl {
+
+// Tables of the optional ISCO cut-off, built on the host in float64 (once per event): the grid
+// (which must increase) and per detector the running sums Kc[k] = sum_{j < k} 4 df f_j^(-7/3) / S_j,
+// k = 0..M, so that <h|h> of a point cut after its first kc bins is A^2 |Q_det|^2 Kc[kc].
+static gwl_status isco_tables(gwl_event ev, const double* fgrid, const double* psd, hipStream_t s) {
+  const int64_t M = ev->M;
+  const int nd = ev->ndet;
+  std::vector<double> f((size_t)M), ps((size_t)M * nd);
+  hipError_t e = hipMemcpyAsync(f.data(), fgrid, sizeof(double) * M, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(ps.data(), psd, sizeof(double) * M * nd, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "grid read-back");
+  for (int64_t k = 1; k < M; ++k)
+    if (!(f[(size_t)k] > f[(size_t)k - 1]))
+      return fail(GWL_E_INVALID, "the ISCO cut-off needs an increasing frequency grid (bin %lld)", (long long)k);
+  std::vector<double> kc((size_t)(M + 1) * nd);
+  for (int d = 0; d < nd; ++d) {
+    double acc = 0.0;
+    kc[(size_t)d * (M + 1)] = 0.0;
+    for (int64_t k = 0; k < M; ++k) {
+      acc += 4.0 * ev->df * pow(f[(size_t)k], -7.0 / 3.0) / ps[(size_t)d * M + k];
+      kc[(size_t)d * (M + 1) + k + 1] = acc;
+    }
+  }
+  e = hipMalloc((void**)&ev->fgrid, sizeof(double) * M);
+  if (e == hipSuccess) e = hipMalloc((void**)&ev->kcum, sizeof(double) * kc.size());
+  if (e == hipSuccess) e = hipMemcpy(ev->fgrid, f.data(), sizeof(double) * M, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(ev->kcum, kc.data(), sizeof(double) * kc.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "ISCO tables");
+  ev->ech.isco = 1;
+  ev->ech.grid_df = M > 1 ? (f[(size_t)M - 1] - f[0]) / (double)(M - 1) : 1.0;
+  e = hipMemcpy(ev->ec, &ev->ech, sizeof(EventConst), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "ISCO tables");
+  return GWL_OK;
+}
+
+}  // namespace gwl
+
 // ------------------------------------------------------------------------------------------------
 // C ABI
 // ------------------------------------------------------------------------------------------------
@@ -107,7 +146,7 @@ gwl_status gwl_event_create(const double* data, const double* psd, const gwl_det
   if (!data || !psd || !fgrid) return fail(GWL_E_INVALID, "data, psd and fgrid must be device pointers");
   if (M < 1 || M > (int64_t)1 << 30) return fail(GWL_E_SHAPE, "M=%lld outside [1, 2^30]", (long long)M);
   if (!(df > 0.0) || !isfinite(df)) return fail(GWL_E_INVALID, "df must be finite and positive");
-  if (flags != 0) return fail(GWL_E_UNSUPPORTED, "flags=0x%x: no flags are implemented", flags);
+  if (flags & ~(unsigned)GWL_F_ISCO_CUTOFF) return fail(GWL_E_UNSUPPORTED, "flags=0x%x: unknown flags", flags);
   EventGeom g;
   gwl_status st = make_geom(dets, ndet, gmst, g);
   if (st != GWL_OK) return st;
@@ -148,6 +187,13 @@ gwl_status gwl_event_create(const double* data, const double* psd, const gwl_det
     return fail(GWL_E_INVALID, "rejected inputs: every PSD value and frequency must be finite and positive and "
                                "every data value finite");
   }
+  if (flags & GWL_F_ISCO_CUTOFF) {
+    st = isco_tables(ev, fgrid, psd, s);
+    if (st != GWL_OK) {
+      gwl_event_destroy(ev);
+      return st;
+    }
+  }
   *out = ev;
   return GWL_OK;
 }
@@ -185,6 +231,8 @@ gwl_status gwl_event_create_rb(const double* data, const double* psd, const gwl_
   for (int i = 0; i < NPARAM; ++i)
     if (!isfinite(theta_fid[i])) return fail(GWL_E_INVALID, "theta_fid[%d] is not finite", i);
   if (!(eps > 0.0) || !isfinite(eps)) return fail(GWL_E_INVALID, "eps must be finite and positive");
+  if (flags & GWL_F_ISCO_CUTOFF)
+    return fail(GWL_E_UNSUPPORTED, "the ISCO cut-off is not available with relative binning");
   gwl_event ev = nullptr;
   gwl_status st = gwl_event_create(data, psd, dets, ndet, fgrid, M, df, gmst, flags, stream, &ev);
   if (st != GWL_OK) return st;
@@ -266,6 +314,7 @@ gwl_status gwl_event_create_rb(const double* data, const double* psd, const gwl_
   ev->g64 = g64;
   ev->M_full = ev->M;
   ev->M = nedge;
+  ev->rb_idx = idx;
   *out = ev;
   return GWL_OK;
 }
@@ -346,27 +395,26 @@ static void cal_tables(const std::vector<double>& f, const std::vector<double>& 
   }
 }
 
-gwl_status gwl_event_create_cal(const double* data, const double* psd, const gwl_detector* dets, int ndet,
-                                const double* fgrid, int64_t M, double df, double gmst, int nnode, unsigned flags,
-                                void* stream, gwl_event* out) {
-  clear_error();
-  if (!out) return fail(GWL_E_INVALID, "out is null");
-  *out = nullptr;
-  if (nnode < 4 || nnode > MAXNODE) return fail(GWL_E_SHAPE, "nnode=%d outside [4, %d]", nnode, MAXNODE);
-  gwl_event ev = nullptr;
-  gwl_status st = gwl_event_create(data, psd, dets, ndet, fgrid, M, df, gmst, flags, stream, &ev);
-  if (st != GWL_OK) return st;
-  hipStream_t s = (hipStream_t)stream;
-  std::vector<double> fh((size_t)M), ph((size_t)M * ndet);
-  hipError_t e = hipMemcpyAsync(fh.data(), fgrid, sizeof(double) * M, hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(ph.data(), psd, sizeof(double) * M * ndet, hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) {
-    gwl_event_destroy(ev);
-    return hip_fail(e, "grid read-back");
-  }
-  std::vector<double> w, tl, kc, basis;
-  cal_tables(fh, ph, ndet, df, nnode, w, tl, ev->cal_j0, ev->cal_kb, kc);
+}  // extern "C"
+
+namespace gwl {
+
+// Attach calibration tables to an event whose bin loop walks rows at the frequencies `frow`
+// (the grid itself, or relative-binning edges): per row the spline weights of its window and its
+// position in its node interval, the interval starts in rows, the per-interval cubic basis; the
+// spline moments K1, K2 of <h_cal|h_cal> always over every grid bin (fgrid, psd).
+static gwl_status attach_cal(gwl_event ev, const std::vector<double>& frow, const std::vector<double>& fgrid,
+                             const std::vector<double>& psd, int nnode) {
+  const int ndet = ev->ndet;
+  const int64_t M = (int64_t)frow.size();
+  std::vector<double> w, tl, kc, kc_rows, basis, wfull, tfull;
+  int j0full[MAXNODE];
+  int64_t kbfull[MAXNODE];
+  // the rows' weights (their spline moments are not used: any positive PSD will do), then the
+  // moments over the grid
+  const std::vector<double> psd_rows((size_t)M * ndet, 1.0);
+  cal_tables(frow, psd_rows, ndet, ev->df, nnode, w, tl, ev->cal_j0, ev->cal_kb, kc_rows);
+  cal_tables(fgrid, psd, ndet, ev->df, nnode, wfull, tfull, j0full, kbfull, kc);
   cal_basis(nnode, ev->cal_j0, basis);
   std::vector<RowCal32> w32((size_t)M);
   for (int64_t k = 0; k < M; ++k)
@@ -378,7 +426,7 @@ gwl_status gwl_event_create_cal(const double* data, const double* psd, const gwl
   w.resize((size_t)(M + TAB_PAD) * 4, 0.0);
   tl.resize((size_t)(M + TAB_PAD), 0.0);
   std::vector<float> t32(tl.begin(), tl.end());
-  e = hipMalloc((void**)&ev->cal32, sizeof(RowCal32) * (M + TAB_PAD));
+  hipError_t e = hipMalloc((void**)&ev->cal32, sizeof(RowCal32) * (M + TAB_PAD));
   if (e == hipSuccess) e = hipMalloc((void**)&ev->cal64, sizeof(RowCal64) * (M + TAB_PAD));
   if (e == hipSuccess) e = hipMalloc((void**)&ev->calt32, sizeof(float) * (M + TAB_PAD));
   if (e == hipSuccess) e = hipMalloc((void**)&ev->calt64, sizeof(double) * (M + TAB_PAD));
@@ -390,19 +438,80 @@ gwl_status gwl_event_create_cal(const double* data, const double* psd, const gwl
   if (e == hipSuccess) e = hipMemcpy(ev->calt64, tl.data(), sizeof(double) * (M + TAB_PAD), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(ev->calB, basis.data(), sizeof(double) * basis.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(ev->kcal, kc.data(), sizeof(double) * kc.size(), hipMemcpyHostToDevice);
-  if (e != hipSuccess) {
-    gwl_event_destroy(ev);
-    return hip_fail(e, "calibration tables");
-  }
+  if (e != hipSuccess) return hip_fail(e, "calibration tables");
   ev->ncal = nnode;
+  return GWL_OK;
+}
+
+static gwl_status read_grid(const double* fgrid, const double* psd, int ndet, int64_t M, hipStream_t s,
+                            std::vector<double>& fh, std::vector<double>& ph) {
+  fh.resize((size_t)M);
+  ph.resize((size_t)M * ndet);
+  hipError_t e = hipMemcpyAsync(fh.data(), fgrid, sizeof(double) * M, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(ph.data(), psd, sizeof(double) * M * ndet, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "grid read-back");
+  return GWL_OK;
+}
+
+}  // namespace gwl
+
+extern "C" {
+
+gwl_status gwl_event_create_cal(const double* data, const double* psd, const gwl_detector* dets, int ndet,
+                                const double* fgrid, int64_t M, double df, double gmst, int nnode, unsigned flags,
+                                void* stream, gwl_event* out) {
+  clear_error();
+  if (!out) return fail(GWL_E_INVALID, "out is null");
+  *out = nullptr;
+  if (nnode < 4 || nnode > MAXNODE) return fail(GWL_E_SHAPE, "nnode=%d outside [4, %d]", nnode, MAXNODE);
+  if (flags & GWL_F_ISCO_CUTOFF)
+    return fail(GWL_E_UNSUPPORTED, "the ISCO cut-off is not available with the calibration model");
+  gwl_event ev = nullptr;
+  gwl_status st = gwl_event_create(data, psd, dets, ndet, fgrid, M, df, gmst, flags, stream, &ev);
+  if (st != GWL_OK) return st;
+  std::vector<double> fh, ph;
+  st = read_grid(fgrid, psd, ndet, M, (hipStream_t)stream, fh, ph);
+  if (st == GWL_OK) st = attach_cal(ev, fh, fh, ph, nnode);
+  if (st != GWL_OK) {
+    gwl_event_destroy(ev);
+    return st;
+  }
+  *out = ev;
+  return GWL_OK;
+}
+
+gwl_status gwl_event_create_rb_cal(const double* data, const double* psd, const gwl_detector* dets, int ndet,
+                                   const double* fgrid, int64_t M, double df, double gmst, const double* theta_fid,
+                                   double eps, int nnode, unsigned flags, void* stream, gwl_event* out) {
+  clear_error();
+  if (!out) return fail(GWL_E_INVALID, "out is null");
+  *out = nullptr;
+  if (nnode < 4 || nnode > MAXNODE) return fail(GWL_E_SHAPE, "nnode=%d outside [4, %d]", nnode, MAXNODE);
+  gwl_event ev = nullptr;
+  gwl_status st = gwl_event_create_rb(data, psd, dets, ndet, fgrid, M, df, gmst, theta_fid, eps, flags, stream, &ev);
+  if (st != GWL_OK) return st;
+  std::vector<double> fh, ph;
+  st = read_grid(fgrid, psd, ndet, M, (hipStream_t)stream, fh, ph);
+  if (st == GWL_OK) {
+    std::vector<double> fe(ev->rb_idx.size());
+    for (size_t i = 0; i < fe.size(); ++i) fe[i] = fh[(size_t)ev->rb_idx[i]];
+    st = attach_cal(ev, fe, fh, ph, nnode);
+  }
+  if (st != GWL_OK) {
+    gwl_event_destroy(ev);
+    return st;
+  }
   *out = ev;
   return GWL_OK;
 }
 
 gwl_status gwl_event_destroy(gwl_event ev) {
   if (!ev) return GWL_OK;
-  for (gwl_workspace& w : ev->ws)
+  for (gwl_workspace& w : ev->ws) {
     if (w.ptr) (void)hipFree(w.ptr);
+    if (w.cnt) (void)hipFree(w.cnt);
+  }
   ev->ws.clear();
   if (ev->cal32) (void)hipFree(ev->cal32);
   if (ev->cal64) (void)hipFree(ev->cal64);
@@ -414,6 +523,8 @@ gwl_status gwl_event_destroy(gwl_event ev) {
   if (ev->tab32) (void)hipFree(ev->tab32);
   if (ev->g32) (void)hipFree(ev->g32);
   if (ev->g64) (void)hipFree(ev->g64);
+  if (ev->fgrid) (void)hipFree(ev->fgrid);
+  if (ev->kcum) (void)hipFree(ev->kcum);
   if (ev->ec) (void)hipFree(ev->ec);
   delete ev;
   return GWL_OK;
@@ -446,10 +557,13 @@ static gwl_status run_logl_cal(gwl_event ev, const double* theta, int64_t B, boo
   sh.npg = (int)((B + WAVE - 1) / WAVE);
   // chunks of about M / want bins, none crossing a node interval (intervals in ln f hold very
   // different numbers of bins, so each is cut into its own number of pieces)
-  // forward: the plain loop's tuned chunk count (the calibrated loop differs only by its per-bin
-  // spline); adjoint: the heuristic, since each of its chunks writes 11 N_det + 8 partial sums per
-  // point and more chunks measured slower
-  const int tuned = grad ? heuristic_nchunk(B, ev->M) : choose_nchunk(ev, B, mixed, false);
+  // forward: about six rounds of 8192 wavefronts (on the c1 shapes 48 chunks per point group, the
+  // count the uncalibrated loop's tuning found best for its own chunked launch, which the calibrated
+  // loop keeps; fewer left the chip's second round of wavefronts partly empty); adjoint: the
+  // heuristic, since each of its chunks writes 11 N_det + 8 partial sums per point and more chunks
+  // measured slower
+  const int tuned = grad ? heuristic_nchunk(B, ev->M)
+                         : (int)std::min<int64_t>(ev->M, (6 * 8192 + sh.npg - 1) / sh.npg);
   const int want = std::min(tuned, MAXCALCHUNK - (n - 1));
   const int64_t target = std::max<int64_t>(1, (ev->M + want - 1) / want);
   int nc = 0;
@@ -472,7 +586,7 @@ static gwl_status run_logl_cal(gwl_event ev, const double* theta, int64_t B, boo
   const int nchunk = sh.nchunk, ncal = 2 * n * nd;
   const size_t bytes = sizeof(double) * ((size_t)NCOEF * Bp + (size_t)ncal * Bp + (size_t)nchunk * nz_cal(nd, grad) * Bp);
   void* ws = nullptr;
-  gwl_status st = event_workspace(ev, s, bytes, &ws);
+  gwl_status st = event_workspace(ev, s, bytes, 0, &ws);
   if (st != GWL_OK) return st;
   double* coef = (double*)ws;
   double* calc = coef + (size_t)NCOEF * Bp;
@@ -498,7 +612,7 @@ static gwl_status logl_common(gwl_event ev, const double* theta, int64_t B, gwl_
   if (st != GWL_OK) return st;
   const bool mixed = use_mixed(ev, prec);
   if (ev->ncal > 0) return run_logl_cal(ev, theta, B, mixed, with_grad, logl, grad, (hipStream_t)stream);
-  const LoopShape sh = make_shape(B, ev->M, choose_nchunk(ev, B, mixed, with_grad));
+  const LoopShape sh = choose_shape(ev, B, mixed, with_grad);
   return run_logl(ev, theta, B, mixed, with_grad, sh, logl, grad, (hipStream_t)stream);
 }
 
@@ -521,8 +635,9 @@ gwl_status gwl_event_reserve(gwl_event ev, int64_t B, gwl_precision prec, int wi
   gwl_status st = check_device(ev->device);
   if (st != GWL_OK) return st;
   void* ws = nullptr;
-  return event_workspace(ev, (hipStream_t)stream, call_workspace_bytes(ev, B, use_mixed(ev, prec), with_grad != 0),
-                         &ws);
+  const bool mixed = use_mixed(ev, prec), grad = with_grad != 0;
+  const size_t ncnt = ev->ncal > 0 ? 0 : workspace_counters(choose_shape(ev, B, mixed, grad), grad);
+  return event_workspace(ev, (hipStream_t)stream, call_workspace_bytes(ev, B, mixed, grad), ncnt, &ws);
 }
 
 gwl_status gwl_launch_shape(gwl_event ev, int64_t B, gwl_precision prec, int with_grad, int* nchunk,
@@ -531,9 +646,22 @@ gwl_status gwl_launch_shape(gwl_event ev, int64_t B, gwl_precision prec, int wit
   if (!ev) return fail(GWL_E_INVALID, "event is null");
   if (B < 1 || B > kMaxBatch) return fail(GWL_E_SHAPE, "B=%lld outside [1, %lld]", (long long)B, (long long)kMaxBatch);
   if (prec != GWL_FP64 && prec != GWL_MIXED) return fail(GWL_E_INVALID, "unknown precision %d", (int)prec);
-  const LoopShape sh = make_shape(B, ev->M, choose_nchunk(ev, B, use_mixed(ev, prec), with_grad != 0));
+  const LoopShape sh = choose_shape(ev, B, use_mixed(ev, prec), with_grad != 0);
   if (nchunk) *nchunk = sh.nchunk;
   if (chunk_bins) *chunk_bins = sh.chunk;
+  return GWL_OK;
+}
+
+gwl_status gwl_launch_layout(gwl_event ev, int64_t B, gwl_precision prec, int with_grad, int* waves, int* groups,
+                             int* setup) {
+  clear_error();
+  if (!ev) return fail(GWL_E_INVALID, "event is null");
+  if (B < 1 || B > kMaxBatch) return fail(GWL_E_SHAPE, "B=%lld outside [1, %lld]", (long long)B, (long long)kMaxBatch);
+  if (prec != GWL_FP64 && prec != GWL_MIXED) return fail(GWL_E_INVALID, "unknown precision %d", (int)prec);
+  const LoopShape sh = choose_shape(ev, B, use_mixed(ev, prec), with_grad != 0);
+  if (waves) *waves = sh.W;
+  if (groups) *groups = sh.G;
+  if (setup) *setup = sh.setup;
   return GWL_OK;
 }
 
@@ -564,32 +692,43 @@ gwl_status gwl_waveform(const double* theta, int64_t B, const gwl_detector* dets
 
 namespace gwl {
 
-size_t workspace_bytes(int64_t Bp, int nchunk, int nd, bool grad) {
-  return sizeof(double) * ((size_t)NCOEF * Bp + (size_t)nchunk * nz_of(nd, grad) * Bp);
+gwl_status run_calibrated(gwl_event ev, const double* theta, int64_t B, bool mixed, bool grad, double* logl,
+                          double* gradout, hipStream_t s) {
+  return run_logl_cal(ev, theta, B, mixed, grad, logl, gradout, s);
 }
+
+size_t workspace_bytes(int64_t Bp, const LoopShape& sh, int nd, bool grad) {
+  const size_t coef = sh.setup ? 0 : (size_t)NCOEF * Bp;
+  const size_t part = (grad || sh.G > 1) ? (size_t)sh.G * nz_of(nd, grad) * Bp : 0;
+  return sizeof(double) * (coef + part);
+}
+
+size_t workspace_counters(const LoopShape& sh, bool grad) { return (!grad && sh.G > 1) ? (size_t)sh.npg : 0; }
 
 // Set-up, bin loop and epilogue on `s`, in the event's workspace for `s`.
 gwl_status run_logl(gwl_event ev, const double* theta, int64_t B, bool mixed, bool grad, const LoopShape& sh,
                     double* logl, double* gradout, hipStream_t s) {
   const int64_t Bp = (int64_t)sh.npg * WAVE;
   void* ws = nullptr;
-  gwl_status st = event_workspace(ev, s, workspace_bytes(Bp, sh.nchunk, ev->ndet, grad), &ws);
+  unsigned int* cnt = nullptr;
+  gwl_status st = event_workspace(ev, s, workspace_bytes(Bp, sh, ev->ndet, grad), workspace_counters(sh, grad), &ws,
+                                  &cnt);
   if (st != GWL_OK) return st;
-  double* coef = (double*)ws;
-  double* part = coef + (size_t)NCOEF * Bp;
-  hipError_t e = enqueue_logl(ev, theta, B, mixed, grad, sh, coef, part, logl, gradout, s);
+  hipError_t e = enqueue_logl(ev, theta, B, mixed, grad, sh, (double*)ws, cnt, logl, gradout, s);
   if (e != hipSuccess) return hip_fail(e, "launch");
   return GWL_OK;
 }
 
-gwl_status event_workspace(gwl_event ev, hipStream_t s, size_t bytes, void** out) {
+gwl_status event_workspace(gwl_event ev, hipStream_t s, size_t bytes, size_t ncnt, void** out, unsigned int** cnt) {
   *out = nullptr;
+  if (cnt) *cnt = nullptr;
   std::lock_guard<std::mutex> lk(ev->ws_mu);
   gwl_workspace* w = nullptr;
   for (gwl_workspace& x : ev->ws)
     if (x.stream == s) w = &x;
-  if (w && w->bytes >= bytes) {
+  if (w && w->bytes >= bytes && w->ncnt >= ncnt) {
     *out = w->ptr;
+    if (cnt) *cnt = w->cnt;
     return GWL_OK;
   }
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -599,31 +738,41 @@ gwl_status event_workspace(gwl_event ev, hipStream_t s, size_t bytes, void** out
     return fail(GWL_E_INVALID, "the call needs %zu bytes of workspace on a stream that is capturing a graph and has %zu: "
                                "reserve it first (gwl_event_reserve, or one call of this size on that stream outside "
                                "capture)", bytes, w ? w->bytes : (size_t)0);
-  const size_t grain = (size_t)2 << 20;
-  const size_t nb = (bytes + grain - 1) / grain * grain;
-  void* p = nullptr;
-  e = hipMalloc(&p, nb);
-  if (e != hipSuccess) return hip_fail(e, "workspace");
-  e = hipMemsetAsync(p, 0, nb, s);
-  if (e == hipSuccess && w && w->ptr) {
-    // the old buffer may still be in use by work queued on s
-    e = hipStreamSynchronize(s);
-    if (e == hipSuccess) e = hipFree(w->ptr);
-    w->ptr = nullptr;
-    w->bytes = 0;
-  }
-  if (e != hipSuccess) {
-    (void)hipFree(p);
-    return hip_fail(e, "workspace");
-  }
   if (!w) {
     ev->ws.push_back(gwl_workspace{});
     w = &ev->ws.back();
     w->stream = s;
   }
+  const size_t grain = (size_t)2 << 20;
+  const size_t nb = std::max(w->bytes, (bytes + grain - 1) / grain * grain);
+  const size_t nc = std::max(w->ncnt, (ncnt + 1023) / 1024 * 1024);
+  void* p = w->ptr;
+  unsigned int* c = w->cnt;
+  if (nb > w->bytes) {
+    e = hipMalloc(&p, nb);
+    if (e != hipSuccess) return hip_fail(e, "workspace");
+  }
+  if (nc > w->ncnt) {
+    e = hipMalloc((void**)&c, nc * sizeof(unsigned int));
+    // the kernels leave their counters at zero; a new array starts there
+    if (e == hipSuccess) e = hipMemsetAsync(c, 0, nc * sizeof(unsigned int), s);
+  }
+  // buffers being replaced may still be in use by work queued on s
+  const bool replace_ptr = p != w->ptr && w->ptr, replace_cnt = c != w->cnt && w->cnt;
+  if (e == hipSuccess && (replace_ptr || replace_cnt)) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    if (p != w->ptr) (void)hipFree(p);
+    if (c != w->cnt && c) (void)hipFree(c);
+    return hip_fail(e, "workspace");
+  }
+  if (replace_ptr) (void)hipFree(w->ptr);
+  if (replace_cnt) (void)hipFree(w->cnt);
   w->ptr = p;
   w->bytes = nb;
+  w->cnt = c;
+  w->ncnt = nc;
   *out = p;
+  if (cnt) *cnt = c;
   return GWL_OK;
 }
 
@@ -634,8 +783,7 @@ size_t call_workspace_bytes(const gwl_event_s* ev, int64_t B, bool mixed, bool g
     return sizeof(double) * ((size_t)NCOEF * Bp + (size_t)2 * ev->ncal * ev->ndet * Bp +
                              (size_t)MAXCALCHUNK * nz_cal(ev->ndet, grad) * Bp);
   }
-  const LoopShape sh = make_shape(B, ev->M, choose_nchunk(ev, B, mixed, grad));
-  return workspace_bytes(Bp, sh.nchunk, ev->ndet, grad);
+  return workspace_bytes(Bp, choose_shape(ev, B, mixed, grad), ev->ndet, grad);
 }
 
 // ---- bin-loop timing (gwl_profile_*) ----
@@ -664,18 +812,21 @@ static void prof_end(hipStream_t s, hipEvent_t a, hipEvent_t b) {
 }
 
 hipError_t enqueue_logl(gwl_event ev, const double* theta, int64_t B, bool mixed, bool grad, const LoopShape& sh,
-                        double* coef, double* part, double* logl, double* gradout, hipStream_t s) {
+                        double* ws, unsigned int* cnt, double* logl, double* gradout, hipStream_t s) {
   const int64_t Bp = (int64_t)sh.npg * WAVE;
-  hipError_t e = launch_setup(ev->ndet, ev->geom, ev->ec, mixed, theta, B, Bp, coef, s);
+  double* coef = sh.setup ? nullptr : ws;
+  double* part = (grad || sh.G > 1) ? ws + (sh.setup ? 0 : (size_t)NCOEF * Bp) : nullptr;
+  hipError_t e = hipSuccess;
+  if (!sh.setup) e = launch_setup(ev->ndet, ev->geom, ev->ec, mixed, theta, B, Bp, coef, s);
   hipEvent_t pa = nullptr, pb = nullptr;
   const bool prof = e == hipSuccess && prof_begin(s, pa, pb);
   if (e == hipSuccess)
-    e = launch_bins(ev->ndet, mixed, grad, mixed ? ev->tab32 : ev->tab64, ev->g32, ev->g64, coef, B, Bp, ev->M, sh,
-                    part, s);
+    e = launch_eval(ev->ndet, mixed, grad, mixed ? ev->tab32 : ev->tab64, ev->g64, theta, ev->geom, ev->ec, coef, B, Bp,
+                    ev->M, sh, part, cnt, logl, ev->fgrid, ev->kcum, s);
   if (prof) prof_end(s, pa, pb);
-  if (e == hipSuccess)
-    e = launch_epilogue(ev->ndet, grad, mixed, ev->geom, ev->ec, theta, coef, B, Bp, sh.nchunk, part, logl, gradout,
-                        s);
+  if (e == hipSuccess && grad)
+    e = launch_epilogue(ev->ndet, true, mixed, ev->geom, ev->ec, theta, coef, B, Bp, sh.G, part, logl, gradout, s,
+                        ev->fgrid, ev->kcum, ev->M);
   return e;
 }
 

@@ -1,9 +1,10 @@
-// Tile choice for the bin loop: a cache of measured choices keyed by launch shape, a
+// Tile choice for the evaluation kernel: a cache of measured choices keyed by launch shape, a
 // heuristic when nothing is cached, and the timing search behind gwl_autotune.
 //
-// The one free shape parameter of a single-event launch is the number of bin chunks: more
-// chunks give the chip more wavefronts (latency hiding, fewer idle SIMDs at the tail), fewer
-// chunks give each wavefront a longer run per coefficient load and fewer partial sums.
+// The free shape parameters of a single-event launch: W wavefronts per workgroup (chunks reduced
+// in LDS), G workgroups per point group (more wavefronts for latency hiding and a shorter tail,
+// against partial sums through memory and a release/acquire per workgroup), and whether the
+// per-point set-up runs in the kernel (one launch less, at the set-up's register cost).
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -31,7 +32,7 @@ struct Key {
   }
 };
 struct Entry {
-  int nchunk;
+  int W, G, setup;
   double ms;
 };
 
@@ -90,8 +91,9 @@ bool load_cache(const char* path) {
     long long M;
     MKey mk;
     MEntry me;
-    if (sscanf(line, " {\"ndet\": %d, \"mixed\": %d, \"grad\": %d, \"M\": %lld, \"npg_bucket\": %d, \"nchunk\": %d, \"ms\": %lf}",
-               &k.nd, &k.mixed, &k.grad, &M, &k.npg_bucket, &e.nchunk, &e.ms) == 7) {
+    if (sscanf(line, " {\"ndet\": %d, \"mixed\": %d, \"grad\": %d, \"M\": %lld, \"npg_bucket\": %d, \"waves\": %d, "
+               "\"groups\": %d, \"setup\": %d, \"ms\": %lf}",
+               &k.nd, &k.mixed, &k.grad, &M, &k.npg_bucket, &e.W, &e.G, &e.setup, &e.ms) == 9) {
       k.M = M;
       g_cache[k] = e;
     } else if (sscanf(line, " {\"multi\": 1, \"ndet\": %d, \"mixed\": %d, \"grad\": %d, \"events\": %d, \"sig\": \"%llx\", "
@@ -113,8 +115,10 @@ bool save_cache(const char* path) {
   const size_t n = g_cache.size() + g_mcache.size();
   for (const auto& kv : g_cache) {
     const Key& k = kv.first;
-    fprintf(f, "  {\"ndet\": %d, \"mixed\": %d, \"grad\": %d, \"M\": %lld, \"npg_bucket\": %d, \"nchunk\": %d, \"ms\": %.6f}%s\n",
-            k.nd, k.mixed, k.grad, (long long)k.M, k.npg_bucket, kv.second.nchunk, kv.second.ms, ++i < n ? "," : "");
+    fprintf(f, "  {\"ndet\": %d, \"mixed\": %d, \"grad\": %d, \"M\": %lld, \"npg_bucket\": %d, \"waves\": %d, "
+               "\"groups\": %d, \"setup\": %d, \"ms\": %.6f}%s\n",
+            k.nd, k.mixed, k.grad, (long long)k.M, k.npg_bucket, kv.second.W, kv.second.G, kv.second.setup, kv.second.ms,
+            ++i < n ? "," : "");
   }
   for (const auto& kv : g_mcache) {
     const MKey& k = kv.first;
@@ -127,19 +131,36 @@ bool save_cache(const char* path) {
   return true;
 }
 
-__global__ void k_fill_theta(double* theta, int64_t B) {
+// Rows of P >= 11 values: a fixed, valid parameter point with a small per-point variation, then
+// zeros (calibration node values); the cost of the evaluation does not depend on the values.
+__global__ void k_fill_theta(double* theta, int64_t B, int P) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= B) return;
-  // a fixed, valid parameter point with a small per-point variation; the cost of the
-  // evaluation does not depend on the values
   const double row[NPARAM] = {30.0, 0.8, 0.1, -0.2, 400.0, 2.0, -0.5, 0.6, 1.0, 0.7, 0.0};
-  for (int i = 0; i < NPARAM; ++i) theta[p * NPARAM + i] = row[i];
-  theta[p * NPARAM + 0] += 1e-6 * (double)(p % 1024);
+  for (int i = 0; i < NPARAM; ++i) theta[p * P + i] = row[i];
+  for (int i = NPARAM; i < P; ++i) theta[p * P + i] = 0.0;
+  theta[p * P + 0] += 1e-6 * (double)(p % 1024);
 }
 
 }  // namespace
 
 namespace gwl {
+
+LoopShape heuristic_shape(int64_t B, int64_t M, bool mixed, bool grad) {
+  // eight wavefronts per workgroup, enough workgroups for about eight wavefronts per SIMD (1024
+  // SIMDs) while chunks keep at least 32 bins, and the set-up inside the kernel when the whole
+  // launch is small (a set-up launch and its gap are then a large part of the call)
+  (void)mixed;
+  (void)grad;
+  const int W = 8;
+  const int64_t npg = (B + WAVE - 1) / WAVE;
+  int64_t G = (8192 + npg * W - 1) / (npg * W);
+  const int64_t gmax = std::max<int64_t>(1, (M + 32 * W - 1) / (32 * W));
+  if (G > gmax) G = gmax;
+  if (G < 1) G = 1;
+  const int setup = npg * G <= 512 ? 1 : 0;
+  return make_shape(B, M, W, (int)G, setup);
+}
 
 int heuristic_nchunk(int64_t B, int64_t M) {
   // aim for ~8 wavefronts per SIMD (1024 SIMDs) with chunks of at least 32 bins (short
@@ -153,9 +174,9 @@ int heuristic_nchunk(int64_t B, int64_t M) {
   return (int)want;
 }
 
-hipError_t fill_theta(double* theta, int64_t B, hipStream_t s) {
+hipError_t fill_theta(double* theta, int64_t B, hipStream_t s, int P) {
   if (B <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill_theta, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, theta, B);
+  hipLaunchKernelGGL(k_fill_theta, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, theta, B, P);
   return hipGetLastError();
 }
 
@@ -171,13 +192,13 @@ void choose_multi_shape(const gwl_event* evs, int E, const int64_t* B_e, bool mi
   *descending = it->second.descending != 0;
 }
 
-int choose_nchunk(const gwl_event_s* ev, int64_t B, bool mixed, bool grad) {
+LoopShape choose_shape(const gwl_event_s* ev, int64_t B, bool mixed, bool grad) {
   {
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_cache.find(make_key(ev->ndet, mixed, grad, ev->M, B));
-    if (it != g_cache.end()) return it->second.nchunk;
+    if (it != g_cache.end()) return make_shape(B, ev->M, it->second.W, it->second.G, it->second.setup);
   }
-  return heuristic_nchunk(B, ev->M);
+  return heuristic_shape(B, ev->M, mixed, grad);
 }
 
 }  // namespace gwl
@@ -201,79 +222,68 @@ gwl_status gwl_autotune(const char* cache_path, gwl_event ev, int64_t B, gwl_pre
   if (cache_path) load_cache(cache_path);  // keep entries of other shapes
   const bool mixed = use_mixed(ev, prec), grad = with_grad != 0;
 
-  // candidate chunk counts: powers of two around the heuristic, then a second pass around the
-  // best of those (3/4 .. 3/2 of it), each launch shape timed once (the chunk count a shape really
-  // uses can differ from the request)
-  const int h = heuristic_nchunk(B, ev->M);
-  std::vector<int> cand;
-  const int mult[] = {1, 2, 4, 8, 16};
-  for (int m : mult) {
-    cand.push_back(h / m);
-    cand.push_back(h * m);
-  }
+  // candidate shapes: W in {4, 5, 8, 10, 16} wavefronts per workgroup, G in powers of two up to
+  // chunks of 16 bins (and the heuristic's G), the set-up in or out of the kernel; launches of
+  // more than 64 wavefronts per SIMD are skipped
+  const LoopShape h = heuristic_shape(B, ev->M, mixed, grad);
+  const int64_t npg = (B + WAVE - 1) / WAVE;
   std::vector<LoopShape> shapes;
-  auto add_shapes = [&](const std::vector<int>& cs) {
-    std::vector<LoopShape> out;
-    for (int c : cs) {
-      if (c < 1 || (int64_t)c > ev->M) continue;
-      const LoopShape sh = make_shape(B, ev->M, c);
-      bool seen = false;
-      for (const LoopShape& u : shapes) seen |= (u.nchunk == sh.nchunk);
-      if (!seen) {
-        shapes.push_back(sh);
-        out.push_back(sh);
-      }
-    }
-    return out;
+  auto add = [&](int W, int G, int setup) {
+    const LoopShape sh = make_shape(B, ev->M, W, G, setup);
+    if ((int64_t)sh.items * sh.W > 65536 && !(sh.W == h.W && sh.G == h.G)) return;
+    for (const LoopShape& u : shapes)
+      if (u.W == sh.W && u.G == sh.G && u.setup == sh.setup) return;
+    shapes.push_back(sh);
   };
-  const std::vector<LoopShape> first = add_shapes(cand);
-
-  const int64_t Bp = (B + WAVE - 1) / WAVE * WAVE;
-  int maxc = 1;
-  for (const LoopShape& u : first) maxc = u.nchunk > maxc ? u.nchunk : maxc;
-  maxc = (int)std::min<int64_t>(ev->M, 3 * (int64_t)maxc / 2 + 1);  // room for the second pass
+  add(h.W, h.G, h.setup);
+  const int ws_[] = {4, 5, 8, 10, 16};
+  for (int W : ws_) {
+    const int64_t gmax = std::max<int64_t>(1, (ev->M + 16 * W - 1) / (16 * W));
+    for (int64_t G = 1; G <= gmax; G *= 2) {
+      if (npg * G * W < 256 && G * 2 <= gmax) continue;  // far too few wavefronts: skip
+      for (int setup = 0; setup < 2; ++setup) add(W, (int)G, setup);
+    }
+    for (int setup = 0; setup < 2; ++setup) add(W, h.G, setup);
+  }
+  const int64_t Bp = npg * WAVE;
+  size_t ws_bytes = 0, ws_cnt = 0;
+  for (const LoopShape& u : shapes) {
+    ws_bytes = std::max(ws_bytes, workspace_bytes(Bp, u, ev->ndet, grad));
+    ws_cnt = std::max(ws_cnt, workspace_counters(u, grad));
+  }
   double *theta = nullptr, *logl = nullptr, *grad_out = nullptr, *ws = nullptr;
+  unsigned int* cnt = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipMalloc((void**)&theta, sizeof(double) * NPARAM * (size_t)B);
   if (e == hipSuccess) e = hipMalloc((void**)&logl, sizeof(double) * (size_t)B);
   if (e == hipSuccess && grad) e = hipMalloc((void**)&grad_out, sizeof(double) * NPARAM * (size_t)B);
-  if (e == hipSuccess) e = hipMalloc((void**)&ws, workspace_bytes(Bp, maxc, ev->ndet, grad));
+  if (e == hipSuccess) e = hipMalloc((void**)&ws, std::max<size_t>(ws_bytes, 8));
+  if (e == hipSuccess) e = hipMalloc((void**)&cnt, sizeof(unsigned int) * std::max<size_t>(ws_cnt, 1));
+  if (e == hipSuccess) e = hipMemset(cnt, 0, sizeof(unsigned int) * std::max<size_t>(ws_cnt, 1));
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_fill_theta, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, 0, theta, B);
+    hipLaunchKernelGGL(k_fill_theta, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, 0, theta, B, NPARAM);
     e = hipGetLastError();
   }
-  int best = h;
+  LoopShape best = h;
   double best_ms = 1e300;
-  auto time_shapes = [&](const std::vector<LoopShape>& list) {
-    for (size_t i = 0; e == hipSuccess && i < list.size(); ++i) {
-      const LoopShape& sh = list[i];
-      if (sh.nchunk > maxc) continue;  // beyond the workspace (not reached: maxc bounds the second pass)
-      double* coef = ws;
-      double* part = ws + (size_t)NCOEF * Bp;
-      float ms_min = 1e30f;
-      for (int rep = 0; rep < 6 && e == hipSuccess; ++rep) {
-        e = hipEventRecord(e0, 0);
-        if (e == hipSuccess) e = enqueue_logl(ev, theta, B, mixed, grad, sh, coef, part, logl, grad_out, 0);
-        if (e == hipSuccess) e = hipEventRecord(e1, 0);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.0f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (rep > 0 && ms < ms_min) ms_min = ms;  // first run is a warm-up
-      }
-      if (e == hipSuccess && ms_min < best_ms) {
-        best_ms = ms_min;
-        best = sh.nchunk;
-      }
+  for (size_t i = 0; e == hipSuccess && i < shapes.size(); ++i) {
+    const LoopShape& sh = shapes[i];
+    float ms_min = 1e30f;
+    for (int rep = 0; rep < 6 && e == hipSuccess; ++rep) {
+      e = hipEventRecord(e0, 0);
+      if (e == hipSuccess) e = enqueue_logl(ev, theta, B, mixed, grad, sh, ws, cnt, logl, grad_out, 0);
+      if (e == hipSuccess) e = hipEventRecord(e1, 0);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (rep > 0 && ms < ms_min) ms_min = ms;  // first run is a warm-up
     }
-  };
-  time_shapes(first);
-  if (e == hipSuccess) {
-    std::vector<int> fine;
-    const int num[] = {6, 7, 9, 10, 11, 12};  // eighths of the best count
-    for (int q : num) fine.push_back((int)(((int64_t)best * q + 4) / 8));
-    time_shapes(add_shapes(fine));
+    if (e == hipSuccess && ms_min < best_ms) {
+      best_ms = ms_min;
+      best = sh;
+    }
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
@@ -281,10 +291,11 @@ gwl_status gwl_autotune(const char* cache_path, gwl_event ev, int64_t B, gwl_pre
   if (logl) (void)hipFree(logl);
   if (grad_out) (void)hipFree(grad_out);
   if (ws) (void)hipFree(ws);
+  if (cnt) (void)hipFree(cnt);
   if (e != hipSuccess) return hip_fail(e, "autotune");
   {
     std::lock_guard<std::mutex> lk(g_mu);
-    g_cache[make_key(ev->ndet, mixed, grad, ev->M, B)] = Entry{best, best_ms};
+    g_cache[make_key(ev->ndet, mixed, grad, ev->M, B)] = Entry{best.W, best.G, best.setup, best_ms};
   }
   if (cache_path && !save_cache(cache_path)) return fail(GWL_E_INVALID, "cannot write %s", cache_path);
   return GWL_OK;
@@ -300,11 +311,12 @@ gwl_status gwl_multi_autotune(const char* cache_path, const gwl_event* evs, int 
   if (!evs || !B_e) return fail(GWL_E_INVALID, "evs and B_e must be host arrays");
   if (E < 1 || E > 4096) return fail(GWL_E_SHAPE, "E=%d outside [1, 4096]", E);
   if (prec != GWL_FP64 && prec != GWL_MIXED) return fail(GWL_E_INVALID, "unknown precision %d", (int)prec);
-  int64_t total = 0;
+  int64_t total = 0, total_p = 0;   // points, and values of theta (rows of 11 + 2 nnode ndet)
   for (int e = 0; e < E; ++e) {
     if (!evs[e]) return fail(GWL_E_INVALID, "event %d is null", e);
     if (B_e[e] < 0 || B_e[e] > kMaxBatch) return fail(GWL_E_SHAPE, "B_e[%d] out of range", e);
     total += B_e[e];
+    total_p += B_e[e] * (NPARAM + 2 * (int64_t)evs[e]->ncal * evs[e]->ndet);
   }
   gwl_status st = check_device(evs[0]->device);
   if (st != GWL_OK) return st;
@@ -312,24 +324,26 @@ gwl_status gwl_multi_autotune(const char* cache_path, const gwl_event* evs, int 
   const bool mixed = prec == GWL_MIXED, grad = with_grad != 0;
 
   // synthetic inputs for every event, in one allocation each for theta, logl and grad
-  const size_t nt = (size_t)(total > 0 ? total : 1);
+  const size_t nt = (size_t)(total > 0 ? total : 1), ntp = (size_t)(total_p > 0 ? total_p : 1);
   double *theta = nullptr, *logl = nullptr, *gout = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  hipError_t err = hipMalloc((void**)&theta, sizeof(double) * NPARAM * nt);
+  hipError_t err = hipMalloc((void**)&theta, sizeof(double) * ntp);
   if (err == hipSuccess) err = hipMalloc((void**)&logl, sizeof(double) * nt);
-  if (err == hipSuccess && grad) err = hipMalloc((void**)&gout, sizeof(double) * NPARAM * nt);
-  if (err == hipSuccess) err = fill_theta(theta, total, 0);
-  if (err == hipSuccess) err = hipEventCreate(&e0);
-  if (err == hipSuccess) err = hipEventCreate(&e1);
+  if (err == hipSuccess && grad) err = hipMalloc((void**)&gout, sizeof(double) * ntp);
   std::vector<const double*> tp(E);
   std::vector<double*> lp(E), gp(E);
-  int64_t off = 0;
+  int64_t off = 0, offp = 0;
   for (int e = 0; e < E; ++e) {
-    tp[e] = theta + NPARAM * off;
+    const int P = NPARAM + 2 * evs[e]->ncal * evs[e]->ndet;
+    if (err == hipSuccess) err = fill_theta(theta + offp, B_e[e], 0, P);
+    tp[e] = theta + offp;
     lp[e] = logl + off;
-    gp[e] = grad ? gout + NPARAM * off : nullptr;
+    gp[e] = grad ? gout + offp : nullptr;
     off += B_e[e];
+    offp += B_e[e] * P;
   }
+  if (err == hipSuccess) err = hipEventCreate(&e0);
+  if (err == hipSuccess) err = hipEventCreate(&e1);
   int best_chunk = 0, best_desc = 0;
   double best_ms = 1e300;
   auto try_plan = [&](int chunk, int desc) {

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libgwlike.so")
 
 GWL_FP64 = 0
 GWL_MIXED = 1
+GWL_F_ISCO_CUTOFF = 1
 NPARAM = 11
 MAX_DET = 4
 
@@ -61,6 +62,8 @@ def lib() -> ctypes.CDLL:
         "gwl_event_rb_info": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64)], cint),
         "gwl_event_create_cal": ([vp, vp, ctypes.POINTER(Detector), cint, vp, i64, dbl, dbl, cint, ctypes.c_uint, vp,
                                   ctypes.POINTER(vp)], cint),
+        "gwl_event_create_rb_cal": ([vp, vp, ctypes.POINTER(Detector), cint, vp, i64, dbl, dbl, _c_double_p, dbl, cint,
+                                     ctypes.c_uint, vp, ctypes.POINTER(vp)], cint),
         "gwl_event_info": ([vp, ctypes.POINTER(cint), ctypes.POINTER(i64), ctypes.POINTER(dbl)], cint),
         "gwl_logl_batch": ([vp, vp, i64, cint, vp, vp], cint),
         "gwl_logl_grad": ([vp, vp, i64, cint, vp, vp, vp], cint),
@@ -76,6 +79,8 @@ def lib() -> ctypes.CDLL:
         "gwl_autotune_load": ([ctypes.c_char_p], cint),
         "gwl_launch_shape": ([vp, i64, cint, cint, ctypes.POINTER(cint), ctypes.POINTER(cint)], cint),
         "gwl_event_reserve": ([vp, i64, cint, cint, vp], cint),
+        "gwl_launch_layout": ([vp, i64, cint, cint, ctypes.POINTER(cint), ctypes.POINTER(cint), ctypes.POINTER(cint)],
+                              cint),
         "gwl_profile_enable": ([cint], cint),
         "gwl_profile_read": ([ctypes.POINTER(i64), ctypes.POINTER(dbl)], cint),
         "gwl_slice_ends": ([i64, cint, cint] + [vp] * 9 + [vp], cint),
@@ -136,10 +141,12 @@ class Event:
               rb_eps radians of the phase bound apart (see gwl_event_create_rb).
     calibration_nodes  optional n >= 4: a calibration model per detector (see gwl_event_create_cal);
               theta then has 11 + 2 n ndet columns.
+    isco_cutoff  the model is zero above each point's ISCO frequency (GWL_F_ISCO_CUTOFF).
     """
 
     def __init__(self, data: torch.Tensor, psd: torch.Tensor, dets: Sequence, fgrid: torch.Tensor, df: float,
-                 gmst: float = 0.0, fiducial=None, rb_eps: float = 0.1, calibration_nodes: int = 0):
+                 gmst: float = 0.0, fiducial=None, rb_eps: float = 0.1, calibration_nodes: int = 0,
+                 isco_cutoff: bool = False):
         data = _dev(data, "data", torch.complex128)
         psd = _dev(psd, "psd", torch.float64)
         fgrid = _dev(fgrid, "fgrid", torch.float64)
@@ -150,9 +157,18 @@ class Event:
         self.device = data.device
         h = ctypes.c_void_p()
         self.ncal = int(calibration_nodes)
+        if isco_cutoff and (self.ncal or fiducial is not None):
+            raise ValueError("the ISCO cut-off is available on plain events only")
         if self.ncal and fiducial is not None:
-            raise ValueError("relative binning and the calibration model cannot be combined")
-        if self.ncal:
+            fid = [float(x) for x in fiducial]
+            if len(fid) != NPARAM:
+                raise ValueError("fiducial must have 11 parameters")
+            fid = (ctypes.c_double * NPARAM)(*fid)
+            _check("gwl_event_create_rb_cal", lib().gwl_event_create_rb_cal(
+                ctypes.c_void_p(data.data_ptr()), ctypes.c_void_p(psd.data_ptr()), darr, nd,
+                ctypes.c_void_p(fgrid.data_ptr()), self.M, self.df, self.gmst, fid, float(rb_eps), self.ncal, 0,
+                _stream(data), ctypes.byref(h)))
+        elif self.ncal:
             _check("gwl_event_create_cal", lib().gwl_event_create_cal(
                 ctypes.c_void_p(data.data_ptr()), ctypes.c_void_p(psd.data_ptr()), darr, nd,
                 ctypes.c_void_p(fgrid.data_ptr()), self.M, self.df, self.gmst, self.ncal, 0, _stream(data),
@@ -160,7 +176,8 @@ class Event:
         elif fiducial is None:
             _check("gwl_event_create", lib().gwl_event_create(
                 ctypes.c_void_p(data.data_ptr()), ctypes.c_void_p(psd.data_ptr()), darr, nd,
-                ctypes.c_void_p(fgrid.data_ptr()), self.M, self.df, self.gmst, 0, _stream(data), ctypes.byref(h)))
+                ctypes.c_void_p(fgrid.data_ptr()), self.M, self.df, self.gmst, GWL_F_ISCO_CUTOFF if isco_cutoff else 0,
+                _stream(data), ctypes.byref(h)))
         else:
             fid = [float(x) for x in fiducial]
             if len(fid) != NPARAM:
@@ -298,7 +315,8 @@ class MultiPlan:
     """Many events of uneven size evaluated by one persistent launch captured in a HIP graph.
 
     events   list of Event (same detector count, same device); batches: points per event.
-    launch(thetas) takes one float64 CUDA tensor [B_e, 11] per event and returns
+    launch(thetas) takes one float64 CUDA tensor [B_e, P_e] per event (P_e = 11, or 11 + 2 n ndet
+    on a calibrated event, whose own kernels run after the persistent launch) and returns
     (logls, grads or None, latency_us or None).
     """
 
@@ -320,14 +338,13 @@ class MultiPlan:
         E = len(self.events)
         if len(thetas) != E:
             raise ValueError("one theta tensor per event is required")
-        thetas = [_theta(t) for t in thetas]
+        thetas = [_theta(t, ev) for t, ev in zip(thetas, self.events)]
         for t, b in zip(thetas, self.batches):
             if t.shape[0] != b:
                 raise ValueError("theta batch sizes must match the plan")
         dev = thetas[0].device
         logls = [torch.empty(b, dtype=torch.float64, device=dev) for b in self.batches]
-        grads = [torch.empty(b, NPARAM, dtype=torch.float64, device=dev) for b in self.batches] \
-            if self.with_grad else None
+        grads = [torch.empty_like(t) for t in thetas] if self.with_grad else None
         tp = (ctypes.c_void_p * E)(*[t.data_ptr() for t in thetas])
         lp = (ctypes.c_void_p * E)(*[t.data_ptr() for t in logls])
         gp = (ctypes.c_void_p * E)(*[t.data_ptr() for t in grads]) if grads is not None else None
@@ -389,6 +406,14 @@ def reserve(ev: Event, batch: int, precision="mixed", with_grad: bool = False, s
         stream = torch.cuda.current_stream(ev.device)
     _check("gwl_event_reserve", lib().gwl_event_reserve(ev.handle, int(batch), _prec(precision), int(bool(with_grad)),
                                                         ctypes.c_void_p(stream.cuda_stream)))
+
+
+def launch_layout(ev: Event, batch: int, precision="mixed", with_grad: bool = False):
+    """(wavefronts per workgroup, workgroups per point group, set-up inside the kernel) of a call."""
+    w, g, st = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check("gwl_launch_layout", lib().gwl_launch_layout(ev.handle, int(batch), _prec(precision), int(bool(with_grad)),
+                                                        ctypes.byref(w), ctypes.byref(g), ctypes.byref(st)))
+    return w.value, g.value, bool(st.value)
 
 
 def autotune_load(cache_path: str) -> None:

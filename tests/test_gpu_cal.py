@@ -96,7 +96,74 @@ def test_tiny_grid_with_empty_node_intervals():
     np.testing.assert_allclose(got, ref, rtol=1e-9, atol=1e-9)
 
 
-def test_calibrated_events_rejected_by_multi_plans():
-    spec, f, psd, data, dets, ev = make(1, 10, f_hi=100.0)
-    with pytest.raises(gw.GWLError):
-        gw.MultiPlan([ev], [10], "mixed")
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_calibrated_events_in_multi_plans(prec):
+    """A plan mixing calibrated events (their own kernels after the persistent launch, theta of
+    11 + 2 n ndet columns), a calibrated relative-binning event and plain events: every event's
+    values and gradients equal its single-event calls (bit for bit on the calibrated ones, which run
+    the same kernels); a calibrated event's values against the oracle."""
+    from tests.test_rb_oracle import near
+    n = 6
+    spec, f, psd, data, dets = event_inputs(1, f_hi=300.0)
+    t = lambda x: torch.tensor(x, device=DEV)
+    evs = [gw.Event(t(data), t(psd), dets, t(f), spec.df, calibration_nodes=n),
+           gw.Event(t(data), t(psd), dets, t(f), spec.df),
+           gw.Event(t(data), t(psd), dets, t(f), spec.df, fiducial=spec.theta0, rb_eps=0.2, calibration_nodes=n),
+           gw.Event(t(data), t(psd), dets, t(f), spec.df, calibration_nodes=n)]
+    rng = np.random.default_rng(31)
+    batches = [70, 129, 40, 0]
+    thetas = [cal_theta(synth.theta_batch(spec, 70), 3, n, rng, 0.05), synth.theta_batch(spec, 129),
+              cal_theta(near(spec.theta0, 40, seed=3, scale=0.3), 3, n, rng, 0.05), np.zeros((0, 11 + 6 * n))]
+    tt = [t(x) for x in thetas]
+    plan = gw.MultiPlan(evs, batches, prec, with_grad=True)
+    logls, grads, lat = plan.launch(tt, latency=True)
+    for ev, x, l, g, b in zip(evs, tt, logls, grads, batches):
+        assert l.shape == (b,) and g.shape == x.shape
+        if b == 0:
+            continue
+        sv, sg = gw.logl_grad(x, ev, prec)
+        if ev.ncal:                         # the same kernels as a single call: the same bits
+            assert torch.equal(l, sv) and torch.equal(g, sg)
+        else:                               # the persistent kernel sums in another order
+            assert np.abs(l.cpu().numpy() - sv.cpu().numpy()).max() <= (1e-8 if prec == "fp64" else 2e-4)
+            tol = 1e-8 if prec == "fp64" else 2e-4
+            assert np.abs(g.cpu().numpy() - sg.cpu().numpy()).max() <= tol * max(1.0, float(sg.abs().max()))
+    ref = cal.logl(thetas[0][:4], data, psd, dets, f, spec.df, n).numpy()
+    assert np.abs(logls[0].cpu().numpy()[:4] - ref).max() <= (1e-6 if prec == "fp64" else 1e-3)
+    assert all(x > 0 for x, b in zip(lat, batches) if b > 0) and lat[3] == 0.0
+    plan.close()
+
+
+def test_calibrated_relative_binning_matches_the_composed_oracle():
+    """Relative binning with the calibration model (gwl_event_create_rb_cal) against the oracle's
+    composition of the two: the calibration factor at the edges multiplies h / h0, and
+    <h_cal|h_cal> over every bin. Values in both precisions (both run the float64 edge loop) and
+    the gradient over all 11 + 2 n ndet parameters."""
+    from oracle import rb_oracle as rb
+    from tests.test_rb_oracle import near
+    n, nd, eps = 8, 3, 0.1
+    spec, f, psd, data, dets = event_inputs(1, f_hi=600.0)
+    t = lambda x: torch.tensor(x, device=DEV)
+    ev = gw.Event(t(data), t(psd), dets, t(f), spec.df, fiducial=spec.theta0, rb_eps=eps, calibration_nodes=n)
+    ne, nb = ev.rb_info()
+    summ = rb.summary(data, psd, dets, f, spec.df, spec.theta0, eps)
+    assert (ne, nb) == (len(summ["idx"]), len(f)) and ne < len(f) / 10
+    rng = np.random.default_rng(13)
+    th = cal_theta(near(spec.theta0, 8, seed=12, scale=0.3), nd, n, rng, 0.05)
+    th[0, :11] = spec.theta0
+    ref = rb.logl(th, summ, psd, dets, f, spec.df, nnode=n).numpy()
+    for prec in ("fp64", "mixed"):
+        got = gw.logl(t(th), ev, prec).cpu().numpy()
+        err = np.abs(got - ref)
+        tol = 1e-9 * np.maximum(1.0, np.abs(ref)) if prec == "fp64" else 1e-3
+        print(f"calibrated RB ({ne} edges of {nb} bins) {prec}: max |dlogL| vs composed oracle {err.max():.3e}")
+        assert np.all(err <= tol)
+    _, gref = rb.logl_grad(th[:3], summ, psd, dets, f, spec.df, nnode=n)
+    widths = np.concatenate([WIDTHS, np.full(2 * n * nd, 0.1)])
+    for prec in ("fp64", "mixed"):
+        _, g = gw.logl_grad(t(th[:3]), ev, prec)
+        gs, rs = g.cpu().numpy() * widths, gref.numpy() * widths
+        scale = np.maximum(np.abs(rs), 1e-3 * np.abs(rs).max(axis=1, keepdims=True))
+        err = np.abs(gs - rs) / scale
+        print(f"calibrated RB gradient {prec}: max scaled error {err.max():.3e}")
+        assert err.max() <= 1e-8

@@ -52,14 +52,15 @@ def test_c0_every_point(c0, prec):
 
 def use_bench_shapes(spec, ev, batch, prec, grad):
     """Load the committed tile shapes, as the benchmark does, and check that a call of this
-    shape launches with the tuned chunk count."""
+    shape launches with the tuned layout (wavefronts per workgroup, workgroups per point group,
+    set-up in the kernel)."""
     cache = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
                          "paper_1909_11873_amd", "tuning_gfx950.json")
     gw.autotune_load(cache)
-    want = [e["nchunk"] for e in json.load(open(cache))["entries"]
+    want = [(e["waves"], e["groups"], bool(e["setup"])) for e in json.load(open(cache))["entries"]
             if tuple(e.get(k) for k in ("ndet", "M", "mixed", "grad", "npg_bucket")) ==
             (spec.ndet, spec.nbins, int(prec == "mixed"), int(grad), batch // 64)]
-    assert len(want) == 1 and gw.launch_shape(ev, batch, prec, grad)[0] == want[0]
+    assert len(want) == 1 and gw.launch_layout(ev, batch, prec, grad) == want[0]
 
 
 @pytest.fixture(scope="module")

@@ -108,6 +108,11 @@ def _inner_drops_last_bin():
     return lambda a, b, psd, df: 4.0 * df * torch.sum((torch.real(torch.conj(a) * b) / psd)[..., :-1])
 
 
+def _isco_orbital_not_gw():
+    orig = o.isco_frequency
+    return lambda theta: 0.5 * orig(theta)
+
+
 MUTATIONS = [
     ("phi2 mistyped", "pn_coefficients", lambda: _wrap_pn(1, lambda p, e, a, b: p + 0.01),
      [lambda: pins.test_phase_derivative_matches_2pn_time_frequency_relation(0.0, 0.0)]),
@@ -149,6 +154,8 @@ MUTATIONS = [
     ("GMST sign", "source_frame", _gmst_sign, [pins.test_sidereal_angle_turns_the_sky_with_the_earth]),
     ("inner product drops the last bin", "inner", _inner_drops_last_bin,
      [pins.test_discrete_likelihood_converges_to_the_frequency_integral]),
+    ("ISCO at the orbital frequency", "isco_frequency", _isco_orbital_not_gw,
+     [pins.test_isco_frequency_is_twice_the_kepler_frequency_at_6m]),
 ]
 
 

@@ -650,3 +650,34 @@ def test_oracle_matches_50_digit_per_bin_evaluation():
                 tot += dh - hh
                 mag += abs(dh) + hh
         assert abs(got - float(tot)) <= 1e-12 * float(mag), (b, got, float(tot))
+
+
+# ------------------------------------------------------------------------------------------
+# Optional high-frequency cut at the innermost stable circular orbit
+# ------------------------------------------------------------------------------------------
+def test_isco_frequency_is_twice_the_kepler_frequency_at_6m():
+    G_SI = 6.6743e-11
+    for mc, q in [(10.0, 0.5), (30.0, 0.8), (1.2, 1.0)]:
+        th = torch.tensor([mc, q, 0.0, 0.0, 400.0, 0, 0, 0, 0, 0, 0], dtype=DT)
+        eta = q / (1 + q) ** 2
+        m_kg = mc * eta ** -0.6 * (TSUN * C ** 3 / G_SI)          # total mass, kg (G Msun / c^3 = TSUN)
+        r = 6.0 * G_SI * m_kg / C ** 2
+        f_orb = math.sqrt(G_SI * m_kg / r ** 3) / (2 * math.pi)
+        assert float(o.isco_frequency(th)) == pytest.approx(2.0 * f_orb, rel=1e-12)
+
+
+def test_isco_cut_equals_the_likelihood_on_the_truncated_grid():
+    f, psd, data, dets, df = small_event(m=800, df=0.5)          # 20 .. 419.5 Hz
+    th = draw(6, seed=51)
+    th[:, 0] = [12.0, 25.0, 40.0, 55.0, 8.0, 60.0]                # cut-offs across and above the band
+    for row in th:
+        fi = float(o.isco_frequency(torch.tensor(row)))
+        m = int(np.searchsorted(f, fi, side="right"))             # bins with f <= f_isco
+        got = float(o.logl(row[None], data, psd, dets, f, df, isco=True)[0])
+        if m == 0:
+            assert got == 0.0
+            continue
+        want = float(o.logl(row[None], data[:, :m], psd[:, :m], dets, f[:m], df)[0])
+        assert got == pytest.approx(want, rel=1e-12, abs=1e-12)
+        if m == len(f):
+            assert got == pytest.approx(float(o.logl(row[None], data, psd, dets, f, df)[0]), rel=1e-12)

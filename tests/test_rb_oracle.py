@@ -89,3 +89,26 @@ def test_gradient_matches_central_differences(small):
         tm[i] -= h
         fd = (rb.logl(tp[None], summ, psd, dets, f, spec.df) - rb.logl(tm[None], summ, psd, dets, f, spec.df)) / (2 * h)
         assert float(g[0, i]) == pytest.approx(float(fd[0]), rel=1e-5, abs=1e-6)
+
+
+def _cal_cols(k, nnode, ndet, seed, scale=0.05):
+    return np.random.default_rng(seed).normal(0.0, scale, (k, 2 * nnode * ndet))
+
+
+def test_calibrated_rb_reduces_to_plain_rb_at_zero_calibration(small):
+    spec, f, psd, data, dets = small
+    summ = rb.summary(data, psd, dets, f, spec.df, spec.theta0, 0.3)
+    th = near(spec.theta0, 3, seed=4)
+    cal = np.concatenate([th, np.zeros((3, 2 * 6 * 3))], axis=1)
+    np.testing.assert_allclose(rb.logl(cal, summ, psd, dets, f, spec.df, nnode=6).numpy(),
+                               rb.logl(th, summ, psd, dets, f, spec.df).numpy(), rtol=1e-13, atol=1e-10)
+
+
+def test_calibrated_rb_is_exact_when_every_bin_is_an_edge(small):
+    """Every bin an edge: the binned, calibrated likelihood is the calibration oracle's."""
+    from oracle import cal_oracle as co
+    spec, f, psd, data, dets = small
+    summ = rb.summary(data, psd, dets, f, spec.df, spec.theta0, 1e-12)
+    th = np.concatenate([near(spec.theta0, 3, seed=5, scale=5.0), _cal_cols(3, 5, 3, seed=6)], axis=1)
+    np.testing.assert_allclose(rb.logl(th, summ, psd, dets, f, spec.df, nnode=5).numpy(),
+                               co.logl(th, data, psd, dets, f, spec.df, 5).numpy(), rtol=1e-10, atol=1e-8)
