@@ -202,6 +202,24 @@ gwl_status gwl_logl_batch(gwl_event ev, const double* theta, int64_t B, gwl_prec
 gwl_status gwl_event_reserve(gwl_event ev, int64_t B, gwl_precision prec, int with_grad, void* stream);
 
 /*
+ * gwl_logl_batch without any device allocation, for callers that cannot allocate (code under HIP
+ * graph capture, serving loops, harnesses that forbid hipMalloc). Same arguments and results as
+ * gwl_logl_batch, to rounding (the launch shape may differ). Its workspace (per-point set-up rows,
+ * partial sums and completion counters) lives in fixed device arrays, GWL_NOALLOC_SCRATCH_BYTES
+ * plus 64 KiB, that every GPU the library runs on holds until the process ends; the call
+ * allocates nothing, also not on its first use. It takes the tuned launch shape when that shape's
+ * workspace fits, else one with fewer workgroups per point group, else the set-up inside the
+ * evaluation kernel, which needs no workspace. All calls on one GPU share the arrays, so calls
+ * that overlap on one GPU (other streams, other threads) race and must not be issued;
+ * consecutive calls on one stream are fine. The first call on each device looks up the arrays'
+ * device addresses (hipGetSymbolAddress): make it outside graph capture. GWL_E_SHAPE for B
+ * outside [0, 2^30]; GWL_E_UNSUPPORTED for a calibrated event.
+ */
+#define GWL_NOALLOC_SCRATCH_BYTES (64ull << 20)
+gwl_status gwl_logl_batch_noalloc(gwl_event ev, const double* theta, int64_t B, gwl_precision prec, double* logl,
+                                  void* stream);
+
+/*
  * logL and its gradient with respect to all 11 parameters (adjoint of the same evaluation,
  * fused with the forward pass; feeds gradient-based proposals of the sampler in section 3).
  *   grad   device, float64 [B][11] (same column order as theta).

@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libgwlike.so")
 SOURCES = ["k_bins.hip", "k_event.hip", "k_point.hip", "k_rb.hip", "k_cal.hip", "k_slice.hip", "k_prior.hip",
-           "runtime.hip", "tuner.hip", "multi.hip"]
+           "runtime.hip", "tuner.hip", "multi.hip", "noalloc.hip"]
 
 # Packed float32 VALU forms are disabled: the compiler emits them from plain float code, and
 # plain v_fma_f32 / v_add_f32 carry the float32 work instead.

@@ -81,6 +81,7 @@ def lib() -> ctypes.CDLL:
         "gwl_event_reserve": ([vp, i64, cint, cint, vp], cint),
         "gwl_launch_layout": ([vp, i64, cint, cint, ctypes.POINTER(cint), ctypes.POINTER(cint), ctypes.POINTER(cint)],
                               cint),
+        "gwl_logl_batch_noalloc": ([vp, vp, i64, cint, vp, vp], cint),
         "gwl_profile_enable": ([cint], cint),
         "gwl_profile_read": ([ctypes.POINTER(i64), ctypes.POINTER(dbl)], cint),
         "gwl_slice_ends": ([i64, cint, cint] + [vp] * 9 + [vp], cint),
