@@ -33,12 +33,13 @@ PEAK_FP32 = 157.3e12   # FP32 vector FLOP/s (published; needs packed FMA)
 # transcendental VALU ops (v_sin_f32 / v_cos_f32): half the FP32 lane rate on gfx950,
 # 256 CU x 64 lanes/clk x 2.4 GHz / 2
 PEAK_TRANS = 256 * 64 * 2.4e9 / 2
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_bins_mixed_c1.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_eval_mixed_c1.txt")
 # tile shapes measured on an MI355X by the library's autotuner (gwl_autotune / gwl_multi_autotune);
 # loaded so that timed launches use a fixed, tuned shape; --retune measures them again
 TUNE_FILE = os.path.join(ROOT, "paper_1909_11873_amd", "tuning_gfx950.json")
 KERNEL_SOURCES = ["paper_1909_11873_amd/csrc/k_bins.hip", "paper_1909_11873_amd/csrc/gwl_bins.h",
-                  "paper_1909_11873_amd/csrc/gwl_common.h", "paper_1909_11873_amd/csrc/gwl_device.h"]
+                  "paper_1909_11873_amd/csrc/gwl_common.h", "paper_1909_11873_amd/csrc/gwl_device.h",
+                  "paper_1909_11873_amd/csrc/gwl_epilogue.h", "paper_1909_11873_amd/csrc/gwl_launch.h"]
 
 
 def work_per_point_bin(ndet: int, mixed: bool, grad: bool = False):
@@ -93,18 +94,29 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(nchunk: int):
-    """HBM bytes per bin-loop launch from the committed counter summary, if it was taken with the
-    same kernel source and the same launch shape (number of bin chunks)."""
+def read_traffic(layout: str):
+    """HBM bytes per evaluation launch from the committed counter summary, if it was taken with the
+    same kernel source and the same launch layout (waves per workgroup, workgroups per point group,
+    set-up inside the kernel)."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     text = open(TRAFFIC_FILE).read()
     m_hash = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
     m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
-    m_shape = re.search(r"launch_nchunk:\s*(\d+)", text)
-    if not (m_hash and m_bytes and m_shape) or m_hash.group(1) != kernel_hash() or int(m_shape.group(1)) != nchunk:
+    m_shape = re.search(r"launch_layout:\s*(\S+)", text)
+    if not (m_hash and m_bytes and m_shape) or m_hash.group(1) != kernel_hash() or m_shape.group(1) != layout:
         return None
     return float(m_bytes.group(1))
+
+
+def layout_key(shape) -> str:
+    return f"W{shape['waves']}G{shape['groups']}S{int(bool(shape['setup']))}"
+
+
+def kernel_name(nd: int, mixed: bool, grad: bool, shape) -> str:
+    """The evaluation kernel's name as the profiler prints it: k_eval<ND, MIXED, GRAD, SETUP, CUT>."""
+    b = lambda x: "true" if x else "false"
+    return f"gwl::k_eval<{nd}, {b(mixed)}, {b(grad)}, {b(shape['setup'])}, false>"
 
 
 def load_or_tune(tune_out):
@@ -674,12 +686,13 @@ def main():
     ach, peak, frac = roofline(nd, True, M, B, r["mixed_kern_median"])
     a64, p64, f64 = roofline(nd, False, M, B, r["fp64_kern_median"])
     agm, pgm, fgm = roofline(nd, True, M, r["grad_batch"], r["grad_mixed_kern_median"], True)
-    traffic = read_traffic(r["shapes"]["mixed"]["nchunk"]) if args.config == 1 else None
-    mixed_line = {"value": B * r["mixed_steps"] / r["mixed_wall"], "kernel": f"k_bins_mixed<{nd},false>",
+    sh = r["shapes"]
+    traffic = read_traffic(layout_key(sh["mixed"])) if args.config == 1 else None
+    mixed_line = {"value": B * r["mixed_steps"] / r["mixed_wall"], "kernel": kernel_name(nd, True, False, sh["mixed"]),
                   "kernel_ms_median": r["mixed_kern_median"] * 1e3, "kernel_ms_mean": r["mixed_kern"] * 1e3,
                   "call_ms_median": r["mixed_call_median"] * 1e3,
                   "roofline": {"bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": frac}}
-    fp64_line = {"value": r["fp64_evals"], "kernel": f"k_bins_f64<{nd},false>",
+    fp64_line = {"value": r["fp64_evals"], "kernel": kernel_name(nd, False, False, sh["fp64"]),
                  "kernel_ms_median": r["fp64_kern_median"] * 1e3, "kernel_ms_mean": r["fp64_kern"] * 1e3,
                  "call_ms_median": r["fp64_call_median"] * 1e3,
                  "roofline": {"bound": "alu", "achieved": a64, "peak": p64, "unit": "TFLOP/s", "frac": f64}}
@@ -689,7 +702,7 @@ def main():
         steps_head, wall_head, dtype, prec = r["fp64_steps"], r["fp64_wall"], "f64", "fp64"
     elif args.config == 3:     # the gradient workload: forward + adjoint, mixed
         metric = f"logL+gradient evals/sec ({band}, 11 parameters) mixed vs FP64; frac VALU peak"
-        head = {"value": r["grad_mixed_evals"], "kernel": f"k_bins_mixed<{nd},true>",
+        head = {"value": r["grad_mixed_evals"], "kernel": kernel_name(nd, True, True, sh["mixed_grad"]),
                 "kernel_ms_median": r["grad_mixed_kern_median"] * 1e3, "kernel_ms_mean": r["grad_mixed_kern"] * 1e3,
                 "call_ms_median": r["grad_mixed_call_median"] * 1e3,
                 "roofline": {"bound": "alu", "achieved": agm, "peak": pgm, "unit": "TFLOP/s", "frac": fgm}}

@@ -38,11 +38,25 @@ def test_roofline_fraction_is_one_at_the_model_minimum_time():
     assert half == pytest.approx(0.5, rel=1e-12)
 
 
-def test_traffic_summary_is_used_only_for_its_kernel_source_and_shape():
+def test_traffic_summary_is_used_only_for_its_kernel_source_and_layout(tmp_path, monkeypatch):
+    layout = bench.layout_key({"waves": 16, "groups": 1, "setup": False})
+    assert layout == "W16G1S0"
+    f = tmp_path / "traffic.txt"
+    f.write_text(f"launch_layout: {layout}\nhbm_bytes_per_launch: 1.25e+08\n"
+                 f"kernel_source_sha256_16: {bench.kernel_hash()}\n")
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    assert bench.read_traffic(layout) == pytest.approx(1.25e8)
+    assert bench.read_traffic("W8G2S1") is None                  # another launch layout
+    f.write_text(f"launch_layout: {layout}\nhbm_bytes_per_launch: 1.25e+08\nkernel_source_sha256_16: 0123\n")
+    assert bench.read_traffic(layout) is None                    # counters taken on other kernel sources
+
+
+def test_committed_traffic_summary_parses():
+    import os
+    if not os.path.exists(bench.TRAFFIC_FILE):
+        pytest.skip("no HBM counter summary committed for the evaluation kernel")
     text = open(bench.TRAFFIC_FILE).read()
-    nchunk = int(text.split("launch_nchunk:")[1].split()[0])
-    assert bench.read_traffic(nchunk + 1) is None              # another launch shape
+    layout = text.split("launch_layout:")[1].split()[0]
     if bench.kernel_hash() not in text:
         pytest.skip("the kernel sources changed since the traffic counters were taken")
-    value = bench.read_traffic(nchunk)
-    assert value == pytest.approx(float(text.split("hbm_bytes_per_launch:")[1].split()[0]))
+    assert bench.read_traffic(layout) == pytest.approx(float(text.split("hbm_bytes_per_launch:")[1].split()[0]))
