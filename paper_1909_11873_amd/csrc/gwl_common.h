@@ -32,8 +32,8 @@ struct EventConst {
   int bad;            // nonzero if an input value was rejected
   int pad;
   int isco;           // 1: the model is zero above the ISCO frequency (GWL_F_ISCO_CUTOFF)
-  int pad2;
-  double grid_df;     // (fmax - fmin) / (M - 1): first guess of a frequency's bin
+  int uniform;        // 1: every grid step is grid_df to within 8 ulp of fmax (see grid_is_uniform)
+  double grid_df;     // (fmax - fmin) / (M - 1): first guess of a frequency's bin, uniform step
   double fmin, fmax;  // lowest and highest grid frequency
   double gmax[NBASIS];// max over [fmin, fmax] of |g_m(f)|: bounds the phase range of a point
   // Relative binning: the fiducial waveform's phase coefficients and detector shifts. The set-up

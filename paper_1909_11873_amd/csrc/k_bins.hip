@@ -99,7 +99,7 @@ using TabRow = typename std::conditional<MIXED, RowMixed<ND>, RowF64<ND>>::type;
 // Wavefronts per SIMD that the register budget must allow (as the bin loop alone needs): the
 // reduction and epilogue after the loop would otherwise let the compiler take registers that
 // cost a wavefront per SIMD. The in-kernel set-up needs more and is not bounded.
-template <int ND, bool MIXED, bool GRAD, bool SETUP, bool CUT>
+template <int ND, bool MIXED, bool GRAD, bool SETUP, bool CUT, bool ROT>
 constexpr int eval_waves_per_eu() {
   return (SETUP || CUT) ? 1 : (ND > 3 ? 1 : (MIXED ? (GRAD ? 5 : 8) : (GRAD ? 4 : 5)));
 }
@@ -107,10 +107,11 @@ constexpr int eval_waves_per_eu() {
 // CUT: the optional ISCO cut-off; every lane keeps only the bins at or below its point's ISCO
 // frequency (isco_bins over fgrid), the wavefront stops at the last bin any of its lanes keeps,
 // and <h|h> takes the kept bins' share of K_det from the per-detector running sums kcum
-// [ND][M + 1].
-template <int ND, bool MIXED, bool GRAD, bool SETUP, bool CUT>
+// [ND][M + 1]. ROT (float64, uniform grids): the detectors after the first take their phasors by
+// rotation from the first's (bin_loop_f64_rot).
+template <int ND, bool MIXED, bool GRAD, bool SETUP, bool CUT, bool ROT>
 __global__ __launch_bounds__(WAVE * MAX_EVAL_WAVES)
-__attribute__((amdgpu_waves_per_eu(eval_waves_per_eu<ND, MIXED, GRAD, SETUP, CUT>()))) void k_eval(
+__attribute__((amdgpu_waves_per_eu(eval_waves_per_eu<ND, MIXED, GRAD, SETUP, CUT, ROT>()))) void k_eval(
     const TabRow<ND, MIXED>* __restrict__ tab, const RowGradF64* __restrict__ gtab, const double* __restrict__ theta,
     EventGeom geo, const EventConst* __restrict__ ec, const double* __restrict__ coef, int64_t B, int64_t Bp, int64_t M,
     LoopShape sh, double* __restrict__ part, unsigned int* __restrict__ cnt, double* __restrict__ logl,
@@ -191,8 +192,12 @@ __attribute__((amdgpu_waves_per_eu(eval_waves_per_eu<ND, MIXED, GRAD, SETUP, CUT
       load_coef<ND, double>(coef, Bp, pc, GRAD, a, T, cr, ci);
     }
     to_table_units<ND>(a, T);
-    bin_loop_f64<ND, GRAD, const TabRow<ND, MIXED>*, const RowGradF64*, CUT>(tab, gtab, k0, k1, a, T, cr, ci, tbl,
-                                                                              tot, kc);
+    if constexpr (ROT)
+      bin_loop_f64_rot<ND, GRAD, const TabRow<ND, MIXED>*, const RowGradF64*>(tab, gtab, k0, k1, a, T, cr, ci, tbl,
+                                                                              ec->grid_df, tot);
+    else
+      bin_loop_f64<ND, GRAD, const TabRow<ND, MIXED>*, const RowGradF64*, CUT>(tab, gtab, k0, k1, a, T, cr, ci, tbl,
+                                                                                tot, kc);
   }
 
   // the W chunk sums of this workgroup, added in wavefront order by the first wavefront; the
@@ -268,33 +273,38 @@ __attribute__((amdgpu_waves_per_eu(eval_waves_per_eu<ND, MIXED, GRAD, SETUP, CUT
 }
 
 template <int ND, bool MIXED, bool GRAD>
-static hipError_t eval_setup(bool setup, bool cut, const void* tab, const RowGradF64* gtab, const double* theta,
+static hipError_t eval_setup(bool setup, bool cut, bool rot, const void* tab, const RowGradF64* gtab, const double* theta,
                              const EventGeom& geo, const EventConst* ec, const double* coef, int64_t B, int64_t Bp,
                              int64_t M, const LoopShape& sh, double* part, unsigned int* cnt, double* logl,
                              const double* fgrid, const double* kcum, hipStream_t s) {
   const dim3 grid((unsigned)(sh.gper * NXCD)), block((unsigned)(sh.W * WAVE));
   const size_t lds = eval_lds_doubles(MIXED, sh) * sizeof(double);
   const TabRow<ND, MIXED>* t = (const TabRow<ND, MIXED>*)tab;
-#define GWL_EVAL(ST, CU)                                                                                          \
-  hipLaunchKernelGGL((k_eval<ND, MIXED, GRAD, ST, CU>), grid, block, lds, s, t, gtab, theta, geo, ec, coef, B, Bp, M, \
-                     sh, part, cnt, logl, fgrid, kcum)
+#define GWL_EVAL(ST, CU, RO)                                                                                  \
+  hipLaunchKernelGGL((k_eval<ND, MIXED, GRAD, ST, CU, RO>), grid, block, lds, s, t, gtab, theta, geo, ec, coef, B, \
+                     Bp, M, sh, part, cnt, logl, fgrid, kcum)
   if (cut) {
-    if (setup) GWL_EVAL(true, true); else GWL_EVAL(false, true);
+    if (setup) GWL_EVAL(true, true, false); else GWL_EVAL(false, true, false);
+  } else if (MIXED || !rot) {
+    if (setup) GWL_EVAL(true, false, false); else GWL_EVAL(false, false, false);
   } else {
-    if (setup) GWL_EVAL(true, false); else GWL_EVAL(false, false);
+    if constexpr (!MIXED) {
+      if (setup) GWL_EVAL(true, false, true); else GWL_EVAL(false, false, true);
+    }
   }
 #undef GWL_EVAL
   return hipGetLastError();
 }
 
 template <int ND>
-static hipError_t eval_nd(bool mixed, bool grad, bool cut, const void* tab, const RowGradF64* gtab,
+static hipError_t eval_nd(bool mixed, bool grad, bool cut, bool rot, const void* tab, const RowGradF64* gtab,
                           const double* theta, const EventGeom& geo, const EventConst* ec, const double* coef,
                           int64_t B, int64_t Bp, int64_t M, const LoopShape& sh, double* part, unsigned int* cnt,
                           double* logl, const double* fgrid, const double* kcum, hipStream_t s) {
   const bool st = sh.setup != 0;
 #define GWL_EV(MX, GR) \
-  return eval_setup<ND, MX, GR>(st, cut, tab, gtab, theta, geo, ec, coef, B, Bp, M, sh, part, cnt, logl, fgrid, kcum, s)
+  return eval_setup<ND, MX, GR>(st, cut, rot, tab, gtab, theta, geo, ec, coef, B, Bp, M, sh, part, cnt, logl, fgrid, \
+                                kcum, s)
   if (mixed) {
     if (grad) GWL_EV(true, true);
     GWL_EV(true, false);
@@ -304,7 +314,7 @@ static hipError_t eval_nd(bool mixed, bool grad, bool cut, const void* tab, cons
 #undef GWL_EV
 }
 
-hipError_t launch_eval(int nd, bool mixed, bool grad, const void* tab, const RowGradF64* gtab, const double* theta,
+hipError_t launch_eval(int nd, bool mixed, bool grad, bool rot, const void* tab, const RowGradF64* gtab, const double* theta,
                        const EventGeom& geo, const EventConst* ec, const double* coef, int64_t B, int64_t Bp,
                        int64_t M, const LoopShape& sh, double* part, unsigned int* cnt, double* logl,
                        const double* fgrid, const double* kcum, hipStream_t s) {
@@ -315,10 +325,10 @@ hipError_t launch_eval(int nd, bool mixed, bool grad, const void* tab, const Row
   const bool cut = fgrid != nullptr;
   if (cut && !kcum) return hipErrorInvalidValue;
   switch (nd) {
-    case 1: return eval_nd<1>(mixed, grad, cut, tab, gtab, theta, geo, ec, coef, B, Bp, M, sh, part, cnt, logl, fgrid, kcum, s);
-    case 2: return eval_nd<2>(mixed, grad, cut, tab, gtab, theta, geo, ec, coef, B, Bp, M, sh, part, cnt, logl, fgrid, kcum, s);
-    case 3: return eval_nd<3>(mixed, grad, cut, tab, gtab, theta, geo, ec, coef, B, Bp, M, sh, part, cnt, logl, fgrid, kcum, s);
-    case 4: return eval_nd<4>(mixed, grad, cut, tab, gtab, theta, geo, ec, coef, B, Bp, M, sh, part, cnt, logl, fgrid, kcum, s);
+    case 1: return eval_nd<1>(mixed, grad, cut, rot, tab, gtab, theta, geo, ec, coef, B, Bp, M, sh, part, cnt, logl, fgrid, kcum, s);
+    case 2: return eval_nd<2>(mixed, grad, cut, rot, tab, gtab, theta, geo, ec, coef, B, Bp, M, sh, part, cnt, logl, fgrid, kcum, s);
+    case 3: return eval_nd<3>(mixed, grad, cut, rot, tab, gtab, theta, geo, ec, coef, B, Bp, M, sh, part, cnt, logl, fgrid, kcum, s);
+    case 4: return eval_nd<4>(mixed, grad, cut, rot, tab, gtab, theta, geo, ec, coef, B, Bp, M, sh, part, cnt, logl, fgrid, kcum, s);
   }
   return hipErrorInvalidValue;
 }

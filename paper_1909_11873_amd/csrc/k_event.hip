@@ -179,7 +179,7 @@ __global__ __launch_bounds__(PREP_BLOCK) void k_prep_final(const double* __restr
     e.bad = red[ND + 1][0] != 0.0 || !isfinite(um);
     e.pad = 0;
     e.isco = 0;
-    e.pad2 = 0;
+    e.uniform = 0;
     e.grid_df = 0.0;
     e.fmin = red[ND + 2][0];
     e.fmax = red[ND + 3][0];

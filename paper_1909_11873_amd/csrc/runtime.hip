@@ -91,6 +91,17 @@ gwl_status check_device(int dev) {
 
 namespace gwl {
 
+// A grid is uniform when every step f_{k+1} - f_k equals the mean step (f_{M-1} - f_0) / (M - 1)
+// to within 8 ulp of the highest frequency: a grid built as f_0 + k df in float64 is uniform.
+static bool grid_is_uniform(const std::vector<double>& f, double& step) {
+  const size_t M = f.size();
+  step = M > 1 ? (f[M - 1] - f[0]) / (double)(M - 1) : 1.0;
+  const double tol = 8.0 * ldexp(fabs(f[M - 1]), -52);
+  for (size_t k = 0; k + 1 < M; ++k)
+    if (!(fabs((f[k + 1] - f[k]) - step) <= tol)) return false;
+  return true;
+}
+
 // Tables of the optional ISCO cut-off, built on the host in float64 (once per event): the grid
 // (which must increase) and per detector the running sums Kc[k] = sum_{j < k} 4 df f_j^(-7/3) / S_j,
 // k = 0..M, so that <h|h> of a point cut after its first kc bins is A^2 |Q_det|^2 Kc[kc].
@@ -187,6 +198,21 @@ gwl_status gwl_event_create(const double* data, const double* psd, const gwl_det
     return fail(GWL_E_INVALID, "rejected inputs: every PSD value and frequency must be finite and positive and "
                                "every data value finite");
   }
+  // the grid's step, and whether the float64 loop may carry detector phasors by a fixed rotation
+  {
+    std::vector<double> fh((size_t)M);
+    e = hipMemcpyAsync(fh.data(), fgrid, sizeof(double) * M, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) {
+      ev->ech.uniform = grid_is_uniform(fh, ev->ech.grid_df) ? 1 : 0;
+      e = hipMemcpyAsync(ev->ec, &ev->ech, sizeof(EventConst), hipMemcpyHostToDevice, s);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      gwl_event_destroy(ev);
+      return hip_fail(e, "grid read-back");
+    }
+  }
   if (flags & GWL_F_ISCO_CUTOFF) {
     st = isco_tables(ev, fgrid, psd, s);
     if (st != GWL_OK) {
@@ -277,7 +303,8 @@ gwl_status gwl_event_create_rb(const double* data, const double* psd, const gwl_
     gwl_event_destroy(ev);
     return fail(GWL_E_INVALID, "theta_fid is outside the model's domain");
   }
-  // edge tables
+  // edge tables (the edges are not a uniform grid)
+  ev->ech.uniform = 0;
   if (e == hipSuccess) e = hipMemcpyAsync(ev->ec, &ev->ech, sizeof(EventConst), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMalloc((void**)&d_idx, sizeof(int64_t) * nedge);
   if (e == hipSuccess) e = hipMemcpyAsync(d_idx, idx.data(), sizeof(int64_t) * nedge, hipMemcpyHostToDevice, s);
@@ -821,7 +848,7 @@ hipError_t enqueue_logl(gwl_event ev, const double* theta, int64_t B, bool mixed
   hipEvent_t pa = nullptr, pb = nullptr;
   const bool prof = e == hipSuccess && prof_begin(s, pa, pb);
   if (e == hipSuccess)
-    e = launch_eval(ev->ndet, mixed, grad, mixed ? ev->tab32 : ev->tab64, ev->g64, theta, ev->geom, ev->ec, coef, B, Bp,
+    e = launch_eval(ev->ndet, mixed, grad, ev->ech.uniform != 0, mixed ? ev->tab32 : ev->tab64, ev->g64, theta, ev->geom, ev->ec, coef, B, Bp,
                     ev->M, sh, part, cnt, logl, ev->fgrid, ev->kcum, s);
   if (prof) prof_end(s, pa, pb);
   if (e == hipSuccess && grad)
