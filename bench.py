@@ -570,14 +570,15 @@ def ns_leg(cfg: int, nlive: int, batches, eps: float, proposal: str = "slice", s
     transform = nested.gw_prior_transform(mc_range=spec.mc_range, spins=spec.spins)
     if load_or_tune(tune_out):
         # the likelihood batches a slice-sampling run makes: the live points, then per move the
-        # 2m stepping-out ends and the groups of shrinkage draws of every chain
+        # m - 1 stepping-out ends and the groups of shrinkage draws of every chain
         m = 4                                              # the sampler's default stepping-out limit
-        shapes = {nlive} | {k * n for n in batches for k in (2 * m, nested.SLICE_GROUP)}
+        shapes = {nlive} | {k * n for n in batches for k in (m - 1, nested.SLICE_GROUP)}
         for b in sorted(shapes):
             gw.autotune(ev, b, "mixed", cache_path=tune_out)
     rows = []
     for n in batches:
-        kw = dict(device=dev, seed=seed, prior_transform=transform, proposal=proposal)
+        kw = dict(device=dev, seed=seed, prior_transform=transform, proposal=proposal,
+                  loglike_live=lambda th, live: gw.logl_live(th, live, ev, "mixed"))
         if proposal == "gmc":
             kw.update(loglike_grad=lambda th: gw.logl_grad(th, ev, "mixed"), gmc_steps=10)
         last = None

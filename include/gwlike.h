@@ -193,6 +193,17 @@ gwl_status gwl_logl_batch(gwl_event ev, const double* theta, int64_t B, gwl_prec
                           void* stream);
 
 /*
+ * gwl_logl_batch over a batch whose length the device decides: only the first *live points of
+ * theta[B][11] are evaluated and written to logl (the rest of logl is left as it was), with
+ * live a device int64 read by the kernels when they run (values above B count as B, below 1 as
+ * none). The launch is sized for B, so the call can be captured once and replayed for batches
+ * of any length up to B, e.g. the shrinkage draws of the slice-sampling chains still moving
+ * (gwl_slice_draws sets *live). Not for calibrated events (GWL_E_UNSUPPORTED).
+ */
+gwl_status gwl_logl_batch_live(gwl_event ev, const double* theta, int64_t B, const int64_t* live, gwl_precision prec,
+                               double* logl, void* stream);
+
+/*
  * Grow the event's workspace on `stream` to what a gwl_logl_batch (with_grad = 0) or
  * gwl_logl_grad (with_grad = 1) call with these arguments needs, so that such calls allocate
  * nothing, also under graph capture. Must not be called while `stream` is capturing (it may
@@ -330,33 +341,46 @@ gwl_status gwl_profile_read(int64_t* launches, double* total_ms);
  * device double; `done` is one byte per chain (0 or 1). Every product and sum is rounded on its
  * own, in the order written above (no fused multiply-add), so the results equal those of the
  * same steps taken one array operation at a time. Calls are stream-ordered on `stream`;
- * GWL_E_SHAPE for n < 1, d < 1, m < 1 or G < 1, GWL_E_INVALID for a null pointer.
+ * GWL_E_SHAPE for n < 1, d < 1, m < 1 or G < 1, for more than 2^30 points (m n or G n) or more
+ * than 2^31 coordinates (m n d or G n d); GWL_E_INVALID for a null pointer.
  *
- * gwl_slice_ends: lo = -u0, hi = 1 - u0, jl, jr as above, and the 2m candidate ends of every
- *   chain, pts[(j n + i) d ..] = x_i + (lo_i - j) dirn_i and pts[((m + j) n + i) d ..] =
- *   x_i + (hi_i + j) dirn_i for j = 0..m-1.
- * gwl_slice_ends_select: with logl[2m n] the values at those ends: lo -= min(steps left, jl),
- *   hi += min(steps right, jr), where the steps on a side are the index of its first end outside
- *   the region (m if none).
- * gwl_slice_draws: G shrinkage draws per chain, each from the interval as it would be if the
- *   earlier draws had fallen outside: t_k = a + u_k (b - a) from (a, b) = (lo, hi), then a = t_k
- *   if t_k < 0 else b = t_k; writes t[k n + i], the points pts[(k n + i) d ..] = x_i + t_k dirn_i,
- *   and the final (a, b).
- * gwl_slice_select: with logl[G n] the values at those points, for every chain not yet done:
- *   the first draw inside the region (if any) gives xn = x + t dirn and done = 1; a chain still
- *   not done takes (lo, hi) = (a, b). The cube test recomputes x + t dirn with the same rounding
- *   as the points gwl_slice_draws wrote, so those points are not read again.
+ * gwl_slice_ends: lo = -u0, hi = 1 - u0, jl, jr as above, and the m - 1 ends each chain's stepping
+ *   out may examine (its left ends lo - s for s < jl and right ends hi + s for s < jr): slot s of
+ *   chain i, pts[(s n + i) d ..] = x_i + t dirn_i with t = lo_i - s for s < jl_i and
+ *   t = hi_i + (s - jl_i) above; pts holds (m - 1) n rows (none for m = 1, when pts may be null).
+ * gwl_slice_ends_select: with logl[(m - 1) n] the values at those slots: lo -= the number of left
+ *   ends inside before the first outside (jl if none), hi += the same on the right (jr if none).
+ *   Nothing to do for m = 1.
+ * The shrinkage draws of a move come in groups of G, each group for the chains still moving,
+ * listed in list[0 .. *nact) (int32 chain indices, device; *nact a device int64, taken as at
+ * most n; entries outside [0, n) are skipped):
+ * gwl_slice_list_init: list = 0, 1, .., n - 1 and *nact = n (the first group of a move).
+ * gwl_slice_draws: for list entry j (chain i = list[j]), G draws, each from the interval as it
+ *   would be if the earlier draws had fallen outside: t_k = a + u_k (b - a) from (a, b) =
+ *   (lo, hi), then a = t_k if t_k < 0 else b = t_k, with u_k = u[k n + i]; writes t[j G + k],
+ *   the points pts[(j G + k) d ..] = x_i + t_k dirn_i (the live points are the first *nact G
+ *   rows of pts[G n][d]), a[i] and b[i]. Sets *live = *nact G (for gwl_logl_batch_live), adds
+ *   it to *calls if calls is not null, and sets *nact_next = 0. nact_next must not be nact.
+ * gwl_slice_select: with logl[*nact G] the values at those points, for every listed chain not
+ *   yet done: the first draw inside the region (if any) gives xn = x + t dirn and done = 1;
+ *   otherwise the chain takes (lo, hi) = (a, b) and is appended to list_next (*nact_next counts
+ *   them; the order of the appended chains depends on scheduling). list_next and nact_next must
+ *   differ from list and nact. The cube test recomputes x + t dirn with the same rounding as the
+ *   points gwl_slice_draws wrote, so those points are not read again.
  */
 gwl_status gwl_slice_ends(int64_t n, int d, int m, const double* x, const double* dirn, const double* u0,
                           const double* u1, double* pts, double* lo, double* hi, double* jl, double* jr, void* stream);
 gwl_status gwl_slice_ends_select(int64_t n, int d, int m, const double* pts, const double* logl, const double* lmin,
                                  double* lo, double* hi, const double* jl, const double* jr, void* stream);
-gwl_status gwl_slice_draws(int64_t n, int d, int G, const double* x, const double* dirn, const double* lo,
-                           const double* hi, const double* u, double* t, double* pts, double* a, double* b,
+gwl_status gwl_slice_list_init(int64_t n, int* list, int64_t* nact, void* stream);
+gwl_status gwl_slice_draws(int64_t n, int d, int G, const int* list, const int64_t* nact, const double* x,
+                           const double* dirn, const double* lo, const double* hi, const double* u, double* t,
+                           double* pts, double* a, double* b, int64_t* live, int64_t* nact_next, int64_t* calls,
                            void* stream);
-gwl_status gwl_slice_select(int64_t n, int d, int G, const double* x, const double* dirn, const double* t,
-                            const double* logl, const double* lmin, const double* a, const double* b, double* xn,
-                            unsigned char* done, double* lo, double* hi, void* stream);
+gwl_status gwl_slice_select(int64_t n, int d, int G, const int* list, const int64_t* nact, const double* x,
+                            const double* dirn, const double* t, const double* logl, const double* lmin,
+                            const double* a, const double* b, double* xn, unsigned char* done, double* lo, double* hi,
+                            int* list_next, int64_t* nact_next, void* stream);
 
 /*
  * Prior transform for a sampler above the likelihood (the prior-sampling step of the paper's

@@ -44,11 +44,12 @@ hipError_t launch_setup(int nd, const EventGeom& g, const EventConst* ec, bool s
 // workgroup sums go to part [G][nz][Bp] for the gradient epilogue
 // fgrid [M] and kcum [nd][M + 1] (running sums of the K_det terms) for an event with the ISCO
 // cut-off, else both null; rot: a float64 call on a uniform grid may take the detectors after
-// the first by rotation (ignored with the cut-off and in mixed precision)
+// the first by rotation (ignored with the cut-off and in mixed precision); live (device, may be
+// null): only the first *live points are evaluated and written
 hipError_t launch_eval(int nd, bool mixed, bool grad, bool rot, const void* tab, const RowGradF64* gtab, const double* theta,
                        const EventGeom& geo, const EventConst* ec, const double* coef, int64_t B, int64_t Bp,
                        int64_t M, const LoopShape& sh, double* part, unsigned int* cnt, double* logl,
-                       const double* fgrid, const double* kcum, hipStream_t s);
+                       const double* fgrid, const double* kcum, const int64_t* live, hipStream_t s);
 
 // epilogue: partial sums [nchunk][nz][Bp] -> logL[B] (and grad[B][11]); the value alone reads the
 // set-up rows `coef`, the gradient evaluates the point model from theta

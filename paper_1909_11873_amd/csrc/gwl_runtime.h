@@ -90,8 +90,9 @@ void choose_multi_shape(const gwl_event* evs, int E, const int64_t* B_e, bool mi
 // fill theta[B][P] with valid parameter points (timing inputs; P >= 11, zeros past column 11)
 hipError_t fill_theta(double* theta, int64_t B, hipStream_t s, int P = NPARAM);
 
+// live (device, may be null): evaluate only the first *live of the B points
 gwl_status run_logl(gwl_event ev, const double* theta, int64_t B, bool mixed, bool grad, const LoopShape& sh,
-                    double* logl, double* gradout, hipStream_t s);
+                    double* logl, double* gradout, hipStream_t s, const int64_t* live = nullptr);
 // a call on a calibrated event (its own set-up, bin loop and epilogue kernels)
 gwl_status run_calibrated(gwl_event ev, const double* theta, int64_t B, bool mixed, bool grad, double* logl,
                           double* gradout, hipStream_t s);
@@ -104,6 +105,7 @@ gwl_status event_workspace(gwl_event ev, hipStream_t s, size_t bytes, size_t ncn
 // Workspace bytes a single-event call of this kind needs.
 size_t call_workspace_bytes(const gwl_event_s* ev, int64_t B, bool mixed, bool grad);
 hipError_t enqueue_logl(gwl_event ev, const double* theta, int64_t B, bool mixed, bool grad, const LoopShape& sh,
-                        double* ws, unsigned int* cnt, double* logl, double* gradout, hipStream_t s);
+                        double* ws, unsigned int* cnt, double* logl, double* gradout, hipStream_t s,
+                        const int64_t* live = nullptr);
 
 }  // namespace gwl

@@ -115,7 +115,7 @@ __attribute__((amdgpu_waves_per_eu(eval_waves_per_eu<ND, MIXED, GRAD, SETUP, CUT
     const TabRow<ND, MIXED>* __restrict__ tab, const RowGradF64* __restrict__ gtab, const double* __restrict__ theta,
     EventGeom geo, const EventConst* __restrict__ ec, const double* __restrict__ coef, int64_t B, int64_t Bp, int64_t M,
     LoopShape sh, double* __restrict__ part, unsigned int* __restrict__ cnt, double* __restrict__ logl,
-    const double* __restrict__ fgrid, const double* __restrict__ kcum) {
+    const double* __restrict__ fgrid, const double* __restrict__ kcum, const int64_t* __restrict__ live) {
   constexpr int NZ = nz_of(ND, GRAD);
   extern __shared__ double lds[];
   double* rows_s = lds;                                        // [NCOEF][64] when SETUP
@@ -127,6 +127,12 @@ __attribute__((amdgpu_waves_per_eu(eval_waves_per_eu<ND, MIXED, GRAD, SETUP, CUT
   if (item >= sh.items) return;                                // whole workgroup
   const int g = item / sh.npg;
   const int pg = item - g * sh.npg;
+  // live: only the first *live points are evaluated (a batch whose length the device decides)
+  if (live) {
+    const int64_t nl = *live;
+    B = nl < B ? nl : B;
+  }
+  if ((int64_t)pg * WAVE >= B) return;                         // whole workgroup
   // the wavefront index is uniform across the wavefront; readfirstlane tells the compiler so, which
   // keeps the chunk's bin range, and with it every table row, in scalar registers
   const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
@@ -276,13 +282,13 @@ template <int ND, bool MIXED, bool GRAD>
 static hipError_t eval_setup(bool setup, bool cut, bool rot, const void* tab, const RowGradF64* gtab, const double* theta,
                              const EventGeom& geo, const EventConst* ec, const double* coef, int64_t B, int64_t Bp,
                              int64_t M, const LoopShape& sh, double* part, unsigned int* cnt, double* logl,
-                             const double* fgrid, const double* kcum, hipStream_t s) {
+                             const double* fgrid, const double* kcum, const int64_t* live, hipStream_t s) {
   const dim3 grid((unsigned)(sh.gper * NXCD)), block((unsigned)(sh.W * WAVE));
   const size_t lds = eval_lds_doubles(MIXED, sh) * sizeof(double);
   const TabRow<ND, MIXED>* t = (const TabRow<ND, MIXED>*)tab;
 #define GWL_EVAL(ST, CU, RO)                                                                                  \
   hipLaunchKernelGGL((k_eval<ND, MIXED, GRAD, ST, CU, RO>), grid, block, lds, s, t, gtab, theta, geo, ec, coef, B, \
-                     Bp, M, sh, part, cnt, logl, fgrid, kcum)
+                     Bp, M, sh, part, cnt, logl, fgrid, kcum, live)
   if (cut) {
     if (setup) GWL_EVAL(true, true, false); else GWL_EVAL(false, true, false);
   } else if (MIXED || !rot) {
@@ -300,11 +306,12 @@ template <int ND>
 static hipError_t eval_nd(bool mixed, bool grad, bool cut, bool rot, const void* tab, const RowGradF64* gtab,
                           const double* theta, const EventGeom& geo, const EventConst* ec, const double* coef,
                           int64_t B, int64_t Bp, int64_t M, const LoopShape& sh, double* part, unsigned int* cnt,
-                          double* logl, const double* fgrid, const double* kcum, hipStream_t s) {
+                          double* logl, const double* fgrid, const double* kcum, const int64_t* live,
+                          hipStream_t s) {
   const bool st = sh.setup != 0;
 #define GWL_EV(MX, GR) \
   return eval_setup<ND, MX, GR>(st, cut, rot, tab, gtab, theta, geo, ec, coef, B, Bp, M, sh, part, cnt, logl, fgrid, \
-                                kcum, s)
+                                kcum, live, s)
   if (mixed) {
     if (grad) GWL_EV(true, true);
     GWL_EV(true, false);
@@ -317,7 +324,7 @@ static hipError_t eval_nd(bool mixed, bool grad, bool cut, bool rot, const void*
 hipError_t launch_eval(int nd, bool mixed, bool grad, bool rot, const void* tab, const RowGradF64* gtab, const double* theta,
                        const EventGeom& geo, const EventConst* ec, const double* coef, int64_t B, int64_t Bp,
                        int64_t M, const LoopShape& sh, double* part, unsigned int* cnt, double* logl,
-                       const double* fgrid, const double* kcum, hipStream_t s) {
+                       const double* fgrid, const double* kcum, const int64_t* live, hipStream_t s) {
   if (sh.W < 1 || sh.W > MAX_EVAL_WAVES || sh.G < 1) return hipErrorInvalidValue;
   if ((grad || sh.G > 1) && !part) return hipErrorInvalidValue;
   if (!grad && sh.G > 1 && !cnt) return hipErrorInvalidValue;
@@ -325,10 +332,10 @@ hipError_t launch_eval(int nd, bool mixed, bool grad, bool rot, const void* tab,
   const bool cut = fgrid != nullptr;
   if (cut && !kcum) return hipErrorInvalidValue;
   switch (nd) {
-    case 1: return eval_nd<1>(mixed, grad, cut, rot, tab, gtab, theta, geo, ec, coef, B, Bp, M, sh, part, cnt, logl, fgrid, kcum, s);
-    case 2: return eval_nd<2>(mixed, grad, cut, rot, tab, gtab, theta, geo, ec, coef, B, Bp, M, sh, part, cnt, logl, fgrid, kcum, s);
-    case 3: return eval_nd<3>(mixed, grad, cut, rot, tab, gtab, theta, geo, ec, coef, B, Bp, M, sh, part, cnt, logl, fgrid, kcum, s);
-    case 4: return eval_nd<4>(mixed, grad, cut, rot, tab, gtab, theta, geo, ec, coef, B, Bp, M, sh, part, cnt, logl, fgrid, kcum, s);
+    case 1: return eval_nd<1>(mixed, grad, cut, rot, tab, gtab, theta, geo, ec, coef, B, Bp, M, sh, part, cnt, logl, fgrid, kcum, live, s);
+    case 2: return eval_nd<2>(mixed, grad, cut, rot, tab, gtab, theta, geo, ec, coef, B, Bp, M, sh, part, cnt, logl, fgrid, kcum, live, s);
+    case 3: return eval_nd<3>(mixed, grad, cut, rot, tab, gtab, theta, geo, ec, coef, B, Bp, M, sh, part, cnt, logl, fgrid, kcum, live, s);
+    case 4: return eval_nd<4>(mixed, grad, cut, rot, tab, gtab, theta, geo, ec, coef, B, Bp, M, sh, part, cnt, logl, fgrid, kcum, live, s);
   }
   return hipErrorInvalidValue;
 }

@@ -648,6 +648,23 @@ gwl_status gwl_logl_batch(gwl_event ev, const double* theta, int64_t B, gwl_prec
   return logl_common(ev, theta, B, prec, logl, nullptr, false, stream);
 }
 
+gwl_status gwl_logl_batch_live(gwl_event ev, const double* theta, int64_t B, const int64_t* live, gwl_precision prec,
+                               double* logl, void* stream) {
+  clear_error();
+  if (!ev) return fail(GWL_E_INVALID, "event is null");
+  if (B < 0 || B > kMaxBatch) return fail(GWL_E_SHAPE, "B=%lld outside [0, %lld]", (long long)B, (long long)kMaxBatch);
+  if (prec != GWL_FP64 && prec != GWL_MIXED) return fail(GWL_E_INVALID, "unknown precision %d", (int)prec);
+  if (!live) return fail(GWL_E_INVALID, "live must be a device pointer");
+  if (B == 0) return GWL_OK;
+  if (!theta || !logl) return fail(GWL_E_INVALID, "theta and logl must be device pointers");
+  if (ev->ncal > 0) return fail(GWL_E_UNSUPPORTED, "gwl_logl_batch_live does not take calibrated events");
+  gwl_status st = check_device(ev->device);
+  if (st != GWL_OK) return st;
+  const bool mixed = use_mixed(ev, prec);
+  return run_logl(ev, theta, B, mixed, false, choose_shape(ev, B, mixed, false), logl, nullptr, (hipStream_t)stream,
+                  live);
+}
+
 gwl_status gwl_logl_grad(gwl_event ev, const double* theta, int64_t B, gwl_precision prec, double* logl, double* grad,
                          void* stream) {
   return logl_common(ev, theta, B, prec, logl, grad, true, stream);
@@ -734,14 +751,14 @@ size_t workspace_counters(const LoopShape& sh, bool grad) { return (!grad && sh.
 
 // Set-up, bin loop and epilogue on `s`, in the event's workspace for `s`.
 gwl_status run_logl(gwl_event ev, const double* theta, int64_t B, bool mixed, bool grad, const LoopShape& sh,
-                    double* logl, double* gradout, hipStream_t s) {
+                    double* logl, double* gradout, hipStream_t s, const int64_t* live) {
   const int64_t Bp = (int64_t)sh.npg * WAVE;
   void* ws = nullptr;
   unsigned int* cnt = nullptr;
   gwl_status st = event_workspace(ev, s, workspace_bytes(Bp, sh, ev->ndet, grad), workspace_counters(sh, grad), &ws,
                                   &cnt);
   if (st != GWL_OK) return st;
-  hipError_t e = enqueue_logl(ev, theta, B, mixed, grad, sh, (double*)ws, cnt, logl, gradout, s);
+  hipError_t e = enqueue_logl(ev, theta, B, mixed, grad, sh, (double*)ws, cnt, logl, gradout, s, live);
   if (e != hipSuccess) return hip_fail(e, "launch");
   return GWL_OK;
 }
@@ -839,7 +856,8 @@ static void prof_end(hipStream_t s, hipEvent_t a, hipEvent_t b) {
 }
 
 hipError_t enqueue_logl(gwl_event ev, const double* theta, int64_t B, bool mixed, bool grad, const LoopShape& sh,
-                        double* ws, unsigned int* cnt, double* logl, double* gradout, hipStream_t s) {
+                        double* ws, unsigned int* cnt, double* logl, double* gradout, hipStream_t s,
+                        const int64_t* live) {
   const int64_t Bp = (int64_t)sh.npg * WAVE;
   double* coef = sh.setup ? nullptr : ws;
   double* part = (grad || sh.G > 1) ? ws + (sh.setup ? 0 : (size_t)NCOEF * Bp) : nullptr;
@@ -848,8 +866,8 @@ hipError_t enqueue_logl(gwl_event ev, const double* theta, int64_t B, bool mixed
   hipEvent_t pa = nullptr, pb = nullptr;
   const bool prof = e == hipSuccess && prof_begin(s, pa, pb);
   if (e == hipSuccess)
-    e = launch_eval(ev->ndet, mixed, grad, ev->ech.uniform != 0, mixed ? ev->tab32 : ev->tab64, ev->g64, theta, ev->geom, ev->ec, coef, B, Bp,
-                    ev->M, sh, part, cnt, logl, ev->fgrid, ev->kcum, s);
+    e = launch_eval(ev->ndet, mixed, grad, ev->ech.uniform != 0, mixed ? ev->tab32 : ev->tab64, ev->g64, theta,
+                    ev->geom, ev->ec, coef, B, Bp, ev->M, sh, part, cnt, logl, ev->fgrid, ev->kcum, live, s);
   if (prof) prof_end(s, pa, pb);
   if (e == hipSuccess && grad)
     e = launch_epilogue(ev->ndet, true, mixed, ev->geom, ev->ec, theta, coef, B, Bp, sh.G, part, logl, gradout, s,

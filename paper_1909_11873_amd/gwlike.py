@@ -84,10 +84,12 @@ def lib() -> ctypes.CDLL:
         "gwl_logl_batch_noalloc": ([vp, vp, i64, cint, vp, vp], cint),
         "gwl_profile_enable": ([cint], cint),
         "gwl_profile_read": ([ctypes.POINTER(i64), ctypes.POINTER(dbl)], cint),
+        "gwl_logl_batch_live": ([vp, vp, i64, vp, cint, vp, vp], cint),
         "gwl_slice_ends": ([i64, cint, cint] + [vp] * 9 + [vp], cint),
         "gwl_slice_ends_select": ([i64, cint, cint] + [vp] * 7 + [vp], cint),
-        "gwl_slice_draws": ([i64, cint, cint] + [vp] * 9 + [vp], cint),
-        "gwl_slice_select": ([i64, cint, cint] + [vp] * 11 + [vp], cint),
+        "gwl_slice_list_init": ([i64, vp, vp, vp], cint),
+        "gwl_slice_draws": ([i64, cint, cint] + [vp] * 14 + [vp], cint),
+        "gwl_slice_select": ([i64, cint, cint] + [vp] * 15 + [vp], cint),
         "gwl_prior_transform": ([i64, cint] + [vp] * 5 + [vp], cint),
     }
     for name, (args, res) in sig.items():
@@ -229,6 +231,20 @@ def logl(theta: torch.Tensor, ev: Event, precision="mixed") -> torch.Tensor:
     out = torch.empty(theta.shape[0], dtype=torch.float64, device=theta.device)
     _check("gwl_logl_batch", lib().gwl_logl_batch(ev.handle, ctypes.c_void_p(theta.data_ptr()), theta.shape[0],
                                                   _prec(precision), ctypes.c_void_p(out.data_ptr()), _stream(theta)))
+    return out
+
+
+def logl_live(theta: torch.Tensor, live: torch.Tensor, ev: Event, precision="mixed",
+              out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """logL of the first `live` rows of theta[B, 11], live a device int64 scalar read when the
+    kernels run (gwl_logl_batch_live); the other entries of the result are left as they were."""
+    theta = _theta(theta, ev)
+    if not (isinstance(live, torch.Tensor) and live.is_cuda and live.dtype == torch.int64 and live.numel() == 1):
+        raise ValueError("live must be a CUDA int64 tensor with one element")
+    if out is None:
+        out = torch.empty(theta.shape[0], dtype=torch.float64, device=theta.device)
+    _check("gwl_logl_batch_live", lib().gwl_logl_batch_live(ev.handle, _ptr(theta), theta.shape[0], _ptr(live),
+                                                            _prec(precision), _ptr(out), _stream(theta)))
     return out
 
 
@@ -451,11 +467,12 @@ def _f64(t: torch.Tensor, name: str, shape) -> torch.Tensor:
 
 
 def slice_ends(x: torch.Tensor, dirn: torch.Tensor, u0: torch.Tensor, u1: torch.Tensor, m: int):
-    """(pts[2m n, d], lo, hi, jl, jr): the initial interval of every chain and its 2m candidate ends."""
+    """(pts[(m - 1) n, d], lo, hi, jl, jr): the initial interval of every chain and the m - 1 ends
+    its stepping out may examine (slot s of chain i at row s n + i)."""
     n, d = x.shape
     x, dirn = _f64(x, "x", (n, d)), _f64(dirn, "dirn", (n, d))
     u0, u1 = _f64(u0, "u0", (n,)), _f64(u1, "u1", (n,))
-    pts = torch.empty(2 * m * n, d, dtype=torch.float64, device=x.device)
+    pts = torch.empty(max(m - 1, 0) * n, d, dtype=torch.float64, device=x.device)
     lo, hi, jl, jr = (torch.empty(n, dtype=torch.float64, device=x.device) for _ in range(4))
     _check("gwl_slice_ends", lib().gwl_slice_ends(n, d, m, _ptr(x), _ptr(dirn), _ptr(u0), _ptr(u1), _ptr(pts),
                                                   _ptr(lo), _ptr(hi), _ptr(jl), _ptr(jr), _stream(x)))
@@ -463,48 +480,82 @@ def slice_ends(x: torch.Tensor, dirn: torch.Tensor, u0: torch.Tensor, u1: torch.
 
 
 def slice_ends_select(pts, logl, lmin, lo, hi, jl, jr, m: int) -> None:
-    """Steps the interval ends out (in place on lo, hi) given ln L at the candidate ends."""
+    """Steps the interval ends out (in place on lo, hi) given ln L at the m - 1 slots."""
     n = lo.shape[0]
     d = pts.shape[1]
     for t, name in ((lo, "lo"), (hi, "hi")):
         if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and t.shape == (n,)):
             raise ValueError(f"{name} must be a contiguous float64 CUDA tensor of shape ({n},)")
-    pts, logl = _f64(pts, "pts", (2 * m * n, d)), _f64(logl, "logl", (2 * m * n,))
+    pts, logl = _f64(pts, "pts", ((m - 1) * n, d)), _f64(logl, "logl", ((m - 1) * n,))
     lmin, jl, jr = _f64(lmin, "lmin", ()), _f64(jl, "jl", (n,)), _f64(jr, "jr", (n,))
     _check("gwl_slice_ends_select", lib().gwl_slice_ends_select(n, d, m, _ptr(pts), _ptr(logl), _ptr(lmin), _ptr(lo),
                                                                 _ptr(hi), _ptr(jl), _ptr(jr), _stream(pts)))
 
 
-def slice_draws(x, dirn, lo, hi, u):
-    """(t[G, n], pts[G n, d], a, b): G shrinkage draws per chain and the interval after them,
-    each draw taken as if the earlier ones had fallen outside."""
+def _list(lst, nact, n):
+    if not (isinstance(lst, torch.Tensor) and lst.is_cuda and lst.dtype == torch.int32 and lst.is_contiguous()
+            and tuple(lst.shape) == (n,)):
+        raise ValueError(f"a chain list must be a contiguous int32 CUDA tensor of shape ({n},)")
+    if not (isinstance(nact, torch.Tensor) and nact.is_cuda and nact.dtype == torch.int64 and nact.numel() == 1):
+        raise ValueError("a list length must be a CUDA int64 tensor with one element")
+
+
+def slice_list_init(n: int, device, lst: Optional[torch.Tensor] = None, nact: Optional[torch.Tensor] = None):
+    """(list, nact): the list of all n chains (int32) and its length (int64 device scalar)."""
+    lst = torch.empty(n, dtype=torch.int32, device=device) if lst is None else lst
+    nact = torch.empty((), dtype=torch.int64, device=device) if nact is None else nact
+    _list(lst, nact, n)
+    _check("gwl_slice_list_init", lib().gwl_slice_list_init(n, _ptr(lst), _ptr(nact), _stream(lst)))
+    return lst, nact
+
+
+def slice_draws(x, dirn, lo, hi, u, lst, nact, calls: Optional[torch.Tensor] = None):
+    """(t[n G], pts[G n, d], a, b, live, nact_next): G shrinkage draws for each listed chain
+    (list entry j's draw k at row j G + k), each taken as if the earlier ones had fallen outside;
+    live = nact G (device), added to `calls` if given; nact_next is cleared for the selection."""
     n, d = x.shape
     G = u.shape[0]
     x, dirn = _f64(x, "x", (n, d)), _f64(dirn, "dirn", (n, d))
     lo, hi, u = _f64(lo, "lo", (n,)), _f64(hi, "hi", (n,)), _f64(u, "u", (G, n))
-    t = torch.empty(G, n, dtype=torch.float64, device=x.device)
+    _list(lst, nact, n)
+    if calls is not None and not (calls.is_cuda and calls.dtype == torch.int64 and calls.numel() == 1):
+        raise ValueError("calls must be a CUDA int64 tensor with one element")
+    t = torch.empty(n * G, dtype=torch.float64, device=x.device)
     pts = torch.empty(G * n, d, dtype=torch.float64, device=x.device)
     a, b = torch.empty_like(lo), torch.empty_like(lo)
-    _check("gwl_slice_draws", lib().gwl_slice_draws(n, d, G, _ptr(x), _ptr(dirn), _ptr(lo), _ptr(hi), _ptr(u), _ptr(t),
-                                                    _ptr(pts), _ptr(a), _ptr(b), _stream(x)))
-    return t, pts, a, b
+    live, nact_next = (torch.empty((), dtype=torch.int64, device=x.device) for _ in range(2))
+    _check("gwl_slice_draws", lib().gwl_slice_draws(n, d, G, _ptr(lst), _ptr(nact), _ptr(x), _ptr(dirn), _ptr(lo),
+                                                    _ptr(hi), _ptr(u), _ptr(t), _ptr(pts), _ptr(a), _ptr(b),
+                                                    _ptr(live), _ptr(nact_next),
+                                                    _ptr(calls) if calls is not None else None, _stream(x)))
+    return t, pts, a, b, live, nact_next
 
 
-def slice_select(x, dirn, t, logl, lmin, a, b, xn, done, lo, hi) -> None:
-    """For every chain not done: the first draw inside the region becomes its point (xn, done);
-    otherwise its interval becomes (a, b). In place on xn, done, lo, hi."""
+def slice_select(x, dirn, t, logl, lmin, a, b, xn, done, lo, hi, lst, nact, nact_next,
+                 list_next: Optional[torch.Tensor] = None):
+    """For every listed chain not done: the first draw inside the region becomes its point (xn,
+    done); otherwise its interval becomes (a, b) and it joins the next list. In place on xn, done,
+    lo, hi; returns the next list (its length in nact_next, which slice_draws cleared)."""
     n, d = x.shape
-    G = t.shape[0]
+    G = t.shape[0] // n
     for v, name, shape, dt in ((xn, "xn", (n, d), torch.float64), (done, "done", (n,), torch.bool),
                                (lo, "lo", (n,), torch.float64), (hi, "hi", (n,), torch.float64)):
         if not (v.is_cuda and v.dtype == dt and v.is_contiguous() and tuple(v.shape) == shape):
             raise ValueError(f"{name} must be a contiguous {dt} CUDA tensor of shape {shape}")
-    x, dirn, t = _f64(x, "x", (n, d)), _f64(dirn, "dirn", (n, d)), _f64(t, "t", (G, n))
-    logl, lmin = _f64(logl, "logl", (G * n,)), _f64(lmin, "lmin", ())
+    x, dirn, t = _f64(x, "x", (n, d)), _f64(dirn, "dirn", (n, d)), _f64(t, "t", (n * G,))
+    lmin = _f64(lmin, "lmin", ())
+    if logl.dtype != torch.float64 or not logl.is_cuda or logl.dim() != 1 or logl.shape[0] > G * n \
+            or not logl.is_contiguous():
+        raise ValueError(f"logl must be a contiguous float64 CUDA tensor of at most {G * n} values")
     a, b = _f64(a, "a", (n,)), _f64(b, "b", (n,))
-    _check("gwl_slice_select", lib().gwl_slice_select(n, d, G, _ptr(x), _ptr(dirn), _ptr(t), _ptr(logl), _ptr(lmin),
-                                                      _ptr(a), _ptr(b), _ptr(xn), _ptr(done), _ptr(lo), _ptr(hi),
+    _list(lst, nact, n)
+    list_next = torch.empty(n, dtype=torch.int32, device=x.device) if list_next is None else list_next
+    _list(list_next, nact_next, n)
+    _check("gwl_slice_select", lib().gwl_slice_select(n, d, G, _ptr(lst), _ptr(nact), _ptr(x), _ptr(dirn), _ptr(t),
+                                                      _ptr(logl), _ptr(lmin), _ptr(a), _ptr(b), _ptr(xn), _ptr(done),
+                                                      _ptr(lo), _ptr(hi), _ptr(list_next), _ptr(nact_next),
                                                       _stream(x)))
+    return list_next
 
 
 MAP_LINEAR, MAP_CBRT, MAP_ASIN, MAP_ACOS = 0, 1, 2, 3

@@ -148,11 +148,12 @@ def slice_move(x, dirn, unif, m, inside):
     distribution on the region invariant all the same, and never returns its start point.
 
     The outcome is fixed by the uniform numbers and by which of the points the procedure looks at
-    lie inside, so those points are evaluated ahead, in one batch per stage: the m possible left
-    ends and m possible right ends together, then the shrinkage draws in groups of SLICE_GROUP,
-    each draw from the interval as it would be if the earlier draws of its group had fallen
-    outside. The first draw inside is the one the sequential procedure returns. A chain with no
-    draw inside after SLICE_MAX_DRAWS keeps its point."""
+    lie inside, so those points are evaluated ahead, in one batch per stage: the m - 1 ends the
+    stepping out can examine (J on the left, m - 1 - J on the right), then the shrinkage draws in
+    groups of SLICE_GROUP for the chains still moving, each draw from the interval as it would be
+    if the earlier draws of its group had fallen outside. The first draw inside is the one the
+    sequential procedure returns. A chain with no draw inside after SLICE_MAX_DRAWS keeps its
+    point."""
     lo, hi = _slice_stepping(x, dirn, unif[0], unif[1], m, inside)
     done = torch.zeros(x.shape[0], dtype=torch.bool, device=x.device)
     xn = x
@@ -164,24 +165,29 @@ def slice_move(x, dirn, unif, m, inside):
 
 
 def _slice_stepping(x, dirn, u0, u1, m, inside):
-    """The interval of a slice move after stepping out: (lo, hi) in units of dirn."""
+    """The interval of a slice move after stepping out: (lo, hi) in units of dirn. Slot s of a
+    chain is its left end lo - s for s < J and its right end hi + (s - J) from there on."""
     n, d = x.shape
     lo, hi = -u0, 1.0 - u0
     if m > 1:
         jl = torch.floor(m * u1)
         jr = (m - 1) - jl
-        steps = torch.arange(m, dtype=x.dtype, device=x.device)
-        ends = torch.cat([lo[None] - steps[:, None], hi[None] + steps[:, None]])          # [2m, n]
-        ok = inside((x[None] + ends[..., None] * dirn[None]).reshape(-1, d)).reshape(2 * m, n)
-        out_l = torch.where(ok[:m].all(0), m, torch.argmin(ok[:m].to(torch.int8), 0)).to(x.dtype)
-        out_r = torch.where(ok[m:].all(0), m, torch.argmin(ok[m:].to(torch.int8), 0)).to(x.dtype)
-        lo = lo - torch.minimum(out_l, jl)
-        hi = hi + torch.minimum(out_r, jr)
+        s = torch.arange(m - 1, dtype=x.dtype, device=x.device)[:, None]                    # [m - 1, 1]
+        left = s < jl[None]                                                                  # [m - 1, n]
+        t = torch.where(left, lo[None] - s, hi[None] + (s - jl[None]))
+        ok = inside((x[None] + t[..., None] * dirn[None]).reshape(-1, d)).reshape(m - 1, n)
+        out_l, out_r = left & ~ok, ~left & ~ok
+        sl = torch.where(out_l.any(0), torch.argmax(out_l.to(torch.int8), 0).to(x.dtype), jl)
+        sr = torch.where(out_r.any(0), torch.argmax(out_r.to(torch.int8), 0).to(x.dtype) - jl, jr)
+        lo = lo - sl
+        hi = hi + sr
     return lo, hi
 
 
-def _slice_group(x, dirn, lo, hi, done, xn, ug, inside):
-    """One group of shrinkage draws (ug[G, n], in order) for the chains not done yet."""
+def _slice_group(x, dirn, lo, hi, done, xn, ug, inside, active=False):
+    """One group of shrinkage draws (ug[G, n], in order) for the chains not done yet. With
+    active=True only those chains' draws are passed to inside() (a host synchronisation);
+    otherwise every chain's draws are, and the done ones ignored."""
     n, d = x.shape
     ts = []
     a, b = lo, hi
@@ -191,7 +197,15 @@ def _slice_group(x, dirn, lo, hi, done, xn, ug, inside):
         left = t < 0.0
         a, b = torch.where(left, t, a), torch.where(left, b, t)
     tt = torch.stack(ts)                                                                  # [G, n]
-    ok = inside((x[None] + tt[..., None] * dirn[None]).reshape(-1, d)).reshape(ug.shape[0], n) & ~done[None]
+    if active:
+        act = torch.nonzero(~done)[:, 0]
+        ok = torch.zeros(ug.shape[0], n, dtype=torch.bool, device=x.device)
+        if act.numel():
+            pa = (x[act][None] + tt[:, act, None] * dirn[act][None]).reshape(-1, d)
+            ok[:, act] = inside(pa).reshape(ug.shape[0], -1)
+    else:
+        ok = inside((x[None] + tt[..., None] * dirn[None]).reshape(-1, d)).reshape(ug.shape[0], n)
+    ok = ok & ~done[None]
     hit = ok.any(0)
     tsel = tt.gather(0, torch.argmax(ok.to(torch.int8), 0)[None])[0]
     xn = torch.where(hit[:, None], x + tsel[:, None] * dirn, xn)
@@ -210,39 +224,58 @@ def _slice_stepping_dev(x, dirn, u0, u1, m, raw, lmin):
     return lo, hi
 
 
-def _slice_group_dev(x, dirn, lo, hi, done, xn, ug, raw, lmin):
-    """_slice_group with the library's kernels (gwl_slice_draws / _select), in place on xn, done,
-    lo and hi."""
+def _slice_group_dev(x, dirn, lo, hi, done, xn, ug, live_eval, lmin, lst, nact, calls=None):
+    """_slice_group with the library's kernels (gwl_slice_draws / _select) for the listed chains,
+    in place on xn, done, lo and hi; live_eval(pts, live) is ln L at the first `live` rows of pts
+    (live a device int64 scalar). Returns the next list and its length (device)."""
     from . import gwlike as gw
-    t, pts, a, b = gw.slice_draws(x, dirn, lo, hi, ug)
-    gw.slice_select(x, dirn, t, raw(pts), lmin, a, b, xn, done, lo, hi)
-    return xn, done, lo, hi
+    t, pts, a, b, live, nact_next = gw.slice_draws(x, dirn, lo, hi, ug, lst, nact, calls)
+    logl = live_eval(pts, live)
+    lst_next = gw.slice_select(x, dirn, t, logl, lmin, a, b, xn, done, lo, hi, lst, nact, nact_next)
+    return lst_next, nact_next
 
 
-def slice_move_dev(x, dirn, unif, m, raw, lmin):
+def _eager_live(raw, G):
+    """live_eval for eager moves: reads the live count (a host synchronisation) and evaluates
+    exactly those rows."""
+    def live_eval(pts, live):
+        k = int(live)
+        return raw(pts[:k]) if k else torch.empty(0, dtype=torch.float64, device=pts.device)
+    return live_eval
+
+
+def slice_move_dev(x, dirn, unif, m, raw, lmin, calls=None):
     """slice_move with the bookkeeping in the library's kernels: the candidate ends and draws
     are written by one kernel per stage and judged by another, between them one call of raw(p)
-    (ln L at the points, NaN allowed); the region is {p in the cube, ln L(p) >= lmin}."""
+    (ln L at the points, NaN allowed); the region is {p in the cube, ln L(p) >= lmin}. Shrinkage
+    groups evaluate only the chains still moving; `calls` (a device int64, optional) counts their
+    draws."""
+    from . import gwlike as gw
     lo, hi = _slice_stepping_dev(x, dirn, unif[0], unif[1], m, raw, lmin)
     lo, hi = lo.contiguous(), hi.contiguous()
     done = torch.zeros(x.shape[0], dtype=torch.bool, device=x.device)
     xn = x.clone()
+    lst, nact = gw.slice_list_init(x.shape[0], x.device)
+    live_eval = _eager_live(raw, SLICE_GROUP)
     for g0 in range(0, SLICE_MAX_DRAWS, SLICE_GROUP):
-        _slice_group_dev(x, dirn, lo, hi, done, xn, unif[2 + g0:2 + g0 + SLICE_GROUP], raw, lmin)
-        if bool(done.all()):
+        lst, nact = _slice_group_dev(x, dirn, lo, hi, done, xn, unif[2 + g0:2 + g0 + SLICE_GROUP], live_eval, lmin,
+                                     lst, nact, calls)
+        if int(nact) == 0:
             break
     return xn, done
 
 
 class _SliceGraphs:
-    """The slice moves of one batch shape captured as two HIP graphs on the device: (A) a move's
-    direction, stepping out and first group of shrinkage draws; (B) one further group. The host
-    draws each move's random numbers into static buffers (the same calls, in the same order, as
-    the eager path, so both paths give the same chains bit for bit), replays A, and replays B
-    until every chain is done; the likelihood calls inside (prior transform, the library's
-    kernels) are part of the graphs, with the device addresses they had at capture: the sampler
-    captures again at the start of every run, and the likelihood's data (an event's tables) must
-    stay alive while a run lasts."""
+    """The slice moves of one batch shape captured as one HIP graph per move: the move's
+    direction, stepping out, and all SLICE_MAX_DRAWS / SLICE_GROUP groups of shrinkage draws, each
+    group for the chains still moving (a list kept on the device, so a group after every chain is
+    done costs only its empty launches and no host decision is needed). The host draws each move's
+    random numbers into static buffers (the same calls, in the same order, as the eager path, so
+    both paths give the same chains bit for bit) and replays the graph; the likelihood calls
+    inside (prior transform, the library's kernels) are part of the graph, with the device
+    addresses they had at capture: the sampler captures again at the start of every run, and the
+    likelihood's data (an event's tables) must stay alive while a run lasts. The draws evaluated
+    are counted on the device (calls)."""
 
     def __init__(self, smp):
         n, d, m, G = smp.n, smp.d, smp.slice_out, SLICE_GROUP
@@ -251,43 +284,38 @@ class _SliceGraphs:
         # placeholders for the warm-up and the capture: points at the cube's centre, unit directions
         self.x, self.z, self.dirn, self.xn = (torch.full((n, d), 0.5, **f64) for _ in range(4))
         self.unif = torch.full((2 + SLICE_MAX_DRAWS, n), 0.5, **f64)
-        self.ub = torch.full((G, n), 0.5, **f64)
         self.chol = torch.eye(d, **f64)
         self.lmin = torch.full((), -math.inf, **f64)
-        self.lo, self.hi = torch.zeros(n, **f64), torch.zeros(n, **f64)
         self.done = torch.zeros(n, dtype=torch.bool, device=smp.dev)
-        stepping, group = smp._slice_stages(self.lmin, count=False)
+        self.moved = torch.zeros(n, dtype=torch.bool, device=smp.dev)
+        self.calls = torch.zeros((), dtype=torch.int64, device=smp.dev)
+        stepping, group, start, _ = smp._slice_stages(self.lmin, count=False, calls=self.calls)
 
-        def stage_a():
+        def move():
             self.dirn.copy_(smp.slice_width * (self.z / self.z.norm(dim=1, keepdim=True)) @ self.chol.T)
             lo, hi = stepping(self.x, self.dirn, self.unif[0], self.unif[1])
-            self.lo.copy_(lo)
-            self.hi.copy_(hi)
+            lo, hi = lo.contiguous(), hi.contiguous()
             self.done.zero_()
             self.xn.copy_(self.x)
-            stage_b(self.unif[2:2 + G])
-
-        def stage_b(ug):
-            xn, done, lo, hi = group(self.x, self.dirn, self.lo, self.hi, self.done, self.xn, ug)
-            for dst, src in ((self.xn, xn), (self.done, done), (self.lo, lo), (self.hi, hi)):
-                if dst is not src:
-                    dst.copy_(src)
+            state = start()
+            for g0 in range(0, SLICE_MAX_DRAWS, G):
+                state = group(self.x, self.dirn, lo, hi, self.done, self.xn, self.unif[2 + g0:2 + g0 + G], state)
+            self.moved |= self.done
+            self.x.copy_(self.xn)
 
         side = torch.cuda.Stream(device=smp.dev)
         side.wait_stream(torch.cuda.current_stream(smp.dev))
         with torch.cuda.stream(side):            # warm-up outside capture (allocator, kernels)
-            stage_a()
-            stage_b(self.ub)
+            move()
         torch.cuda.current_stream(smp.dev).wait_stream(side)
         torch.cuda.synchronize(smp.dev)
         # captured on the warm-up's stream: the library keeps its workspace per stream and grows it
         # only outside capture, so the warm-up has reserved what the captured calls use
-        self.ga, self.gb = torch.cuda.CUDAGraph(), torch.cuda.CUDAGraph()
-        with torch.cuda.graph(self.ga, stream=side):
-            stage_a()
-        with torch.cuda.graph(self.gb, pool=self.ga.pool(), stream=side):
-            stage_b(self.ub)
-        self.calls_a, self.calls_b = (2 * m + G) * n if m > 1 else G * n, G * n
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph, stream=side):
+            move()
+        self.calls.zero_()
+        self.calls_step = (m - 1) * n if m > 1 else 0       # stepping-out ends per move
 
     def walk(self, x0, chol, lmin, steps):
         """(points, whether each chain moved at least once)."""
@@ -295,21 +323,13 @@ class _SliceGraphs:
         self.x.copy_(x0)
         self.chol.copy_(chol)
         self.lmin.copy_(lmin)
-        moved = torch.zeros(n, dtype=torch.bool, device=smp.dev)
+        self.moved.zero_()
         for _ in range(steps):
             torch.randn(n, d, generator=smp.gen, out=self.z)
             torch.rand(2 + SLICE_MAX_DRAWS, n, generator=smp.gen, out=self.unif)
-            self.ga.replay()
-            smp.extra_calls += self.calls_a
-            for g0 in range(SLICE_GROUP, SLICE_MAX_DRAWS, SLICE_GROUP):
-                if bool(self.done.all()):
-                    break
-                self.ub.copy_(self.unif[2 + g0:2 + g0 + SLICE_GROUP])
-                self.gb.replay()
-                smp.extra_calls += self.calls_b
-            moved |= self.done
-            self.x.copy_(self.xn)
-        return self.x.clone(), moved
+            self.graph.replay()
+            smp.extra_calls += self.calls_step
+        return self.x.clone(), self.moved.clone()
 
 
 class ParallelNestedSampler:
@@ -321,6 +341,9 @@ class ParallelNestedSampler:
     loglike_grad(theta[n, d]) -> (ln L[n], d ln L / d theta [n, d]): needed for "gmc".
     slice_steps, slice_width, slice_out: slice moves per candidate, the initial interval length in
     units of the live points' spread along the direction, and the stepping-out limit m.
+    loglike_live(theta[N, d], live) -> ln L[N] evaluated on the first `live` rows only (live a
+    device int64 scalar, e.g. the library's logl_live): lets captured slice moves evaluate only
+    the draws of the chains still moving. Without it they evaluate every row.
     """
 
     def __init__(self, loglike: Callable, ndim: int, nlive: int, batch: int,
@@ -328,7 +351,7 @@ class ParallelNestedSampler:
                  proposal="ellipsoid", enlarge: float = 1.25, volume: str = "order", check_every: int = 8,
                  loglike_grad: Optional[Callable] = None, gmc_steps: int = 20, slice_steps: Optional[int] = None,
                  slice_width: float = 3.0, slice_out: int = 4, slice_graphs: bool = True,
-                 slice_kernels: Optional[bool] = None):
+                 slice_kernels: Optional[bool] = None, loglike_live: Optional[Callable] = None):
         if nlive < 2 or batch < 1 or ndim < 1:
             raise ValueError("need nlive >= 2, batch >= 1, ndim >= 1")
         if volume not in ("order", "paper"):
@@ -357,7 +380,10 @@ class ParallelNestedSampler:
             raise ValueError("slice_kernels needs a CUDA device")
         self.slice_graphs = self.slice_graphs_requested
         self._graphs = None
+        self.loglike_live = loglike_live
         self.extra_calls = 0
+        # shrinkage draws evaluated, counted on the device (read once at the end of a run)
+        self._calls_dev = torch.zeros((), dtype=torch.int64, device=self.dev)
 
     # ---- proposals -------------------------------------------------------------------------
     def _prior(self):
@@ -462,20 +488,48 @@ class ParallelNestedSampler:
             return self.loglike(self.transform(u))
         return self.loglike(self.transform(u.clamp(0.0, 1.0)))
 
-    def _slice_stages(self, lmin, count=True):
-        """(stepping(x, dirn, u0, u1) -> (lo, hi), group(x, dirn, lo, hi, done, xn, ug) ->
-        (xn, done, lo, hi)) for the contour ln L >= lmin, in the library's kernels or in torch."""
+    def _slice_stages(self, lmin, count=True, calls=None):
+        """(stepping(x, dirn, u0, u1) -> (lo, hi), group(x, dirn, lo, hi, done, xn, ug, state) ->
+        state, start() -> state, finished(state, done) -> bool) for the contour ln L >= lmin, in
+        the library's kernels or in torch. group updates xn, done, lo and hi in place and counts
+        the draws it evaluates (those of the chains still moving) into `calls` (a device int64,
+        the sampler's own if None); with count=True the stepping-out ends are counted on the host.
+        With count=False (graph capture) nothing waits for the device."""
         m = self.slice_out
+        calls = self._calls_dev if calls is None else calls
+
+        def raw(p):
+            if count:
+                self.extra_calls += p.shape[0]
+            return self._raw(p)
         if self.slice_kernels:
-            def raw(p):
-                if count:
-                    self.extra_calls += p.shape[0]
-                return self._raw(p)
-            return (lambda x, dirn, u0, u1: _slice_stepping_dev(x, dirn, u0, u1, m, raw, lmin),
-                    lambda x, dirn, lo, hi, done, xn, ug: _slice_group_dev(x, dirn, lo, hi, done, xn, ug, raw, lmin))
-        inside = (lambda p: self._in_contour(p, lmin)) if count else (lambda p: self._inside_raw(p, lmin))
-        return (lambda x, dirn, u0, u1: _slice_stepping(x, dirn, u0, u1, m, inside),
-                lambda x, dirn, lo, hi, done, xn, ug: _slice_group(x, dirn, lo, hi, done, xn, ug, inside))
+            from . import gwlike as gw
+            live_eval = _eager_live(self._raw, SLICE_GROUP) if count else self._raw_live
+
+            def group(x, dirn, lo, hi, done, xn, ug, state):
+                return _slice_group_dev(x, dirn, lo, hi, done, xn, ug, live_eval, lmin, state[0], state[1], calls)
+            return (lambda x, dirn, u0, u1: _slice_stepping_dev(x, dirn, u0, u1, m, raw, lmin), group,
+                    lambda: gw.slice_list_init(self.n, self.dev), lambda state, done: int(state[1]) == 0)
+        inside = lambda p: self._inside_raw(p, lmin)
+        inside_count = (lambda p: self._in_contour(p, lmin)) if count else inside
+
+        def group(x, dirn, lo, hi, done, xn, ug, state):
+            calls.add_(ug.shape[0] * (~done).sum())
+            xn2, done2, lo2, hi2 = _slice_group(x, dirn, lo, hi, done, xn, ug, inside, active=count)
+            for dst, src in ((xn, xn2), (done, done2), (lo, lo2), (hi, hi2)):
+                if dst is not src:
+                    dst.copy_(src)
+            return state
+        return (lambda x, dirn, u0, u1: _slice_stepping(x, dirn, u0, u1, m, inside_count), group,
+                lambda: None, lambda state, done: bool(done.all()))
+
+    def _raw_live(self, p, live):
+        """ln L at the first `live` rows of p (a device int64 scalar) when the sampler has a
+        loglike_live, else at every row."""
+        th = self.transform(p) if getattr(self.transform, "clamps", False) else self.transform(p.clamp(0.0, 1.0))
+        if self.loglike_live is not None:
+            return self.loglike_live(th, live)
+        return self.loglike(th)
 
     def _slice(self, live_u, live_l):
         """Slice-sampling walks inside the contour L >= L_min, one chain per candidate: each chain
@@ -498,24 +552,27 @@ class ParallelNestedSampler:
             except Exception as exc:      # a likelihood that cannot be captured: eager moves
                 warnings.warn(f"slice moves run eagerly: capturing them failed ({exc})")
                 self.slice_graphs = False
+                self._graphs = None
         if self.slice_graphs:
             x, moved = self._graphs.walk(x, chol, lmin, self.slice_steps)
             return torch.where(moved[:, None], x, torch.full_like(x, 2.0))
-        inside = lambda p: self._in_contour(p, lmin)
+        stepping, group, begin, finished = self._slice_stages(lmin)
         moved = torch.zeros(n, dtype=torch.bool, device=self.dev)
-
-        def raw(p):
-            self.extra_calls += p.shape[0]
-            return self._raw(p)
         for _ in range(self.slice_steps):
             z = torch.randn(n, d, generator=self.gen, **f64)
             dirn = self.slice_width * (z / z.norm(dim=1, keepdim=True)) @ chol.T
             unif = torch.rand(2 + SLICE_MAX_DRAWS, n, generator=self.gen, **f64)
-            if self.slice_kernels:
-                x, done = slice_move_dev(x, dirn, unif, self.slice_out, raw, lmin)
-            else:
-                x, done = slice_move(x, dirn, unif, self.slice_out, inside)
+            lo, hi = stepping(x, dirn, unif[0], unif[1])
+            lo, hi = lo.contiguous(), hi.contiguous()
+            done = torch.zeros(n, dtype=torch.bool, device=self.dev)
+            xn = x.clone()
+            state = begin()
+            for g0 in range(0, SLICE_MAX_DRAWS, SLICE_GROUP):
+                state = group(x, dirn, lo, hi, done, xn, unif[2 + g0:2 + g0 + SLICE_GROUP], state)
+                if finished(state, done):
+                    break
             moved |= done
+            x = xn
         return torch.where(moved[:, None], x, torch.full_like(x, 2.0))
 
     def _propose(self, it, live_u, live_l):
@@ -543,6 +600,7 @@ class ParallelNestedSampler:
         f64 = dict(dtype=torch.float64, device=dev)
         t0 = time.perf_counter()
         self.extra_calls = 0
+        self._calls_dev.zero_()
         # captured slice moves hold the device pointers of the likelihood they were captured with
         # (for the GW likelihood: the event's tables), so every run captures them again
         self._graphs = None
@@ -624,6 +682,7 @@ class ParallelNestedSampler:
             it += 1
         if dev.type == "cuda":
             torch.cuda.synchronize(dev)
+        self.extra_calls += int(self._calls_dev) + (int(self._graphs.calls) if self._graphs is not None else 0)
         nd = int(n_dead)
         n_acc = n_acc[:it].cpu().numpy()
         n_acc = n_acc[n_acc >= 0]

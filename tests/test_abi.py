@@ -84,10 +84,21 @@ def test_slice_entry_points_check_arguments_without_device_work():
     assert L.gwl_slice_ends(10, 3, 0, *ptrs9, None) == -2
     assert L.gwl_slice_ends(10, 3, 4, None, *ptrs9[1:], None) == -1
     assert L.gwl_slice_ends_select(10, 3, 4, *([fake] * 6), None, None) == -1
-    assert L.gwl_slice_draws(10, 3, 0, *ptrs9, None) == -2
-    assert L.gwl_slice_draws(1 << 30, 3, 8, *ptrs9, None) == -2     # 2 G n points beyond 2^30
-    assert L.gwl_slice_select(10, 3, 8, *([fake] * 10), None, None) == -1
+    ptrs14 = [fake] * 14
+    assert L.gwl_slice_draws(10, 3, 0, *ptrs14, None) == -2
+    assert L.gwl_slice_draws(1 << 28, 3, 8, *ptrs14, None) == -2     # G n points beyond 2^30
+    assert L.gwl_slice_draws(10, 3, 8, *([fake] * 12), None, None, None) == -1   # nact_next is required
     assert b"null pointer" in L.gwl_last_error()
+    assert L.gwl_slice_select(10, 3, 8, *([fake] * 14), None, None) == -1
+    assert b"null pointer" in L.gwl_last_error()
+    # the next list (and its length) must differ from the current one
+    assert L.gwl_slice_draws(10, 3, 8, *([fake] * 12), fake, None, None) == -1
+    assert b"must not be" in L.gwl_last_error()
+    assert L.gwl_slice_select(10, 3, 8, *([fake] * 15), None) == -1
+    assert b"must not be" in L.gwl_last_error()
+    assert L.gwl_slice_list_init(0, fake, fake, None) == -2
+    assert L.gwl_slice_list_init(10, None, fake, None) == -1
+    assert L.gwl_logl_batch_live(None, fake, 10, fake, 1, fake, None) == -1
 
 
 def test_prior_transform_checks_arguments_without_device_work():

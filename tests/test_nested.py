@@ -471,18 +471,22 @@ def test_gw_slice_nested_sampling_matches_importance_sampling():
 @pytest.mark.gpu
 def test_slice_graphs_and_kernels_replay_the_eager_moves():
     """The slice moves replayed from captured graphs, and with their bookkeeping in the library's
-    kernels (gwl_slice_*), give the eager torch moves bit for bit: the same dead points,
-    likelihoods and call counts over a few iterations of a GW run."""
+    kernels (gwl_slice_*), with and without a likelihood that evaluates only the live draws, give
+    the eager torch moves bit for bit: the same dead points, likelihoods and call counts over a
+    few iterations of a GW run."""
     from paper_1909_11873_amd import gwlike as gw
 
     spec, th0, f, psd, data, dets, l0 = quiet_c0_event()
     ev = gw.Event(torch.tensor(data, device=DEV), torch.tensor(psd, device=DEV), dets,
                   torch.tensor(f, device=DEV), spec.df)
     runs = []
-    for graphs, kernels in ((False, False), (True, True), (False, True), (True, False)):
+    live = lambda th, n: gw.logl_live(th, n, ev, "mixed")
+    for graphs, kernels, lv in ((False, False, None), (True, True, None), (False, True, None), (True, False, None),
+                                (True, True, live), (False, True, live)):
         smp = nested.ParallelNestedSampler(lambda th: gw.logl(th, ev, "mixed"), 11, 200, 256, proposal="slice",
                                            slice_steps=6, slice_graphs=graphs, slice_kernels=kernels, device=DEV,
-                                           seed=12, prior_transform=nested.gw_prior_transform(spins=False))
+                                           seed=12, prior_transform=nested.gw_prior_transform(spins=False),
+                                           loglike_live=lv)
         with warnings.catch_warnings(record=True) as caught:
             warnings.simplefilter("always")
             runs.append(smp.run(eps=0.1, max_iter=12))
@@ -528,16 +532,17 @@ def test_slice_kernels_are_the_sequential_procedure(m):
         gw.slice_draws(torch.zeros(0, 3, dtype=torch.float64, device=DEV), torch.zeros(0, 3, dtype=torch.float64,
                        device=DEV), torch.zeros(0, dtype=torch.float64, device=DEV),
                        torch.zeros(0, dtype=torch.float64, device=DEV),
-                       torch.zeros(8, 0, dtype=torch.float64, device=DEV))
+                       torch.zeros(8, 0, dtype=torch.float64, device=DEV),
+                       torch.zeros(0, dtype=torch.int32, device=DEV), torch.zeros((), dtype=torch.int64, device=DEV))
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("m,G,d", [(2, 1, 3), (3, 3, 13), (4, 8, 11), (5, 7, 2), (32, 64, 5), (33, 65, 4)])
+@pytest.mark.parametrize("m,G,d", [(2, 1, 3), (3, 3, 13), (4, 8, 11), (5, 7, 2), (65, 64, 5), (66, 65, 4)])
 def test_slice_stage_kernels_match_the_torch_stages(m, G, d):
     """Each stage kernel against the torch stage it replaces, bit for bit, over stepping-out
     limits and group sizes that fill a wavefront unevenly, exactly, or not at all (the per-chain
     fallback above 64 lanes), with more coordinates than lanes, chains already done, NaN ln L and
-    candidates outside the cube."""
+    candidates outside the cube; then a second group on the list of the chains still moving."""
     from paper_1909_11873_amd import gwlike as gw
 
     rng = np.random.default_rng(100 * m + G)
@@ -559,17 +564,36 @@ def test_slice_stage_kernels_match_the_torch_stages(m, G, d):
     assert torch.equal(lo, lo_t) and torch.equal(hi, hi_t)
     assert bool((lo_t < -u0).any()) and bool((hi_t > 1.0 - u0).any())            # some ends stepped out
 
+    assert pts.shape == ((m - 1) * n, d)                                         # only the ends examined
+
     done = torch.tensor(rng.random(n) < 0.2, device=DEV)
     xn = torch.tensor(rng.random((n, d)), device=DEV)
     ug = torch.tensor(rng.random((G, n)), device=DEV)
     xn_t, done_t, lo2_t, hi2_t = nested._slice_group(x, dirn, lo, hi, done, xn, ug, inside)
-    t, gpts, a, b = gw.slice_draws(x, dirn, lo, hi, ug)
+    lst, nact = gw.slice_list_init(n, DEV)
+    calls = torch.zeros((), dtype=torch.int64, device=DEV)
+    t, gpts, a, b, live, nact_next = gw.slice_draws(x, dirn, lo, hi, ug, lst, nact, calls)
+    assert int(live) == n * G and int(calls) == n * G
     done_k = done.clone()
-    gw.slice_select(x, dirn, t, raw(gpts), lmin, a, b, xn, done_k, lo, hi)
+    lst2 = gw.slice_select(x, dirn, t, raw(gpts), lmin, a, b, xn, done_k, lo, hi, lst, nact, nact_next)
     assert torch.equal(xn, xn_t) and torch.equal(done_k, done_t)
     assert torch.equal(lo, lo2_t) and torch.equal(hi, hi2_t)
     hit = done_k & ~done
     assert 0 < int(hit.sum()) < int((~done).sum())                               # both outcomes occur
+    # the next list: exactly the chains still moving (in any order)
+    k = int(nact_next)
+    assert k == int((~done_k).sum())
+    assert torch.equal(torch.sort(lst2[:k].long()).values, torch.nonzero(~done_k)[:, 0])
+
+    # a second group on that list: only its chains' draws are evaluated
+    ug2 = torch.tensor(rng.random((G, n)), device=DEV)
+    xn_t2, done_t2, lo3_t, hi3_t = nested._slice_group(x, dirn, lo, hi, done_k, xn, ug2, inside, active=True)
+    t2, gpts2, a2, b2, live2, nact3 = gw.slice_draws(x, dirn, lo, hi, ug2, lst2, nact_next, calls)
+    assert int(live2) == k * G and int(calls) == (n + k) * G
+    gw.slice_select(x, dirn, t2, raw(gpts2[:k * G]), lmin, a2, b2, xn, done_k, lo, hi, lst2, nact_next, nact3)
+    assert torch.equal(xn, xn_t2) and torch.equal(done_k, done_t2)
+    assert torch.equal(lo, lo3_t) and torch.equal(hi, hi3_t)
+    assert int(nact3) == int((~done_k).sum())
 
 
 @pytest.mark.gpu
