@@ -540,6 +540,16 @@ def scaled_grad_error(g, gref):
     return np.abs(gs - rs) / scale
 
 
+def _trace_marker(dev, k: int) -> None:
+    """One gwl_slice_list_init launch of k * 256 chains: a kernel of that grid marks a point in a
+    profiler's kernel trace (synchronised, so nothing overlaps it)."""
+    import torch
+    from paper_1909_11873_amd import gwlike as gw
+    torch.cuda.synchronize()
+    gw.slice_list_init(k * 256, dev)
+    torch.cuda.synchronize()
+
+
 def ns_leg(cfg: int, nlive: int, batches, eps: float, proposal: str = "slice", snr: float = 20.0, seed: int = 1,
            tune_out=None):
     """Static parallel nested sampling on one event through the mixed-precision kernels, once per
@@ -572,7 +582,7 @@ def ns_leg(cfg: int, nlive: int, batches, eps: float, proposal: str = "slice", s
         # the likelihood batches a slice-sampling run makes: the live points, then per move the
         # m - 1 stepping-out ends and the groups of shrinkage draws of every chain
         m = 4                                              # the sampler's default stepping-out limit
-        shapes = {nlive} | {k * n for n in batches for k in (m - 1, nested.SLICE_GROUP)}
+        shapes = {nlive} | {k * n for n in batches for k in (m - 1,) + tuple(set(nested.SLICE_GROUPS))}
         for b in sorted(shapes):
             gw.autotune(ev, b, "mixed", cache_path=tune_out)
     rows = []
@@ -585,7 +595,9 @@ def ns_leg(cfg: int, nlive: int, batches, eps: float, proposal: str = "slice", s
         smp = nested.ParallelNestedSampler(lambda th: gw.logl(th, ev, "mixed"), 11, nlive, n, **kw)
         smp.run(eps=1e3, max_iter=2)           # warm-up (kernels, allocator)
         torch.cuda.synchronize()
+        _trace_marker(dev, 97)                 # a launch a kernel trace can find: the timed run starts
         res = smp.run(eps=eps, max_iter=20000)
+        _trace_marker(dev, 89)                 # ... and ends
         w = np.exp(res.log_w)
         mc = float(np.sum(w * res.theta[:, 0]))
         nbar = float(res.n_accepted.mean()) if res.niter else 0.0

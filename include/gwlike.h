@@ -198,7 +198,9 @@ gwl_status gwl_logl_batch(gwl_event ev, const double* theta, int64_t B, gwl_prec
  * live a device int64 read by the kernels when they run (values above B count as B, below 1 as
  * none). The launch is sized for B, so the call can be captured once and replayed for batches
  * of any length up to B, e.g. the shrinkage draws of the slice-sampling chains still moving
- * (gwl_slice_draws sets *live). Not for calibrated events (GWL_E_UNSUPPORTED).
+ * (gwl_slice_draws sets *live). Point groups past *live leave the evaluation kernel at once; the
+ * launch splits each point group's bins over enough workgroups that a quarter of the point groups
+ * still fill the chip. Not for calibrated events (GWL_E_UNSUPPORTED).
  */
 gwl_status gwl_logl_batch_live(gwl_event ev, const double* theta, int64_t B, const int64_t* live, gwl_precision prec,
                                double* logl, void* stream);
@@ -355,6 +357,8 @@ gwl_status gwl_profile_read(int64_t* launches, double* total_ms);
  * listed in list[0 .. *nact) (int32 chain indices, device; *nact a device int64, taken as at
  * most n; entries outside [0, n) are skipped):
  * gwl_slice_list_init: list = 0, 1, .., n - 1 and *nact = n (the first group of a move).
+ * gwl_slice_move_begin: the start of a move in one launch: xn = x, done = 0 and the list of all
+ *   chains (as gwl_slice_list_init). gwl_slice_move_end: moved |= done (bytes) and x = xn.
  * gwl_slice_draws: for list entry j (chain i = list[j]), G draws, each from the interval as it
  *   would be if the earlier draws had fallen outside: t_k = a + u_k (b - a) from (a, b) =
  *   (lo, hi), then a = t_k if t_k < 0 else b = t_k, with u_k = u[k n + i]; writes t[j G + k],
@@ -373,6 +377,10 @@ gwl_status gwl_slice_ends(int64_t n, int d, int m, const double* x, const double
 gwl_status gwl_slice_ends_select(int64_t n, int d, int m, const double* pts, const double* logl, const double* lmin,
                                  double* lo, double* hi, const double* jl, const double* jr, void* stream);
 gwl_status gwl_slice_list_init(int64_t n, int* list, int64_t* nact, void* stream);
+gwl_status gwl_slice_move_begin(int64_t n, int d, const double* x, double* xn, unsigned char* done, int* list,
+                                int64_t* nact, void* stream);
+gwl_status gwl_slice_move_end(int64_t n, int d, const unsigned char* done, unsigned char* moved, const double* xn,
+                              double* x, void* stream);
 gwl_status gwl_slice_draws(int64_t n, int d, int G, const int* list, const int64_t* nact, const double* x,
                            const double* dirn, const double* lo, const double* hi, const double* u, double* t,
                            double* pts, double* a, double* b, int64_t* live, int64_t* nact_next, int64_t* calls,

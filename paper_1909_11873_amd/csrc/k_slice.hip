@@ -44,18 +44,58 @@ __global__ __launch_bounds__(SLICE_BLOCK) void k_slice_ends(int64_t n, int m, co
 __global__ __launch_bounds__(SLICE_BLOCK) void k_slice_end_points(int64_t n, int d, int m,
                                                                   const double* __restrict__ x,
                                                                   const double* __restrict__ dirn,
-                                                                  const double* __restrict__ lo,
-                                                                  const double* __restrict__ hi,
-                                                                  const double* __restrict__ jl,
-                                                                  double* __restrict__ pts) {
+                                                                  const double* __restrict__ u0,
+                                                                  const double* __restrict__ u1,
+                                                                  double* __restrict__ pts, double* __restrict__ lo,
+                                                                  double* __restrict__ hi, double* __restrict__ jl,
+                                                                  double* __restrict__ jr) {
   const int64_t e = (int64_t)blockIdx.x * SLICE_BLOCK + threadIdx.x;
   if (e >= (int64_t)(m - 1) * n * d) return;
   const int64_t r = e / d, c = e - r * d;
   const int64_t s = r / n;
   const int64_t i = r - s * n;
+  // the interval as k_slice_ends writes it, recomputed by every thread of the chain
+  const double l0 = -u0[i], h0 = 1.0 - u0[i], nl = floor((double)m * u1[i]);
+  if (s == 0 && c == 0) {
+    lo[i] = l0;
+    hi[i] = h0;
+    jl[i] = nl;
+    jr[i] = (double)(m - 1) - nl;
+  }
   const double sd = (double)s;
-  const double t = sd < jl[i] ? lo[i] - sd : hi[i] + (sd - jl[i]);
+  const double t = sd < nl ? l0 - sd : h0 + (sd - nl);
   pts[e] = x[i * d + c] + t * dirn[i * d + c];
+}
+
+// The start of a move: xn = x, done = 0, and the list of all n chains (one thread per
+// coordinate). The end of a move: moved |= done, x = xn.
+__global__ __launch_bounds__(SLICE_BLOCK) void k_slice_move_begin(int64_t n, int d, const double* __restrict__ x,
+                                                                  double* __restrict__ xn,
+                                                                  unsigned char* __restrict__ done,
+                                                                  int* __restrict__ list,
+                                                                  int64_t* __restrict__ nact) {
+  const int64_t e = (int64_t)blockIdx.x * SLICE_BLOCK + threadIdx.x;
+  if (e >= n * d) return;
+  xn[e] = x[e];
+  if (e == 0) *nact = n;
+  if (e % d == 0) {
+    const int64_t i = e / d;
+    done[i] = 0;
+    list[i] = (int)i;
+  }
+}
+
+__global__ __launch_bounds__(SLICE_BLOCK) void k_slice_move_end(int64_t n, int d, const unsigned char* __restrict__ done,
+                                                                unsigned char* __restrict__ moved,
+                                                                const double* __restrict__ xn,
+                                                                double* __restrict__ x) {
+  const int64_t e = (int64_t)blockIdx.x * SLICE_BLOCK + threadIdx.x;
+  if (e >= n * d) return;
+  x[e] = xn[e];
+  if (e % d == 0) {
+    const int64_t i = e / d;
+    moved[i] = (unsigned char)(moved[i] | done[i]);
+  }
 }
 
 // lo -= the number of left ends inside before the first outside (jl if none), hi += the same on
@@ -89,9 +129,11 @@ __global__ __launch_bounds__(SLICE_BLOCK) void k_slice_ends_select(int64_t n, in
 // are the first *nact G rows; the group's selection writes the list of the chains that are still
 // moving after it (in an order that depends on scheduling; every chain's own steps do not).
 
-// Draws and their points, one thread per listed chain. Thread 0 also publishes the group's live
-// point count (*live = *nact G), adds it to *calls (if not null), and clears the next list's
-// length for the selection that follows.
+// Draws and their points, one thread per coordinate of a listed chain: each thread repeats its
+// chain's G draws (a few operations each) and writes its coordinate of every draw, so the stores
+// of a draw are spread over d threads; the chain's coordinate-0 thread writes t, a and b. Thread
+// 0 also publishes the group's live point count (*live = *nact G), adds it to *calls (if not
+// null), and clears the next list's length for the selection that follows.
 __global__ __launch_bounds__(SLICE_BLOCK) void k_slice_draws(int64_t n, int d, int G, const int* __restrict__ list,
                                                              const int64_t* __restrict__ nact,
                                                              const double* __restrict__ x,
@@ -103,31 +145,33 @@ __global__ __launch_bounds__(SLICE_BLOCK) void k_slice_draws(int64_t n, int d, i
                                                              double* __restrict__ b, int64_t* __restrict__ live,
                                                              int64_t* __restrict__ nact_next,
                                                              int64_t* __restrict__ calls) {
-  const int64_t j = (int64_t)blockIdx.x * SLICE_BLOCK + threadIdx.x;
+  const int64_t e = (int64_t)blockIdx.x * SLICE_BLOCK + threadIdx.x;
   const int64_t na = min(max(*nact, (int64_t)0), n);
-  if (j == 0) {
+  if (e == 0) {
     *live = na * G;
     *nact_next = 0;
     if (calls) *calls += na * G;
   }
+  const int64_t j = e / d, c = e - j * d;
   if (j >= na) return;
   const int64_t i = list[j];
   if (i < 0 || i >= n) return;                   // not a chain index
-  const double* xi = x + i * d;
-  const double* di = dirn + i * d;
+  const double xc = x[i * d + c], dc = dirn[i * d + c];
   double ai = lo[i], bi = hi[i];
   for (int k = 0; k < G; ++k) {
     const int64_t r = j * G + k;
     const double tk = ai + u[(int64_t)k * n + i] * (bi - ai);
-    t[r] = tk;
-    for (int c = 0; c < d; ++c) pts[r * d + c] = xi[c] + tk * di[c];
+    pts[r * d + c] = xc + tk * dc;
+    if (c == 0) t[r] = tk;
     if (tk < 0.0)
       ai = tk;
     else
       bi = tk;
   }
-  a[i] = ai;
-  b[i] = bi;
+  if (c == 0) {
+    a[i] = ai;
+    b[i] = bi;
+  }
 }
 
 // One listed chain that stays (no draw inside) joins the next list: the wavefront's stayers take
@@ -334,10 +378,11 @@ gwl_status gwl_slice_ends(int64_t n, int d, int m, const double* x, const double
   if (!x || !dirn || !u0 || !u1 || (m > 1 && !pts) || !lo || !hi || !jl || !jr)
     return fail(GWL_E_INVALID, "gwl_slice_ends: null pointer");
   hipStream_t s = (hipStream_t)stream;
-  hipLaunchKernelGGL(k_slice_ends, dim3(grid_of(n)), dim3(SLICE_BLOCK), 0, s, n, m, u0, u1, lo, hi, jl, jr);
-  if (m > 1)
+  if (m > 1)   // one launch: the slots' points and, from each chain's first thread, its interval
     hipLaunchKernelGGL(k_slice_end_points, dim3(grid_of((int64_t)(m - 1) * n * d)), dim3(SLICE_BLOCK), 0, s, n, d, m,
-                       x, dirn, (const double*)lo, (const double*)hi, (const double*)jl, pts);
+                       x, dirn, u0, u1, pts, lo, hi, jl, jr);
+  else
+    hipLaunchKernelGGL(k_slice_ends, dim3(grid_of(n)), dim3(SLICE_BLOCK), 0, s, n, m, u0, u1, lo, hi, jl, jr);
   return launched("gwl_slice_ends");
 }
 
@@ -358,6 +403,28 @@ gwl_status gwl_slice_ends_select(int64_t n, int d, int m, const double* pts, con
   return launched("gwl_slice_ends_select");
 }
 
+gwl_status gwl_slice_move_begin(int64_t n, int d, const double* x, double* xn, unsigned char* done, int* list,
+                                int64_t* nact, void* stream) {
+  clear_error();
+  gwl_status st = check_shape(n, d, 1);
+  if (st != GWL_OK) return st;
+  if (!x || !xn || !done || !list || !nact) return fail(GWL_E_INVALID, "gwl_slice_move_begin: null pointer");
+  hipLaunchKernelGGL(k_slice_move_begin, dim3(grid_of(n * d)), dim3(SLICE_BLOCK), 0, (hipStream_t)stream, n, d, x, xn,
+                     done, list, nact);
+  return launched("gwl_slice_move_begin");
+}
+
+gwl_status gwl_slice_move_end(int64_t n, int d, const unsigned char* done, unsigned char* moved, const double* xn,
+                              double* x, void* stream) {
+  clear_error();
+  gwl_status st = check_shape(n, d, 1);
+  if (st != GWL_OK) return st;
+  if (!done || !moved || !xn || !x) return fail(GWL_E_INVALID, "gwl_slice_move_end: null pointer");
+  hipLaunchKernelGGL(k_slice_move_end, dim3(grid_of(n * d)), dim3(SLICE_BLOCK), 0, (hipStream_t)stream, n, d, done,
+                     moved, xn, x);
+  return launched("gwl_slice_move_end");
+}
+
 gwl_status gwl_slice_list_init(int64_t n, int* list, int64_t* nact, void* stream) {
   clear_error();
   if (n < 1 || n > kMaxBatch) return fail(GWL_E_SHAPE, "n=%lld outside [1, 2^30]", (long long)n);
@@ -376,8 +443,8 @@ gwl_status gwl_slice_draws(int64_t n, int d, int G, const int* list, const int64
   if (!list || !nact || !x || !dirn || !lo || !hi || !u || !t || !pts || !a || !b || !live || !nact_next)
     return fail(GWL_E_INVALID, "gwl_slice_draws: null pointer");
   if (nact_next == nact) return fail(GWL_E_INVALID, "gwl_slice_draws: nact_next must not be nact");
-  hipLaunchKernelGGL(k_slice_draws, dim3(grid_of(n)), dim3(SLICE_BLOCK), 0, (hipStream_t)stream, n, d, G, list, nact,
-                     x, dirn, lo, hi, u, t, pts, a, b, live, nact_next, calls);
+  hipLaunchKernelGGL(k_slice_draws, dim3(grid_of(n * d)), dim3(SLICE_BLOCK), 0, (hipStream_t)stream, n, d, G, list,
+                     nact, x, dirn, lo, hi, u, t, pts, a, b, live, nact_next, calls);
   return launched("gwl_slice_draws");
 }
 

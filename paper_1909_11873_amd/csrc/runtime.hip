@@ -661,8 +661,15 @@ gwl_status gwl_logl_batch_live(gwl_event ev, const double* theta, int64_t B, con
   gwl_status st = check_device(ev->device);
   if (st != GWL_OK) return st;
   const bool mixed = use_mixed(ev, prec);
-  return run_logl(ev, theta, B, mixed, false, choose_shape(ev, B, mixed, false), logl, nullptr, (hipStream_t)stream,
-                  live);
+  // the shape for B, with at least enough workgroups per point group that a quarter of the point
+  // groups still give every CU two workgroups (chunks of at least 32 bins): a partly live batch
+  // then still fills the chip
+  LoopShape sh = choose_shape(ev, B, mixed, false);
+  const int64_t want = (4 * 2 * 256 + sh.npg - 1) / sh.npg;
+  const int64_t gcap = std::max<int64_t>(1, ev->M / (32 * (int64_t)sh.W));
+  const int G = (int)std::min<int64_t>(std::max<int64_t>(sh.G, want), std::max<int64_t>(gcap, sh.G));
+  if (G != sh.G) sh = make_shape(B, ev->M, sh.W, G, sh.setup);
+  return run_logl(ev, theta, B, mixed, false, sh, logl, nullptr, (hipStream_t)stream, live);
 }
 
 gwl_status gwl_logl_grad(gwl_event ev, const double* theta, int64_t B, gwl_precision prec, double* logl, double* grad,

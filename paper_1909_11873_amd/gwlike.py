@@ -88,6 +88,8 @@ def lib() -> ctypes.CDLL:
         "gwl_slice_ends": ([i64, cint, cint] + [vp] * 9 + [vp], cint),
         "gwl_slice_ends_select": ([i64, cint, cint] + [vp] * 7 + [vp], cint),
         "gwl_slice_list_init": ([i64, vp, vp, vp], cint),
+        "gwl_slice_move_begin": ([i64, cint] + [vp] * 5 + [vp], cint),
+        "gwl_slice_move_end": ([i64, cint] + [vp] * 4 + [vp], cint),
         "gwl_slice_draws": ([i64, cint, cint] + [vp] * 14 + [vp], cint),
         "gwl_slice_select": ([i64, cint, cint] + [vp] * 15 + [vp], cint),
         "gwl_prior_transform": ([i64, cint] + [vp] * 5 + [vp], cint),
@@ -507,6 +509,36 @@ def slice_list_init(n: int, device, lst: Optional[torch.Tensor] = None, nact: Op
     _list(lst, nact, n)
     _check("gwl_slice_list_init", lib().gwl_slice_list_init(n, _ptr(lst), _ptr(nact), _stream(lst)))
     return lst, nact
+
+
+def _flags(t, name, n):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.bool and t.is_contiguous()
+            and tuple(t.shape) == (n,)):
+        raise ValueError(f"{name} must be a contiguous bool CUDA tensor of shape ({n},)")
+
+
+def slice_move_begin(x, xn, done, lst: Optional[torch.Tensor] = None, nact: Optional[torch.Tensor] = None):
+    """The start of a move in one launch: xn = x, done = False, and the list of all chains.
+    Returns (list, nact)."""
+    n, d = x.shape
+    x, xn = _f64(x, "x", (n, d)), _f64(xn, "xn", (n, d))
+    _flags(done, "done", n)
+    lst = torch.empty(n, dtype=torch.int32, device=x.device) if lst is None else lst
+    nact = torch.empty((), dtype=torch.int64, device=x.device) if nact is None else nact
+    _list(lst, nact, n)
+    _check("gwl_slice_move_begin", lib().gwl_slice_move_begin(n, d, _ptr(x), _ptr(xn), _ptr(done), _ptr(lst),
+                                                              _ptr(nact), _stream(x)))
+    return lst, nact
+
+
+def slice_move_end(done, moved, xn, x) -> None:
+    """The end of a move in one launch: moved |= done, x = xn."""
+    n, d = x.shape
+    x, xn = _f64(x, "x", (n, d)), _f64(xn, "xn", (n, d))
+    _flags(done, "done", n)
+    _flags(moved, "moved", n)
+    _check("gwl_slice_move_end", lib().gwl_slice_move_end(n, d, _ptr(done), _ptr(moved), _ptr(xn), _ptr(x),
+                                                          _stream(x)))
 
 
 def slice_draws(x, dirn, lo, hi, u, lst, nact, calls: Optional[torch.Tensor] = None):

@@ -127,8 +127,17 @@ def gw_prior_transform(mc_range=(10.0, 60.0), dl_range=(100.0, 2000.0), tc_half=
     return transform
 
 
-SLICE_MAX_DRAWS = 48     # shrinkage draws per slice move before a chain gives up that move
-SLICE_GROUP = 8          # shrinkage draws evaluated together
+SLICE_GROUPS = (8, 8, 16, 16)     # shrinkage draws evaluated together, group by group
+SLICE_MAX_DRAWS = sum(SLICE_GROUPS)   # draws per slice move before a chain gives up that move
+SLICE_GROUP = SLICE_GROUPS[0]
+
+
+def _slice_groups():
+    """(first row of unif, group size) of every shrinkage group of a move."""
+    off = 2
+    for g in SLICE_GROUPS:
+        yield off, g
+        off += g
 
 
 def slice_move(x, dirn, unif, m, inside):
@@ -150,15 +159,15 @@ def slice_move(x, dirn, unif, m, inside):
     The outcome is fixed by the uniform numbers and by which of the points the procedure looks at
     lie inside, so those points are evaluated ahead, in one batch per stage: the m - 1 ends the
     stepping out can examine (J on the left, m - 1 - J on the right), then the shrinkage draws in
-    groups of SLICE_GROUP for the chains still moving, each draw from the interval as it would be
+    groups (SLICE_GROUPS) for the chains still moving, each draw from the interval as it would be
     if the earlier draws of its group had fallen outside. The first draw inside is the one the
     sequential procedure returns. A chain with no draw inside after SLICE_MAX_DRAWS keeps its
     point."""
     lo, hi = _slice_stepping(x, dirn, unif[0], unif[1], m, inside)
     done = torch.zeros(x.shape[0], dtype=torch.bool, device=x.device)
     xn = x
-    for g0 in range(0, SLICE_MAX_DRAWS, SLICE_GROUP):
-        xn, done, lo, hi = _slice_group(x, dirn, lo, hi, done, xn, unif[2 + g0:2 + g0 + SLICE_GROUP], inside)
+    for r0, G in _slice_groups():
+        xn, done, lo, hi = _slice_group(x, dirn, lo, hi, done, xn, unif[r0:r0 + G], inside)
         if bool(done.all()):
             break
     return xn, done
@@ -235,7 +244,7 @@ def _slice_group_dev(x, dirn, lo, hi, done, xn, ug, live_eval, lmin, lst, nact, 
     return lst_next, nact_next
 
 
-def _eager_live(raw, G):
+def _eager_live(raw):
     """live_eval for eager moves: reads the live count (a host synchronisation) and evaluates
     exactly those rows."""
     def live_eval(pts, live):
@@ -253,13 +262,12 @@ def slice_move_dev(x, dirn, unif, m, raw, lmin, calls=None):
     from . import gwlike as gw
     lo, hi = _slice_stepping_dev(x, dirn, unif[0], unif[1], m, raw, lmin)
     lo, hi = lo.contiguous(), hi.contiguous()
-    done = torch.zeros(x.shape[0], dtype=torch.bool, device=x.device)
-    xn = x.clone()
-    lst, nact = gw.slice_list_init(x.shape[0], x.device)
-    live_eval = _eager_live(raw, SLICE_GROUP)
-    for g0 in range(0, SLICE_MAX_DRAWS, SLICE_GROUP):
-        lst, nact = _slice_group_dev(x, dirn, lo, hi, done, xn, unif[2 + g0:2 + g0 + SLICE_GROUP], live_eval, lmin,
-                                     lst, nact, calls)
+    done = torch.empty(x.shape[0], dtype=torch.bool, device=x.device)
+    xn = torch.empty_like(x)
+    lst, nact = gw.slice_move_begin(x, xn, done)
+    live_eval = _eager_live(raw)
+    for r0, G in _slice_groups():
+        lst, nact = _slice_group_dev(x, dirn, lo, hi, done, xn, unif[r0:r0 + G], live_eval, lmin, lst, nact, calls)
         if int(nact) == 0:
             break
     return xn, done
@@ -267,7 +275,7 @@ def slice_move_dev(x, dirn, unif, m, raw, lmin, calls=None):
 
 class _SliceGraphs:
     """The slice moves of one batch shape captured as one HIP graph per move: the move's
-    direction, stepping out, and all SLICE_MAX_DRAWS / SLICE_GROUP groups of shrinkage draws, each
+    direction, stepping out, and all its groups of shrinkage draws (SLICE_GROUPS), each
     group for the chains still moving (a list kept on the device, so a group after every chain is
     done costs only its empty launches and no host decision is needed). The host draws each move's
     random numbers into static buffers (the same calls, in the same order, as the eager path, so
@@ -278,7 +286,7 @@ class _SliceGraphs:
     are counted on the device (calls)."""
 
     def __init__(self, smp):
-        n, d, m, G = smp.n, smp.d, smp.slice_out, SLICE_GROUP
+        n, d, m = smp.n, smp.d, smp.slice_out
         f64 = dict(dtype=torch.float64, device=smp.dev)
         self.smp = smp
         # placeholders for the warm-up and the capture: points at the cube's centre, unit directions
@@ -289,19 +297,16 @@ class _SliceGraphs:
         self.done = torch.zeros(n, dtype=torch.bool, device=smp.dev)
         self.moved = torch.zeros(n, dtype=torch.bool, device=smp.dev)
         self.calls = torch.zeros((), dtype=torch.int64, device=smp.dev)
-        stepping, group, start, _ = smp._slice_stages(self.lmin, count=False, calls=self.calls)
+        stepping, group, begin, _, end = smp._slice_stages(self.lmin, count=False, calls=self.calls)
 
         def move():
             self.dirn.copy_(smp.slice_width * (self.z / self.z.norm(dim=1, keepdim=True)) @ self.chol.T)
             lo, hi = stepping(self.x, self.dirn, self.unif[0], self.unif[1])
             lo, hi = lo.contiguous(), hi.contiguous()
-            self.done.zero_()
-            self.xn.copy_(self.x)
-            state = start()
-            for g0 in range(0, SLICE_MAX_DRAWS, G):
-                state = group(self.x, self.dirn, lo, hi, self.done, self.xn, self.unif[2 + g0:2 + g0 + G], state)
-            self.moved |= self.done
-            self.x.copy_(self.xn)
+            state = begin(self.x, self.xn, self.done)
+            for r0, G in _slice_groups():
+                state = group(self.x, self.dirn, lo, hi, self.done, self.xn, self.unif[r0:r0 + G], state)
+            end(self.done, self.moved, self.xn, self.x)
 
         side = torch.cuda.Stream(device=smp.dev)
         side.wait_stream(torch.cuda.current_stream(smp.dev))
@@ -490,8 +495,9 @@ class ParallelNestedSampler:
 
     def _slice_stages(self, lmin, count=True, calls=None):
         """(stepping(x, dirn, u0, u1) -> (lo, hi), group(x, dirn, lo, hi, done, xn, ug, state) ->
-        state, start() -> state, finished(state, done) -> bool) for the contour ln L >= lmin, in
-        the library's kernels or in torch. group updates xn, done, lo and hi in place and counts
+        state, begin(x, xn, done) -> state (xn = x, done = False), finished(state, done) -> bool,
+        end(done, moved, xn, x) (moved |= done, x = xn)) for the contour ln L >= lmin, in the
+        library's kernels or in torch. group updates xn, done, lo and hi in place and counts
         the draws it evaluates (those of the chains still moving) into `calls` (a device int64,
         the sampler's own if None); with count=True the stepping-out ends are counted on the host.
         With count=False (graph capture) nothing waits for the device."""
@@ -504,12 +510,14 @@ class ParallelNestedSampler:
             return self._raw(p)
         if self.slice_kernels:
             from . import gwlike as gw
-            live_eval = _eager_live(self._raw, SLICE_GROUP) if count else self._raw_live
+            # eager and captured moves evaluate the same rows with the same launches, so their
+            # likelihood values agree bit for bit
+            live_eval = self._raw_live
 
             def group(x, dirn, lo, hi, done, xn, ug, state):
                 return _slice_group_dev(x, dirn, lo, hi, done, xn, ug, live_eval, lmin, state[0], state[1], calls)
             return (lambda x, dirn, u0, u1: _slice_stepping_dev(x, dirn, u0, u1, m, raw, lmin), group,
-                    lambda: gw.slice_list_init(self.n, self.dev), lambda state, done: int(state[1]) == 0)
+                    gw.slice_move_begin, lambda state, done: int(state[1]) == 0, gw.slice_move_end)
         inside = lambda p: self._inside_raw(p, lmin)
         inside_count = (lambda p: self._in_contour(p, lmin)) if count else inside
 
@@ -520,8 +528,16 @@ class ParallelNestedSampler:
                 if dst is not src:
                     dst.copy_(src)
             return state
+
+        def begin(x, xn, done):
+            done.zero_()
+            xn.copy_(x)
+
+        def end(done, moved, xn, x):
+            moved |= done
+            x.copy_(xn)
         return (lambda x, dirn, u0, u1: _slice_stepping(x, dirn, u0, u1, m, inside_count), group,
-                lambda: None, lambda state, done: bool(done.all()))
+                begin, lambda state, done: bool(done.all()), end)
 
     def _raw_live(self, p, live):
         """ln L at the first `live` rows of p (a device int64 scalar) when the sampler has a
@@ -556,23 +572,22 @@ class ParallelNestedSampler:
         if self.slice_graphs:
             x, moved = self._graphs.walk(x, chol, lmin, self.slice_steps)
             return torch.where(moved[:, None], x, torch.full_like(x, 2.0))
-        stepping, group, begin, finished = self._slice_stages(lmin)
+        stepping, group, begin, finished, end = self._slice_stages(lmin)
         moved = torch.zeros(n, dtype=torch.bool, device=self.dev)
+        done = torch.empty(n, dtype=torch.bool, device=self.dev)
+        xn = torch.empty_like(x)
         for _ in range(self.slice_steps):
             z = torch.randn(n, d, generator=self.gen, **f64)
             dirn = self.slice_width * (z / z.norm(dim=1, keepdim=True)) @ chol.T
             unif = torch.rand(2 + SLICE_MAX_DRAWS, n, generator=self.gen, **f64)
             lo, hi = stepping(x, dirn, unif[0], unif[1])
             lo, hi = lo.contiguous(), hi.contiguous()
-            done = torch.zeros(n, dtype=torch.bool, device=self.dev)
-            xn = x.clone()
-            state = begin()
-            for g0 in range(0, SLICE_MAX_DRAWS, SLICE_GROUP):
-                state = group(x, dirn, lo, hi, done, xn, unif[2 + g0:2 + g0 + SLICE_GROUP], state)
+            state = begin(x, xn, done)
+            for r0, G in _slice_groups():
+                state = group(x, dirn, lo, hi, done, xn, unif[r0:r0 + G], state)
                 if finished(state, done):
                     break
-            moved |= done
-            x = xn
+            end(done, moved, xn, x)
         return torch.where(moved[:, None], x, torch.full_like(x, 2.0))
 
     def _propose(self, it, live_u, live_l):

@@ -1,8 +1,8 @@
-"""gwl_logl_batch_live (a batch whose length the device decides) against gwl_logl_batch on the
-same rows: the first *live points are evaluated exactly as a full call evaluates them, the rest of
-the output is left as it was, in both precisions, at a tuned shape with several workgroups per
-point group and at the heuristic one, and under graph capture with the length changed between
-replays."""
+"""gwl_logl_batch_live (a batch whose length the device decides): the first *live points come out
+bit for bit as in the same call with every point live, and within rounding of gwl_logl_batch
+(whose launch may split the bins differently); the rest of the output is left as it was; both
+precisions, at tuned and heuristic shapes, and under graph capture with the length changed
+between replays."""
 import numpy as np
 import pytest
 import torch
@@ -28,7 +28,10 @@ def test_live_rows_equal_a_full_call(cfg, B, f_hi):
     spec, ev = _event(cfg, f_hi)
     th = torch.tensor(synth.theta_batch(spec, B), device=DEV)
     for prec in ("fp64", "mixed"):
-        full = gw.logl(th, ev, prec)
+        ref = gw.logl(th, ev, prec)
+        full = gw.logl_live(th, torch.tensor(B, dtype=torch.int64, device=DEV), ev, prec)
+        tol = 1e-9 * ref.abs().clamp(min=1.0) if prec == "fp64" else 2e-4
+        assert bool(((full - ref).abs() <= tol).all()), prec
         for n in (0, 1, 63, 64, 65, B // 3, B - 1, B, B + 100):
             live = torch.tensor(n, dtype=torch.int64, device=DEV)
             out = torch.full((B,), 123.5, dtype=torch.float64, device=DEV)
@@ -43,8 +46,8 @@ def test_live_length_changes_between_graph_replays():
     spec, ev = _event(1)
     B = 2048
     th = torch.tensor(synth.theta_batch(spec, B), device=DEV)
-    full = gw.logl(th, ev, "mixed")
     live = torch.tensor(B, dtype=torch.int64, device=DEV)
+    full = gw.logl_live(th, live, ev, "mixed")
     out = torch.zeros(B, dtype=torch.float64, device=DEV)
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
