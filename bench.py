@@ -114,9 +114,10 @@ def layout_key(shape) -> str:
 
 
 def kernel_name(nd: int, mixed: bool, grad: bool, shape) -> str:
-    """The evaluation kernel's name as the profiler prints it: k_eval<ND, MIXED, GRAD, SETUP, CUT>."""
+    """The evaluation kernel's name as the profiler prints it: k_eval<ND, MIXED, GRAD, SETUP, CUT,
+    ROT> (no ISCO cut; the float64 loop on the workloads' uniform grids rotates the phasors)."""
     b = lambda x: "true" if x else "false"
-    return f"gwl::k_eval<{nd}, {b(mixed)}, {b(grad)}, {b(shape['setup'])}, false>"
+    return f"gwl::k_eval<{nd}, {b(mixed)}, {b(grad)}, {b(shape['setup'])}, false, {b(not mixed)}>"
 
 
 def load_or_tune(tune_out):
