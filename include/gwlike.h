@@ -266,6 +266,16 @@ gwl_status gwl_multi_plan_create(const gwl_event* evs, int E, const int64_t* B_e
                                  int with_grad, gwl_plan* out);
 
 /*
+ * gwl_multi_plan_create with the queue order chosen by the caller: order 0 takes the tuned one (as
+ * gwl_multi_plan_create), 1 queues events by ascending work (small events finish first: lower
+ * per-event latency), 2 by descending work (large items first, small ones fill the tail of the
+ * launch). The chunk length is the tuned one either way. Results do not depend on the order (every item writes its
+ * own partial sums, added in a fixed order). GWL_E_INVALID for another order.
+ */
+gwl_status gwl_multi_plan_create_order(const gwl_event* evs, int E, const int64_t* B_e, gwl_precision prec,
+                                       int with_grad, int order, gwl_plan* out);
+
+/*
  * Run a plan. theta[e], logl[e], grad[e] are device pointers ([B_e][P_e], [B_e], [B_e][P_e], P_e = 11
  * or 11 + 2 nnode ndet on a calibrated event);
  * grad may be null when the plan has no gradient. The pointer tables are host arrays of E

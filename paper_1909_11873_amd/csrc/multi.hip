@@ -507,6 +507,22 @@ gwl_status gwl_multi_plan_create(const gwl_event* evs, int E, const int64_t* B_e
   return build_plan(evs, E, B_e, prec, with_grad, chunk, desc, out);
 }
 
+gwl_status gwl_multi_plan_create_order(const gwl_event* evs, int E, const int64_t* B_e, gwl_precision prec,
+                                       int with_grad, int order, gwl_plan* out) {
+  clear_error();
+  if (order < 0 || order > 2) return fail(GWL_E_INVALID, "order must be 0 (tuned), 1 (ascending) or 2 (descending)");
+  int chunk = 0;
+  bool desc = false;
+  if (evs && B_e && E >= 1 && E <= 4096) {
+    bool ok = true;
+    for (int e = 0; e < E; ++e) ok &= evs[e] != nullptr;
+    if (ok) choose_multi_shape(evs, E, B_e, prec == GWL_MIXED, with_grad != 0, &chunk, &desc);
+  }
+  if (order == 1) desc = false;
+  if (order == 2) desc = true;
+  return build_plan(evs, E, B_e, prec, with_grad, chunk, desc, out);
+}
+
 gwl_status gwl_plan_info(gwl_plan pl, int* chunk, int* descending, int64_t* items) {
   clear_error();
   if (!pl) return fail(GWL_E_INVALID, "plan is null");

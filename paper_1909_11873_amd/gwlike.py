@@ -70,6 +70,8 @@ def lib() -> ctypes.CDLL:
         "gwl_waveform": ([vp, i64, ctypes.POINTER(Detector), cint, vp, i64, dbl, vp, vp], cint),
         "gwl_multi_plan_create": ([ctypes.POINTER(vp), cint, ctypes.POINTER(i64), cint, cint, ctypes.POINTER(vp)],
                                   cint),
+        "gwl_multi_plan_create_order": ([ctypes.POINTER(vp), cint, ctypes.POINTER(i64), cint, cint, cint,
+                                         ctypes.POINTER(vp)], cint),
         "gwl_multi_launch": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), _c_double_p, vp],
                              cint),
         "gwl_plan_destroy": ([vp], cint),
@@ -336,10 +338,16 @@ class MultiPlan:
     events   list of Event (same detector count, same device); batches: points per event.
     launch(thetas) takes one float64 CUDA tensor [B_e, P_e] per event (P_e = 11, or 11 + 2 n ndet
     on a calibrated event, whose own kernels run after the persistent launch) and returns
-    (logls, grads or None, latency_us or None).
+    (logls, grads or None, latency_us or None). order: "tuned" (the autotuner's queue order),
+    "ascending" (small events first) or "descending" (large events first).
     """
 
-    def __init__(self, events: Sequence[Event], batches: Sequence[int], precision="mixed", with_grad: bool = False):
+    ORDERS = {"tuned": 0, "ascending": 1, "descending": 2}
+
+    def __init__(self, events: Sequence[Event], batches: Sequence[int], precision="mixed", with_grad: bool = False,
+                 order: str = "tuned"):
+        if order not in self.ORDERS:
+            raise ValueError(f"order must be one of {sorted(self.ORDERS)}")
         self.events = list(events)
         self.batches = [int(b) for b in batches]
         if len(self.events) != len(self.batches) or not self.events:
@@ -349,8 +357,9 @@ class MultiPlan:
         evs = (ctypes.c_void_p * E)(*[ev.handle.value for ev in self.events])
         bs = (ctypes.c_int64 * E)(*self.batches)
         h = ctypes.c_void_p()
-        _check("gwl_multi_plan_create", lib().gwl_multi_plan_create(evs, E, bs, _prec(precision),
-                                                                    int(self.with_grad), ctypes.byref(h)))
+        _check("gwl_multi_plan_create_order", lib().gwl_multi_plan_create_order(evs, E, bs, _prec(precision),
+                                                                                int(self.with_grad),
+                                                                                self.ORDERS[order], ctypes.byref(h)))
         self._h = h
 
     def launch(self, thetas: Sequence[torch.Tensor], latency: bool = False):

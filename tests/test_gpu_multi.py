@@ -101,6 +101,24 @@ def test_multi_graph_replays_are_identical(events):
     plan.close()
 
 
+def test_queue_order_does_not_change_results(events):
+    """Plans queued by ascending and by descending work give the same values and gradients bit
+    for bit (each item writes its own partial sums, added in a fixed order)."""
+    thetas = [torch.tensor(e["th"], device=DEV).reshape(-1, 11) for e in events]
+    out = {}
+    for order in ("ascending", "descending", "tuned"):
+        plan = gw.MultiPlan([e["ev"] for e in events], BATCHES, "mixed", with_grad=True, order=order)
+        l, g, lat = plan.launch(thetas, latency=True)
+        out[order] = ([x.cpu().numpy() for x in l], [x.cpu().numpy() for x in g])
+        assert plan.info()[1] == (order == "descending") or order == "tuned"
+        plan.close()
+    for order in ("descending", "tuned"):
+        for a, b in zip(out["ascending"][0] + out["ascending"][1], out[order][0] + out[order][1]):
+            assert np.array_equal(a, b)
+    with pytest.raises(ValueError):
+        gw.MultiPlan([e["ev"] for e in events], BATCHES, "mixed", order="random")
+
+
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_multi_autotune_roundtrip(events, prec, tmp_path):
     """The tuner times plan shapes, records the fastest, and a new plan for the same workload
