@@ -147,19 +147,17 @@ struct PointModel {
   bool valid;
 };
 
-template <class T, int ND>
-__device__ inline void point_model(const T th[NPARAM], const EventGeom& g, PointModel<T>& pm) {
+// The model splits into an intrinsic half (masses, spins, distance, phase: a_m, c0, A and the
+// domain check) and an extrinsic half (sky position, orientation, time: T_det and Q_det), which
+// the in-kernel set-up runs on two wavefronts at once.
+template <class T>
+__device__ inline void point_intrinsic(const T th[NPARAM], PointModel<T>& pm) {
   const T& mc = th[0];
   const T& q = th[1];
   const T& chi1 = th[2];
   const T& chi2 = th[3];
   const T& dl = th[4];
-  const T& ra = th[5];
-  const T& dec = th[6];
-  const T& inc = th[7];
-  const T& psi = th[8];
   const T& phic = th[9];
-  const T& tc = th[10];
 
   const double qv = val(q), mcv = val(mc), dlv = val(dl), c1 = val(chi1), c2 = val(chi2);
   bool ok = (qv > 0.0) && (qv <= 1.0) && (mcv > 0.0) && (dlv > 0.0) && (fabs(c1) < 1.0) && (fabs(c2) < 1.0);
@@ -201,6 +199,15 @@ __device__ inline void point_model(const T th[NPARAM], const EventGeom& g, Point
   pm.c0 = pref * c5 * (1.0 + lpm) - (phic + kPi / 4.0) * (1.0 / kTwoPi);
 
   pm.amp = 0.45643546458763845 * 0.46619407703541166 * xpow(kTsun * mc, 5.0 / 6.0) * (kC / kMpc) / dl;
+}
+
+template <class T, int ND>
+__device__ inline void point_extrinsic(const T th[NPARAM], const EventGeom& g, PointModel<T>& pm) {
+  const T& ra = th[5];
+  const T& dec = th[6];
+  const T& inc = th[7];
+  const T& psi = th[8];
+  const T& tc = th[10];
 
   // polarisation basis of the source at (ra - gmst, dec), rotated by psi
   const T h = ra - g.gmst;
@@ -226,6 +233,12 @@ __device__ inline void point_model(const T th[NPARAM], const EventGeom& g, Point
     const double* r = g.r[d];
     pm.tdet[d] = tc - (r[0] * k0 + r[1] * k1 + r[2] * k2) * (1.0 / kC);
   }
+}
+
+template <class T, int ND>
+__device__ inline void point_model(const T th[NPARAM], const EventGeom& g, PointModel<T>& pm) {
+  point_intrinsic<T>(th, pm);
+  point_extrinsic<T, ND>(th, g, pm);
 }
 
 // ---------------------------------------------------------------------------------------------

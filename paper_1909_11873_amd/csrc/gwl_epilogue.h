@@ -10,6 +10,28 @@
 
 namespace gwl {
 
+// E G: the constant phase factor E = exp(-2 pi i c0) (c0 in cycles) times the gain G.
+__device__ inline void phase_gain(double c0raw, double gr, double gi, double& egr, double& egi) {
+  const double c0 = c0raw - rint(c0raw);
+  double es, ecs;
+  sincos_cycles_f64(c0, es, ecs);
+  egr = ecs * gr + es * gi;
+  egi = ecs * gi - es * gr;
+}
+
+// Whether the phase sum_m a_m g_m(f) + f T_det stays below PHASE_LIMIT cycles on the event's
+// grid (a and T after the fiducial's offsets; always true without an event).
+template <int ND>
+__device__ inline bool rows_in_range(const double* a, const double* T, const EventConst* ec) {
+  if (!ec) return true;
+  double bound = 0.0, tmax = 0.0;
+#pragma unroll
+  for (int m = 0; m < NBASIS; ++m) bound = fma(fabs(a[m]), ec->gmax[m], bound);
+#pragma unroll
+  for (int d = 0; d < ND; ++d) tmax = fmax(tmax, fabs(T[d]));
+  return fma(tmax, ec->fmax, bound) < PHASE_LIMIT;
+}
+
 // Set-up rows (layout CO_*) of one point; false if the point is outside the model's domain or,
 // given the event (ec), its phase could exceed PHASE_LIMIT cycles somewhere on the grid.
 // With `scaled` (float32 tables) the event's (gain_r, gain_i) undoes the mean gain of the bin
@@ -27,10 +49,8 @@ __device__ inline bool setup_rows(const double (&th)[NPARAM], const EventGeom& g
   for (int j = 0; j < NCOEF; ++j) rows[j] = 0.0;
 #pragma unroll
   for (int m = 0; m < NBASIS; ++m) rows[CO_A + m] = pm.a[m] - (ec ? ec->fa[m] : 0.0);
-  const double c0 = pm.c0 - rint(pm.c0);
-  double es, ecs;
-  sincos_cycles_f64(c0, es, ecs);
-  const double egr = ecs * gr + es * gi, egi = ecs * gi - es * gr;  // E G
+  double egr, egi;
+  phase_gain(pm.c0, gr, gi, egr, egi);
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
     rows[CO_T + d] = pm.tdet[d] - (ec ? ec->fT[d] : 0.0);
@@ -41,17 +61,36 @@ __device__ inline bool setup_rows(const double (&th)[NPARAM], const EventGeom& g
   }
   rows[CO_C0] = pm.c0;
   rows[CO_AMP] = pm.amp;
-  bool in_range = true;
-  if (ec) {
-    // bound on |sum_m a_m g_m(f) + f T_det| over the grid
-    double bound = 0.0, tmax = 0.0;
-#pragma unroll
-    for (int m = 0; m < NBASIS; ++m) bound = fma(fabs(rows[CO_A + m]), ec->gmax[m], bound);
-#pragma unroll
-    for (int d = 0; d < ND; ++d) tmax = fmax(tmax, fabs(rows[CO_T + d]));
-    in_range = fma(tmax, ec->fmax, bound) < PHASE_LIMIT;
-  }
+  const bool in_range = rows_in_range<ND>(&rows[CO_A], &rows[CO_T], ec);
   return pm.valid && in_range;
+}
+
+// The in-kernel set-up in two halves, each writing its rows of one point into the LDS rows
+// [NCOEF][WAVE] (lane = point), so that two wavefronts can run them at once. The intrinsic half
+// writes CO_A (less the fiducial's), CO_C0 and CO_AMP, NaN for a point outside the model's
+// domain; the extrinsic half writes CO_T (less the fiducial's), CO_QR and CO_QI. The phase
+// range check and the adjoint factors c_det then come from these rows (rows_in_range,
+// phase_gain), with the same arithmetic as setup_rows.
+__device__ inline void setup_lds_intrinsic(const double (&th)[NPARAM], const EventConst* ec, double* rows_s, int lane) {
+  PointModel<double> pm;
+  point_intrinsic<double>(th, pm);
+  const double nan = __builtin_nan("");
+#pragma unroll
+  for (int m = 0; m < NBASIS; ++m) rows_s[(CO_A + m) * WAVE + lane] = pm.valid ? pm.a[m] - (ec ? ec->fa[m] : 0.0) : nan;
+  rows_s[CO_C0 * WAVE + lane] = pm.valid ? pm.c0 : nan;
+  rows_s[CO_AMP * WAVE + lane] = pm.valid ? pm.amp : nan;
+}
+template <int ND>
+__device__ inline void setup_lds_extrinsic(const double (&th)[NPARAM], const EventGeom& g, const EventConst* ec,
+                                           double* rows_s, int lane) {
+  PointModel<double> pm;
+  point_extrinsic<double, ND>(th, g, pm);
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    rows_s[(CO_T + d) * WAVE + lane] = pm.tdet[d] - (ec ? ec->fT[d] : 0.0);
+    rows_s[(CO_QR + d) * WAVE + lane] = pm.qr[d];
+    rows_s[(CO_QI + d) * WAVE + lane] = pm.qi[d];
+  }
 }
 
 // Divide the measured mean gain of the float32 hardware phasor out of the complex sums Z_det

@@ -151,32 +151,57 @@ __attribute__((amdgpu_waves_per_eu(eval_waves_per_eu<ND, MIXED, GRAD, SETUP, CUT
   }
 
   if constexpr (!MIXED) fill_phasor_table(tbl);
+  // in-kernel set-up: the intrinsic half on wavefront 0, the extrinsic half on wavefront 1 (on
+  // wavefront 0 too when the workgroup has one)
   if constexpr (SETUP) {
-    if (w == 0) {
+    const int wx = sh.W > 1 ? 1 : 0;
+    if (w == 0 || w == wx) {
       double th[NPARAM];
 #pragma unroll
       for (int i = 0; i < NPARAM; ++i) th[i] = theta[pc * NPARAM + i];
-      double rows[NCOEF];
-      const bool valid = setup_rows<ND>(th, geo, ec, MIXED, rows);
-      const double nan = __builtin_nan("");
-#pragma unroll
-      for (int j = 0; j < NCOEF; ++j) rows_s[j * WAVE + lane] = valid ? rows[j] : nan;
+      if (w == 0) setup_lds_intrinsic(th, ec, rows_s, lane);
+      if (w == wx) setup_lds_extrinsic<ND>(th, geo, ec, rows_s, lane);
     }
   }
   if (SETUP || !MIXED) __syncthreads();
 
   double a[NBASIS], T[ND];
   double tot[NZ];
+  bool in_range = true;
+  if constexpr (SETUP) {
+#pragma unroll
+    for (int m = 0; m < NBASIS; ++m) a[m] = rows_s[(CO_A + m) * WAVE + lane];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) T[d] = rows_s[(CO_T + d) * WAVE + lane];
+    // a point whose phase could leave the supported range gets NaN sums (and value)
+    in_range = rows_in_range<ND>(a, T, ec);
+    if (!in_range) a[0] = __builtin_nan("");
+  }
+  // c_det = E G Q_det from the set-up rows (the adjoint's projection factors)
+  auto lds_factors = [&](double (&crd)[ND], double (&cid)[ND]) {
+    double egr, egi;
+    phase_gain(rows_s[CO_C0 * WAVE + lane], (MIXED && ec) ? ec->gain_r : 1.0, (MIXED && ec) ? ec->gain_i : 0.0, egr,
+               egi);
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      const double qr = rows_s[(CO_QR + d) * WAVE + lane], qi = rows_s[(CO_QI + d) * WAVE + lane];
+      crd[d] = egr * qr - egi * qi;
+      cid[d] = egr * qi + egi * qr;
+    }
+  };
   if constexpr (MIXED) {
     float cr[ND], ci[ND];
     if constexpr (SETUP) {
 #pragma unroll
-      for (int m = 0; m < NBASIS; ++m) a[m] = rows_s[(CO_A + m) * WAVE + lane];
+      for (int d = 0; d < ND; ++d) cr[d] = ci[d] = 0.0f;
+      if constexpr (GRAD) {
+        double crd[ND], cid[ND];
+        lds_factors(crd, cid);
 #pragma unroll
-      for (int d = 0; d < ND; ++d) {
-        T[d] = rows_s[(CO_T + d) * WAVE + lane];
-        cr[d] = GRAD ? (float)rows_s[(CO_CR + d) * WAVE + lane] : 0.0f;
-        ci[d] = GRAD ? (float)rows_s[(CO_CI + d) * WAVE + lane] : 0.0f;
+        for (int d = 0; d < ND; ++d) {
+          cr[d] = (float)crd[d];
+          ci[d] = (float)cid[d];
+        }
       }
     } else {
       load_coef<ND, float>(coef, Bp, pc, GRAD, a, T, cr, ci);
@@ -187,13 +212,8 @@ __attribute__((amdgpu_waves_per_eu(eval_waves_per_eu<ND, MIXED, GRAD, SETUP, CUT
     double cr[ND], ci[ND];
     if constexpr (SETUP) {
 #pragma unroll
-      for (int m = 0; m < NBASIS; ++m) a[m] = rows_s[(CO_A + m) * WAVE + lane];
-#pragma unroll
-      for (int d = 0; d < ND; ++d) {
-        T[d] = rows_s[(CO_T + d) * WAVE + lane];
-        cr[d] = GRAD ? rows_s[(CO_CR + d) * WAVE + lane] : 0.0;
-        ci[d] = GRAD ? rows_s[(CO_CI + d) * WAVE + lane] : 0.0;
-      }
+      for (int d = 0; d < ND; ++d) cr[d] = ci[d] = 0.0;
+      if constexpr (GRAD) lds_factors(cr, ci);
     } else {
       load_coef<ND, double>(coef, Bp, pc, GRAD, a, T, cr, ci);
     }
@@ -258,7 +278,7 @@ __attribute__((amdgpu_waves_per_eu(eval_waves_per_eu<ND, MIXED, GRAD, SETUP, CUT
     if (MIXED) apply_gain<ND>(e, tot);
     double qr[ND], qi[ND], amp, c0f;
     if constexpr (SETUP) {
-      amp = rows_s[CO_AMP * WAVE + lane];
+      amp = in_range ? rows_s[CO_AMP * WAVE + lane] : __builtin_nan("");
       c0f = rows_s[CO_C0 * WAVE + lane];
 #pragma unroll
       for (int d = 0; d < ND; ++d) {
