@@ -249,16 +249,21 @@ def gpu_leg(cfg: int, steps: int, warmup: int, parity_inputs, tune_out=None, rb_
         shapes[key] = {"nchunk": nchunk, "chunk_bins": chunk, "waves": waves, "groups": groups, "setup": setup}
 
     def timed(fn, k, w):
-        """(wall seconds of k calls, mean bin-loop kernel seconds over them); the bin-loop launches
-        are bracketed by HIP events on the stream they run on."""
+        """(wall seconds of k calls, mean bin-loop kernel seconds over k more calls). The wall clock
+        runs with nothing added to the calls; in the second pass the bin-loop launches are
+        bracketed by HIP events on the stream they run on (two events and two records per call,
+        which would otherwise count in a short call's wall time)."""
         warm_up(fn, w)
-        gw.profile_read()
-        gw.profile_enable(True)
         t0 = time.perf_counter()
         for _ in range(k):
             fn()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        gw.profile_read()
+        gw.profile_enable(True)
+        for _ in range(k):
+            fn()
+        torch.cuda.synchronize()
         gw.profile_enable(False)
         n, kms = gw.profile_read()
         return wall, kms / max(n, 1) / 1e3

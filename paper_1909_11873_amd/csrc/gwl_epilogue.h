@@ -10,13 +10,20 @@
 
 namespace gwl {
 
-// E G: the constant phase factor E = exp(-2 pi i c0) (c0 in cycles) times the gain G.
+// E G: the constant phase factor E = exp(-2 pi i c0) (c0 in cycles) times the gain G. This and
+// adjoint_factor spell out their fused multiply-adds, so that every kernel forming c_det rounds
+// the same way (the in-kernel set-up and the set-up kernel give bitwise equal gradients).
 __device__ inline void phase_gain(double c0raw, double gr, double gi, double& egr, double& egi) {
   const double c0 = c0raw - rint(c0raw);
   double es, ecs;
   sincos_cycles_f64(c0, es, ecs);
-  egr = ecs * gr + es * gi;
-  egi = ecs * gi - es * gr;
+  egr = fma(ecs, gr, es * gi);
+  egi = fma(ecs, gi, -(es * gr));
+}
+// c_det = (E G) Q_det
+__device__ inline void adjoint_factor(double egr, double egi, double qr, double qi, double& cr, double& ci) {
+  cr = fma(egr, qr, -(egi * qi));
+  ci = fma(egr, qi, egi * qr);
 }
 
 // Whether the phase sum_m a_m g_m(f) + f T_det stays below PHASE_LIMIT cycles on the event's
@@ -56,8 +63,7 @@ __device__ inline bool setup_rows(const double (&th)[NPARAM], const EventGeom& g
     rows[CO_T + d] = pm.tdet[d] - (ec ? ec->fT[d] : 0.0);
     rows[CO_QR + d] = pm.qr[d];
     rows[CO_QI + d] = pm.qi[d];
-    rows[CO_CR + d] = egr * pm.qr[d] - egi * pm.qi[d];
-    rows[CO_CI + d] = egr * pm.qi[d] + egi * pm.qr[d];
+    adjoint_factor(egr, egi, pm.qr[d], pm.qi[d], rows[CO_CR + d], rows[CO_CI + d]);
   }
   rows[CO_C0] = pm.c0;
   rows[CO_AMP] = pm.amp;

@@ -184,9 +184,7 @@ __attribute__((amdgpu_waves_per_eu(eval_waves_per_eu<ND, MIXED, GRAD, SETUP, CUT
                egi);
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
-      const double qr = rows_s[(CO_QR + d) * WAVE + lane], qi = rows_s[(CO_QI + d) * WAVE + lane];
-      crd[d] = egr * qr - egi * qi;
-      cid[d] = egr * qi + egi * qr;
+      adjoint_factor(egr, egi, rows_s[(CO_QR + d) * WAVE + lane], rows_s[(CO_QI + d) * WAVE + lane], crd[d], cid[d]);
     }
   };
   if constexpr (MIXED) {
