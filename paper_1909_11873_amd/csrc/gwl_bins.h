@@ -296,6 +296,14 @@ __device__ __forceinline__ void bin_loop_f64(TabP tab, GradP gtab,
 // most the Earth's light-crossing time, 0.043 s: under 90 cycles at 2 kHz). Per detector after
 // the first this replaces the phase shift, the table lookup and the series (15 float64
 // instructions and one LDS read) by two complex multiplies (8). a and T are in table units.
+//
+// The forward pass needs only the sums Z_det = sum_k u_k conj(p_0,k) conj(r_det,k), so it does
+// not form each detector's phasor: over a block of bins kb..ke-1 it runs the Horner recurrence
+// G <- G rho + u_k conj(p_0,k) (rho = exp(2 pi i step (T_det - T_0))), which leaves
+// G = sum_k u_k conj(p_0,k) rho^(ke-1-k), and closes the block with Z_det += G conj(r_det,ke-1),
+// r_det taken exactly at the block's last bin. Since |rho| = 1 this is the same sum; the
+// recurrence costs one complex multiply-add per bin and detector (8 instructions) where the
+// phasor, its rotation and the multiply-accumulate cost 12.
 constexpr int NROT = 32;
 template <int ND, bool GRAD, class TabP, class GradP>
 __device__ __forceinline__ void bin_loop_f64_rot(TabP tab, GradP gtab, int k0, int k1, const double (&a)[NBASIS],
@@ -316,6 +324,42 @@ __device__ __forceinline__ void bin_loop_f64_rot(TabP tab, GradP gtab, int k0, i
     sincos_tbl(step * D[d], tbl, pim[d], pr[d]);  // the ratio exp(2 pi i step D_d)
   }
   RowF64<ND> cur = load_row_f64<ND>(tab, k0);
+  if constexpr (!GRAD) {
+    for (int kb = k0; kb < k1; kb += NROT) {
+      double gr[ND], gi[ND];
+#pragma unroll
+      for (int d = 0; d < ND; ++d) gr[d] = gi[d] = 0.0;
+      const int ke = kb + NROT < k1 ? kb + NROT : k1;
+      double flast = cur.f;
+#pragma unroll 2
+      for (int k = kb; k < ke; ++k) {
+        const RowF64<ND> nxt = load_row_f64<ND>(tab, k + 1);
+        const double psi = phase_poly(a, cur.x, cur.w, cur.w2, cur.lnf);
+        double c0, s0;
+        sincos_tbl(fma(cur.f, T[0], psi), tbl, s0, c0);
+        z[0] = fma(cur.u[0], c0, fma(cur.u[1], s0, z[0]));       // u_0 conj(p_0)
+        z[1] = fma(cur.u[1], c0, fma(-cur.u[0], s0, z[1]));
+#pragma unroll
+        for (int d = 1; d < ND; ++d) {
+          const double ur = cur.u[2 * d], ui = cur.u[2 * d + 1];
+          const double ar = fma(ur, c0, ui * s0), ai = fma(ui, c0, -(ur * s0));  // u_d conj(p_0)
+          const double t = gr[d];
+          gr[d] = fma(t, pr[d], fma(-gi[d], pim[d], ar));
+          gi[d] = fma(t, pim[d], fma(gi[d], pr[d], ai));
+        }
+        flast = cur.f;
+        cur = nxt;
+      }
+#pragma unroll
+      for (int d = 1; d < ND; ++d) {
+        double qr, qi;
+        sincos_tbl(flast * D[d], tbl, qi, qr);                    // exact r_det at the last bin
+        z[2 * d] = fma(gr[d], qr, fma(gi[d], qi, z[2 * d]));     // G conj(r_det)
+        z[2 * d + 1] = fma(gi[d], qr, fma(-gr[d], qi, z[2 * d + 1]));
+      }
+    }
+    return;
+  }
   for (int kb = k0; kb < k1; kb += NROT) {
     double qr[ND], qi[ND];
     qr[0] = 1.0;

@@ -40,7 +40,8 @@ struct MultiEvDev {
   int item0, nitems;       // first item in the queue, item count
   int f64;                 // 1: float64 tables and loop (every event of a float64 plan, and the
                            // relative-binning events of a mixed one)
-  int pad;
+  int rot;                 // 1: the float64 loop on a uniform grid rotates the detectors' phasors
+  double step;             // the uniform grid's spacing (rot)
 };
 
 struct MultiIODev {
@@ -146,8 +147,12 @@ __global__ __launch_bounds__(BLOCK, (ND <= 3 ? (GRAD && MIXED && !ANYF64 ? 5 : 4
         double cr[ND], ci[ND];
         load_coef<ND, double>(ev.coef, ev.Bp, pc, GRAD, a, T, cr, ci);
         to_table_units<ND>(a, T);
-        bin_loop_f64<ND, GRAD>((const_as_ptr<RowF64<ND>>)ev.tab, (const_as_ptr<RowGradF64>)ev.gtab, k0, k1, a, T,
-                               cr, ci, tbl, tot);
+        if (ev.rot)
+          bin_loop_f64_rot<ND, GRAD>((const_as_ptr<RowF64<ND>>)ev.tab, (const_as_ptr<RowGradF64>)ev.gtab, k0, k1, a,
+                                     T, cr, ci, tbl, ev.step, tot);
+        else
+          bin_loop_f64<ND, GRAD>((const_as_ptr<RowF64<ND>>)ev.tab, (const_as_ptr<RowGradF64>)ev.gtab, k0, k1, a, T,
+                                 cr, ci, tbl, tot);
       }
     }
     global_as_ptr<double> part = (global_as_ptr<double>)ev.part;
@@ -434,6 +439,8 @@ gwl_status build_plan(const gwl_event* evs, int E, const int64_t* B_e, gwl_preci
     d.nitems = d.npg * d.nchunk;
     item0 += d.nitems;
     d.f64 = use_mixed(ev, prec) ? 0 : 1;
+    d.rot = d.f64 && ev->ech.uniform != 0 ? 1 : 0;
+    d.step = ev->ech.grid_df;
     d.tab = d.f64 ? ev->tab64 : ev->tab32;
     d.gtab = ev->g64;
     d.ec = ev->ec;
