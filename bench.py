@@ -87,10 +87,16 @@ def NPARAM_ALL(nd: int, nodes: int) -> int:
 
 
 def kernel_hash() -> str:
+    """Hash of the evaluation kernel's sources with comments and blank lines removed, so that a
+    counter summary stays matched to the code it measured across edits of comments only."""
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        code = "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+        h.update(code.encode())
     return h.hexdigest()[:16]
 
 

@@ -19,9 +19,9 @@
 // on the G partial sums.
 //
 // The per-point set-up (phase coefficients, shifts, projection factors) either comes from the
-// set-up kernel's rows or is computed here by the first wavefront of each workgroup and handed
-// to the others through LDS (sh.setup): that saves a launch for small calls, at the price of the
-// set-up's registers in this kernel.
+// set-up kernel's rows or is computed here and handed to every wavefront through LDS
+// (sh.setup): the intrinsic half on the first wavefront, the extrinsic half on the second. That
+// saves a launch for small calls, at the price of the set-up's registers in this kernel.
 //
 // Mixed precision: float64 for the phase polynomial, the f T_det term and the reduction to
 // [0, 1) cycles (v_fract_f64); float32 for the phasor (hardware sin/cos, which take cycles)
