@@ -100,15 +100,16 @@ __device__ inline void setup_lds_extrinsic(const double (&th)[NPARAM], const Eve
 }
 
 // Divide the measured mean gain of the float32 hardware phasor out of the complex sums Z_det
-// (the leading 2 ND entries; the adjoint moments carry the gain in c_det).
+// (the leading 2 ND entries; the adjoint moments carry the gain in c_det). Explicit fused
+// multiply-adds: every kernel that applies it rounds alike.
 template <int ND, int NZ>
 __device__ inline void apply_gain(const EventConst& ec, double (&acc)[NZ]) {
   const double gr = ec.gain_r, gi = ec.gain_i;
 #pragma unroll
   for (int z = 0; z < 2 * ND; z += 2) {
     const double re = acc[z], im = acc[z + 1];
-    acc[z] = re * gr - im * gi;
-    acc[z + 1] = re * gi + im * gr;
+    acc[z] = fma(re, gr, -(im * gi));
+    acc[z + 1] = fma(re, gi, im * gr);
   }
 }
 

@@ -11,7 +11,11 @@ namespace gwl {
 // wavefronts per (point group, chunk group), each wavefront one chunk of `chunk` bins, G
 // workgroups per point group (nchunk = W G chunks in all); the items = npg G workgroups are
 // dealt so that each accelerator die works through a contiguous range of chunk groups. `setup`:
-// the per-point set-up runs inside the kernel instead of the set-up kernel.
+// the per-point set-up runs inside the kernel instead of the set-up kernel. `sepepi` (value
+// only, G > 1, set-up kernel): the G workgroup sums of a point are added and the value formed
+// by a second kernel instead of by the last workgroup to finish, which needs no device-scope
+// fences (each fence writes back and invalidates the die's L2, which slows every workgroup still
+// in its bin loop).
 constexpr int MAX_EVAL_WAVES = 16;
 struct LoopShape {
   int npg;      // point groups = ceil(B / 64)
@@ -22,8 +26,9 @@ struct LoopShape {
   int items;    // workgroups = npg G
   int gper;     // workgroups per die = ceil(items / NXCD)
   int setup;    // 1: set-up inside the evaluation kernel
+  int sepepi;   // 1: the value's reduction over the G workgroups and its epilogue in a second kernel
 };
-LoopShape make_shape(int64_t B, int64_t M, int W, int G, int setup);
+LoopShape make_shape(int64_t B, int64_t M, int W, int G, int setup, int sepepi = 0);
 size_t eval_lds_doubles(bool mixed, const LoopShape& sh);
 
 // event preparation: per-bin tables, K_det and the float32 scale
@@ -50,6 +55,14 @@ hipError_t launch_eval(int nd, bool mixed, bool grad, bool rot, const void* tab,
                        const EventGeom& geo, const EventConst* ec, const double* coef, int64_t B, int64_t Bp,
                        int64_t M, const LoopShape& sh, double* part, unsigned int* cnt, double* logl,
                        const double* fgrid, const double* kcum, const int64_t* live, hipStream_t s);
+
+// the value's epilogue after an evaluation launch with sh.sepepi: part [G][nz][Bp] -> logl[B],
+// the G sums added in workgroup order (as the last-arriving workgroup adds them), then the value
+// from the set-up rows coef; fgrid, kcum (both or neither) for the ISCO cut-off; live as in
+// launch_eval
+hipError_t launch_value_epilogue(int nd, bool mixed, const EventConst* ec, const double* theta, const double* coef,
+                                 int64_t B, int64_t Bp, int G, const double* part, double* logl, const double* fgrid,
+                                 const double* kcum, int64_t M, const int64_t* live, hipStream_t s);
 
 // epilogue: partial sums [nchunk][nz][Bp] -> logL[B] (and grad[B][11]); the value alone reads the
 // set-up rows `coef`, the gradient evaluates the point model from theta

@@ -40,7 +40,7 @@
 
 namespace gwl {
 
-LoopShape make_shape(int64_t B, int64_t M, int W, int G, int setup) {
+LoopShape make_shape(int64_t B, int64_t M, int W, int G, int setup, int sepepi) {
   LoopShape s;
   s.npg = (int)((B + WAVE - 1) / WAVE);
   if (W < 1) W = 1;
@@ -56,6 +56,7 @@ LoopShape make_shape(int64_t B, int64_t M, int W, int G, int setup) {
   s.items = s.npg * G;
   s.gper = (s.items + NXCD - 1) / NXCD;
   s.setup = setup ? 1 : 0;
+  s.sepepi = (sepepi && G > 1 && !setup) ? 1 : 0;
   return s;
 }
 
@@ -72,6 +73,8 @@ size_t eval_lds_doubles(bool mixed, const LoopShape& sh) {
 
 // logL of one point from its reduced sums and set-up values (A, c0, Q_det):
 //   sum_det [ uref Re(A E Q_det Z_det) - 1/2 A^2 |Q_det|^2 K_det ],  E = exp(-2 pi i c0).
+// The fused multiply-adds are spelled out, so that the evaluation kernel and the separate value
+// epilogue round alike.
 template <int ND, int NZ>
 __device__ inline double value_from_rows(const double (&acc)[NZ], double amp, double c0f, const double (&qr)[ND],
                                          const double (&qi)[ND], const EventConst& ec, double uref) {
@@ -82,11 +85,11 @@ __device__ inline double value_from_rows(const double (&acc)[NZ], double amp, do
   double out = 0.0;
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
-    const double xr = amp * (er * qr[d] - ei * qi[d]);
-    const double xi = amp * (er * qi[d] + ei * qr[d]);
-    const double dh = uref * (xr * acc[2 * d] - xi * acc[2 * d + 1]);
-    const double hh = amp * amp * (qr[d] * qr[d] + qi[d] * qi[d]) * ec.K[d];
-    out += dh - 0.5 * hh;
+    const double xr = amp * fma(er, qr[d], -(ei * qi[d]));
+    const double xi = amp * fma(er, qi[d], ei * qr[d]);
+    const double dh = uref * fma(xr, acc[2 * d], -(xi * acc[2 * d + 1]));
+    const double hh = amp * amp * fma(qr[d], qr[d], qi[d] * qi[d]) * ec.K[d];
+    out += fma(-0.5, hh, dh);
   }
   return out;
 }
@@ -254,6 +257,7 @@ __attribute__((amdgpu_waves_per_eu(eval_waves_per_eu<ND, MIXED, GRAD, SETUP, CUT
   }
   if constexpr (!GRAD) {
     if (sh.G > 1) {
+      if (sh.sepepi) return;  // k_value_epilogue adds them
       // the last of the point group's G workgroups adds the G partial sums in workgroup order
       __threadfence();
       const unsigned int prev = atomicAdd(&cnt[pg], lane == 0 ? 1u : 0u);
@@ -339,13 +343,86 @@ static hipError_t eval_nd(bool mixed, bool grad, bool cut, bool rot, const void*
 #undef GWL_EV
 }
 
+// The value's epilogue as a kernel of its own (LoopShape::sepepi): one thread per point adds the
+// G workgroup sums in workgroup order, as the last-arriving workgroup of k_eval does, and forms
+// the value from the set-up rows, so both paths give the same bits.
+constexpr int EPI_BLOCK = 256;
+template <int ND, bool MIXED, bool CUT>
+__global__ __launch_bounds__(EPI_BLOCK) void k_value_epilogue(const EventConst* __restrict__ ec,
+                                                              const double* __restrict__ theta,
+                                                              const double* __restrict__ coef, int64_t B, int64_t Bp,
+                                                              int G, const double* __restrict__ part,
+                                                              double* __restrict__ logl, const double* __restrict__ fgrid,
+                                                              const double* __restrict__ kcum, int64_t M,
+                                                              const int64_t* __restrict__ live) {
+  constexpr int NZ = nz_of(ND, false);
+  const int64_t p = (int64_t)blockIdx.x * EPI_BLOCK + threadIdx.x;
+  if (live) {
+    const int64_t nl = *live;
+    B = nl < B ? nl : B;
+  }
+  if (p >= B) return;
+  double tot[NZ];
+#pragma unroll
+  for (int z = 0; z < NZ; ++z) tot[z] = 0.0;
+  for (int gg = 0; gg < G; ++gg) {
+#pragma unroll
+    for (int z = 0; z < NZ; ++z) tot[z] += part[((int64_t)gg * NZ + z) * Bp + p];
+  }
+  EventConst e = *ec;
+  if constexpr (CUT) {
+    const int kc = isco_bins(theta[p * NPARAM], theta[p * NPARAM + 1], fgrid, M, *ec);
+#pragma unroll
+    for (int d = 0; d < ND; ++d) e.K[d] = kcum[(int64_t)d * (M + 1) + kc];
+  }
+  if (MIXED) apply_gain<ND>(e, tot);
+  double qr[ND], qi[ND];
+  const double amp = coef[CO_AMP * Bp + p], c0f = coef[CO_C0 * Bp + p];
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    qr[d] = coef[(CO_QR + d) * Bp + p];
+    qi[d] = coef[(CO_QI + d) * Bp + p];
+  }
+  logl[p] = value_from_rows<ND, NZ>(tot, amp, c0f, qr, qi, e, MIXED ? e.uref : 1.0);
+}
+
+hipError_t launch_value_epilogue(int nd, bool mixed, const EventConst* ec, const double* theta, const double* coef,
+                                 int64_t B, int64_t Bp, int G, const double* part, double* logl, const double* fgrid,
+                                 const double* kcum, int64_t M, const int64_t* live, hipStream_t s) {
+  if (!coef || !part || G < 1) return hipErrorInvalidValue;
+  const bool cut = fgrid != nullptr;
+  if (cut && !kcum) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((B + EPI_BLOCK - 1) / EPI_BLOCK));
+#define GWL_VEPI(N, MX, CU)                                                                                   \
+  hipLaunchKernelGGL((k_value_epilogue<N, MX, CU>), grid, dim3(EPI_BLOCK), 0, s, ec, theta, coef, B, Bp, G, \
+                     part, logl, fgrid, kcum, M, live)
+#define GWL_VEPI_ND(N)                                               \
+  case N:                                                            \
+    if (mixed) {                                                     \
+      if (cut) GWL_VEPI(N, true, true); else GWL_VEPI(N, true, false);    \
+    } else {                                                         \
+      if (cut) GWL_VEPI(N, false, true); else GWL_VEPI(N, false, false);  \
+    }                                                                \
+    break;
+  switch (nd) {
+    GWL_VEPI_ND(1)
+    GWL_VEPI_ND(2)
+    GWL_VEPI_ND(3)
+    GWL_VEPI_ND(4)
+    default: return hipErrorInvalidValue;
+  }
+#undef GWL_VEPI_ND
+#undef GWL_VEPI
+  return hipGetLastError();
+}
+
 hipError_t launch_eval(int nd, bool mixed, bool grad, bool rot, const void* tab, const RowGradF64* gtab, const double* theta,
                        const EventGeom& geo, const EventConst* ec, const double* coef, int64_t B, int64_t Bp,
                        int64_t M, const LoopShape& sh, double* part, unsigned int* cnt, double* logl,
                        const double* fgrid, const double* kcum, const int64_t* live, hipStream_t s) {
   if (sh.W < 1 || sh.W > MAX_EVAL_WAVES || sh.G < 1) return hipErrorInvalidValue;
   if ((grad || sh.G > 1) && !part) return hipErrorInvalidValue;
-  if (!grad && sh.G > 1 && !cnt) return hipErrorInvalidValue;
+  if (!grad && sh.G > 1 && !sh.sepepi && !cnt) return hipErrorInvalidValue;
   if (!sh.setup && !coef) return hipErrorInvalidValue;
   const bool cut = fgrid != nullptr;
   if (cut && !kcum) return hipErrorInvalidValue;

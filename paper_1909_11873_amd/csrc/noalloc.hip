@@ -85,7 +85,7 @@ gwl_status gwl_logl_batch_noalloc(gwl_event ev, const double* theta, int64_t B, 
   // and the set-up in the kernel (which needs no workspace) as the last resort
   LoopShape sh = choose_shape(ev, B, mixed, false);
   while (sh.G > 1 && (workspace_bytes(Bp, sh, nd, false) > kScratchBytes || workspace_counters(sh, false) > kScratchCounters))
-    sh = make_shape(B, ev->M, sh.W, sh.G / 2, sh.setup);
+    sh = make_shape(B, ev->M, sh.W, sh.G / 2, sh.setup, sh.sepepi);
   if (workspace_bytes(Bp, sh, nd, false) > kScratchBytes) sh = make_shape(B, ev->M, sh.W, 1, 1);
   if (workspace_bytes(Bp, sh, nd, false) > kScratchBytes || workspace_counters(sh, false) > kScratchCounters)
     return fail(GWL_E_INTERNAL, "no launch shape fits the static scratch");

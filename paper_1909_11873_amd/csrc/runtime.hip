@@ -663,12 +663,14 @@ gwl_status gwl_logl_batch_live(gwl_event ev, const double* theta, int64_t B, con
   const bool mixed = use_mixed(ev, prec);
   // the shape for B, with at least enough workgroups per point group that a quarter of the point
   // groups still give every CU two workgroups (chunks of at least 32 bins): a partly live batch
-  // then still fills the chip
+  // then still fills the chip. With the set-up kernel, the G workgroup sums go to the separate
+  // epilogue kernel: at these workgroup counts the last-arriver's device-scope fences cost more
+  // than the second launch (on c1 shapes with 8192 points, 240 against 196 us)
   LoopShape sh = choose_shape(ev, B, mixed, false);
   const int64_t want = (4 * 2 * 256 + sh.npg - 1) / sh.npg;
   const int64_t gcap = std::max<int64_t>(1, ev->M / (32 * (int64_t)sh.W));
   const int G = (int)std::min<int64_t>(std::max<int64_t>(sh.G, want), std::max<int64_t>(gcap, sh.G));
-  if (G != sh.G) sh = make_shape(B, ev->M, sh.W, G, sh.setup);
+  sh = make_shape(B, ev->M, sh.W, G, sh.setup, 1);
   return run_logl(ev, theta, B, mixed, false, sh, logl, nullptr, (hipStream_t)stream, live);
 }
 
@@ -754,7 +756,9 @@ size_t workspace_bytes(int64_t Bp, const LoopShape& sh, int nd, bool grad) {
   return sizeof(double) * (coef + part);
 }
 
-size_t workspace_counters(const LoopShape& sh, bool grad) { return (!grad && sh.G > 1) ? (size_t)sh.npg : 0; }
+size_t workspace_counters(const LoopShape& sh, bool grad) {
+  return (!grad && sh.G > 1 && !sh.sepepi) ? (size_t)sh.npg : 0;
+}
 
 // Set-up, bin loop and epilogue on `s`, in the event's workspace for `s`.
 gwl_status run_logl(gwl_event ev, const double* theta, int64_t B, bool mixed, bool grad, const LoopShape& sh,
@@ -875,6 +879,10 @@ hipError_t enqueue_logl(gwl_event ev, const double* theta, int64_t B, bool mixed
   if (e == hipSuccess)
     e = launch_eval(ev->ndet, mixed, grad, ev->ech.uniform != 0, mixed ? ev->tab32 : ev->tab64, ev->g64, theta,
                     ev->geom, ev->ec, coef, B, Bp, ev->M, sh, part, cnt, logl, ev->fgrid, ev->kcum, live, s);
+  // the value's reduction over the G workgroups in its own kernel (timed with the evaluation)
+  if (e == hipSuccess && !grad && sh.G > 1 && sh.sepepi)
+    e = launch_value_epilogue(ev->ndet, mixed, ev->ec, theta, coef, B, Bp, sh.G, part, logl, ev->fgrid, ev->kcum,
+                              ev->M, live, s);
   if (prof) prof_end(s, pa, pb);
   if (e == hipSuccess && grad)
     e = launch_epilogue(ev->ndet, true, mixed, ev->geom, ev->ec, theta, coef, B, Bp, sh.G, part, logl, gradout, s,

@@ -32,7 +32,7 @@ struct Key {
   }
 };
 struct Entry {
-  int W, G, setup;
+  int W, G, setup, sepepi;
   double ms;
 };
 
@@ -91,7 +91,11 @@ bool load_cache(const char* path) {
     long long M;
     MKey mk;
     MEntry me;
+    e.sepepi = 0;
     if (sscanf(line, " {\"ndet\": %d, \"mixed\": %d, \"grad\": %d, \"M\": %lld, \"npg_bucket\": %d, \"waves\": %d, "
+               "\"groups\": %d, \"setup\": %d, \"sepepi\": %d, \"ms\": %lf}",
+               &k.nd, &k.mixed, &k.grad, &M, &k.npg_bucket, &e.W, &e.G, &e.setup, &e.sepepi, &e.ms) == 10 ||
+        sscanf(line, " {\"ndet\": %d, \"mixed\": %d, \"grad\": %d, \"M\": %lld, \"npg_bucket\": %d, \"waves\": %d, "
                "\"groups\": %d, \"setup\": %d, \"ms\": %lf}",
                &k.nd, &k.mixed, &k.grad, &M, &k.npg_bucket, &e.W, &e.G, &e.setup, &e.ms) == 9) {
       k.M = M;
@@ -116,9 +120,9 @@ bool save_cache(const char* path) {
   for (const auto& kv : g_cache) {
     const Key& k = kv.first;
     fprintf(f, "  {\"ndet\": %d, \"mixed\": %d, \"grad\": %d, \"M\": %lld, \"npg_bucket\": %d, \"waves\": %d, "
-               "\"groups\": %d, \"setup\": %d, \"ms\": %.6f}%s\n",
-            k.nd, k.mixed, k.grad, (long long)k.M, k.npg_bucket, kv.second.W, kv.second.G, kv.second.setup, kv.second.ms,
-            ++i < n ? "," : "");
+               "\"groups\": %d, \"setup\": %d, \"sepepi\": %d, \"ms\": %.6f}%s\n",
+            k.nd, k.mixed, k.grad, (long long)k.M, k.npg_bucket, kv.second.W, kv.second.G, kv.second.setup,
+            kv.second.sepepi, kv.second.ms, ++i < n ? "," : "");
   }
   for (const auto& kv : g_mcache) {
     const MKey& k = kv.first;
@@ -196,7 +200,8 @@ LoopShape choose_shape(const gwl_event_s* ev, int64_t B, bool mixed, bool grad) 
   {
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_cache.find(make_key(ev->ndet, mixed, grad, ev->M, B));
-    if (it != g_cache.end()) return make_shape(B, ev->M, it->second.W, it->second.G, it->second.setup);
+    if (it != g_cache.end())
+      return make_shape(B, ev->M, it->second.W, it->second.G, it->second.setup, it->second.sepepi);
   }
   return heuristic_shape(B, ev->M, mixed, grad);
 }
@@ -228,12 +233,18 @@ gwl_status gwl_autotune(const char* cache_path, gwl_event ev, int64_t B, gwl_pre
   const LoopShape h = heuristic_shape(B, ev->M, mixed, grad);
   const int64_t npg = (B + WAVE - 1) / WAVE;
   std::vector<LoopShape> shapes;
-  auto add = [&](int W, int G, int setup) {
-    const LoopShape sh = make_shape(B, ev->M, W, G, setup);
+  auto add1 = [&](int W, int G, int setup, int sepepi) {
+    const LoopShape sh = make_shape(B, ev->M, W, G, setup, sepepi);
     if ((int64_t)sh.items * sh.W > 65536 && !(sh.W == h.W && sh.G == h.G)) return;
     for (const LoopShape& u : shapes)
-      if (u.W == sh.W && u.G == sh.G && u.setup == sh.setup) return;
+      if (u.W == sh.W && u.G == sh.G && u.setup == sh.setup && u.sepepi == sh.sepepi) return;
     shapes.push_back(sh);
+  };
+  // the value's reduction over G > 1 workgroups either by the last workgroup (fenced) or by the
+  // separate epilogue kernel (with the set-up kernel only)
+  auto add = [&](int W, int G, int setup) {
+    add1(W, G, setup, 0);
+    if (!grad && G > 1 && !setup) add1(W, G, setup, 1);
   };
   add(h.W, h.G, h.setup);
   const int ws_[] = {4, 5, 8, 10, 16};
@@ -295,7 +306,7 @@ gwl_status gwl_autotune(const char* cache_path, gwl_event ev, int64_t B, gwl_pre
   if (e != hipSuccess) return hip_fail(e, "autotune");
   {
     std::lock_guard<std::mutex> lk(g_mu);
-    g_cache[make_key(ev->ndet, mixed, grad, ev->M, B)] = Entry{best.W, best.G, best.setup, best_ms};
+    g_cache[make_key(ev->ndet, mixed, grad, ev->M, B)] = Entry{best.W, best.G, best.setup, best.sepepi, best_ms};
   }
   if (cache_path && !save_cache(cache_path)) return fail(GWL_E_INVALID, "cannot write %s", cache_path);
   return GWL_OK;

@@ -22,14 +22,15 @@ CACHE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
                      "tuning_gfx950.json")
 
 
-def load_layout(path, nd, M, prec, grad, batch, waves, groups, setup):
-    """Make (waves, groups, setup) the layout of calls with this shape (the tuner's cache format)."""
+def load_layout(path, nd, M, prec, grad, batch, waves, groups, setup, sepepi=0):
+    """Make (waves, groups, setup) the layout of calls with this shape (the tuner's cache format);
+    sepepi: the value's reduction over the groups by the separate epilogue kernel."""
     npg = (batch + 63) // 64
     bucket = 1
     while bucket < npg:
         bucket *= 2
     entry = {"ndet": nd, "mixed": int(prec == "mixed"), "grad": int(grad), "M": M, "npg_bucket": bucket,
-             "waves": waves, "groups": groups, "setup": setup, "ms": 1.0}
+             "waves": waves, "groups": groups, "setup": setup, "sepepi": sepepi, "ms": 1.0}
     with open(path, "w") as fh:
         fh.write('{"arch": "gfx950", "entries": [\n  ' + json.dumps(entry) + "\n]}\n")
     gw.autotune_load(path)
@@ -104,4 +105,54 @@ def test_out_of_range_point_is_nan_with_the_split_setup(events, tmp_path):
                 v = v.cpu().numpy()
                 assert np.isnan(v[5]) and np.isfinite(v[[4, 6]]).all()
     finally:
+        gw.autotune_load(CACHE)
+
+
+@pytest.mark.parametrize("cfg", [0, 1])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_separate_value_epilogue_matches_the_last_workgroup(events, cfg, prec, tmp_path):
+    """The value's reduction over G workgroups by the separate epilogue kernel gives the bits of
+    the last-arriving workgroup's reduction (same order, same epilogue arithmetic), also for the
+    first rows of a live-length call."""
+    spec, f, psd, data, dets, ev, th = events[cfg]
+    t = torch.tensor(th, device=DEV)
+    path = str(tmp_path / "layout.json")
+    try:
+        for waves, groups in ((16, 8), (4, 3), (1, 16)):
+            got = []
+            for sepepi in (0, 1):
+                load_layout(path, len(dets), len(f), prec, False, len(th), waves, groups, 0, sepepi)
+                got.append(gw.logl(t, ev, prec).cpu().numpy())
+            assert np.array_equal(got[0], got[1]), (waves, groups)
+        live = torch.tensor([len(th) // 3], dtype=torch.int64, device=DEV)
+        out = torch.full((len(th),), 7.0, dtype=torch.float64, device=DEV)
+        gw.logl_live(t, live, ev, prec, out=out)
+        v = out.cpu().numpy()
+        n = len(th) // 3
+        assert np.all(v[n:] == 7.0) and np.all(np.isfinite(v[:n]))
+        ref = gw.logl(t, ev, prec).cpu().numpy()[:n]
+        assert np.abs(v[:n] - ref).max() <= (1e-4 if prec == "mixed" else 1e-9)
+    finally:
+        gw.autotune_load(CACHE)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_separate_value_epilogue_with_the_isco_cutoff(prec, tmp_path):
+    """With the ISCO cut-off the separate epilogue takes each point's kept share of K_det as the
+    fused one does: bitwise equal values."""
+    spec, f, psd, data, dets = event_inputs(1, f_hi=600.0)
+    ev = gw.Event(torch.tensor(data, device=DEV), torch.tensor(psd, device=DEV), dets,
+                  torch.tensor(f, device=DEV), spec.df, isco_cutoff=True)
+    th = synth.theta_batch(spec, 500)
+    th[:, 0] = np.linspace(20.0, 60.0, len(th))     # cut-offs across the band
+    t = torch.tensor(th, device=DEV)
+    path = str(tmp_path / "layout.json")
+    try:
+        got = []
+        for sepepi in (0, 1):
+            load_layout(path, len(dets), len(f), prec, False, len(th), 8, 4, 0, sepepi)
+            got.append(gw.logl(t, ev, prec).cpu().numpy())
+        assert np.all(np.isfinite(got[0])) and np.array_equal(got[0], got[1])
+    finally:
+        ev.close()
         gw.autotune_load(CACHE)
