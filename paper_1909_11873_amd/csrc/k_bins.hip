@@ -54,7 +54,7 @@ LoopShape make_shape(int64_t B, int64_t M, int W, int G, int setup, int sepepi) 
   s.nchunk = W * G;
   s.chunk = (int)((M + s.nchunk - 1) / s.nchunk);
   s.items = s.npg * G;
-  s.gper = (s.items + NXCD - 1) / NXCD;
+  s.gper = (s.npg + NXCD - 1) / NXCD * G;  // workgroups per die: its point groups, G each
   s.setup = setup ? 1 : 0;
   s.sepepi = (sepepi && G > 1 && !setup) ? 1 : 0;
   return s;
@@ -125,11 +125,15 @@ __attribute__((amdgpu_waves_per_eu(eval_waves_per_eu<ND, MIXED, GRAD, SETUP, CUT
   double* tail = lds + (SETUP ? NCOEF * WAVE : 0);             // table, then the reduction buffer
   double2* tbl = reinterpret_cast<double2*>(tail);
 
+  // the dies take the point groups in turn (pg = xcd mod NXCD), each point group with all G of its
+  // workgroups: a point group's set-up rows are then read by one die only, and a partly live
+  // batch stays spread over the dies
   const int bid = blockIdx.x;
-  const int item = (bid % NXCD) * sh.gper + bid / NXCD;        // dies take contiguous item ranges
-  if (item >= sh.items) return;                                // whole workgroup
-  const int g = item / sh.npg;
-  const int pg = item - g * sh.npg;
+  const int xcd = bid % NXCD, loc = bid / NXCD;
+  const int pgl = loc / sh.G;
+  const int g = loc - pgl * sh.G;
+  const int pg = pgl * NXCD + xcd;
+  if (pg >= sh.npg) return;                                    // whole workgroup
   // live: only the first *live points are evaluated (a batch whose length the device decides)
   if (live) {
     const int64_t nl = *live;
