@@ -817,7 +817,8 @@ def main():
     roof = dict(head["roofline"])
     roof.update({"traffic": traffic if prec == "mixed" and args.config == 1 else None, "kernel": head["kernel"],
                  "kernel_ms": head["kernel_ms_median"], "kernel_ms_mean": head["kernel_ms_mean"],
-                 "timing": "median over 50 launches of HIP events around the kernel on its stream"})
+                 "timing": ("median over 50 launches of HIP events on its stream around the evaluation kernel and, "
+                           "where the launch shape has one, its value-epilogue kernel")})
     line = {
         "metric": metric,
         "value": head["value"], "unit": "evals/s", "n_gpus": 1, "steps": steps_head, "warmup": args.warmup,

@@ -10,7 +10,8 @@ namespace gwl {
 // Shape of one evaluation launch: points in groups of 64 (one wavefront), a workgroup of W
 // wavefronts per (point group, chunk group), each wavefront one chunk of `chunk` bins, G
 // workgroups per point group (nchunk = W G chunks in all); the items = npg G workgroups are
-// dealt so that the dies take the point groups in turn, each with all G of its workgroups. `setup`:
+// dealt either so that the dies take the point groups in turn, each with all G of its
+// workgroups (pgmaj), or so that each die takes a contiguous range of chunk groups. `setup`:
 // the per-point set-up runs inside the kernel instead of the set-up kernel. `sepepi` (value
 // only, G > 1, set-up kernel): the G workgroup sums of a point are added and the value formed
 // by a second kernel instead of by the last workgroup to finish, which needs no device-scope
@@ -24,9 +25,10 @@ struct LoopShape {
   int nchunk;   // W G
   int chunk;    // bins per chunk
   int items;    // workgroups = npg G
-  int gper;     // workgroups per die = ceil(npg / NXCD) G
+  int gper;     // workgroups per die: ceil(npg / NXCD) G (pgmaj), else ceil(items / NXCD)
   int setup;    // 1: set-up inside the evaluation kernel
   int sepepi;   // 1: the value's reduction over the G workgroups and its epilogue in a second kernel
+  int pgmaj;    // 1: the dies take the point groups in turn (the set-up rows outweigh the table)
 };
 LoopShape make_shape(int64_t B, int64_t M, int W, int G, int setup, int sepepi = 0);
 size_t eval_lds_doubles(bool mixed, const LoopShape& sh);

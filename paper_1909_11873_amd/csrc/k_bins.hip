@@ -54,7 +54,13 @@ LoopShape make_shape(int64_t B, int64_t M, int W, int G, int setup, int sepepi) 
   s.nchunk = W * G;
   s.chunk = (int)((M + s.nchunk - 1) / s.nchunk);
   s.items = s.npg * G;
-  s.gper = (s.npg + NXCD - 1) / NXCD * G;  // workgroups per die: its point groups, G each
+  // how the dies share the work: by point groups (each die reads its points' set-up rows, 30
+  // doubles a point, and the whole per-bin table) when the rows outweigh the table (about 8
+  // doubles a bin), else by ranges of chunk groups (each die reads its part of the table and
+  // every point's rows): c1 (65,536 points, 16,225 bins) goes by point groups, the 128 s event
+  // (4,096 points, 259,585 bins) by chunk groups
+  s.pgmaj = (int64_t)s.npg * WAVE * NCOEF >= M * 8 ? 1 : 0;
+  s.gper = s.pgmaj ? (s.npg + NXCD - 1) / NXCD * G : (s.items + NXCD - 1) / NXCD;
   s.setup = setup ? 1 : 0;
   s.sepepi = (sepepi && G > 1 && !setup) ? 1 : 0;
   return s;
@@ -125,15 +131,24 @@ __attribute__((amdgpu_waves_per_eu(eval_waves_per_eu<ND, MIXED, GRAD, SETUP, CUT
   double* tail = lds + (SETUP ? NCOEF * WAVE : 0);             // table, then the reduction buffer
   double2* tbl = reinterpret_cast<double2*>(tail);
 
-  // the dies take the point groups in turn (pg = xcd mod NXCD), each point group with all G of its
-  // workgroups: a point group's set-up rows are then read by one die only, and a partly live
-  // batch stays spread over the dies
+  // sh.pgmaj: the dies take the point groups in turn (pg = xcd mod NXCD), each point group with all
+  // G of its workgroups (a point group's set-up rows are read by one die only, and a partly live
+  // batch stays spread over the dies); else each die takes a contiguous range of items, chunk
+  // group major (a die reads its part of the per-bin table only)
   const int bid = blockIdx.x;
   const int xcd = bid % NXCD, loc = bid / NXCD;
-  const int pgl = loc / sh.G;
-  const int g = loc - pgl * sh.G;
-  const int pg = pgl * NXCD + xcd;
-  if (pg >= sh.npg) return;                                    // whole workgroup
+  int g, pg;
+  if (sh.pgmaj) {
+    const int pgl = loc / sh.G;
+    g = loc - pgl * sh.G;
+    pg = pgl * NXCD + xcd;
+    if (pg >= sh.npg) return;                                  // whole workgroup
+  } else {
+    const int item = xcd * sh.gper + loc;
+    if (item >= sh.items) return;                              // whole workgroup
+    g = item / sh.npg;
+    pg = item - g * sh.npg;
+  }
   // live: only the first *live points are evaluated (a batch whose length the device decides)
   if (live) {
     const int64_t nl = *live;
