@@ -307,7 +307,11 @@ gwl_status gwl_multi_autotune(const char* cache_path, const gwl_event* evs, int 
 /*
  * Time candidate tile shapes for (event, B, precision, with_grad) on the device and record the
  * fastest in the JSON cache file `cache_path` (created or updated; null = in-memory only).
- * Later calls with a matching shape use the cached choice. Synchronises the device.
+ * Candidates vary the wavefronts per workgroup, the workgroups per group of 64 points, whether
+ * the per-point set-up runs in the evaluation kernel and, for the value with several workgroups
+ * per point group, whether the last workgroup to finish or a second kernel adds their sums (the
+ * same bits either way). Later calls with a matching shape use the cached choice. Synchronises
+ * the device.
  */
 gwl_status gwl_autotune(const char* cache_path, gwl_event ev, int64_t B, gwl_precision prec, int with_grad);
 
@@ -320,7 +324,8 @@ gwl_status gwl_launch_shape(gwl_event ev, int64_t B, gwl_precision prec, int wit
 /* The evaluation kernel's layout for such a call: wavefronts per workgroup (each takes one chunk
  * of bins for the workgroup's 64 points; the chunks are added in LDS), workgroups per group of 64
  * points (nchunk = waves x groups), and whether the per-point set-up runs inside that kernel (1)
- * or in a set-up kernel before it (0). Any output pointer may be null. */
+ * or in a set-up kernel before it (0). (Which kernel adds the workgroups' sums is not reported:
+ * it does not change the result.) Any output pointer may be null. */
 gwl_status gwl_launch_layout(gwl_event ev, int64_t B, gwl_precision prec, int with_grad, int* waves, int* groups,
                              int* setup);
 
