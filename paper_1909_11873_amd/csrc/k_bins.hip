@@ -58,8 +58,9 @@ LoopShape make_shape(int64_t B, int64_t M, int W, int G, int setup, int sepepi) 
   // doubles a point, and the whole per-bin table) when the rows outweigh the table (about 8
   // doubles a bin), else by ranges of chunk groups (each die reads its part of the table and
   // every point's rows): c1 (65,536 points, 16,225 bins) goes by point groups, the 128 s event
-  // (4,096 points, 259,585 bins) by chunk groups
-  s.pgmaj = (int64_t)s.npg * WAVE * NCOEF >= M * 8 ? 1 : 0;
+  // (4,096 points, 259,585 bins) by chunk groups; so do batches of fewer than 8 point groups,
+  // whose workgroups would otherwise not reach every die
+  s.pgmaj = (s.npg >= NXCD && (int64_t)s.npg * WAVE * NCOEF >= M * 8) ? 1 : 0;
   s.gper = s.pgmaj ? (s.npg + NXCD - 1) / NXCD * G : (s.items + NXCD - 1) / NXCD;
   s.setup = setup ? 1 : 0;
   s.sepepi = (sepepi && G > 1 && !setup) ? 1 : 0;
@@ -131,18 +132,25 @@ __attribute__((amdgpu_waves_per_eu(eval_waves_per_eu<ND, MIXED, GRAD, SETUP, CUT
   double* tail = lds + (SETUP ? NCOEF * WAVE : 0);             // table, then the reduction buffer
   double2* tbl = reinterpret_cast<double2*>(tail);
 
-  // sh.pgmaj: the dies take the point groups in turn (pg = xcd mod NXCD), each point group with all
-  // G of its workgroups (a point group's set-up rows are read by one die only, and a partly live
-  // batch stays spread over the dies); else each die takes a contiguous range of items, chunk
-  // group major (a die reads its part of the per-bin table only)
+  // sh.pgmaj: each die takes whole point groups, all G workgroups of each (a point group's set-up
+  // rows are read by one die only): a contiguous range of point-group-major items (balanced to
+  // one item), or, for a live-length call, the point groups in turn (pg = xcd mod NXCD), so that a
+  // partly live batch stays spread over the dies. Else each die takes a contiguous range of items,
+  // chunk group major (a die reads its part of the per-bin table only).
   const int bid = blockIdx.x;
   const int xcd = bid % NXCD, loc = bid / NXCD;
   int g, pg;
-  if (sh.pgmaj) {
+  if (sh.pgmaj && live) {
     const int pgl = loc / sh.G;
     g = loc - pgl * sh.G;
     pg = pgl * NXCD + xcd;
     if (pg >= sh.npg) return;                                  // whole workgroup
+  } else if (sh.pgmaj) {
+    const int per = (sh.items + NXCD - 1) / NXCD;
+    const int item = xcd * per + loc;
+    if (loc >= per || item >= sh.items) return;                // whole workgroup
+    pg = item / sh.G;
+    g = item - pg * sh.G;
   } else {
     const int item = xcd * sh.gper + loc;
     if (item >= sh.items) return;                              // whole workgroup
