@@ -186,44 +186,51 @@ __device__ inline double epilogue_value_rows(const double (&acc)[NZ], const doub
 // with c_det = E G Q_det).
 // Every d(.) comes from one-direction dual numbers pushed through the same point model, one
 // parameter at a time (11 passes; this keeps the register footprint of the epilogue small).
+// One pass: the derivative with respect to parameter j; `value` and `valid` are the same in every
+// pass (the primal part does not depend on the direction).
+template <int ND>
+__device__ inline double epilogue_gradient_pass(const double (&acc)[nz_of(ND, true)], const double (&th)[NPARAM],
+                                                const EventGeom& g, const EventConst& ec, double uref, int j,
+                                                bool& valid, double& value) {
+  typedef Dual<1> D;
+  D t[NPARAM];
+#pragma unroll
+  for (int i = 0; i < NPARAM; ++i) {
+    t[i].v = th[i];
+    t[i].d[0] = (i == j) ? 1.0 : 0.0;
+  }
+  PointModel<D> pm;
+  point_model<D, ND>(t, g, pm);
+  D c0 = pm.c0;
+  c0.v -= rint(c0.v);
+  const D arg = c0 * kTwoPi;
+  const D er = xcos(arg), ei = -xsin(arg);
+  D tot = dcst<1>(0.0);
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    const D xr = pm.amp * (er * pm.qr[d] - ei * pm.qi[d]);
+    const D xi = pm.amp * (er * pm.qi[d] + ei * pm.qr[d]);
+    const D dh = (xr * acc[2 * d] - xi * acc[2 * d + 1]) * uref;
+    const D hh = pm.amp * pm.amp * (pm.qr[d] * pm.qr[d] + pm.qi[d] * pm.qi[d]) * ec.K[d];
+    tot = tot + dh - 0.5 * hh;
+  }
+  double sm = 0.0;
+#pragma unroll
+  for (int m = 0; m < NBASIS; ++m) sm += pm.a[m].d[0] * acc[3 * ND + m];
+#pragma unroll
+  for (int d = 0; d < ND; ++d) sm += pm.tdet[d].d[0] * acc[2 * ND + d];
+  value = tot.v;
+  valid = pm.valid;
+  return tot.d[0] + kTwoPi * uref * pm.amp.v * sm;
+}
+
 template <int ND>
 __device__ inline double epilogue_gradient(const double (&acc)[nz_of(ND, true)], const double (&th)[NPARAM],
                                            const EventGeom& g, const EventConst& ec, double uref, bool& valid,
                                            double (&gout)[NPARAM]) {
-  typedef Dual<1> D;
   double value = 0.0;
 #pragma unroll 1
-  for (int j = 0; j < NPARAM; ++j) {
-    D t[NPARAM];
-#pragma unroll
-    for (int i = 0; i < NPARAM; ++i) {
-      t[i].v = th[i];
-      t[i].d[0] = (i == j) ? 1.0 : 0.0;
-    }
-    PointModel<D> pm;
-    point_model<D, ND>(t, g, pm);
-    D c0 = pm.c0;
-    c0.v -= rint(c0.v);
-    const D arg = c0 * kTwoPi;
-    const D er = xcos(arg), ei = -xsin(arg);
-    D tot = dcst<1>(0.0);
-#pragma unroll
-    for (int d = 0; d < ND; ++d) {
-      const D xr = pm.amp * (er * pm.qr[d] - ei * pm.qi[d]);
-      const D xi = pm.amp * (er * pm.qi[d] + ei * pm.qr[d]);
-      const D dh = (xr * acc[2 * d] - xi * acc[2 * d + 1]) * uref;
-      const D hh = pm.amp * pm.amp * (pm.qr[d] * pm.qr[d] + pm.qi[d] * pm.qi[d]) * ec.K[d];
-      tot = tot + dh - 0.5 * hh;
-    }
-    double sm = 0.0;
-#pragma unroll
-    for (int m = 0; m < NBASIS; ++m) sm += pm.a[m].d[0] * acc[3 * ND + m];
-#pragma unroll
-    for (int d = 0; d < ND; ++d) sm += pm.tdet[d].d[0] * acc[2 * ND + d];
-    gout[j] = tot.d[0] + kTwoPi * uref * pm.amp.v * sm;
-    value = tot.v;
-    valid = pm.valid;
-  }
+  for (int j = 0; j < NPARAM; ++j) gout[j] = epilogue_gradient_pass<ND>(acc, th, g, ec, uref, j, valid, value);
   return value;
 }
 
