@@ -281,7 +281,9 @@ gwl_status gwl_multi_plan_create_order(const gwl_event* evs, int E, const int64_
  * grad may be null when the plan has no gradient. The pointer tables are host arrays of E
  * entries. If event_latency_us is non-null it receives, per event, the time from the start of
  * the launch to the completion of that event's results (device clock), and the call then
- * synchronises `stream`.
+ * synchronises `stream`. Calibrated events run on side streams of the plan's own, forked from
+ * `stream` after the persistent launch and joined back into it before the call returns: work
+ * queued on `stream` afterwards sees every result.
  */
 gwl_status gwl_multi_launch(gwl_plan pl, const double* const* theta, double* const* logl, double* const* grad,
                             double* event_latency_us, void* stream);

@@ -93,9 +93,10 @@ hipError_t fill_theta(double* theta, int64_t B, hipStream_t s, int P = NPARAM);
 // live (device, may be null): evaluate only the first *live of the B points
 gwl_status run_logl(gwl_event ev, const double* theta, int64_t B, bool mixed, bool grad, const LoopShape& sh,
                     double* logl, double* gradout, hipStream_t s, const int64_t* live = nullptr);
-// a call on a calibrated event (its own set-up, bin loop and epilogue kernels)
+// a call on a calibrated event (its own set-up, bin loop and epilogue kernels) in the workspace
+// ws of ws_bytes bytes (at least call_workspace_bytes), which the caller owns
 gwl_status run_calibrated(gwl_event ev, const double* theta, int64_t B, bool mixed, bool grad, double* logl,
-                          double* gradout, hipStream_t s);
+                          double* gradout, hipStream_t s, void* ws, size_t ws_bytes);
 
 // The event's workspace on stream s, grown to at least `bytes` if needed (zero-filled when it
 // grows). Growing is refused while s is capturing a graph (GWL_E_INVALID): the caller reserves it

@@ -226,6 +226,14 @@ struct gwl_plan_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipEvent_t io_done = nullptr;
+  // calibrated events run on side streams (default priority) after the graph, the calibrated
+  // events in turn, each stream in a workspace of the plan's own sized for its largest event
+  static constexpr int kCalStreams = 4;
+  hipStream_t cal_s[kCalStreams] = {};
+  void* cal_ws[kCalStreams] = {};
+  size_t cal_ws_bytes[kCalStreams] = {};
+  hipEvent_t cal_fork = nullptr;
+  hipEvent_t cal_join[kCalStreams] = {};
 };
 
 namespace {
@@ -237,12 +245,21 @@ size_t ctl_bytes(int E) {
   return sizeof(gwl::MultiCtl) + sizeof(unsigned int) * (size_t)((E + 1) & ~1) + sizeof(unsigned long long) * E;
 }
 
+// precision of calibrated event e's own kernels in plan pl (as its single call would take)
+bool mixed_cal(const gwl_plan_s* pl, int e) { return pl->mixed && use_mixed(pl->evs[e], GWL_MIXED); }
+
 void plan_free(gwl_plan pl) {
   if (!pl) return;
   if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
   if (pl->graph) (void)hipGraphDestroy(pl->graph);
   if (pl->cap) (void)hipStreamDestroy(pl->cap);
   if (pl->io_done) (void)hipEventDestroy(pl->io_done);
+  for (int i = 0; i < gwl_plan_s::kCalStreams; ++i) {
+    if (pl->cal_s[i]) (void)hipStreamDestroy(pl->cal_s[i]);
+    if (pl->cal_join[i]) (void)hipEventDestroy(pl->cal_join[i]);
+    if (pl->cal_ws[i]) (void)hipFree(pl->cal_ws[i]);
+  }
+  if (pl->cal_fork) (void)hipEventDestroy(pl->cal_fork);
   if (pl->d_evs) (void)hipFree(pl->d_evs);
   if (pl->d_geoms) (void)hipFree(pl->d_geoms);
   if (pl->d_io) (void)hipFree(pl->d_io);
@@ -481,6 +498,22 @@ gwl_status build_plan(const gwl_event* evs, int E, const int64_t* B_e, gwl_preci
   }
   if (err == hipSuccess) err = hipEventCreateWithFlags(&pl->io_done, hipEventDisableTiming);
   if (err == hipSuccess) err = hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking);
+  if (!pl->cal.empty()) {
+    if (err == hipSuccess) err = hipEventCreateWithFlags(&pl->cal_fork, hipEventDisableTiming);
+    for (int i = 0; i < gwl_plan_s::kCalStreams && err == hipSuccess; ++i) {
+      err = hipStreamCreateWithFlags(&pl->cal_s[i], hipStreamNonBlocking);
+      if (err == hipSuccess) err = hipEventCreateWithFlags(&pl->cal_join[i], hipEventDisableTiming);
+    }
+    int next = 0;
+    for (int e : pl->cal) {
+      if (pl->B[e] == 0) continue;
+      const int i = next++ % gwl_plan_s::kCalStreams;
+      pl->cal_ws_bytes[i] = std::max(pl->cal_ws_bytes[i],
+                                     call_workspace_bytes(pl->evs[e], pl->B[e], mixed_cal(pl, e), pl->grad));
+    }
+    for (int i = 0; i < gwl_plan_s::kCalStreams && err == hipSuccess; ++i)
+      if (pl->cal_ws_bytes[i] > 0) err = hipMalloc(&pl->cal_ws[i], pl->cal_ws_bytes[i]);
+  }
   // capture the whole evaluation once
   if (err == hipSuccess) err = hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal);
   if (err == hipSuccess) {
@@ -567,20 +600,40 @@ gwl_status gwl_multi_launch(gwl_plan pl, const double* const* theta, double* con
   if (err == hipSuccess) err = hipEventRecord(pl->io_done, s);
   if (err == hipSuccess) err = hipGraphLaunch(pl->exec, s);
   if (err != hipSuccess) return hip_fail(err, "multi-event launch");
-  // calibrated events: their own set-up, bin-loop and epilogue kernels on the same stream, each
-  // followed by a clock stamp in the event's slot
+  // calibrated events: their own set-up, bin-loop and epilogue kernels, each followed by a clock
+  // stamp in the event's slot, dealt in turn to the plan's side streams after the graph (one small
+  // event at a time leaves most of the chip idle); the caller's stream then waits for them all
   unsigned long long* tev_dev = (unsigned long long*)((unsigned char*)pl->d_ctl + sizeof(MultiCtl) +
                                                       sizeof(unsigned int) * (size_t)((pl->E + 1) & ~1));
-  for (int e : pl->cal) {
-    if (pl->B[e] == 0) continue;
-    st = run_calibrated(pl->evs[e], theta[e], pl->B[e], pl->mixed && use_mixed(pl->evs[e], GWL_MIXED), pl->grad,
-                        logl[e], pl->grad ? grad[e] : nullptr, s);
-    if (st != GWL_OK) return st;
-    int q = 0;
-    while (pl->order[q] != e) ++q;
-    hipLaunchKernelGGL(k_multi_stamp, dim3(1), dim3(1), 0, s, tev_dev + q);
-    err = hipGetLastError();
+  if (!pl->cal.empty()) {
+    constexpr int NS = gwl_plan_s::kCalStreams;
+    err = hipEventRecord(pl->cal_fork, s);
+    for (int i = 0; i < NS && err == hipSuccess; ++i) err = hipStreamWaitEvent(pl->cal_s[i], pl->cal_fork, 0);
     if (err != hipSuccess) return hip_fail(err, "multi-event launch");
+    int next = 0;
+    for (int e : pl->cal) {
+      if (pl->B[e] == 0) continue;
+      const int i = next++ % NS;
+      hipStream_t cs = pl->cal_s[i];
+      st = run_calibrated(pl->evs[e], theta[e], pl->B[e], mixed_cal(pl, e), pl->grad, logl[e],
+                          pl->grad ? grad[e] : nullptr, cs, pl->cal_ws[i], pl->cal_ws_bytes[i]);
+      if (st != GWL_OK) break;
+      int q = 0;
+      while (pl->order[q] != e) ++q;
+      hipLaunchKernelGGL(k_multi_stamp, dim3(1), dim3(1), 0, cs, tev_dev + q);
+      err = hipGetLastError();
+      if (err != hipSuccess) break;
+    }
+    // join, also after a failure, so that nothing queued on a side stream outlives the call's order
+    hipError_t jerr = hipSuccess;
+    for (int i = 0; i < NS; ++i) {
+      hipError_t e1 = hipEventRecord(pl->cal_join[i], pl->cal_s[i]);
+      if (e1 == hipSuccess) e1 = hipStreamWaitEvent(s, pl->cal_join[i], 0);
+      if (e1 != hipSuccess && jerr == hipSuccess) jerr = e1;
+    }
+    if (st != GWL_OK) return st;
+    if (err != hipSuccess) return hip_fail(err, "multi-event launch");
+    if (jerr != hipSuccess) return hip_fail(jerr, "multi-event launch");
   }
   if (event_latency_us) {
     const unsigned char* ctl = (const unsigned char*)pl->d_ctl;

@@ -575,8 +575,10 @@ gwl_status gwl_event_info(gwl_event ev, int* ndet, int64_t* M, double* df) {
 }
 
 // Calibrated evaluation: chunks are pieces of node intervals; workspace from the stream pool.
+// ws_given: a workspace of ws_bytes bytes owned by the caller (a multi-event plan), used instead of
+// the event's own workspace on s
 static gwl_status run_logl_cal(gwl_event ev, const double* theta, int64_t B, bool mixed, bool grad, double* logl,
-                               double* gradout, hipStream_t s) {
+                               double* gradout, hipStream_t s, void* ws_given = nullptr, size_t ws_bytes = 0) {
   const int nd = ev->ndet, n = ev->ncal;
   CalShape sh;
   memset(&sh, 0, sizeof sh);
@@ -612,9 +614,13 @@ static gwl_status run_logl_cal(gwl_event ev, const double* theta, int64_t B, boo
   const int64_t Bp = (int64_t)sh.npg * WAVE;
   const int nchunk = sh.nchunk, ncal = 2 * n * nd;
   const size_t bytes = sizeof(double) * ((size_t)NCOEF * Bp + (size_t)ncal * Bp + (size_t)nchunk * nz_cal(nd, grad) * Bp);
-  void* ws = nullptr;
-  gwl_status st = event_workspace(ev, s, bytes, 0, &ws);
-  if (st != GWL_OK) return st;
+  void* ws = ws_given;
+  if (ws_given) {
+    if (ws_bytes < bytes) return fail(GWL_E_INTERNAL, "calibrated loop: workspace of %zu bytes, %zu needed", ws_bytes, bytes);
+  } else {
+    gwl_status st = event_workspace(ev, s, bytes, 0, &ws);
+    if (st != GWL_OK) return st;
+  }
   double* coef = (double*)ws;
   double* calc = coef + (size_t)NCOEF * Bp;
   double* part = calc + (size_t)ncal * Bp;
@@ -746,8 +752,8 @@ gwl_status gwl_waveform(const double* theta, int64_t B, const gwl_detector* dets
 namespace gwl {
 
 gwl_status run_calibrated(gwl_event ev, const double* theta, int64_t B, bool mixed, bool grad, double* logl,
-                          double* gradout, hipStream_t s) {
-  return run_logl_cal(ev, theta, B, mixed, grad, logl, gradout, s);
+                          double* gradout, hipStream_t s, void* ws, size_t ws_bytes) {
+  return run_logl_cal(ev, theta, B, mixed, grad, logl, gradout, s, ws, ws_bytes);
 }
 
 size_t workspace_bytes(int64_t Bp, const LoopShape& sh, int nd, bool grad) {
