@@ -256,89 +256,155 @@ __global__ __launch_bounds__(BLOCK) void k_bins_cal(const void* __restrict__ tab
   for (int zz = 0; zz < NZ; ++zz) part[((int64_t)c * NZ + zz) * Bp + p] = tot[zz];
 }
 
-// Epilogue: gather the chunks (window moments to their nodes), then value and gradient.
+// Epilogue, one workgroup per 64 points. The value alone takes one wavefront. The adjoint takes
+// four, which first share the gather: the value sums one component at a time and the window
+// moments of one detector and kind (amplitude or phase) at a time, each summed in chunk order.
+// Chunks come in interval order and an interval's window of four nodes starts at
+// clamp(j - 1, 0, n - 4), which never moves back and moves by at most one node, so a node's
+// moment is final once the window has moved past it: the task keeps the window in four
+// registers and turns each finished node into its gradient at once. The 11 signal-parameter
+// derivatives (one dual-number pass each, the first also giving the value) are then dealt to
+// the wavefronts in turn.
+constexpr int EPC_WAVES = 4;
+
+// With alpha the point's amplitude node values for a detector: r_i = K1_i + (K2 alpha)_i. The
+// effective K_det = K_det + 2 alpha.K1 + alpha.K2.alpha = K_det + sum_i alpha_i (2 K1_i + (r_i - K1_i)),
+// and the amplitude node gradient takes 2 r_i.
+__device__ __forceinline__ double cal_r(const double* __restrict__ K1, const double* __restrict__ K2,
+                                        const double* __restrict__ al, int n, int i) {
+  double r = K1[i];
+  for (int l = 0; l < n; ++l) r += K2[i * n + l] * al[l];
+  return r;
+}
+
 template <int ND, bool GRAD>
-__global__ __launch_bounds__(CAL_PT_BLOCK) void k_epilogue_cal(EventGeom g, const EventConst* __restrict__ ec,
-                                                               const double* __restrict__ kcal, const double* __restrict__ theta,
-                                                               int P, int64_t B, int64_t Bp, CalShape sh, bool scaled,
-                                                               const double* __restrict__ part, double* __restrict__ logl,
-                                                               double* __restrict__ grad) {
-  const int64_t p = (int64_t)blockIdx.x * CAL_PT_BLOCK + threadIdx.x;
-  if (p >= B) return;
+__global__ __launch_bounds__((GRAD ? EPC_WAVES : 1) * WAVE) void k_epilogue_cal(
+    EventGeom g, const EventConst* __restrict__ ec, const double* __restrict__ kcal, const double* __restrict__ theta,
+    int P, int64_t B, int64_t Bp, CalShape sh, bool scaled, const double* __restrict__ part, double* __restrict__ logl,
+    double* __restrict__ grad) {
   constexpr int NZ = nz_cal(ND, GRAD), NZU = nz_of(ND, GRAD);
   constexpr int MA = 3 * ND + NBASIS, MB = MA + 4 * ND;
+  constexpr int NW = GRAD ? EPC_WAVES : 1;
+  __shared__ double acc_s[NZU][WAVE];
+  __shared__ double ks_s[ND][WAVE];   // K_det's calibration term per point
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+  const int lane = (int)(threadIdx.x % WAVE);
+  const int64_t p = (int64_t)blockIdx.x * WAVE + lane;   // p < Bp: the partial sums have Bp rows
   const int n = sh.nnode, nchunk = sh.nchunk;
-  const EventConst e = *ec;
-  double acc[NZU];
-#pragma unroll
-  for (int zz = 0; zz < NZU; ++zz) acc[zz] = 0.0;
-  double mA[ND][MAXNODE], mB[ND][MAXNODE];
-#pragma unroll
-  for (int d = 0; d < ND; ++d)
-    for (int i = 0; i < MAXNODE; ++i) mA[d][i] = mB[d][i] = 0.0;
-  // chunk-order sums; the value sums' loop is unrolled to keep several chunks' loads in flight
-#pragma unroll 8
-  for (int c = 0; c < nchunk; ++c) {
-#pragma unroll
-    for (int zz = 0; zz < NZU; ++zz) acc[zz] += part[((int64_t)c * NZ + zz) * Bp + p];
-  }
   if constexpr (GRAD) {
+    for (int z = w; z < NZU; z += NW) {
+      double a = 0.0;
+#pragma unroll 8
+      for (int c = 0; c < nchunk; ++c) a += part[((int64_t)c * NZ + z) * Bp + p];
+      acc_s[z][lane] = a;
+    }
+  } else {
+    // one wavefront: every component in one chunk loop, so that their loads for several chunks
+    // are in flight together
+    double a[NZU];
+#pragma unroll
+    for (int z = 0; z < NZU; ++z) a[z] = 0.0;
+#pragma unroll 8
     for (int c = 0; c < nchunk; ++c) {
-      const int j0 = sh.j0[sh.cj[c]];
 #pragma unroll
-      for (int d = 0; d < ND; ++d)
+      for (int z = 0; z < NZU; ++z) a[z] += part[((int64_t)c * NZ + z) * Bp + p];
+    }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          mA[d][j0 + i] += part[((int64_t)c * NZ + MA + 4 * d + i) * Bp + p];
-          mB[d][j0 + i] += part[((int64_t)c * NZ + MB + 4 * d + i) * Bp + p];
+    for (int z = 0; z < NZU; ++z) acc_s[z][lane] = a[z];
+  }
+  const bool live = p < B;
+  const double nan = __builtin_nan("");
+  const EventConst e = *ec;
+  const double uref = scaled ? e.uref : 1.0;
+  if constexpr (GRAD) {
+    // node gradients: amplitude uref A m_i - 1/2 A^2 |Q_det|^2 2 r_i, phase -uref A m_i
+    int t = w - NZU % NW;
+    if (t < 0) t += NW;
+    if (t < 2 * ND) {
+      const int64_t pc = live ? p : B - 1;
+      double th[NPARAM];
+#pragma unroll
+      for (int i = 0; i < NPARAM; ++i) th[i] = theta[pc * P + i];
+      PointModel<double> pm;
+      point_model<double, ND>(th, g, pm);
+      for (; t < 2 * ND; t += NW) {
+        const int d = t >> 1, kind = t & 1;
+        const double* al = theta + pc * P + NPARAM + 2 * n * d;
+        const double* K1 = kcal + (int64_t)d * (n + n * n);
+        const double* K2 = K1 + n;
+        double hh = 0.0;   // A^2 |Q_det|^2 (selected with constant indices: pm stays in registers)
+#pragma unroll
+        for (int dd = 0; dd < ND; ++dd)
+          if (dd == d) hh = pm.amp * pm.amp * (pm.qr[dd] * pm.qr[dd] + pm.qi[dd] * pm.qi[dd]);
+        double* out = grad + pc * P + NPARAM + 2 * n * d + (kind ? n : 0);
+        const int base = (kind ? MB : MA) + 4 * d;
+        double ks = 0.0;   // the amplitude task also sums K_det's calibration term
+        auto finish = [&](int i, double m) {
+          double x;
+          if (kind) {
+            x = -uref * pm.amp * m;
+          } else {
+            const double r = cal_r(K1, K2, al, n, i);
+            ks += al[i] * (2.0 * K1[i] + (r - K1[i]));
+            x = uref * pm.amp * m - 0.5 * hh * (2.0 * r);
+          }
+          if (live) out[i] = pm.valid ? x : nan;
+        };
+        double win[4] = {0.0, 0.0, 0.0, 0.0};
+        int wb = 0;   // the window holds nodes wb .. wb + 3
+        for (int c = 0; c < nchunk; ++c) {
+          const int j0 = sh.j0[sh.cj[c]];
+          for (; wb < j0; ++wb) {
+            finish(wb, win[0]);
+            win[0] = win[1];
+            win[1] = win[2];
+            win[2] = win[3];
+            win[3] = 0.0;
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) win[i] += part[((int64_t)c * NZ + base + i) * Bp + p];
         }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (wb + i < n) finish(wb + i, win[i]);
+        for (int i = wb + 4; i < n; ++i) finish(i, 0.0);
+        if (!kind) ks_s[d][lane] = ks;
+      }
+    }
+  } else {
+    const int64_t pc = live ? p : B - 1;
+    for (int d = 0; d < ND; ++d) {
+      const double* al = theta + pc * P + NPARAM + 2 * n * d;
+      const double* K1 = kcal + (int64_t)d * (n + n * n);
+      const double* K2 = K1 + n;
+      double ks = 0.0;
+      for (int i = 0; i < n; ++i) ks += al[i] * (2.0 * K1[i] + (cal_r(K1, K2, al, n, i) - K1[i]));
+      ks_s[d][lane] = ks;
     }
   }
+  __syncthreads();
+  if (!live) return;
+  double acc[NZU];
+#pragma unroll
+  for (int z = 0; z < NZU; ++z) acc[z] = acc_s[z][lane];
   if (scaled) apply_gain<ND>(e, acc);
-  const double uref = scaled ? e.uref : 1.0;
   double th[NPARAM];
 #pragma unroll
   for (int i = 0; i < NPARAM; ++i) th[i] = theta[p * P + i];
-  // per detector: effective K = K + 2 alpha.K1 + alpha.K2.alpha, and its gradient 2 (K1 + K2 alpha)
   EventConst ek = e;
-  double dk[ND][MAXNODE];
 #pragma unroll
-  for (int d = 0; d < ND; ++d) {
-    const double* al = theta + p * P + NPARAM + 2 * n * d;
-    const double* K1 = kcal + (int64_t)d * (n + n * n);
-    const double* K2 = K1 + n;
-    double s = 0.0;
-    for (int i = 0; i < n; ++i) {
-      double r = K1[i];
-      for (int l = 0; l < n; ++l) r += K2[i * n + l] * al[l];
-      dk[d][i] = 2.0 * r;
-      s += al[i] * (2.0 * K1[i] + (r - K1[i]));
-    }
-    ek.K[d] = e.K[d] + s;
-  }
+  for (int d = 0; d < ND; ++d) ek.K[d] = e.K[d] + ks_s[d][lane];
   bool valid;
-  const double nan = __builtin_nan("");
   if constexpr (!GRAD) {
     const double v = epilogue_value<ND, NZU>(acc, th, g, ek, uref, valid);
     logl[p] = valid ? v : nan;
   } else {
-    double gout[NPARAM];
-    const double v = epilogue_gradient<ND>(acc, th, g, ek, uref, valid, gout);
-    logl[p] = valid ? v : nan;
-#pragma unroll
-    for (int i = 0; i < NPARAM; ++i) grad[p * P + i] = valid ? gout[i] : nan;
-    // calibration node gradients
-    PointModel<double> pm;
-    point_model<double, ND>(th, g, pm);
-#pragma unroll
-    for (int d = 0; d < ND; ++d) {
-      const double hh = pm.amp * pm.amp * (pm.qr[d] * pm.qr[d] + pm.qi[d] * pm.qi[d]);
-      for (int i = 0; i < n; ++i) {
-        const double ga = uref * pm.amp * mA[d][i] - 0.5 * hh * dk[d][i];
-        const double gp = -uref * pm.amp * mB[d][i];
-        grad[p * P + NPARAM + 2 * n * d + i] = valid ? ga : nan;
-        grad[p * P + NPARAM + 2 * n * d + n + i] = valid ? gp : nan;
-      }
+#pragma unroll 1
+    for (int j = w; j < NPARAM; j += NW) {
+      double value;
+      const double gj = epilogue_gradient_pass<ND>(acc, th, g, ek, uref, j, valid, value);
+      grad[p * P + j] = valid ? gj : nan;
+      if (j == 0) logl[p] = valid ? value : nan;
     }
   }
 }
@@ -361,13 +427,13 @@ static hipError_t cal_nd(bool mixed, bool grad, const EventGeom& g, const EventC
     if (grad) GWL_CB(false, true); else GWL_CB(false, false);
   }
 #undef GWL_CB
-  const dim3 egrid((unsigned)((B + CAL_PT_BLOCK - 1) / CAL_PT_BLOCK));
+  const dim3 egrid((unsigned)((B + WAVE - 1) / WAVE));
   if (grad)
-    hipLaunchKernelGGL((k_epilogue_cal<ND, true>), egrid, dim3(CAL_PT_BLOCK), 0, s, g, ec, kcal, theta, P, B, Bp, sh,
-                       mixed, (const double*)part, logl, gradout);
+    hipLaunchKernelGGL((k_epilogue_cal<ND, true>), egrid, dim3(EPC_WAVES * WAVE), 0, s, g, ec, kcal, theta, P, B, Bp,
+                       sh, mixed, (const double*)part, logl, gradout);
   else
-    hipLaunchKernelGGL((k_epilogue_cal<ND, false>), egrid, dim3(CAL_PT_BLOCK), 0, s, g, ec, kcal, theta, P, B, Bp, sh,
-                       mixed, (const double*)part, logl, gradout);
+    hipLaunchKernelGGL((k_epilogue_cal<ND, false>), egrid, dim3(WAVE), 0, s, g, ec, kcal, theta, P, B, Bp, sh, mixed,
+                       (const double*)part, logl, gradout);
   return hipGetLastError();
 }
 
