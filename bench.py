@@ -56,7 +56,7 @@ def work_per_point_bin(ndet: int, mixed: bool, grad: bool = False):
     sum over detectors (ADD, one fewer than detectors): 14 flops per detector - 1; then the 8
     basis moments (8 FMA).
 
-    The survey's planning count, 2M(11 + N_det) float64 flops per evaluation (28 per point-bin at
+    A coarser planning count, 2M(11 + N_det) float64 flops per evaluation (28 per point-bin at
     three detectors), prices the phase at 11 FMA and each detector's shift at one FMA; the kernels'
     Horner form in x = f^(1/3) with the log terms folded in needs 7 FMA + 2 MUL, and the count here
     adds one operation per detector for the reduction to one cycle: 25 at three detectors. The
