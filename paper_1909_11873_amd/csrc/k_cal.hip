@@ -136,8 +136,15 @@ __device__ __forceinline__ bool locate_cal(const CalShape& sh, int& c, int& j, i
   return true;
 }
 
+// Wavefronts per SIMD the register budget must allow: three for the mixed adjoint up to three
+// detectors (its window moments' float64 totals live in LDS for that), otherwise no bound.
 template <int ND, bool MIXED, bool GRAD>
-__global__ __launch_bounds__(BLOCK) void k_bins_cal(const void* __restrict__ tabv, const void* __restrict__ gtabv,
+constexpr int cal_waves_per_eu() {
+  return (MIXED && GRAD && ND <= 3) ? 3 : 1;
+}
+
+template <int ND, bool MIXED, bool GRAD>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(cal_waves_per_eu<ND, MIXED, GRAD>()))) void k_bins_cal(const void* __restrict__ tabv, const void* __restrict__ gtabv,
                                                     const void* __restrict__ calwv, const void* __restrict__ caltv,
                                                     const double* __restrict__ calB, const double* __restrict__ coef,
                                                     const double* __restrict__ calc, int64_t B, int64_t Bp,
@@ -145,6 +152,10 @@ __global__ __launch_bounds__(BLOCK) void k_bins_cal(const void* __restrict__ tab
   typedef typename std::conditional<MIXED, float, double>::type T_;
   constexpr int NZ = nz_cal(ND, GRAD);
   __shared__ double2 tbl[MIXED ? 1 : PH_TBL];  // the float64 phasor table
+  // mixed adjoint: the float64 totals of the 8 ND window moments stay in LDS (one column per
+  // lane, so no barrier), which keeps the kernel at three wavefronts per SIMD instead of two
+  constexpr int NNODE = 8 * ND, NZU = NZ - NNODE;
+  __shared__ double ntot[MIXED && GRAD ? NNODE : 1][MIXED && GRAD ? BLOCK : 1];
   if constexpr (!MIXED) {
     fill_phasor_table(tbl);
     __syncthreads();
@@ -188,6 +199,22 @@ __global__ __launch_bounds__(BLOCK) void k_bins_cal(const void* __restrict__ tab
   double tot[NZ];
 #pragma unroll
   for (int zz = 0; zz < NZ; ++zz) tot[zz] = 0.0;
+  if constexpr (MIXED && GRAD) {
+#pragma unroll
+    for (int i = 0; i < NNODE; ++i) ntot[i][threadIdx.x] = 0.0;
+  }
+  // a float32 block's sums into the float64 totals
+  auto flush = [&](const float (&z)[NZ]) {
+    if constexpr (MIXED && GRAD) {
+#pragma unroll
+      for (int zz = 0; zz < NZU; ++zz) tot[zz] += (double)z[zz];
+#pragma unroll
+      for (int i = 0; i < NNODE; ++i) ntot[i][threadIdx.x] += (double)z[NZU + i];
+    } else {
+#pragma unroll
+      for (int zz = 0; zz < NZ; ++zz) tot[zz] += (double)z[zz];
+    }
+  };
   if constexpr (MIXED) {
     const RowMixed<ND>* tab = (const RowMixed<ND>*)tabv;
     const RowGradF32* gt = (const RowGradF32*)gtabv;
@@ -217,8 +244,7 @@ __global__ __launch_bounds__(BLOCK) void k_bins_cal(const void* __restrict__ tab
           if constexpr (GRAD) cwc = cwn;
           tc = tn;
         }
-#pragma unroll
-        for (int zz = 0; zz < NZ; ++zz) tot[zz] += (double)z[zz];
+        flush(z);
       }
       if (k < kend) {
         float z[NZ];
@@ -226,9 +252,12 @@ __global__ __launch_bounds__(BLOCK) void k_bins_cal(const void* __restrict__ tab
         for (int zz = 0; zz < NZ; ++zz) z[zz] = 0.0f;
         for (; k < kend; ++k)
           cal_bin<ND, GRAD, float>(load_row_mixed<ND>(tab, k), cw[k], ct[k], gt, k, a, T, cr, ci, kA, kP, tbl, z);
-#pragma unroll
-        for (int zz = 0; zz < NZ; ++zz) tot[zz] += (double)z[zz];
+        flush(z);
       }
+    }
+    if constexpr (GRAD) {
+#pragma unroll
+      for (int i = 0; i < NNODE; ++i) tot[NZU + i] = ntot[i][threadIdx.x];
     }
   } else {
     const RowF64<ND>* tab = (const RowF64<ND>*)tabv;
