@@ -257,8 +257,9 @@ gwl_status gwl_waveform(const double* theta, int64_t B, const gwl_detector* dets
  * evaluation (queue reset, per-point set-up, persistent kernel, per-event finalisation) in a
  * HIP graph bound to the events. The events must outlive the plan. Calibrated events (of
  * gwl_event_create_cal or gwl_event_create_rb_cal) are not in the persistent queue: each launch
- * runs their own set-up, bin-loop and epilogue kernels on the same stream after the graph, with
- * theta and grad of 11 + 2 nnode ndet columns; the ISCO cut-off is not supported in plans.
+ * runs their own set-up, bin-loop and epilogue kernels after the graph (on side streams of the
+ * plan's own, joined back into the launch's stream; workspaces allocated here), with theta and
+ * grad of 11 + 2 nnode ndet columns; the ISCO cut-off is not supported in plans.
  *   evs       host [E] event handles;  B_e host int64 [E] (each >= 0)
  *   with_grad 0: logL only; 1: logL and gradient
  */
