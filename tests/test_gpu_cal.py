@@ -193,3 +193,26 @@ def test_many_calibrated_events_share_the_plans_side_streams():
         plan.close()
         for ev in evs:
             ev.close()
+
+
+@pytest.mark.parametrize("ndet", [1, 2, 4])
+def test_calibrated_gradient_other_detector_counts(ndet):
+    """The calibrated adjoint at 1, 2 and 4 detectors (the mixed kernel keeps its window moments'
+    float64 totals in LDS, 8 ndet per lane) against the oracle's gradient over all
+    11 + 2 n ndet parameters, on a batch spanning several point groups."""
+    n = 6
+    spec, f, psd, data, dets, ev = make(1, n, f_hi=300.0, ndet=ndet)
+    rng = np.random.default_rng(60 + ndet)
+    th = cal_theta(synth.theta_batch(spec, 150), ndet, n, rng, 0.05)
+    th[0, :11] = spec.theta0
+    idx = np.array([0, 1, 77, 149])
+    _, gref = cal.logl_grad(th[idx], data, psd, dets, f, spec.df, n)
+    widths = np.concatenate([WIDTHS, np.full(2 * n * ndet, 0.1)])
+    for prec, tol in (("fp64", 1e-8), ("mixed", 1e-4)):
+        _, g = gw.logl_grad(torch.tensor(th, device=DEV), ev, prec)
+        gs, rs = g.cpu().numpy()[idx] * widths, gref.numpy() * widths
+        scale = np.maximum(np.abs(rs), 1e-3 * np.abs(rs).max(axis=1, keepdims=True))
+        err = np.abs(gs - rs) / scale
+        print(f"calibrated gradient, {ndet} detectors, {prec}: max scaled error {err.max():.3e}")
+        assert err.max() <= tol
+    ev.close()
