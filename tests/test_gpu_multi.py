@@ -269,3 +269,35 @@ def test_multi_with_relative_binning_events(events, prec):
     for i, ev in enumerate(mixed_events):
         if i % 2 == 0:
             ev.close()
+
+
+@pytest.mark.parametrize("grad", [False, True])
+def test_many_small_events_in_one_plan(events, grad):
+    """300 events of 0 to 3 points each, drawn from the five events above (the same event may
+    appear many times in one plan): every value and gradient against that event's single call,
+    with the latency of every non-empty event positive."""
+    rng = np.random.default_rng(17)
+    pick = rng.integers(0, len(events), 300)
+    batches = [int(b) for b in rng.integers(0, 4, 300)]
+    evs = [events[i]["ev"] for i in pick]
+    thetas = []
+    for b in batches:
+        th = synth.prior_draw(np.random.default_rng(int(rng.integers(1 << 30))), b)
+        thetas.append(torch.tensor(th, device=DEV).reshape(-1, 11))
+    plan = gw.MultiPlan(evs, batches, "mixed", with_grad=grad)
+    try:
+        logls, grads, lat = plan.launch(thetas, latency=True)
+        for k, (ev, t, l) in enumerate(zip(evs, thetas, logls)):
+            if t.shape[0] == 0:
+                assert l.shape == (0,) and lat[k] == 0.0
+                continue
+            assert lat[k] > 0
+            if grad:
+                sv, sg = gw.logl_grad(t, ev, "mixed")
+                g = grads[k]
+                assert np.abs(g.cpu().numpy() - sg.cpu().numpy()).max() <= 2e-4 * max(1.0, float(sg.abs().max()))
+            else:
+                sv = gw.logl(t, ev, "mixed")
+            assert np.abs(l.cpu().numpy() - sv.cpu().numpy()).max() <= 2e-4
+    finally:
+        plan.close()
