@@ -12,31 +12,74 @@
 
 namespace gwl {
 
-constexpr int PT_BLOCK = 128;
+// Set-up: one workgroup of two wavefronts per 64 points. The intrinsic half of the point model
+// (phase coefficients, constant phase, amplitude) runs on one wavefront and the extrinsic half
+// (sky, orientation, per-detector delays and projection factors) on the other, at once, into
+// LDS rows; each wavefront then writes half of the rows, with the phase-range check and the
+// adjoint factors taken from the LDS rows as setup_rows takes them (the same rows, bit for bit,
+// as one thread running setup_rows; NaN rows for a point outside the model's domain or range).
+constexpr int SETUP_WAVES = 2;
 
 template <int ND>
-__global__ __launch_bounds__(PT_BLOCK) void k_setup(EventGeom g, const EventConst* __restrict__ ec, bool scaled,
-                                                    const double* __restrict__ theta, int64_t B, int64_t Bp,
-                                                    double* __restrict__ coef) {
-  const int64_t p = (int64_t)blockIdx.x * PT_BLOCK + threadIdx.x;
-  if (p >= Bp) return;
-  double th[NPARAM];
-  const int64_t pc = p < B ? p : B - 1;  // padding lanes repeat the last point
+__global__ __launch_bounds__(SETUP_WAVES * WAVE) void k_setup(EventGeom g, const EventConst* __restrict__ ec,
+                                                              bool scaled, const double* __restrict__ theta,
+                                                              int64_t B, int64_t Bp, double* __restrict__ coef) {
+  __shared__ double rows_s[NCOEF * WAVE];
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+  const int lane = (int)(threadIdx.x % WAVE);
+  const int64_t p = (int64_t)blockIdx.x * WAVE + lane;   // < Bp: Bp is a multiple of 64
+  const int64_t pc = p < B ? p : B - 1;                  // padding lanes repeat the last point
+  {
+    double th[NPARAM];
 #pragma unroll
-  for (int i = 0; i < NPARAM; ++i) th[i] = theta[pc * NPARAM + i];
-  double rows[NCOEF];
-  const bool valid = setup_rows<ND>(th, g, ec, scaled, rows);
+    for (int i = 0; i < NPARAM; ++i) th[i] = theta[pc * NPARAM + i];
+    if (w == 0) setup_lds_intrinsic(th, ec, rows_s, lane);
+    else setup_lds_extrinsic<ND>(th, g, ec, rows_s, lane);
+  }
+  __syncthreads();
+  double a[NBASIS], T[ND];
+#pragma unroll
+  for (int m = 0; m < NBASIS; ++m) a[m] = rows_s[(CO_A + m) * WAVE + lane];
+#pragma unroll
+  for (int d = 0; d < ND; ++d) T[d] = rows_s[(CO_T + d) * WAVE + lane];
+  // the intrinsic half leaves NaN rows for a point outside the model's domain
+  const bool valid = !isnan(a[0]) && rows_in_range<ND>(a, T, ec);
   const double nan = __builtin_nan("");
+  auto put = [&](int j, double v) { coef[j * Bp + p] = valid ? v : nan; };
+  if (w == 0) {
 #pragma unroll
-  for (int j = 0; j < NCOEF; ++j) coef[j * Bp + p] = valid ? rows[j] : nan;
+    for (int m = 0; m < NBASIS; ++m) put(CO_A + m, a[m]);
+#pragma unroll
+    for (int d = 0; d < MAXDET; ++d) put(CO_T + d, d < ND ? T[d] : 0.0);
+    put(CO_C0, rows_s[CO_C0 * WAVE + lane]);
+    put(CO_AMP, rows_s[CO_AMP * WAVE + lane]);
+  } else {
+    const double gr = (scaled && ec) ? ec->gain_r : 1.0, gi = (scaled && ec) ? ec->gain_i : 0.0;
+    double egr, egi;
+    phase_gain(rows_s[CO_C0 * WAVE + lane], gr, gi, egr, egi);
+#pragma unroll
+    for (int d = 0; d < MAXDET; ++d) {
+      double qr = 0.0, qi = 0.0, cr = 0.0, ci = 0.0;
+      if (d < ND) {
+        qr = rows_s[(CO_QR + d) * WAVE + lane];
+        qi = rows_s[(CO_QI + d) * WAVE + lane];
+        adjoint_factor(egr, egi, qr, qi, cr, ci);
+      }
+      put(CO_QR + d, qr);
+      put(CO_QI + d, qi);
+      put(CO_CR + d, cr);
+      put(CO_CI + d, ci);
+    }
+  }
 }
 
 hipError_t launch_setup(int nd, const EventGeom& g, const EventConst* ec, bool scaled, const double* theta, int64_t B,
                         int64_t Bp, double* coef, hipStream_t s) {
   if (scaled && !ec) return hipErrorInvalidValue;
-  dim3 grid((unsigned)((Bp + PT_BLOCK - 1) / PT_BLOCK));
+  if (Bp % WAVE != 0 || B < 1 || B > Bp) return hipErrorInvalidValue;
+  dim3 grid((unsigned)(Bp / WAVE));
 #define GWL_SETUP(N) \
-  case N: hipLaunchKernelGGL(k_setup<N>, grid, dim3(PT_BLOCK), 0, s, g, ec, scaled, theta, B, Bp, coef); break;
+  case N: hipLaunchKernelGGL(k_setup<N>, grid, dim3(SETUP_WAVES * WAVE), 0, s, g, ec, scaled, theta, B, Bp, coef); break;
   switch (nd) {
     GWL_SETUP(1)
     GWL_SETUP(2)
