@@ -22,32 +22,36 @@
 #include "gwl_device.h"
 #include "gwl_epilogue.h"
 #include "gwl_launch.h"
+#include "gwl_setup.h"
 
 namespace gwl {
 
-constexpr int CAL_PT_BLOCK = 128;
-
+// Set-up of a calibrated call: the point model's rows as k_setup writes them (two wavefronts per
+// 64 points, one per half of the model), and the calibration node values turned from theta's
+// columns 11.. into rows calc [ncal][Bp], each wavefront copying half of them; every row of a
+// point with a non-finite node value is NaN.
 template <int ND>
-__global__ __launch_bounds__(CAL_PT_BLOCK) void k_setup_cal(EventGeom g, const EventConst* __restrict__ ec, bool scaled,
-                                                            const double* __restrict__ theta, int P, int ncal,
-                                                            int64_t B, int64_t Bp, double* __restrict__ coef,
-                                                            double* __restrict__ calc) {
-  const int64_t p = (int64_t)blockIdx.x * CAL_PT_BLOCK + threadIdx.x;
-  if (p >= Bp) return;
-  const int64_t pc = p < B ? p : B - 1;
-  double th[NPARAM];
-#pragma unroll
-  for (int i = 0; i < NPARAM; ++i) th[i] = theta[pc * P + i];
-  double rows[NCOEF];
-  bool valid = setup_rows<ND>(th, g, ec, scaled, rows);
-  for (int j = 0; j < ncal; ++j) {
+__global__ __launch_bounds__(2 * WAVE) void k_setup_cal(EventGeom g, const EventConst* __restrict__ ec, bool scaled,
+                                                        const double* __restrict__ theta, int P, int ncal, int64_t B,
+                                                        int64_t Bp, double* __restrict__ coef,
+                                                        double* __restrict__ calc) {
+  __shared__ double rows_s[NCOEF * WAVE];
+  __shared__ int ok_s[2][WAVE];
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+  const int lane = (int)(threadIdx.x % WAVE);
+  const int64_t p = (int64_t)blockIdx.x * WAVE + lane;   // < Bp: Bp is a multiple of 64
+  const int64_t pc = p < B ? p : B - 1;                  // padding lanes repeat the last point
+  setup_halves<ND>(w, lane, theta + pc * P, g, ec, rows_s);
+  const int half = (ncal + 1) / 2, j0 = w * half, j1 = w == 0 ? half : ncal;
+  bool ok = true;
+  for (int j = j0; j < j1; ++j) {
     const double v = theta[pc * P + NPARAM + j];
-    valid &= isfinite(v);
+    ok &= isfinite(v);
     calc[(int64_t)j * Bp + p] = v;
   }
-  const double nan = __builtin_nan("");
-#pragma unroll
-  for (int j = 0; j < NCOEF; ++j) coef[j * Bp + p] = valid ? rows[j] : nan;
+  ok_s[w][lane] = ok ? 1 : 0;
+  __syncthreads();
+  setup_rows_write<ND>(w, lane, rows_s, ec, scaled, ok_s[0][lane] && ok_s[1][lane], coef, Bp, p);
 }
 
 // One bin of the calibrated loop. T_ is float (mixed: hardware phasors, float32 products) or
@@ -444,8 +448,9 @@ static hipError_t cal_nd(bool mixed, bool grad, const EventGeom& g, const EventC
                          const double* theta, int P, int64_t B, int64_t Bp, const CalShape& sh, double* coef,
                          double* calc, double* part, double* logl, double* gradout, hipStream_t s) {
   const int ncal = 2 * sh.nnode * ND;
-  hipLaunchKernelGGL(k_setup_cal<ND>, dim3((unsigned)((Bp + CAL_PT_BLOCK - 1) / CAL_PT_BLOCK)), dim3(CAL_PT_BLOCK), 0,
-                     s, g, ec, mixed, theta, P, ncal, B, Bp, coef, calc);
+  if (Bp % WAVE != 0 || B < 1 || B > Bp) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_setup_cal<ND>, dim3((unsigned)(Bp / WAVE)), dim3(2 * WAVE), 0, s, g, ec, mixed, theta, P, ncal,
+                     B, Bp, coef, calc);
   const dim3 grid((unsigned)(sh.gper * NXCD)), block(BLOCK);
 #define GWL_CB(MX, GR) \
   hipLaunchKernelGGL((k_bins_cal<ND, MX, GR>), grid, block, 0, s, tab, gtab, calw, calt, calB, (const double*)coef, \

@@ -9,6 +9,7 @@
 #include "gwl_device.h"
 #include "gwl_epilogue.h"
 #include "gwl_launch.h"
+#include "gwl_setup.h"
 
 namespace gwl {
 
@@ -29,48 +30,9 @@ __global__ __launch_bounds__(SETUP_WAVES * WAVE) void k_setup(EventGeom g, const
   const int lane = (int)(threadIdx.x % WAVE);
   const int64_t p = (int64_t)blockIdx.x * WAVE + lane;   // < Bp: Bp is a multiple of 64
   const int64_t pc = p < B ? p : B - 1;                  // padding lanes repeat the last point
-  {
-    double th[NPARAM];
-#pragma unroll
-    for (int i = 0; i < NPARAM; ++i) th[i] = theta[pc * NPARAM + i];
-    if (w == 0) setup_lds_intrinsic(th, ec, rows_s, lane);
-    else setup_lds_extrinsic<ND>(th, g, ec, rows_s, lane);
-  }
+  setup_halves<ND>(w, lane, theta + pc * NPARAM, g, ec, rows_s);
   __syncthreads();
-  double a[NBASIS], T[ND];
-#pragma unroll
-  for (int m = 0; m < NBASIS; ++m) a[m] = rows_s[(CO_A + m) * WAVE + lane];
-#pragma unroll
-  for (int d = 0; d < ND; ++d) T[d] = rows_s[(CO_T + d) * WAVE + lane];
-  // the intrinsic half leaves NaN rows for a point outside the model's domain
-  const bool valid = !isnan(a[0]) && rows_in_range<ND>(a, T, ec);
-  const double nan = __builtin_nan("");
-  auto put = [&](int j, double v) { coef[j * Bp + p] = valid ? v : nan; };
-  if (w == 0) {
-#pragma unroll
-    for (int m = 0; m < NBASIS; ++m) put(CO_A + m, a[m]);
-#pragma unroll
-    for (int d = 0; d < MAXDET; ++d) put(CO_T + d, d < ND ? T[d] : 0.0);
-    put(CO_C0, rows_s[CO_C0 * WAVE + lane]);
-    put(CO_AMP, rows_s[CO_AMP * WAVE + lane]);
-  } else {
-    const double gr = (scaled && ec) ? ec->gain_r : 1.0, gi = (scaled && ec) ? ec->gain_i : 0.0;
-    double egr, egi;
-    phase_gain(rows_s[CO_C0 * WAVE + lane], gr, gi, egr, egi);
-#pragma unroll
-    for (int d = 0; d < MAXDET; ++d) {
-      double qr = 0.0, qi = 0.0, cr = 0.0, ci = 0.0;
-      if (d < ND) {
-        qr = rows_s[(CO_QR + d) * WAVE + lane];
-        qi = rows_s[(CO_QI + d) * WAVE + lane];
-        adjoint_factor(egr, egi, qr, qi, cr, ci);
-      }
-      put(CO_QR + d, qr);
-      put(CO_QI + d, qi);
-      put(CO_CR + d, cr);
-      put(CO_CI + d, ci);
-    }
-  }
+  setup_rows_write<ND>(w, lane, rows_s, ec, scaled, true, coef, Bp, p);
 }
 
 hipError_t launch_setup(int nd, const EventGeom& g, const EventConst* ec, bool scaled, const double* theta, int64_t B,
