@@ -293,6 +293,7 @@ __attribute__((amdgpu_waves_per_eu(eval_waves_per_eu<ND, MIXED, GRAD, SETUP, CUT
       __threadfence();
 #pragma unroll
       for (int z = 0; z < NZ; ++z) tot[z] = 0.0;
+#pragma unroll 8
       for (int gg = 0; gg < sh.G; ++gg) {
 #pragma unroll
         for (int z = 0; z < NZ; ++z) tot[z] += part[((int64_t)gg * NZ + z) * Bp + p];
@@ -392,6 +393,8 @@ __global__ __launch_bounds__(EPI_BLOCK) void k_value_epilogue(const EventConst* 
   double tot[NZ];
 #pragma unroll
   for (int z = 0; z < NZ; ++z) tot[z] = 0.0;
+  // workgroup order; unrolled so that several workgroups' loads are in flight before their adds
+#pragma unroll 8
   for (int gg = 0; gg < G; ++gg) {
 #pragma unroll
     for (int z = 0; z < NZ; ++z) tot[z] += part[((int64_t)gg * NZ + z) * Bp + p];
