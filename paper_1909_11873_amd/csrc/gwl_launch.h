@@ -13,10 +13,11 @@ namespace gwl {
 // dealt either so that the dies take the point groups in turn, each with all G of its
 // workgroups (pgmaj), or so that each die takes a contiguous range of chunk groups. `setup`:
 // the per-point set-up runs inside the kernel instead of the set-up kernel. `sepepi` (value
-// only, G > 1, set-up kernel): the G workgroup sums of a point are added and the value formed
-// by a second kernel instead of by the last workgroup to finish, which needs no device-scope
-// fences (each fence writes back and invalidates the die's L2, which slows every workgroup still
-// in its bin loop).
+// only, G > 1): the G workgroup sums of a point are added and the value formed by a second
+// kernel instead of by the last workgroup to finish, which needs no device-scope fences (each
+// fence writes back and invalidates the die's L2, which slows every workgroup still in its bin
+// loop); with the set-up in the kernel, its first workgroup per point group leaves the rows
+// that second kernel reads.
 constexpr int MAX_EVAL_WAVES = 16;
 struct LoopShape {
   int npg;      // point groups = ceil(B / 64)
@@ -54,7 +55,7 @@ hipError_t launch_setup(int nd, const EventGeom& g, const EventConst* ec, bool s
 // the first by rotation (ignored with the cut-off and in mixed precision); live (device, may be
 // null): only the first *live points are evaluated and written
 hipError_t launch_eval(int nd, bool mixed, bool grad, bool rot, const void* tab, const RowGradF64* gtab, const double* theta,
-                       const EventGeom& geo, const EventConst* ec, const double* coef, int64_t B, int64_t Bp,
+                       const EventGeom& geo, const EventConst* ec, double* coef, int64_t B, int64_t Bp,
                        int64_t M, const LoopShape& sh, double* part, unsigned int* cnt, double* logl,
                        const double* fgrid, const double* kcum, const int64_t* live, hipStream_t s);
 

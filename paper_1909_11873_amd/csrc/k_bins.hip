@@ -63,7 +63,7 @@ LoopShape make_shape(int64_t B, int64_t M, int W, int G, int setup, int sepepi) 
   s.pgmaj = (s.npg >= NXCD && (int64_t)s.npg * WAVE * NCOEF >= M * 8) ? 1 : 0;
   s.gper = s.pgmaj ? (s.npg + NXCD - 1) / NXCD * G : (s.items + NXCD - 1) / NXCD;
   s.setup = setup ? 1 : 0;
-  s.sepepi = (sepepi && G > 1 && !setup) ? 1 : 0;
+  s.sepepi = (sepepi && G > 1) ? 1 : 0;
   return s;
 }
 
@@ -123,7 +123,7 @@ template <int ND, bool MIXED, bool GRAD, bool SETUP, bool CUT, bool ROT>
 __global__ __launch_bounds__(WAVE * MAX_EVAL_WAVES)
 __attribute__((amdgpu_waves_per_eu(eval_waves_per_eu<ND, MIXED, GRAD, SETUP, CUT, ROT>()))) void k_eval(
     const TabRow<ND, MIXED>* __restrict__ tab, const RowGradF64* __restrict__ gtab, const double* __restrict__ theta,
-    EventGeom geo, const EventConst* __restrict__ ec, const double* __restrict__ coef, int64_t B, int64_t Bp, int64_t M,
+    EventGeom geo, const EventConst* __restrict__ ec, double* __restrict__ coef, int64_t B, int64_t Bp, int64_t M,
     LoopShape sh, double* __restrict__ part, unsigned int* __restrict__ cnt, double* __restrict__ logl,
     const double* __restrict__ fgrid, const double* __restrict__ kcum, const int64_t* __restrict__ live) {
   constexpr int NZ = nz_of(ND, GRAD);
@@ -284,7 +284,23 @@ __attribute__((amdgpu_waves_per_eu(eval_waves_per_eu<ND, MIXED, GRAD, SETUP, CUT
   }
   if constexpr (!GRAD) {
     if (sh.G > 1) {
-      if (sh.sepepi) return;  // k_value_epilogue adds them
+      if (sh.sepepi) {        // k_value_epilogue adds them
+        if constexpr (SETUP) {
+          // with the set-up in this kernel, the first workgroup of the point group leaves the
+          // rows the epilogue needs (A, c0, Q_det; as the set-up kernel writes them, A NaN for
+          // a point outside the phase range)
+          if (g == 0) {
+            coef[CO_AMP * Bp + p] = in_range ? rows_s[CO_AMP * WAVE + lane] : __builtin_nan("");
+            coef[CO_C0 * Bp + p] = rows_s[CO_C0 * WAVE + lane];
+#pragma unroll
+            for (int d = 0; d < ND; ++d) {
+              coef[(CO_QR + d) * Bp + p] = rows_s[(CO_QR + d) * WAVE + lane];
+              coef[(CO_QI + d) * Bp + p] = rows_s[(CO_QI + d) * WAVE + lane];
+            }
+          }
+        }
+        return;
+      }
       // the last of the point group's G workgroups adds the G partial sums in workgroup order
       __threadfence();
       const unsigned int prev = atomicAdd(&cnt[pg], lane == 0 ? 1u : 0u);
@@ -330,7 +346,7 @@ __attribute__((amdgpu_waves_per_eu(eval_waves_per_eu<ND, MIXED, GRAD, SETUP, CUT
 
 template <int ND, bool MIXED, bool GRAD>
 static hipError_t eval_setup(bool setup, bool cut, bool rot, const void* tab, const RowGradF64* gtab, const double* theta,
-                             const EventGeom& geo, const EventConst* ec, const double* coef, int64_t B, int64_t Bp,
+                             const EventGeom& geo, const EventConst* ec, double* coef, int64_t B, int64_t Bp,
                              int64_t M, const LoopShape& sh, double* part, unsigned int* cnt, double* logl,
                              const double* fgrid, const double* kcum, const int64_t* live, hipStream_t s) {
   const dim3 grid((unsigned)(sh.gper * NXCD)), block((unsigned)(sh.W * WAVE));
@@ -354,7 +370,7 @@ static hipError_t eval_setup(bool setup, bool cut, bool rot, const void* tab, co
 
 template <int ND>
 static hipError_t eval_nd(bool mixed, bool grad, bool cut, bool rot, const void* tab, const RowGradF64* gtab,
-                          const double* theta, const EventGeom& geo, const EventConst* ec, const double* coef,
+                          const double* theta, const EventGeom& geo, const EventConst* ec, double* coef,
                           int64_t B, int64_t Bp, int64_t M, const LoopShape& sh, double* part, unsigned int* cnt,
                           double* logl, const double* fgrid, const double* kcum, const int64_t* live,
                           hipStream_t s) {
@@ -447,7 +463,7 @@ hipError_t launch_value_epilogue(int nd, bool mixed, const EventConst* ec, const
 }
 
 hipError_t launch_eval(int nd, bool mixed, bool grad, bool rot, const void* tab, const RowGradF64* gtab, const double* theta,
-                       const EventGeom& geo, const EventConst* ec, const double* coef, int64_t B, int64_t Bp,
+                       const EventGeom& geo, const EventConst* ec, double* coef, int64_t B, int64_t Bp,
                        int64_t M, const LoopShape& sh, double* part, unsigned int* cnt, double* logl,
                        const double* fgrid, const double* kcum, const int64_t* live, hipStream_t s) {
   if (sh.W < 1 || sh.W > MAX_EVAL_WAVES || sh.G < 1) return hipErrorInvalidValue;

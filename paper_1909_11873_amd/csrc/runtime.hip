@@ -669,9 +669,9 @@ gwl_status gwl_logl_batch_live(gwl_event ev, const double* theta, int64_t B, con
   const bool mixed = use_mixed(ev, prec);
   // the shape for B, with at least enough workgroups per point group that a quarter of the point
   // groups still give every CU two workgroups (chunks of at least 32 bins): a partly live batch
-  // then still fills the chip. With the set-up kernel, the G workgroup sums go to the separate
-  // epilogue kernel: at these workgroup counts the last-arriver's device-scope fences cost more
-  // than the second launch (on c1 shapes with 8192 points, 240 against 196 us)
+  // then still fills the chip. The G workgroup sums go to the separate epilogue kernel (the
+  // set-up in either kernel): at these workgroup counts the last-arriver's device-scope fences
+  // cost more than the second launch (on c1 shapes with 8192 points, 240 against 196 us)
   LoopShape sh = choose_shape(ev, B, mixed, false);
   const int64_t want = (4 * 2 * 256 + sh.npg - 1) / sh.npg;
   const int64_t gcap = std::max<int64_t>(1, ev->M / (32 * (int64_t)sh.W));
@@ -756,8 +756,12 @@ gwl_status run_calibrated(gwl_event ev, const double* theta, int64_t B, bool mix
   return run_logl_cal(ev, theta, B, mixed, grad, logl, gradout, s, ws, ws_bytes);
 }
 
+// The set-up rows [NCOEF][Bp] come first unless the evaluation kernel makes them itself and
+// nothing after it reads them (with the separate value epilogue it leaves that kernel's rows there)
+static bool coef_in_workspace(const LoopShape& sh, bool grad) { return !sh.setup || (!grad && sh.G > 1 && sh.sepepi); }
+
 size_t workspace_bytes(int64_t Bp, const LoopShape& sh, int nd, bool grad) {
-  const size_t coef = sh.setup ? 0 : (size_t)NCOEF * Bp;
+  const size_t coef = coef_in_workspace(sh, grad) ? (size_t)NCOEF * Bp : 0;
   const size_t part = (grad || sh.G > 1) ? (size_t)sh.G * nz_of(nd, grad) * Bp : 0;
   return sizeof(double) * (coef + part);
 }
@@ -876,8 +880,9 @@ hipError_t enqueue_logl(gwl_event ev, const double* theta, int64_t B, bool mixed
                         double* ws, unsigned int* cnt, double* logl, double* gradout, hipStream_t s,
                         const int64_t* live) {
   const int64_t Bp = (int64_t)sh.npg * WAVE;
-  double* coef = sh.setup ? nullptr : ws;
-  double* part = (grad || sh.G > 1) ? ws + (sh.setup ? 0 : (size_t)NCOEF * Bp) : nullptr;
+  const bool with_coef = coef_in_workspace(sh, grad);
+  double* coef = with_coef ? ws : nullptr;
+  double* part = (grad || sh.G > 1) ? ws + (with_coef ? (size_t)NCOEF * Bp : 0) : nullptr;
   hipError_t e = hipSuccess;
   if (!sh.setup) e = launch_setup(ev->ndet, ev->geom, ev->ec, mixed, theta, B, Bp, coef, s);
   hipEvent_t pa = nullptr, pb = nullptr;

@@ -241,10 +241,10 @@ gwl_status gwl_autotune(const char* cache_path, gwl_event ev, int64_t B, gwl_pre
     shapes.push_back(sh);
   };
   // the value's reduction over G > 1 workgroups either by the last workgroup (fenced) or by the
-  // separate epilogue kernel (with the set-up kernel only)
+  // separate epilogue kernel
   auto add = [&](int W, int G, int setup) {
     add1(W, G, setup, 0);
-    if (!grad && G > 1 && !setup) add1(W, G, setup, 1);
+    if (!grad && G > 1) add1(W, G, setup, 1);
   };
   add(h.W, h.G, h.setup);
   const int ws_[] = {4, 5, 8, 10, 16};

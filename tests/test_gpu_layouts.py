@@ -93,9 +93,9 @@ def test_out_of_range_point_is_nan_with_the_split_setup(events, tmp_path):
     t = torch.tensor(th, device=DEV)
     path = str(tmp_path / "layout.json")
     try:
-        for setup in (1, 0):
+        for setup, sepepi in ((1, 0), (1, 1), (0, 0), (0, 1)):
             for grad in (False, True):
-                load_layout(path, 1, len(f), "fp64", grad, len(th), 16, 8, setup)
+                load_layout(path, 1, len(f), "fp64", grad, len(th), 16, 8, setup, sepepi if not grad else 0)
                 if grad:
                     v, g = gw.logl_grad(t, ev, "fp64")
                     g = g.cpu().numpy()
@@ -112,18 +112,21 @@ def test_out_of_range_point_is_nan_with_the_split_setup(events, tmp_path):
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_separate_value_epilogue_matches_the_last_workgroup(events, cfg, prec, tmp_path):
     """The value's reduction over G workgroups by the separate epilogue kernel gives the bits of
-    the last-arriving workgroup's reduction (same order, same epilogue arithmetic), also for the
-    first rows of a live-length call."""
+    the last-arriving workgroup's reduction (same order, same epilogue arithmetic), with the
+    set-up in its own kernel or in the evaluation kernel (whose first workgroup per point group
+    then leaves the epilogue's rows), also for the first rows of a live-length call."""
     spec, f, psd, data, dets, ev, th = events[cfg]
     t = torch.tensor(th, device=DEV)
     path = str(tmp_path / "layout.json")
     try:
         for waves, groups in ((16, 8), (4, 3), (1, 16)):
             got = []
-            for sepepi in (0, 1):
-                load_layout(path, len(dets), len(f), prec, False, len(th), waves, groups, 0, sepepi)
-                got.append(gw.logl(t, ev, prec).cpu().numpy())
-            assert np.array_equal(got[0], got[1]), (waves, groups)
+            for setup in (0, 1):
+                for sepepi in (0, 1):
+                    load_layout(path, len(dets), len(f), prec, False, len(th), waves, groups, setup, sepepi)
+                    got.append(gw.logl(t, ev, prec).cpu().numpy())
+            for other in got[1:]:
+                assert np.array_equal(got[0], other), (waves, groups)
         live = torch.tensor([len(th) // 3], dtype=torch.int64, device=DEV)
         out = torch.full((len(th),), 7.0, dtype=torch.float64, device=DEV)
         gw.logl_live(t, live, ev, prec, out=out)
@@ -139,7 +142,7 @@ def test_separate_value_epilogue_matches_the_last_workgroup(events, cfg, prec, t
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_separate_value_epilogue_with_the_isco_cutoff(prec, tmp_path):
     """With the ISCO cut-off the separate epilogue takes each point's kept share of K_det as the
-    fused one does: bitwise equal values."""
+    fused one does: bitwise equal values, with the set-up in either kernel."""
     spec, f, psd, data, dets = event_inputs(1, f_hi=600.0)
     ev = gw.Event(torch.tensor(data, device=DEV), torch.tensor(psd, device=DEV), dets,
                   torch.tensor(f, device=DEV), spec.df, isco_cutoff=True)
@@ -149,10 +152,11 @@ def test_separate_value_epilogue_with_the_isco_cutoff(prec, tmp_path):
     path = str(tmp_path / "layout.json")
     try:
         got = []
-        for sepepi in (0, 1):
-            load_layout(path, len(dets), len(f), prec, False, len(th), 8, 4, 0, sepepi)
-            got.append(gw.logl(t, ev, prec).cpu().numpy())
-        assert np.all(np.isfinite(got[0])) and np.array_equal(got[0], got[1])
+        for setup in (0, 1):
+            for sepepi in (0, 1):
+                load_layout(path, len(dets), len(f), prec, False, len(th), 8, 4, setup, sepepi)
+                got.append(gw.logl(t, ev, prec).cpu().numpy())
+        assert np.all(np.isfinite(got[0])) and all(np.array_equal(got[0], x) for x in got[1:])
     finally:
         ev.close()
         gw.autotune_load(CACHE)
