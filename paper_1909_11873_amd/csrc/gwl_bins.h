@@ -24,8 +24,10 @@ constexpr int NB = 8;  // bins per float32 block before the float64 flush (mixed
 // of sin(2 pi y) and cos(2 pi y) divided by powers of N (exact).
 constexpr int PH_TBL = 2048;
 static __device__ const PhasorTable<PH_TBL> kPhasorTable = make_phasor_table<PH_TBL>();
-__device__ __forceinline__ void fill_phasor_table(double2* tbl) {
-  for (int k = threadIdx.x; k < PH_TBL; k += blockDim.x) tbl[k] = make_double2(kPhasorTable.e[k].c, kPhasorTable.e[k].s);
+__device__ __forceinline__ void fill_phasor_table(double2* tbl, int first = 0) {
+  // by threads first .. blockDim.x - 1
+  for (int k = (int)threadIdx.x - first; k < PH_TBL; k += (int)blockDim.x - first)
+    tbl[k] = make_double2(kPhasorTable.e[k].c, kPhasorTable.e[k].s);
 }
 template <int ND>
 __device__ __forceinline__ void to_table_units(double (&a)[NBASIS], double (&T)[ND]) {

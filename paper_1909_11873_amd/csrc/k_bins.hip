@@ -180,7 +180,12 @@ __attribute__((amdgpu_waves_per_eu(eval_waves_per_eu<ND, MIXED, GRAD, SETUP, CUT
     k1 = k1 < kmax ? k1 : (kmax > k0 ? kmax : k0);
   }
 
-  if constexpr (!MIXED) fill_phasor_table(tbl);
+  // the float64 phasor table; with the in-kernel set-up and three or more wavefronts, the ones
+  // that do not run a half of the set-up fill it meanwhile
+  if constexpr (!MIXED) {
+    if (!SETUP || sh.W < 3) fill_phasor_table(tbl);
+    else if (w >= 2) fill_phasor_table(tbl, 2 * WAVE);
+  }
   // in-kernel set-up: the intrinsic half on wavefront 0, the extrinsic half on wavefront 1 (on
   // wavefront 0 too when the workgroup has one)
   if constexpr (SETUP) {
